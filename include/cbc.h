@@ -1,0 +1,135 @@
+/*
+ * cbc.h -- C ABI of the MI355X (gfx950) Cholesky-based compression library.
+ *
+ * The library applies a tree tensor network operator (TTNO; an MPO on a chain) to a tree tensor
+ * network state (TTNS; an MPS on a chain) and compresses the product to a target bond dimension,
+ * following Milbradt, Sun, Mendl, Gray, Chan, "Efficient Application of Tensor Network Operators to
+ * Tensor Network States" (arXiv 2601.19650):
+ *   - the problem statement, computing O|psi> for O and psi given as tree tensor networks
+ *     (Sec. I, Eq. abstr_application; Sec. II, Eqs. ttns and ttno);
+ *   - the compression of Sec. III A (tensor trains) and Sec. III B (general trees): environment
+ *     contractions, truncation of the joined leg to the target dimension, QR on the parent leg and
+ *     the environment update, with the output rule closing each subsection;
+ *   - the optional tolerance-adaptive bond dimension of Sec. V;
+ *   - the naive "contract, then compress with truncated SVDs" method of Sec. III C.
+ *
+ * Data model (Sec. II A-C):
+ *   - a rooted tree of n nodes: parent[i] in [0, n) or -1 for exactly one root. The children of i
+ *     are the nodes j with parent[j] == i, in increasing j.
+ *   - state node i has legs (sigma_i, alpha_parent, alpha_child_1, ..., alpha_child_K) and the
+ *     operator node (sigma'_i, sigma_i, beta_parent, beta_child_1, ..., beta_child_K). Tensors are
+ *     stored row-major (last leg fastest) as interleaved complex128 (re, im). The root's parent leg
+ *     is a trivial leg of dimension 1. A node may have d_i = 1 (no physical leg, Sec. II A).
+ *   - all node tensors of one network live in one device buffer; offset[i] is the element offset of
+ *     node i (one element = one complex number).
+ *
+ * Numerics (precision argument):
+ *   CBC_PREC_FP64  -- every contraction, Gram matrix, eigensolve and Cholesky factorisation in FP64.
+ *   CBC_PREC_MIXED -- contractions in FP32 (complex through real MFMA products, FP32 accumulation);
+ *                     Gram matrices are accumulated in FP64, and eigensolves, Cholesky factorisations
+ *                     and triangular inverses run in FP64.
+ *   Truncation keeps the top-k eigenspace of the FP64 Gram matrix of the joined-leg matrix, which is
+ *   the truncated SVD the paper uses, reached through its Gram matrix. The QR on the parent leg is a
+ *   shifted Cholesky-QR with two re-orthogonalisation passes (Cholesky-QR3). Pivots that vanish
+ *   (rank-deficient input) are dropped, which leaves zero slices on that bond.
+ *
+ * Ownership: the caller owns all device memory (inputs, workspace, outputs). The library never frees
+ * caller memory. A context owns only its plan cache (device offset tables, captured graphs), which is
+ * released by cbc_destroy. One context per host thread; a context must not be used concurrently.
+ *
+ * Streams: calls are stream-ordered on the given hipStream_t (passed as void*; NULL = null stream).
+ * cbc_apply synchronises the stream once at the end to return the output bond dimensions.
+ *
+ * Errors: every entry point returns a cbc_status; nothing aborts or throws across the ABI. All
+ * argument validation happens on the host before any device work is queued.
+ */
+#ifndef CBC_H
+#define CBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CBC_OK = 0,
+  CBC_EINVAL = -1,     /* null pointer, max_bond < 1, tol < 0 or not finite, bad precision */
+  CBC_ESHAPE = -2,     /* bad topology (no/two roots, cycle, parent out of range) or dims */
+  CBC_ENOMEM = -3,     /* workspace smaller than cbc_query reported, or a context allocation failed */
+  CBC_EHIP = -4,       /* a HIP runtime call failed */
+  CBC_ENOTPD = -5,     /* reserved: a factorisation failed even after its fallbacks */
+  CBC_EUNSUP = -6,     /* valid input outside what this build supports (see cbc_status_str) */
+  CBC_ENOTBUILT = -7   /* library built without a usable device (no gfx950 GPU visible) */
+} cbc_status;
+
+typedef enum { CBC_PREC_FP64 = 0, CBC_PREC_MIXED = 1 } cbc_precision;
+
+typedef struct cbc_ctx cbc_ctx;
+
+/* Tree and dimensions (host arrays, read during the call only). */
+typedef struct {
+  int32_t n_nodes;
+  const int32_t* parent;   /* parent[i], -1 for the root */
+  const int32_t* phys;     /* d_i >= 1 */
+  const int32_t* chi;      /* state bond of node i to its parent (1 at the root) */
+  const int32_t* dop;      /* operator bond of node i to its parent (1 at the root) */
+} cbc_tree;
+
+/* A network's node tensors: one device buffer of interleaved complex128, host offset array. */
+typedef struct {
+  const void* data;        /* device pointer */
+  const int64_t* offset;   /* host, n_nodes entries, element offsets into data */
+} cbc_tensors;
+
+/* The compressed state. Node i is written at out_offset[i] (from cbc_query) with legs
+ * (sigma_i, bond_parent, bond_child_1, ...) as interleaved complex128; bond[] is written on return. */
+typedef struct {
+  void* data;              /* device pointer, at least out_offset[n_nodes] elements */
+  const int64_t* offset;   /* host, n_nodes + 1 entries as returned by cbc_query */
+  int32_t* bond;           /* host, n_nodes entries: bond of node i to its parent (1 at the root) */
+} cbc_out;
+
+/* Per-call statistics (optional). */
+typedef struct {
+  double contraction_flops;   /* algorithmic flops of the contractions (8 per complex MAC) */
+  double gram_flops;          /* algorithmic flops of the FP64 Gram matrices (8 per complex MAC) */
+  int32_t n_eig;              /* eigensolves performed */
+  int32_t max_eig_dim;        /* largest Gram matrix that was eigensolved */
+  int32_t n_kernels;          /* kernels launched per call */
+  int32_t graph_replayed;     /* 1 if the call replayed a cached hipGraph */
+} cbc_stats;
+
+/* Create / destroy a context. */
+cbc_status cbc_create(cbc_ctx** ctx);
+void cbc_destroy(cbc_ctx* ctx);
+const char* cbc_status_str(cbc_status s);
+
+/* Sizes for a problem: workspace bytes and the output packing (n_nodes + 1 offsets; the last entry is
+ * the total number of complex elements the output buffer must hold). Host only, no device work.
+ * `method` is 0 for cbc_apply and 1 for cbc_apply_naive. */
+cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
+                     int32_t method, size_t* workspace_bytes, int64_t* out_offset);
+
+/* Cholesky-based compression of O|psi> (Sec. III A for chains, Sec. III B for trees).
+ * max_bond >= 1 is the target bond dimension (the paper's D-bar); tol >= 0 additionally drops
+ * directions whose singular value is at most tol times the largest one at that truncation (tol = 0
+ * keeps min(max_bond, rank bound) directions). workspace must hold cbc_query's workspace_bytes. */
+cbc_status cbc_apply(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                     const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
+                     void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
+                     cbc_stats* stats);
+
+/* Naive baseline (Sec. III C, "direct"): contract O|psi> exactly (bonds chi*D), bring it into
+ * canonical form toward the root with Cholesky-QR, then truncate every bond with the top-k
+ * eigenspace of its Gram matrix in a depth-first sweep from the root. Same arguments as cbc_apply. */
+cbc_status cbc_apply_naive(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                           const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
+                           void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
+                           cbc_stats* stats);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CBC_H */

@@ -1,0 +1,42 @@
+/*
+ * cbc_testing.h -- kernel-level entry points of libcbc.so, used by the test suite to check single
+ * steps of the compression on the GPU in isolation. They allocate their own scratch with hipMalloc
+ * and synchronise the stream; they are not part of the production path.
+ *
+ * All matrices are row-major, interleaved complex (complex64 if the *_c128 flag is 0, complex128
+ * otherwise), device pointers. Return values are cbc_status codes from cbc.h.
+ */
+#ifndef CBC_TESTING_H
+#define CBC_TESTING_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* C (M x N) = op(A) op(B), op(X) = X, X^T, conj(X) or X^H by (trans, conj). A is stored M x K (or
+ * K x M if transA), B is K x N (or N x K if transB). acc_fp64 selects FP64 MFMA accumulation,
+ * otherwise FP32 MFMA. tile: 0 = 32x32, 1 = 64x64. This is the contraction kernel of every sweep. */
+int cbc_test_gemm(int M, int N, int K, const void* A, int a_c128, int transA, int conjA,
+                  const void* B, int b_c128, int transB, int conjB, void* C, int c_c128,
+                  int acc_fp64, int tile, void* stream);
+
+/* Truncation eigensolve (Sec. III A "compress ... for example via singular value decomposition",
+ * realised on the FP64 Gram matrix): G (s x s complex128 Hermitian, overwritten) -> U (s x kmax
+ * complex128, top eigenvectors as columns, zero beyond the kept count), lam (kmax doubles,
+ * descending), kkeep (1 int), inv_sqrt_l0 (1 double). */
+int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void* lam, void* kkeep,
+                 void* inv_sqrt_l0, void* stream);
+
+/* One Cholesky + triangular inverse step of the QR on the parent leg (Sec. III A, Eq.
+ * tt_cbc_qr_decomp, realised as Cholesky-QR): G (k x k complex128 Hermitian PSD, overwritten) ->
+ * Cinv (k x k complex128, inverse of the lower Cholesky factor; zero rows and columns for dropped
+ * pivots); shift_rel adds shift_rel * trace(G) to the diagonal first. ndrop (1 int) receives the
+ * number of dropped pivots. */
+int cbc_test_chol_inv(void* G, int k, double shift_rel, double drop_rel, void* Cinv, void* ndrop,
+                      void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,1024 @@
+// C ABI, host-side validation, planner and executor for Cholesky-based compression on gfx950.
+//
+// The planner turns a tree, its dimensions, a target bond dimension and a precision into a static
+// sequence of kernel launches: every tensor shape is fixed by max_bond before any device work, so a
+// call is a fixed launch sequence (and is replayed from a captured hipGraph after the first call).
+// Data-dependent truncation by a tolerance only zeroes slices on device.
+//
+// Sweeps (Sec. III B; Sec. III A is the chain rooted at its first site, which needs only sweeps 2-3):
+//   1. leaves -> root : L^{[i]}     from T, W and the children's L^{[c]} (Eq. cbc_tree_first_contraction)
+//   2. root -> leaves : L^{[(i,k)]} from T, W, L^{[(p,i)]} and siblings' L^{[c]} (Eq. cbc_tree_second_contraction)
+//   3. leaves -> root : Z = T W prod_c R^{[c]}; S = L^{[(p,i)]} Z (Eq. cbc_tree_third_contraction);
+//      QR on the parent leg (Eq. cbc_tree_qr); R^{[i]} = Q^* Z (Eq. cbc_final_contraction, with the
+//      conjugate as in the tensor-train update); the root keeps S.
+// Each truncation joins (sigma', chi...) and keeps the top-k eigenspace of the FP64 Gram matrix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/cbc.h"
+#include "cbc_internal.h"
+
+using namespace cbc;
+
+namespace {
+
+// ------------------------------------------------------------------------------------------------
+// plan representation
+
+enum Src : int { S_NONE = -1, S_WS = 0, S_SCR = 1, S_STATE = 2, S_OP = 3, S_OUT = 4 };
+
+struct TRef {
+  int src = S_NONE;
+  int64_t off = 0;   // bytes for S_WS/S_SCR; node index for S_STATE/S_OP/S_OUT
+  DType dt = DT_C128;
+};
+
+struct Ten {
+  TRef ref;
+  std::vector<int> legs;
+};
+
+enum OpKind : int { K_GEMM, K_EIG, K_FORM_N, K_CHOL, K_CONVERT, K_IDENT, K_WRITE, K_ZERO };
+
+struct Op {
+  OpKind kind;
+  // GEMM
+  TRef A, B, C;
+  int M = 0, N = 0, K = 0;
+  int64_t tAm = 0, tAk = 0, tBk = 0, tBn = 0, tCm = 0, tCn = 0;
+  int conjA = 0, conjB = 0, akf = 0, bkf = 0, tile = 0;
+  DType ta = DT_C128, tb = DT_C128, tc = DT_C128, acc = DT_C128;
+  double alpha = 1.0;
+  TRef adev, adev2;
+  // EIG / FORM_N / CHOL
+  TRef G, U, lam, kkeep, invs, work, Cinv, logs, scale, ndrop, L;
+  int s = 0, kmax = 0, n = 0;
+  double shift_rel = 0.0, drop_rel = 0.0;
+  // CONVERT / IDENT / WRITE / ZERO
+  TRef src, dst;
+  DType ts = DT_C128, td = DT_C128;
+  int64_t count = 0;
+  int a = 0, b = 0;
+  int64_t rest = 0;
+  int nlogs = 0;
+};
+
+struct Plan {
+  std::vector<Op> ops;
+  std::vector<int32_t> tables;
+  int32_t* d_tables = nullptr;
+  size_t persist_bytes = 0, scratch_bytes = 0;
+  std::vector<int64_t> out_off;
+  std::vector<int32_t> out_bond;
+  double cflops = 0.0, gflops = 0.0;
+  int n_eig = 0, max_eig = 0;
+  // misc device slots (persistent workspace offsets)
+  int64_t logs_off = 0, ndrop_off = 0;
+  int64_t state_conv_off = -1, op_conv_off = -1;
+  int64_t state_elems = 0, op_elems = 0;
+  // captured graph
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uintptr_t> gkey;
+  ~Plan() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (d_tables) (void)hipFree(d_tables);
+  }
+};
+
+struct Problem {
+  int n;
+  std::vector<int> parent, phys, chi, dop;
+  std::vector<std::vector<int>> ch;
+  int root;
+  std::vector<int> post;  // children before parents
+};
+
+// ------------------------------------------------------------------------------------------------
+// validation
+
+cbc_status validate_tree(const cbc_tree* t, Problem& P) {
+  if (!t || !t->parent || !t->phys || !t->chi || !t->dop) return CBC_EINVAL;
+  const int n = t->n_nodes;
+  if (n < 1 || n > (1 << 20)) return CBC_ESHAPE;
+  P.n = n;
+  P.parent.assign(t->parent, t->parent + n);
+  P.phys.assign(t->phys, t->phys + n);
+  P.chi.assign(t->chi, t->chi + n);
+  P.dop.assign(t->dop, t->dop + n);
+  P.root = -1;
+  for (int i = 0; i < n; ++i) {
+    const int p = P.parent[i];
+    if (p == -1) {
+      if (P.root >= 0) return CBC_ESHAPE;
+      P.root = i;
+    } else if (p < 0 || p >= n || p == i) {
+      return CBC_ESHAPE;
+    }
+    if (P.phys[i] < 1 || P.chi[i] < 1 || P.dop[i] < 1) return CBC_ESHAPE;
+    if (P.phys[i] > 65536 || P.chi[i] > 65536 || P.dop[i] > 65536) return CBC_ESHAPE;
+  }
+  if (P.root < 0) return CBC_ESHAPE;
+  if (P.chi[P.root] != 1 || P.dop[P.root] != 1) return CBC_ESHAPE;
+  // every node must reach the root (no cycles)
+  for (int i = 0; i < n; ++i) {
+    int j = i, steps = 0;
+    while (j != P.root) {
+      j = P.parent[j];
+      if (++steps > n) return CBC_ESHAPE;
+    }
+  }
+  P.ch.assign(n, {});
+  for (int i = 0; i < n; ++i)
+    if (P.parent[i] >= 0) P.ch[P.parent[i]].push_back(i);
+  // post-order (iterative)
+  P.post.clear();
+  std::vector<std::pair<int, int>> st{{P.root, 0}};
+  while (!st.empty()) {
+    auto& [node, idx] = st.back();
+    if (idx < (int)P.ch[node].size()) {
+      const int c = P.ch[node][idx++];
+      st.push_back({c, 0});
+    } else {
+      P.post.push_back(node);
+      st.pop_back();
+    }
+  }
+  return CBC_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// planner
+
+struct Builder {
+  Plan& P;
+  const Problem& pr;
+  int max_bond;
+  bool tol_on;
+  DType ct, cacc;           // contraction storage type and accumulator
+  std::vector<int64_t> legdim;
+  size_t persist = 0, scratch = 0, scratch_max = 0;
+
+  Builder(Plan& p, const Problem& q, int mb, bool tol, cbc_precision prec)
+      : P(p), pr(q), max_bond(mb), tol_on(tol) {
+    ct = prec == CBC_PREC_MIXED ? DT_C64 : DT_C128;
+    cacc = ct;
+  }
+
+  int leg(int64_t d) {
+    legdim.push_back(d);
+    return (int)legdim.size() - 1;
+  }
+  static size_t esz(DType t) { return t == DT_C128 ? 16 : 8; }
+  static size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+  TRef wsp(size_t bytes, DType dt) {
+    TRef r;
+    r.src = S_WS;
+    r.off = (int64_t)persist;
+    r.dt = dt;
+    persist += al(bytes);
+    return r;
+  }
+  TRef scr(size_t bytes, DType dt) {
+    TRef r;
+    r.src = S_SCR;
+    r.off = (int64_t)scratch;
+    r.dt = dt;
+    scratch += al(bytes);
+    scratch_max = std::max(scratch_max, scratch);
+    return r;
+  }
+  void reset_scratch() { scratch = 0; }
+  int64_t elems(const std::vector<int>& legs) const {
+    int64_t e = 1;
+    for (int l : legs) e *= legdim[l];
+    return e;
+  }
+  Ten alloc(const std::vector<int>& legs, DType dt, bool persistent) {
+    Ten t;
+    t.legs = legs;
+    const size_t bytes = (size_t)elems(legs) * esz(dt);
+    t.ref = persistent ? wsp(bytes, dt) : scr(bytes, dt);
+    return t;
+  }
+  std::vector<int64_t> strides(const std::vector<int>& legs) const {
+    std::vector<int64_t> s(legs.size());
+    int64_t acc = 1;
+    for (int i = (int)legs.size() - 1; i >= 0; --i) {
+      s[i] = acc;
+      acc *= legdim[legs[i]];
+    }
+    return s;
+  }
+  static int pos(const std::vector<int>& v, int x) {
+    for (int i = 0; i < (int)v.size(); ++i)
+      if (v[i] == x) return i;
+    return -1;
+  }
+  // enumerate a multi-index over `legs` (last fastest) -> offsets in two tensors
+  int64_t table(const std::vector<int>& legs, const std::vector<int64_t>& s1,
+                const std::vector<int64_t>& s2, int64_t& t2) {
+    int64_t cnt = 1;
+    for (int l : legs) cnt *= legdim[l];
+    const int64_t t1 = (int64_t)P.tables.size();
+    P.tables.resize(P.tables.size() + 2 * cnt);
+    t2 = t1 + cnt;
+    std::vector<int64_t> idx(legs.size(), 0);
+    for (int64_t e = 0; e < cnt; ++e) {
+      int64_t o1 = 0, o2 = 0;
+      for (size_t j = 0; j < legs.size(); ++j) {
+        o1 += idx[j] * s1[j];
+        o2 += idx[j] * s2[j];
+      }
+      P.tables[t1 + e] = (int32_t)o1;
+      P.tables[t2 + e] = (int32_t)o2;
+      for (int j = (int)legs.size() - 1; j >= 0; --j) {
+        if (++idx[j] < legdim[legs[j]]) break;
+        idx[j] = 0;
+      }
+    }
+    return t1;
+  }
+
+  // C[out] = alpha * sum opA(A) opB(B); legs shared by A and B and absent from `out` are summed.
+  Ten contract(const Ten& A, bool conjA, const Ten& B, bool conjB, const std::vector<int>& out,
+               const TRef& Cref, DType tc, DType acc, int bucket, double alpha = 1.0,
+               TRef adev = TRef(), TRef adev2 = TRef()) {
+    std::vector<int> ml, nl, kl;
+    for (int l : A.legs) {
+      if (pos(out, l) >= 0) ml.push_back(l);
+      else if (pos(B.legs, l) >= 0) kl.push_back(l);
+      else { fprintf(stderr, "cbc: dangling leg\n"); abort(); }
+    }
+    for (int l : B.legs) {
+      if (pos(out, l) >= 0) nl.push_back(l);
+      else if (pos(A.legs, l) < 0) { fprintf(stderr, "cbc: dangling leg\n"); abort(); }
+    }
+    const auto sA = strides(A.legs), sB = strides(B.legs), sC = strides(out);
+    auto pick = [&](const std::vector<int>& legs, const std::vector<int>& of,
+                    const std::vector<int64_t>& st) {
+      std::vector<int64_t> r;
+      for (int l : legs) r.push_back(st[pos(of, l)]);
+      return r;
+    };
+    Op op;
+    op.kind = K_GEMM;
+    op.A = A.ref;
+    op.B = B.ref;
+    op.C = Cref;
+    op.M = (int)elems(ml);
+    op.N = (int)elems(nl);
+    op.K = (int)elems(kl);
+    op.tAm = table(ml, pick(ml, A.legs, sA), pick(ml, out, sC), op.tCm);
+    op.tBn = table(nl, pick(nl, B.legs, sB), pick(nl, out, sC), op.tCn);
+    op.tAk = table(kl, pick(kl, A.legs, sA), pick(kl, B.legs, sB), op.tBk);
+    op.conjA = conjA;
+    op.conjB = conjB;
+    op.akf = !A.legs.empty() && pos(kl, A.legs.back()) >= 0;
+    op.bkf = !B.legs.empty() && pos(kl, B.legs.back()) >= 0;
+    op.ta = A.ref.dt;
+    op.tb = B.ref.dt;
+    op.tc = tc;
+    op.acc = acc;
+    op.alpha = alpha;
+    op.adev = adev;
+    op.adev2 = adev2;
+    op.tile = ((int64_t)op.M * op.N >= (int64_t)64 * 64 * 96) ? 1 : 0;
+    const double f = 8.0 * (double)op.M * op.N * op.K;
+    if (bucket == 0) P.cflops += f;
+    else if (bucket == 1) P.gflops += 0.5 * f;
+    else P.gflops += f;
+    P.ops.push_back(op);
+    Ten r;
+    r.ref = Cref;
+    r.ref.dt = tc;
+    r.legs = out;
+    return r;
+  }
+
+  // ---- problem-level legs ----
+  std::vector<int> sig, sigp, ealpha, ebeta;  // per node; edge legs indexed by child node
+  int rootA = -1, rootB = -1;
+  std::vector<int> slot_alpha(int i) const {
+    std::vector<int> v{pr.parent[i] >= 0 ? ealpha[i] : rootA};
+    for (int c : pr.ch[i]) v.push_back(ealpha[c]);
+    return v;
+  }
+  std::vector<int> slot_beta(int i) const {
+    std::vector<int> v{pr.parent[i] >= 0 ? ebeta[i] : rootB};
+    for (int c : pr.ch[i]) v.push_back(ebeta[c]);
+    return v;
+  }
+  TRef node_ref(int src, int i) const {
+    TRef r;
+    r.src = src;
+    r.off = i;
+    r.dt = ct;
+    return r;
+  }
+
+  // X = T_i absorbed with envs (slot -> env tensor [chi, alpha, beta]); then contracted with W_i.
+  Ten node_contract(int i, const std::vector<std::pair<int, Ten>>& envs, const std::vector<int>& out,
+                    const TRef& dst) {
+    const auto sa = slot_alpha(i), sb = slot_beta(i);
+    Ten T;
+    T.ref = node_ref(S_STATE, i);
+    T.legs.push_back(sig[i]);
+    for (int l : sa) T.legs.push_back(l);
+    Ten W;
+    W.ref = node_ref(S_OP, i);
+    W.legs = {sigp[i], sig[i]};
+    for (int l : sb) W.legs.push_back(l);
+    Ten X = T;
+    std::vector<bool> absorbed(sa.size(), false);
+    for (const auto& [slot, E] : envs) {
+      std::vector<int> o;
+      for (int l : X.legs)
+        if (l != sa[slot]) o.push_back(l);
+      o.push_back(E.legs[0]);
+      o.push_back(E.legs[2]);
+      Ten Xn = alloc(o, ct, false);
+      X = contract(X, false, E, false, o, Xn.ref, ct, cacc, 0);
+      absorbed[slot] = true;
+    }
+    return contract(X, false, W, false, out, dst, ct, cacc, 0);
+  }
+
+  // Truncate the joined leg of Lp (legs: row legs..., a_o, b_o) -> L [chi_new, a_o, b_o] (persistent).
+  Ten truncate(const Ten& Lp, int a_o, int b_o, bool& alias_ok) {
+    std::vector<int> rows(Lp.legs.begin(), Lp.legs.end() - 2);
+    const int64_t m = elems(rows), n = legdim[a_o] * legdim[b_o];
+    const int64_t kmax = std::min<int64_t>({(int64_t)max_bond, m, n});
+    alias_ok = false;
+    if (!tol_on && m <= max_bond && m <= n) {
+      // nothing to truncate: L = L' (the joined leg becomes the new leg)
+      alias_ok = true;
+      const int nl = leg(m);
+      Ten L;
+      L.ref = Lp.ref;
+      L.legs = {nl, a_o, b_o};
+      return L;
+    }
+    const int r = leg(m), c = leg(n), r2 = leg(m), c2 = leg(n);
+    Ten M1{Lp.ref, {r, c}}, M2{Lp.ref, {r2, c}}, M3{Lp.ref, {r, c2}};
+    const int nl = leg(kmax);
+    Ten L = alloc({nl, a_o, b_o}, ct, true);
+    const bool mside = m <= n;
+    const int s = (int)(mside ? m : n);
+    Ten G = alloc(mside ? std::vector<int>{r, r2} : std::vector<int>{c, c2}, DT_C128, false);
+    if (mside) contract(M1, false, M2, true, {r, r2}, G.ref, DT_C128, DT_C128, 1);  // M M^H
+    else contract(M1, true, M3, false, {c, c2}, G.ref, DT_C128, DT_C128, 1);       // M^H M
+    Ten U = alloc({mside ? r : c, nl}, DT_C128, false);
+    TRef lam = scr(sizeof(double) * kmax, DT_C128);
+    TRef kk = scr(256, DT_C128);
+    TRef invs = scr(256, DT_C128);
+    TRef work = scr(sizeof(double) * eig_work_doubles(s, (int)kmax), DT_C128);
+    Op e;
+    e.kind = K_EIG;
+    e.G = G.ref;
+    e.s = s;
+    e.kmax = (int)kmax;
+    e.U = U.ref;
+    e.lam = lam;
+    e.kkeep = kk;
+    e.invs = invs;
+    e.work = work;
+    P.ops.push_back(e);
+    P.n_eig++;
+    P.max_eig = std::max(P.max_eig, s);
+    if (mside) {
+      // L = U^H M / sqrt(lambda_0)
+      Ten Uv{U.ref, {r, nl}};
+      Ten Mv{Lp.ref, {r, a_o, b_o}};
+      contract(Uv, true, Mv, false, {nl, a_o, b_o}, L.ref, ct, cacc, 0, 1.0, invs);
+    } else {
+      Op f;
+      f.kind = K_FORM_N;
+      f.U = U.ref;
+      f.lam = lam;
+      f.kkeep = kk;
+      f.n = (int)n;
+      f.kmax = (int)kmax;
+      f.L = L.ref;
+      f.td = ct;
+      P.ops.push_back(f);
+    }
+    return L;
+  }
+
+  // Q-factor of S [k, rest...] on its first leg: returns Q [k_new, rest...] (scratch, complex128)
+  // and the per-node scale slot. k < prod(rest) is required.
+  Ten cholqr(const Ten& S, int knew_leg, TRef logslot, TRef scaleslot) {
+    const int k = (int)legdim[S.legs[0]];
+    std::vector<int> rest(S.legs.begin() + 1, S.legs.end());
+    const int64_t ns = elems(rest);
+    const int kr = S.legs[0];
+    const int kc = leg(k);
+    Ten cur = S;
+    int cur_row = kr;
+    const double u = 1.1102230246251565e-16;
+    for (int pass = 0; pass < 3; ++pass) {
+      // Gram of the current factor: G[r, r'] = sum cur[r, rest] conj(cur[r', rest])
+      std::vector<int> l2{kc};
+      for (int l : rest) l2.push_back(l);
+      Ten curb{cur.ref, l2};
+      Ten G = alloc({cur_row, kc}, DT_C128, false);
+      contract(cur, false, curb, true, {cur_row, kc}, G.ref, DT_C128, DT_C128, 1);
+      Ten Ci = alloc({knew_leg, cur_row}, DT_C128, false);
+      Op c;
+      c.kind = K_CHOL;
+      c.G = G.ref;
+      c.s = k;
+      c.shift_rel = pass == 0 ? 11.0 * ((double)ns * k + (double)k * (k + 1)) * u : 0.0;
+      c.drop_rel = pass == 0 ? 0.0 : 1e-13;
+      c.Cinv = Ci.ref;
+      if (pass == 0) {
+        c.logs = logslot;
+        c.scale = scaleslot;
+      }
+      TRef nd;
+      nd.src = S_WS;
+      nd.off = P.ndrop_off;
+      c.ndrop = nd;
+      P.ops.push_back(c);
+      // Q = C^{-1} cur
+      std::vector<int> qo{knew_leg};
+      for (int l : rest) qo.push_back(l);
+      Ten Q = alloc(qo, DT_C128, false);
+      contract(Ci, false, cur, false, qo, Q.ref, DT_C128, DT_C128, 2);
+      // next pass works on Q with a fresh row leg id
+      const int nr = leg(k);
+      std::vector<int> ql{nr};
+      for (int l : rest) ql.push_back(l);
+      cur = Ten{Q.ref, ql};
+      cur_row = nr;
+      if (pass == 2) return Ten{Q.ref, qo};
+    }
+    return cur;
+  }
+};
+
+cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc_precision prec) {
+  Builder B(P, pr, max_bond, tol_on, prec);
+  const int n = pr.n;
+  B.sig.resize(n);
+  B.sigp.resize(n);
+  B.ealpha.assign(n, -1);
+  B.ebeta.assign(n, -1);
+  for (int i = 0; i < n; ++i) {
+    B.sig[i] = B.leg(pr.phys[i]);
+    B.sigp[i] = B.leg(pr.phys[i]);
+    if (pr.parent[i] >= 0) {
+      B.ealpha[i] = B.leg(pr.chi[i]);
+      B.ebeta[i] = B.leg(pr.dop[i]);
+    }
+  }
+  B.rootA = B.leg(1);
+  B.rootB = B.leg(1);
+
+  // persistent device slots
+  P.logs_off = (int64_t)B.persist;
+  B.persist += Builder::al(sizeof(double) * n);
+  P.ndrop_off = (int64_t)B.persist;
+  B.persist += 256;
+  {
+    Op z;
+    z.kind = K_ZERO;
+    z.dst.src = S_WS;
+    z.dst.off = P.logs_off;
+    z.count = (int64_t)(P.ndrop_off + 256 - P.logs_off);
+    P.ops.push_back(z);
+  }
+  // mixed precision: convert inputs once
+  if (prec == CBC_PREC_MIXED) {
+    P.state_conv_off = (int64_t)B.persist;
+    B.persist += Builder::al(8 * (size_t)P.state_elems);
+    P.op_conv_off = (int64_t)B.persist;
+    B.persist += Builder::al(8 * (size_t)P.op_elems);
+    Op c1;
+    c1.kind = K_CONVERT;
+    c1.src.src = S_STATE;
+    c1.src.off = -1;
+    c1.ts = DT_C128;
+    c1.dst.src = S_WS;
+    c1.dst.off = P.state_conv_off;
+    c1.td = DT_C64;
+    c1.count = P.state_elems;
+    P.ops.push_back(c1);
+    Op c2 = c1;
+    c2.src.src = S_OP;
+    c2.dst.off = P.op_conv_off;
+    c2.count = P.op_elems;
+    P.ops.push_back(c2);
+  }
+
+  // which sweep-1 environments are consumed
+  std::vector<char> need(n, 0);
+  {
+    std::vector<int> pre(pr.post.rbegin(), pr.post.rend());
+    for (int i : pre) {
+      const int p = pr.parent[i];
+      if (p < 0) continue;
+      need[i] = (pr.ch[p].size() >= 2) || (p != pr.root && need[p]);
+    }
+  }
+  std::vector<Ten> Lsub(n), Lpar(n), R(n);
+  // sweep 1: leaves -> root
+  for (int i : pr.post) {
+    if (i == pr.root || !need[i]) continue;
+    B.reset_scratch();
+    std::vector<std::pair<int, Ten>> envs;
+    std::vector<int> out{B.sigp[i]};
+    for (size_t j = 0; j < pr.ch[i].size(); ++j) {
+      const int c = pr.ch[i][j];
+      envs.push_back({1 + (int)j, Lsub[c]});
+      out.push_back(Lsub[c].legs[0]);
+    }
+    out.push_back(B.ealpha[i]);
+    out.push_back(B.ebeta[i]);
+    const int64_t m = B.elems(std::vector<int>(out.begin(), out.end() - 2));
+    const bool alias = !tol_on && m <= max_bond && m <= (int64_t)pr.chi[i] * pr.dop[i];
+    Ten Lp = B.alloc(out, B.ct, alias);
+    Lp = B.node_contract(i, envs, out, Lp.ref);
+    bool al;
+    Lsub[i] = B.truncate(Lp, B.ealpha[i], B.ebeta[i], al);
+  }
+  // sweep 2: root -> leaves
+  {
+    std::vector<int> pre(pr.post.rbegin(), pr.post.rend());
+    for (int i : pre) {
+      for (size_t kp = 0; kp < pr.ch[i].size(); ++kp) {
+        const int k = pr.ch[i][kp];
+        B.reset_scratch();
+        std::vector<std::pair<int, Ten>> envs;
+        std::vector<int> out{B.sigp[i]};
+        if (i != pr.root) {
+          envs.push_back({0, Lpar[i]});
+          out.push_back(Lpar[i].legs[0]);
+        }
+        for (size_t j = 0; j < pr.ch[i].size(); ++j) {
+          if (j == kp) continue;
+          const int c = pr.ch[i][j];
+          envs.push_back({1 + (int)j, Lsub[c]});
+          out.push_back(Lsub[c].legs[0]);
+        }
+        if (i == pr.root) {
+          out.push_back(B.rootA);
+          out.push_back(B.rootB);
+        }
+        out.push_back(B.ealpha[k]);
+        out.push_back(B.ebeta[k]);
+        const int64_t m = B.elems(std::vector<int>(out.begin(), out.end() - 2));
+        const bool alias = !tol_on && m <= max_bond && m <= (int64_t)pr.chi[k] * pr.dop[k];
+        Ten Lp = B.alloc(out, B.ct, alias);
+        Lp = B.node_contract(i, envs, out, Lp.ref);
+        bool al;
+        Lpar[k] = B.truncate(Lp, B.ealpha[k], B.ebeta[k], al);
+      }
+    }
+  }
+  // sweep 3: leaves -> root
+  P.out_off.assign(n + 1, 0);
+  P.out_bond.assign(n, 1);
+  std::vector<int64_t> out_elems(n, 0);
+  std::vector<Op> writes;  // output writes are queued in node order at the end of each node
+  // output sizes are known only after the children are processed; first compute bonds
+  std::vector<int> kout(n, 1);
+  for (int i : pr.post) {
+    if (i == pr.root) continue;
+    int64_t ns = pr.phys[i];
+    for (int c : pr.ch[i]) ns *= kout[c];
+    const int64_t k = B.legdim[Lpar[i].legs[0]];
+    kout[i] = (int)std::min<int64_t>(k, ns);
+  }
+  for (int i = 0; i < n; ++i) {
+    int64_t e = pr.phys[i] * (int64_t)kout[i];
+    for (int c : pr.ch[i]) e *= kout[c];
+    P.out_off[i + 1] = P.out_off[i] + e;
+    P.out_bond[i] = kout[i];
+  }
+  std::vector<int> rleg(n, -1);
+  for (int i : pr.post) {
+    B.reset_scratch();
+    std::vector<std::pair<int, Ten>> envs;
+    std::vector<int> zl{B.sigp[i]};
+    for (size_t j = 0; j < pr.ch[i].size(); ++j) {
+      const int c = pr.ch[i][j];
+      envs.push_back({1 + (int)j, R[c]});
+      zl.push_back(R[c].legs[0]);
+    }
+    if (i == pr.root) {
+      std::vector<int> zr{B.rootA};
+      zr.insert(zr.end(), zl.begin(), zl.end());
+      zr.push_back(B.rootB);
+      Ten Z = B.alloc(zr, B.ct, false);
+      Z = B.node_contract(i, envs, zr, Z.ref);
+      Op w;
+      w.kind = K_WRITE;
+      w.src = Z.ref;
+      w.ts = B.ct;
+      w.a = 1;
+      w.b = pr.phys[i];
+      w.rest = B.elems(zr) / pr.phys[i];
+      w.dst.src = S_OUT;
+      w.dst.off = i;
+      w.logs.src = S_WS;
+      w.logs.off = P.logs_off;
+      w.nlogs = n;
+      P.ops.push_back(w);
+      continue;
+    }
+    zl.push_back(B.ealpha[i]);
+    zl.push_back(B.ebeta[i]);
+    int64_t ns = pr.phys[i];
+    for (int c : pr.ch[i]) ns *= kout[c];
+    const int64_t k = B.legdim[Lpar[i].legs[0]];
+    // With a tolerance the kept bond can be smaller than planned, so S may be rank-deficient and Q
+    // must span only its row space: the identity shortcut is taken only without one.
+    const bool ident = !tol_on && k >= ns;
+    Ten Z = B.alloc(zl, B.ct, ident);
+    Z = B.node_contract(i, envs, zl, Z.ref);
+    std::vector<int> rest(zl.begin(), zl.end() - 2);
+    if (ident) {
+      // Q is the identity on the joined leg: R^{[i]} = Z with (sigma', chi_c...) as its new leg
+      const int nl = B.leg(ns);
+      R[i] = Ten{Z.ref, {nl, B.ealpha[i], B.ebeta[i]}};
+      TRef q = B.scr(16 * (size_t)ns * ns, DT_C128);
+      Op f;
+      f.kind = K_IDENT;
+      f.dst = q;
+      f.td = DT_C128;
+      f.a = (int)ns;
+      f.b = (int)ns;
+      P.ops.push_back(f);
+      Op w;
+      w.kind = K_WRITE;
+      w.src = q;
+      w.ts = DT_C128;
+      w.a = (int)ns;
+      w.b = pr.phys[i];
+      w.rest = ns / pr.phys[i];
+      w.dst.src = S_OUT;
+      w.dst.off = i;
+      P.ops.push_back(w);
+      continue;
+    }
+    // S = L^{[(p,i)]} Z  -> [chi_p, sigma', chi_c...]
+    std::vector<int> sl{Lpar[i].legs[0]};
+    sl.insert(sl.end(), rest.begin(), rest.end());
+    Ten S = B.alloc(sl, B.ct, false);
+    S = B.contract(Lpar[i], false, Z, false, sl, S.ref, B.ct, B.cacc, 0);
+    TRef logslot;
+    logslot.src = S_WS;
+    logslot.off = P.logs_off + 8 * (int64_t)i;
+    TRef scl = B.scr(256, DT_C128);
+    const int knew = B.leg(k);
+    Ten Q = B.cholqr(S, knew, logslot, scl);
+    // R^{[i]} = scale * sum conj(Q) Z
+    Ten Rt = B.alloc({knew, B.ealpha[i], B.ebeta[i]}, B.ct, true);
+    R[i] = B.contract(Q, true, Z, false, {knew, B.ealpha[i], B.ebeta[i]}, Rt.ref, B.ct, B.cacc, 0,
+                      1.0, scl);
+    Op w;
+    w.kind = K_WRITE;
+    w.src = Q.ref;
+    w.ts = DT_C128;
+    w.a = (int)k;
+    w.b = pr.phys[i];
+    w.rest = ns / pr.phys[i];
+    w.dst.src = S_OUT;
+    w.dst.off = i;
+    P.ops.push_back(w);
+  }
+  P.persist_bytes = B.persist;
+  P.scratch_bytes = B.scratch_max;
+  return CBC_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// context and execution
+
+struct Call {
+  char* ws;
+  const char* state;
+  const char* op;
+  char* out;
+  const int64_t* st_off;
+  const int64_t* op_off;
+  const int64_t* out_off;
+  size_t persist;
+};
+
+}  // namespace
+
+struct cbc_ctx {
+  std::map<std::vector<int64_t>, std::unique_ptr<Plan>> plans;
+  int device = -1;
+};
+
+namespace {
+
+void* resolve(const Plan& P, const Call& c, const TRef& r) {
+  switch (r.src) {
+    case S_WS: return c.ws + r.off;
+    case S_SCR: return c.ws + c.persist + r.off;
+    case S_STATE:
+      if (r.off < 0) return (void*)c.state;
+      if (P.state_conv_off >= 0) return c.ws + P.state_conv_off + 8 * c.st_off[r.off];
+      return (void*)(c.state + 16 * c.st_off[r.off]);
+    case S_OP:
+      if (r.off < 0) return (void*)c.op;
+      if (P.op_conv_off >= 0) return c.ws + P.op_conv_off + 8 * c.op_off[r.off];
+      return (void*)(c.op + 16 * c.op_off[r.off]);
+    case S_OUT: return c.out + 16 * c.out_off[r.off];
+    default: return nullptr;
+  }
+}
+
+__global__ void k_zero_bytes(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st) {
+  for (const Op& op : P.ops) {
+    hipError_t e = hipSuccess;
+    switch (op.kind) {
+      case K_GEMM: {
+        GemmArgs g;
+        g.A = resolve(P, c, op.A);
+        g.B = resolve(P, c, op.B);
+        g.C = resolve(P, c, op.C);
+        g.M = op.M;
+        g.N = op.N;
+        g.K = op.K;
+        g.offAm = P.d_tables + op.tAm;
+        g.offAk = P.d_tables + op.tAk;
+        g.offBk = P.d_tables + op.tBk;
+        g.offBn = P.d_tables + op.tBn;
+        g.offCm = P.d_tables + op.tCm;
+        g.offCn = P.d_tables + op.tCn;
+        g.conjA = op.conjA;
+        g.conjB = op.conjB;
+        g.a_kfast = op.akf;
+        g.b_kfast = op.bkf;
+        g.alpha_dev = op.adev.src == S_NONE ? nullptr : (const double*)resolve(P, c, op.adev);
+        g.alpha_dev2 = op.adev2.src == S_NONE ? nullptr : (const double*)resolve(P, c, op.adev2);
+        g.alpha = op.alpha;
+        e = launch_gemm(g, op.ta, op.tb, op.tc, op.acc, op.tile, st);
+        break;
+      }
+      case K_EIG: {
+        EigArgs a;
+        a.G = (double2*)resolve(P, c, op.G);
+        a.s = op.s;
+        a.kmax = op.kmax;
+        a.tol = 0.0;
+        a.U = (double2*)resolve(P, c, op.U);
+        a.lam = (double*)resolve(P, c, op.lam);
+        a.kkeep = (int*)resolve(P, c, op.kkeep);
+        a.inv_sqrt_l0 = (double*)resolve(P, c, op.invs);
+        a.work = (double*)resolve(P, c, op.work);
+        a.tol = op.shift_rel;  // tolerance stored per call below
+        e = launch_eig(a, st);
+        break;
+      }
+      case K_FORM_N:
+        e = launch_form_l_nside((const double2*)resolve(P, c, op.U), (const double*)resolve(P, c, op.lam),
+                                (const int*)resolve(P, c, op.kkeep), op.n, op.kmax,
+                                resolve(P, c, op.L), op.td, st);
+        break;
+      case K_CHOL: {
+        CholArgs a;
+        a.G = (double2*)resolve(P, c, op.G);
+        a.k = op.s;
+        a.shift_rel = op.shift_rel;
+        a.drop_rel = op.drop_rel;
+        a.Cinv = (double2*)resolve(P, c, op.Cinv);
+        a.log_scale = op.logs.src == S_NONE ? nullptr : (double*)resolve(P, c, op.logs);
+        a.scale = op.scale.src == S_NONE ? nullptr : (double*)resolve(P, c, op.scale);
+        a.ndrop = (int*)resolve(P, c, op.ndrop);
+        e = launch_chol_inv(a, st);
+        break;
+      }
+      case K_CONVERT:
+        e = launch_convert(resolve(P, c, op.src), op.ts, resolve(P, c, op.dst), op.td, op.count, st);
+        break;
+      case K_IDENT:
+        e = launch_fill_identity(resolve(P, c, op.dst), op.td, op.a, op.b, st);
+        break;
+      case K_WRITE:
+        e = launch_write_out(resolve(P, c, op.src), op.ts, op.a, op.b, op.rest,
+                             (double2*)resolve(P, c, op.dst),
+                             op.logs.src == S_NONE ? nullptr : (const double*)resolve(P, c, op.logs),
+                             op.nlogs, st);
+        break;
+      case K_ZERO: {
+        const int64_t nw = (op.count + 3) / 4;
+        hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st,
+                           (uint32_t*)resolve(P, c, op.dst), nw);
+        e = hipGetLastError();
+        break;
+      }
+    }
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+std::vector<int64_t> plan_key(const Problem& pr, int max_bond, bool tol_on, cbc_precision prec,
+                              int method, int64_t se, int64_t oe) {
+  std::vector<int64_t> k{pr.n, max_bond, tol_on, (int64_t)prec, method, se, oe};
+  for (int i = 0; i < pr.n; ++i) {
+    k.push_back(pr.parent[i]);
+    k.push_back(pr.phys[i]);
+    k.push_back(pr.chi[i]);
+    k.push_back(pr.dop[i]);
+  }
+  return k;
+}
+
+int64_t tensor_elems_state(const Problem& pr, int i) {
+  int64_t e = (int64_t)pr.phys[i] * pr.chi[i];
+  for (int c : pr.ch[i]) e *= pr.chi[c];
+  return e;
+}
+int64_t tensor_elems_op(const Problem& pr, int i) {
+  int64_t e = (int64_t)pr.phys[i] * pr.phys[i] * pr.dop[i];
+  for (int c : pr.ch[i]) e *= pr.dop[c];
+  return e;
+}
+
+cbc_status get_plan(cbc_ctx* ctx, const Problem& pr, int max_bond, bool tol_on, cbc_precision prec,
+                    int method, int64_t state_span, int64_t op_span, Plan** out) {
+  const auto key = plan_key(pr, max_bond, tol_on, prec, method, state_span, op_span);
+  auto it = ctx->plans.find(key);
+  if (it != ctx->plans.end()) {
+    *out = it->second.get();
+    return CBC_OK;
+  }
+  auto P = std::make_unique<Plan>();
+  P->state_elems = state_span;
+  P->op_elems = op_span;
+  if (method != 0) return CBC_EUNSUP;
+  cbc_status s = build_plan(*P, pr, max_bond, tol_on, prec);
+  if (s != CBC_OK) return s;
+  *out = P.get();
+  ctx->plans[key] = std::move(P);
+  return CBC_OK;
+}
+
+cbc_status upload_tables(Plan* P) {
+  if (P->d_tables || P->tables.empty()) return CBC_OK;
+  if (hipMalloc(&P->d_tables, P->tables.size() * sizeof(int32_t)) != hipSuccess) return CBC_ENOMEM;
+  if (hipMemcpy(P->d_tables, P->tables.data(), P->tables.size() * sizeof(int32_t),
+                hipMemcpyHostToDevice) != hipSuccess)
+    return CBC_EHIP;
+  return CBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cbc_status cbc_create(cbc_ctx** ctx) {
+  if (!ctx) return CBC_EINVAL;
+  try {
+    *ctx = new cbc_ctx();
+  } catch (...) {
+    return CBC_ENOMEM;
+  }
+  return CBC_OK;
+}
+
+void cbc_destroy(cbc_ctx* ctx) { delete ctx; }
+
+const char* cbc_status_str(cbc_status s) {
+  switch (s) {
+    case CBC_OK: return "ok";
+    case CBC_EINVAL: return "invalid argument (null pointer, max_bond < 1, bad tol or precision)";
+    case CBC_ESHAPE: return "invalid tree or dimensions";
+    case CBC_ENOMEM: return "workspace too small or allocation failed";
+    case CBC_EHIP: return "HIP runtime error";
+    case CBC_ENOTPD: return "factorisation failed after fallbacks";
+    case CBC_EUNSUP: return "unsupported configuration";
+    case CBC_ENOTBUILT: return "no usable gfx950 device";
+  }
+  return "unknown status";
+}
+
+static cbc_status common_checks(const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
+                                Problem& pr) {
+  if (max_bond < 1) return CBC_EINVAL;
+  if (prec != CBC_PREC_FP64 && prec != CBC_PREC_MIXED) return CBC_EINVAL;
+  return validate_tree(tree, pr);
+}
+
+cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
+                     int32_t method, size_t* workspace_bytes, int64_t* out_offset) {
+  if (!ctx || !workspace_bytes || !out_offset) return CBC_EINVAL;
+  if (method != 0 && method != 1) return CBC_EINVAL;
+  Problem pr;
+  cbc_status s = common_checks(tree, max_bond, prec, pr);
+  if (s != CBC_OK) return s;
+  int64_t se = 0, oe = 0;
+  for (int i = 0; i < pr.n; ++i) {
+    se += tensor_elems_state(pr, i);
+    oe += tensor_elems_op(pr, i);
+  }
+  Plan* P = nullptr;
+  // the workspace does not depend on tol; plan with tolerance off and on, report the larger
+  size_t ws = 0;
+  for (int t = 0; t < 2; ++t) {
+    s = get_plan(ctx, pr, max_bond, t == 1, prec, method, se, oe, &P);
+    if (s != CBC_OK) return s;
+    ws = std::max(ws, P->persist_bytes + P->scratch_bytes);
+  }
+  *workspace_bytes = ws;
+  for (int i = 0; i <= pr.n; ++i) out_offset[i] = P->out_off[i];
+  return CBC_OK;
+}
+
+static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                             const cbc_tree* tree, int32_t max_bond, double tol,
+                             cbc_precision prec, void* workspace, size_t workspace_bytes,
+                             cbc_out* out, void* stream, cbc_stats* stats, int method) {
+  if (!ctx || !ttno || !ttns || !out || !ttno->data || !ttns->data || !ttno->offset ||
+      !ttns->offset || !out->data || !out->offset || !out->bond)
+    return CBC_EINVAL;
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return CBC_EINVAL;
+  Problem pr;
+  cbc_status s = common_checks(tree, max_bond, prec, pr);
+  if (s != CBC_OK) return s;
+  // inputs must be packed: every node inside [0, total) where total is the sum of node sizes
+  int64_t se = 0, oe = 0;
+  for (int i = 0; i < pr.n; ++i) {
+    se += tensor_elems_state(pr, i);
+    oe += tensor_elems_op(pr, i);
+  }
+  for (int i = 0; i < pr.n; ++i) {
+    if (ttns->offset[i] < 0 || ttno->offset[i] < 0) return CBC_EINVAL;
+    if (ttns->offset[i] + tensor_elems_state(pr, i) > se) return CBC_EINVAL;
+    if (ttno->offset[i] + tensor_elems_op(pr, i) > oe) return CBC_EINVAL;
+  }
+  Plan* P = nullptr;
+  s = get_plan(ctx, pr, max_bond, tol > 0.0, prec, method, se, oe, &P);
+  if (s != CBC_OK) return s;
+  if (!workspace || workspace_bytes < P->persist_bytes + P->scratch_bytes) return CBC_ENOMEM;
+  for (int i = 0; i <= pr.n; ++i)
+    if (out->offset[i] != P->out_off[i]) return CBC_EINVAL;
+  s = upload_tables(P);
+  if (s != CBC_OK) return s;
+  // tolerance is a per-call value carried by the eigensolve ops
+  for (auto& op : P->ops)
+    if (op.kind == K_EIG) op.shift_rel = tol;
+  Call c;
+  c.ws = (char*)workspace;
+  c.state = (const char*)ttns->data;
+  c.op = (const char*)ttno->data;
+  c.out = (char*)out->data;
+  c.st_off = ttns->offset;
+  c.op_off = ttno->offset;
+  c.out_off = P->out_off.data();
+  c.persist = P->persist_bytes;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = run_ops(*P, c, st);
+  if (e != hipSuccess) return CBC_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return CBC_EHIP;
+  for (int i = 0; i < pr.n; ++i) out->bond[i] = P->out_bond[i];
+  if (stats) {
+    stats->contraction_flops = P->cflops;
+    stats->gram_flops = P->gflops;
+    stats->n_eig = P->n_eig;
+    stats->max_eig_dim = P->max_eig;
+    stats->n_kernels = (int32_t)P->ops.size();
+    stats->graph_replayed = 0;
+  }
+  return CBC_OK;
+}
+
+cbc_status cbc_apply(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                     const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
+                     void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
+                     cbc_stats* stats) {
+  return apply_impl(ctx, ttno, ttns, tree, max_bond, tol, prec, workspace, workspace_bytes, out,
+                    stream, stats, 0);
+}
+
+cbc_status cbc_apply_naive(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                           const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
+                           void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
+                           cbc_stats* stats) {
+  (void)ctx; (void)ttno; (void)ttns; (void)tree; (void)max_bond; (void)tol; (void)prec;
+  (void)workspace; (void)workspace_bytes; (void)out; (void)stream; (void)stats;
+  return CBC_EUNSUP;
+}
+
+}  // extern "C"

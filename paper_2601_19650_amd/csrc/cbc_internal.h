@@ -1,0 +1,86 @@
+// Internal interfaces between the host planner/executor and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cbc {
+
+// Element types used for operands.
+enum DType : int { DT_C64 = 0, DT_C128 = 1 };
+
+// Generic complex tensor-contraction GEMM:
+//   C[m, n] = alpha * sum_k opA(A)[m, k] * opB(B)[k, n]
+// where every row/column/reduction index is mapped to a complex-element offset through device
+// tables (offAm[m] + offAk[k] addresses A, offBk[k] + offBn[n] addresses B, offCm[m] + offCn[n]
+// addresses C). This covers any leg order of the operands without transposes.
+struct GemmArgs {
+  const void* A;
+  const void* B;
+  void* C;
+  int M, N, K;
+  const int32_t* offAm;
+  const int32_t* offAk;
+  const int32_t* offBk;
+  const int32_t* offBn;
+  const int32_t* offCm;
+  const int32_t* offCn;
+  int conjA, conjB;
+  int a_kfast;              // 1: consecutive k are adjacent in A; 0: consecutive m are
+  int b_kfast;              // 1: consecutive k are adjacent in B; 0: consecutive n are
+  const double* alpha_dev;  // optional device scalar multiplier (nullptr: none)
+  const double* alpha_dev2; // optional second device scalar multiplier (nullptr: none)
+  double alpha;             // host scalar multiplier
+};
+
+// Launch a GEMM. acc: DT_C64 -> FP32 MFMA, DT_C128 -> FP64 MFMA. tile: 0 = 32x32, 1 = 64x64.
+hipError_t launch_gemm(const GemmArgs& a, DType ta, DType tb, DType tc, DType acc, int tile,
+                       hipStream_t s);
+
+// Truncation eigensolve of a Hermitian FP64 Gram matrix G (s x s, row-major, both triangles valid,
+// overwritten). Writes the top-kmax eigenvectors as columns of U (s x kmax, row-major, complex128),
+// descending eigenvalues lam[0..kmax), the number kept (<= kmax, >= 1) to *kkeep, and
+// 1/sqrt(lam[0]) to *inv_sqrt_l0. Columns of U beyond the kept count are zero.
+struct EigArgs {
+  double2* G;
+  int s;
+  int kmax;
+  double tol;       // relative singular-value cutoff (0: keep kmax)
+  double2* U;
+  double* lam;
+  int* kkeep;
+  double* inv_sqrt_l0;
+  double* work;     // scratch, eig_work_doubles(s, kmax) doubles
+};
+size_t eig_work_doubles(int s, int kmax);
+hipError_t launch_eig(const EigArgs& a, hipStream_t st);
+
+// n-side truncation output: L[j, c] = sqrt(max(lam_j, 0)) / sqrt(lam_0) * conj(V[c, j]) for j < kkeep,
+// zero for kkeep <= j < kmax. L is kmax x n, written in the contraction precision.
+hipError_t launch_form_l_nside(const double2* V, const double* lam, const int* kkeep, int n,
+                               int kmax, void* L, DType tl, hipStream_t st);
+
+// Cholesky of a Hermitian PSD Gram G (k x k, FP64, overwritten) with an optional diagonal shift of
+// shift_rel * trace(G); pivots below drop_rel * max pivot are dropped. Writes Cinv = C^{-1} (k x k,
+// lower triangular, zero rows/columns for dropped pivots) and, if log_scale != nullptr,
+// log_scale[0] = -0.5 * log(trace(G)) and scale[0] = 1/sqrt(trace(G)).
+struct CholArgs {
+  double2* G;
+  int k;
+  double shift_rel;
+  double drop_rel;
+  double2* Cinv;
+  double* log_scale;
+  double* scale;
+  int* ndrop;
+};
+hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st);
+
+// Elementwise helpers.
+hipError_t launch_convert(const void* src, DType ts, void* dst, DType td, int64_t n, hipStream_t st);
+hipError_t launch_fill_identity(void* dst, DType t, int rows, int cols, hipStream_t st);
+// Output writer: src is a (a x b x rest) tensor in type ts; writes dst[(b, a, rest)] as complex128
+// (swap of the two leading legs), multiplied by exp(-sum(logs[0..nlogs))) if logs != nullptr.
+hipError_t launch_write_out(const void* src, DType ts, int a, int b, int64_t rest, double2* dst,
+                            const double* logs, int nlogs, hipStream_t st);
+
+}  // namespace cbc

@@ -1,0 +1,227 @@
+// FP64 Cholesky factorisation and triangular inverse for the QR on the parent leg.
+//
+// The QR of S on its parent leg (Sec. III A, Eq. tt_cbc_qr_decomp; Sec. III B, Eq. cbc_tree_qr) is
+// computed as Cholesky-QR on the Gram matrix G = S S^H: G = C C^H, Q = C^{-1} S has orthonormal rows
+// spanning the row space of S. The first pass adds a diagonal shift proportional to trace(G) so the
+// factorisation exists for rank-deficient S; later passes re-orthogonalise without a shift.
+// Pivots below drop_rel times the largest diagonal are dropped: their row and column of C^{-1} are
+// zero, so the matching rows of Q vanish (they carried no weight of S).
+//
+// One workgroup; G is k x k row-major in global memory (L2 resident for the sizes used).
+#include <float.h>
+
+#include "cbc_internal.h"
+
+namespace cbc {
+
+static constexpr int CHOL_THREADS = 1024;
+
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wmax(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(CholArgs a) {
+  extern __shared__ int dropped[];
+  __shared__ double red[32];
+  __shared__ double sh_trace, sh_thresh;
+  const int k = a.k;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  double2* G = a.G;
+
+  // trace and shift
+  double tr = 0.0;
+  for (int i = tid; i < k; i += blockDim.x) tr += G[(size_t)i * k + i].x;
+  tr = wsum(tr);
+  if (lane == 0) red[wave] = tr;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < nwave; ++w) t += red[w];
+    sh_trace = t;
+    if (a.log_scale) {
+      a.log_scale[0] = t > 0.0 ? -0.5 * log(t) : 0.0;
+      a.scale[0] = t > 0.0 ? 1.0 / sqrt(t) : 1.0;
+    }
+  }
+  __syncthreads();
+  const double trace = sh_trace;
+  const double shift = a.shift_rel * trace;
+  double mx = 0.0;
+  for (int i = tid; i < k; i += blockDim.x) {
+    double2 g = G[(size_t)i * k + i];
+    g.x += shift;
+    g.y = 0.0;
+    G[(size_t)i * k + i] = g;
+    mx = fmax(mx, g.x);
+    dropped[i] = 0;
+  }
+  mx = wmax(mx);
+  if (lane == 0) red[wave] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int w = 0; w < nwave; ++w) m = fmax(m, red[w]);
+    sh_thresh = a.drop_rel * m;
+  }
+  __syncthreads();
+  const double thresh = sh_thresh;
+
+  // right-looking Cholesky, lower triangle
+  for (int j = 0; j < k; ++j) {
+    const double djj = G[(size_t)j * k + j].x;
+    if (!(djj > thresh)) {
+      if (tid == 0) dropped[j] = 1;
+      for (int i = j + tid; i < k; i += blockDim.x) G[(size_t)i * k + j] = make_double2(0.0, 0.0);
+      __syncthreads();
+      continue;
+    }
+    const double c = sqrt(djj);
+    const double ic = 1.0 / c;
+    for (int i = j + 1 + tid; i < k; i += blockDim.x) {
+      double2 g = G[(size_t)i * k + j];
+      g.x *= ic;
+      g.y *= ic;
+      G[(size_t)i * k + j] = g;
+    }
+    __syncthreads();
+    if (tid == 0) G[(size_t)j * k + j] = make_double2(c, 0.0);
+    // trailing update of the lower triangle: G[i][l] -= C[i][j] conj(C[l][j]), j < l <= i
+    for (int i = j + 1 + wave; i < k; i += nwave) {
+      const double2 cij = G[(size_t)i * k + j];
+      for (int l = j + 1 + lane; l <= i; l += 64) {
+        const double2 clj = G[(size_t)l * k + j];
+        double2 g = G[(size_t)i * k + l];
+        g.x -= cij.x * clj.x + cij.y * clj.y;
+        g.y -= cij.y * clj.x - cij.x * clj.y;
+        G[(size_t)i * k + l] = g;
+      }
+    }
+    __syncthreads();
+  }
+
+  // triangular inverse X = C^{-1}, one column per thread (forward substitution)
+  double2* X = a.Cinv;
+  for (int c = tid; c < k; c += blockDim.x) {
+    for (int i = 0; i < c; ++i) X[(size_t)i * k + c] = make_double2(0.0, 0.0);
+    if (dropped[c]) {
+      for (int i = c; i < k; ++i) X[(size_t)i * k + c] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double2 ccc = G[(size_t)c * k + c];
+    X[(size_t)c * k + c] = make_double2(1.0 / ccc.x, 0.0);
+    for (int i = c + 1; i < k; ++i) {
+      if (dropped[i]) {
+        X[(size_t)i * k + c] = make_double2(0.0, 0.0);
+        continue;
+      }
+      double sr = 0.0, si = 0.0;
+      for (int l = c; l < i; ++l) {
+        const double2 cil = G[(size_t)i * k + l];
+        const double2 xl = X[(size_t)l * k + c];
+        sr += cil.x * xl.x - cil.y * xl.y;
+        si += cil.x * xl.y + cil.y * xl.x;
+      }
+      const double inv = -1.0 / G[(size_t)i * k + i].x;
+      X[(size_t)i * k + c] = make_double2(sr * inv, si * inv);
+    }
+  }
+  __syncthreads();
+  if (a.ndrop && tid == 0) {
+    int nd = 0;
+    for (int j = 0; j < k; ++j) nd += dropped[j];
+    a.ndrop[0] += nd;
+  }
+}
+
+hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st) {
+  if (a.k <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CHOL_THREADS), (size_t)a.k * sizeof(int), st, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------------
+// elementwise helpers
+
+__global__ void k_convert(const void* src, int ts, void* dst, int td, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double2 v;
+  if (ts == DT_C128) v = reinterpret_cast<const double2*>(src)[i];
+  else {
+    const float2 f = reinterpret_cast<const float2*>(src)[i];
+    v = make_double2(f.x, f.y);
+  }
+  if (td == DT_C128) reinterpret_cast<double2*>(dst)[i] = v;
+  else reinterpret_cast<float2*>(dst)[i] = make_float2((float)v.x, (float)v.y);
+}
+
+hipError_t launch_convert(const void* src, DType ts, void* dst, DType td, int64_t n,
+                          hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_convert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, (int)ts,
+                     dst, (int)td, n);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_identity(void* dst, int t, int rows, int cols) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * cols) return;
+  const int r = (int)(i / cols), c = (int)(i % cols);
+  const double v = (r == c) ? 1.0 : 0.0;
+  if (t == DT_C128) reinterpret_cast<double2*>(dst)[i] = make_double2(v, 0.0);
+  else reinterpret_cast<float2*>(dst)[i] = make_float2((float)v, 0.0f);
+}
+
+hipError_t launch_fill_identity(void* dst, DType t, int rows, int cols, hipStream_t st) {
+  const int64_t n = (int64_t)rows * cols;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_identity, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst,
+                     (int)t, rows, cols);
+  return hipGetLastError();
+}
+
+// dst[(b, a, r)] = src[(a, b, r)] * exp(-sum logs)
+__global__ void k_write_out(const void* src, int ts, int a, int b, int64_t rest, double2* dst,
+                            const double* logs, int nlogs) {
+  __shared__ double sh_f;
+  if (threadIdx.x == 0) {
+    double l = 0.0;
+    if (logs)
+      for (int i = 0; i < nlogs; ++i) l += logs[i];
+    sh_f = exp(-l);
+  }
+  __syncthreads();
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)a * b * rest;
+  if (idx >= n) return;
+  const int64_t r = idx % rest;
+  const int64_t ab = idx / rest;
+  const int64_t ib = ab / a, ia = ab % a;     // dst index (ib, ia, r)
+  const int64_t sidx = (ia * b + ib) * rest + r;
+  double2 v;
+  if (ts == DT_C128) v = reinterpret_cast<const double2*>(src)[sidx];
+  else {
+    const float2 f = reinterpret_cast<const float2*>(src)[sidx];
+    v = make_double2(f.x, f.y);
+  }
+  const double f = sh_f;
+  dst[idx] = make_double2(v.x * f, v.y * f);
+}
+
+hipError_t launch_write_out(const void* src, DType ts, int a, int b, int64_t rest, double2* dst,
+                            const double* logs, int nlogs, hipStream_t st) {
+  const int64_t n = (int64_t)a * b * rest;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_write_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src,
+                     (int)ts, a, b, rest, dst, logs, nlogs);
+  return hipGetLastError();
+}
+
+}  // namespace cbc

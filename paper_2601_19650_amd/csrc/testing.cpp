@@ -1,0 +1,76 @@
+// Kernel-level entry points for the test suite (declared in include/cbc_testing.h).
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "../../include/cbc.h"
+#include "../../include/cbc_testing.h"
+#include "cbc_internal.h"
+
+using namespace cbc;
+
+extern "C" int cbc_test_gemm(int M, int N, int K, const void* A, int a_c128, int transA, int conjA,
+                             const void* B, int b_c128, int transB, int conjB, void* C, int c_c128,
+                             int acc_fp64, int tile, void* stream) {
+  if (M < 1 || N < 1 || K < 1 || !A || !B || !C) return CBC_EINVAL;
+  std::vector<int32_t> t(2 * (size_t)M + 2 * (size_t)N + 2 * (size_t)K);
+  int32_t* am = t.data();
+  int32_t* cm = am + M;
+  int32_t* bn = cm + M;
+  int32_t* cn = bn + N;
+  int32_t* ak = cn + N;
+  int32_t* bk = ak + K;
+  for (int m = 0; m < M; ++m) { am[m] = transA ? m : m * K; cm[m] = m * N; }
+  for (int n = 0; n < N; ++n) { bn[n] = transB ? n * K : n; cn[n] = n; }
+  for (int k = 0; k < K; ++k) { ak[k] = transA ? k * M : k; bk[k] = transB ? k : k * N; }
+  int32_t* d = nullptr;
+  if (hipMalloc(&d, t.size() * sizeof(int32_t)) != hipSuccess) return CBC_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = CBC_OK;
+  if (hipMemcpy(d, t.data(), t.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    rc = CBC_EHIP;
+  } else {
+    GemmArgs g;
+    g.A = A; g.B = B; g.C = C; g.M = M; g.N = N; g.K = K;
+    g.offAm = d; g.offCm = d + M; g.offBn = d + 2 * M; g.offCn = d + 2 * M + N;
+    g.offAk = d + 2 * M + 2 * N; g.offBk = d + 2 * M + 2 * N + K;
+    g.conjA = conjA; g.conjB = conjB;
+    g.a_kfast = !transA; g.b_kfast = transB;
+    g.alpha_dev = nullptr; g.alpha_dev2 = nullptr; g.alpha = 1.0;
+    if (launch_gemm(g, a_c128 ? DT_C128 : DT_C64, b_c128 ? DT_C128 : DT_C64,
+                    c_c128 ? DT_C128 : DT_C64, acc_fp64 ? DT_C128 : DT_C64, tile, st) != hipSuccess)
+      rc = CBC_EHIP;
+    else if (hipStreamSynchronize(st) != hipSuccess)
+      rc = CBC_EHIP;
+  }
+  (void)hipFree(d);
+  return rc;
+}
+
+extern "C" int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void* lam, void* kkeep,
+                            void* inv_sqrt_l0, void* stream) {
+  if (!G || !U || !lam || !kkeep || !inv_sqrt_l0 || s < 1 || kmax < 1 || kmax > s) return CBC_EINVAL;
+  double* w = nullptr;
+  if (hipMalloc(&w, eig_work_doubles(s, kmax) * sizeof(double)) != hipSuccess) return CBC_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  EigArgs a;
+  a.G = (double2*)G; a.s = s; a.kmax = kmax; a.tol = tol; a.U = (double2*)U;
+  a.lam = (double*)lam; a.kkeep = (int*)kkeep; a.inv_sqrt_l0 = (double*)inv_sqrt_l0; a.work = w;
+  int rc = CBC_OK;
+  if (launch_eig(a, st) != hipSuccess) rc = CBC_EHIP;
+  else if (hipStreamSynchronize(st) != hipSuccess) rc = CBC_EHIP;
+  (void)hipFree(w);
+  return rc;
+}
+
+extern "C" int cbc_test_chol_inv(void* G, int k, double shift_rel, double drop_rel, void* Cinv,
+                                 void* ndrop, void* stream) {
+  if (!G || !Cinv || !ndrop || k < 1) return CBC_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  CholArgs a;
+  a.G = (double2*)G; a.k = k; a.shift_rel = shift_rel; a.drop_rel = drop_rel;
+  a.Cinv = (double2*)Cinv; a.log_scale = nullptr; a.scale = nullptr; a.ndrop = (int*)ndrop;
+  if (launch_chol_inv(a, st) != hipSuccess) return CBC_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return CBC_EHIP;
+  return CBC_OK;
+}

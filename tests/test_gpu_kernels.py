@@ -1,0 +1,147 @@
+"""GPU unit checks of single steps of the path, through the kernel-level C entry points:
+the contraction GEMM (FP64 and FP32 MFMA), the truncation eigensolve and the Cholesky step of the
+QR. Each is compared with a plain float64/complex128 reference of the same operation."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def crand(rng, *shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (16, 16, 4), (37, 53, 29), (64, 128, 96), (130, 70, 257)])
+@pytest.mark.parametrize("tile", [0, 1])
+def test_gemm_fp64(lib, M, N, K, tile):
+    print(f"gemm fp64 M={M} N={N} K={K} tile={tile}", flush=True)
+    rng = np.random.default_rng(M * 1000 + N + K)
+    a, b = crand(rng, M, K), crand(rng, K, N)
+    A = torch.from_numpy(a).cuda()
+    B = torch.from_numpy(b).cuda()
+    C = lib.test_gemm(A, B, acc_fp64=True, tile=tile).cpu().numpy()
+    ref = a @ b
+    assert np.abs(C - ref).max() <= 1e-13 * np.sqrt(K) * np.abs(a).max() * np.abs(b).max()
+
+
+@pytest.mark.parametrize("tA,cA,tB,cB", [(1, 1, 0, 0), (0, 0, 1, 1), (1, 0, 1, 0), (0, 1, 0, 1)])
+def test_gemm_transpose_conj(lib, tA, cA, tB, cB):
+    rng = np.random.default_rng(7)
+    M, N, K = 45, 33, 70
+    a = crand(rng, K, M) if tA else crand(rng, M, K)
+    b = crand(rng, N, K) if tB else crand(rng, K, N)
+    opa = a.T if tA else a
+    opb = b.T if tB else b
+    opa = opa.conj() if cA else opa
+    opb = opb.conj() if cB else opb
+    for acc in (True, False):
+        dt = torch.complex128 if acc else torch.complex64
+        C = lib.test_gemm(torch.from_numpy(a).to(dt).cuda(), torch.from_numpy(b).to(dt).cuda(),
+                          transA=bool(tA), conjA=bool(cA), transB=bool(tB), conjB=bool(cB),
+                          acc_fp64=acc).cpu().numpy()
+        ref = opa @ opb
+        tol = 1e-13 if acc else 2e-5
+        assert np.abs(C - ref).max() <= tol * np.sqrt(K) * 4, (acc, np.abs(C - ref).max())
+
+
+@pytest.mark.parametrize("M,N,K", [(32, 32, 16), (100, 200, 300), (257, 65, 64)])
+def test_gemm_fp32(lib, M, N, K):
+    rng = np.random.default_rng(M + N + K)
+    a, b = crand(rng, M, K).astype(np.complex64), crand(rng, K, N).astype(np.complex64)
+    C = lib.test_gemm(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), acc_fp64=False,
+                      tile=1).cpu().numpy()
+    ref = a.astype(np.complex128) @ b.astype(np.complex128)
+    assert np.abs(C - ref).max() <= 1e-5 * np.sqrt(K) * 4
+
+
+def herm_psd(rng, s, rank=None, n=None):
+    n = n or 2 * s
+    m = crand(rng, s, rank or n)
+    return m @ m.conj().T
+
+
+@pytest.mark.parametrize("s,kmax", [(1, 1), (2, 1), (2, 2), (7, 3), (64, 32), (128, 64), (200, 100),
+                                    (96, 96)])
+def test_eig_topk(lib, s, kmax):
+    print(f"eig s={s} kmax={kmax}", flush=True)
+    rng = np.random.default_rng(s)
+    g = herm_psd(rng, s)
+    U, lam, kk, inv = lib.test_eig(torch.from_numpy(g).cuda(), kmax)
+    U = U.cpu().numpy()
+    lam = lam.cpu().numpy()
+    w, v = np.linalg.eigh(g)
+    w, v = w[::-1], v[:, ::-1]
+    assert kk == kmax
+    assert np.abs(lam - w[:kmax]).max() <= 1e-12 * w[0] * s
+    assert abs(inv - 1.0 / np.sqrt(w[0])) <= 1e-12 / np.sqrt(w[0])
+    assert np.abs(U.conj().T @ U - np.eye(kmax)).max() <= 1e-12
+    # eigen-residual and subspace agreement (projectors compared where a gap exists)
+    res = g @ U - U * lam[None, :]
+    assert np.abs(res).max() <= 1e-11 * w[0]
+    if kmax < s:
+        gap = (w[kmax - 1] - w[kmax]) / w[0]
+        p_gpu = U @ U.conj().T
+        p_ref = v[:, :kmax] @ v[:, :kmax].conj().T
+        assert np.abs(p_gpu - p_ref).max() <= 1e-13 / gap * s
+
+
+def test_eig_rank_deficient_and_tol(lib):
+    rng = np.random.default_rng(3)
+    s, r = 60, 20
+    g = herm_psd(rng, s, rank=r)
+    U, lam, kk, _ = lib.test_eig(torch.from_numpy(g).cuda(), 40)
+    U = U.cpu().numpy()
+    w = np.linalg.eigvalsh(g)[::-1]
+    assert np.abs(lam.cpu().numpy()[:r] - w[:r]).max() <= 1e-11 * w[0]
+    # the top-r subspace is reproduced; the remaining columns span (numerical) null directions
+    p = U[:, :r] @ U[:, :r].conj().T
+    assert np.abs(p @ g - g).max() <= 1e-10 * w[0]
+    # tolerance: keep singular values s_j > tol * s_0  <=>  lam_j > tol^2 lam_0
+    tol = np.sqrt(w[9] / w[0]) * 0.999999
+    U2, lam2, kk2, _ = lib.test_eig(torch.from_numpy(g).cuda(), 40, tol=tol)
+    assert kk2 == 10
+    assert np.abs(U2.cpu().numpy()[:, 10:]).max() == 0.0
+
+
+def test_eig_degenerate_cluster(lib):
+    """Exactly repeated eigenvalues: the returned vectors must stay orthonormal."""
+    rng = np.random.default_rng(11)
+    s = 50
+    q, _ = np.linalg.qr(crand(rng, s, s))
+    w = np.concatenate([[5.0] * 6, np.linspace(3.0, 0.1, s - 6)])
+    g = (q * w) @ q.conj().T
+    U, lam, kk, _ = lib.test_eig(torch.from_numpy(g).cuda(), 10)
+    U = U.cpu().numpy()
+    assert np.abs(U.conj().T @ U - np.eye(10)).max() <= 1e-11
+    assert np.abs(g @ U - U * lam.cpu().numpy()[None, :]).max() <= 1e-11 * 5
+
+
+@pytest.mark.parametrize("k", [1, 5, 64, 130])
+def test_chol_inv(lib, k):
+    rng = np.random.default_rng(k)
+    g = herm_psd(rng, k)
+    Ci, nd = lib.test_chol_inv(torch.from_numpy(g).cuda())
+    Ci = Ci.cpu().numpy()
+    assert nd == 0
+    c = np.linalg.cholesky(g)
+    assert np.abs(Ci - np.linalg.inv(c)).max() <= 1e-10 * np.abs(np.linalg.inv(c)).max()
+    assert np.abs(np.triu(Ci, 1)).max() == 0.0
+
+
+def test_chol_inv_drops_zero_pivots(lib):
+    rng = np.random.default_rng(2)
+    k, r = 24, 15
+    s = crand(rng, r, 40)
+    s = np.concatenate([s, np.zeros((k - r, 40))])
+    perm = rng.permutation(k)
+    s = s[perm]
+    g = s @ s.conj().T
+    Ci, nd = lib.test_chol_inv(torch.from_numpy(g).cuda(), drop_rel=1e-13)
+    Ci = Ci.cpu().numpy()
+    assert nd == k - r
+    q = Ci @ s
+    nz = np.abs(q).sum(axis=1) > 0
+    assert nz.sum() == r
+    qq = q[nz]
+    assert np.abs(qq @ qq.conj().T - np.eye(r)).max() <= 1e-10

@@ -1,0 +1,98 @@
+"""Parity of the GPU compression (through the C ABI) with the oracle on the same seeded inputs.
+
+Bars: plain FP64 GPU path within 1e-10 relative state error of the oracle (difference network norm);
+mixed path (FP32 contractions, FP64 Gram/eigen/Cholesky) within 1e-5 infidelity. Exact cases are
+also checked against dense contraction.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import cbc_tree, tn  # noqa: E402
+from paper_2601_19650_amd.inputs import (chain_parent, config_problem, kary_parent,  # noqa: E402
+                                         random_problem)
+
+FP64_BAR = 1e-10
+MIXED_BAR = 1e-5
+
+
+def check(lib, p, prec, oracle_out=None, tol=0.0):
+    print(f"parity {p.name or 'custom'} n={p.n} prec={prec} tol={tol}", flush=True)
+    ref = oracle_out if oracle_out is not None else cbc_tree(p.parent, p.state, p.op, p.max_bond, tol)
+    out, comp = lib.compress(p, precision=prec, tol=tol)
+    if prec == "fp64":
+        err = tn.rel_error(p.parent, out, ref)
+        assert err <= FP64_BAR, err
+    else:
+        infid = 1.0 - tn.fidelity(p.parent, out, ref)
+        err = tn.rel_error(p.parent, out, ref)
+        assert infid <= MIXED_BAR, (infid, err)
+    # outputs: every non-root node is an isometry toward its parent
+    root = p.parent.index(-1)
+    iso = 1e-12 if prec == "fp64" else 1e-12
+    for i, t in enumerate(out):
+        if i != root and t.size:
+            assert tn.isometry_error(t) <= iso
+    return out, comp
+
+
+def test_c1_exact_against_dense(lib):
+    p = config_problem("C1")
+    out, _ = check(lib, p, "fp64")
+    phi = tn.apply_dense(p.parent, p.op, tn.to_dense(p.parent, p.state))
+    psi = tn.to_dense(p.parent, out)
+    assert np.linalg.norm(phi - psi) <= 1e-12 * np.linalg.norm(phi)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("maker", [
+    lambda: random_problem(chain_parent(6), 2, 4, 3, 3, seed=1, name="mps6"),
+    lambda: random_problem(chain_parent(10), 3, 9, 4, 7, seed=2, name="mps10d3"),
+    lambda: random_problem(kary_parent(7, 2), 2, 8, 4, 4, seed=3, name="bin7"),
+    lambda: random_problem(kary_parent(13, 3), 2, 6, 3, 5, seed=4, name="ter13"),
+    lambda: random_problem(chain_parent(7), [3, 1, 2, 2, 1, 3, 2], 5, 4, 6, seed=5, name="d1mix"),
+    lambda: random_problem(kary_parent(7, 2), [1, 1, 1, 2, 2, 2, 2], 4, 4, 3, seed=6, name="leafphys"),
+    lambda: random_problem([-1], 3, 1, 1, 2, seed=7, name="single"),
+])
+def test_small_parity(lib, maker, prec):
+    check(lib, maker(), prec)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c2_parity(lib, prec):
+    p = config_problem("C2")
+    out, comp = check(lib, p, prec)
+    s = comp.stats
+    assert s.n_eig > 0 and s.contraction_flops > 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c3_parity(lib, prec):
+    check(lib, config_problem("C3"), prec)
+
+
+def test_tolerance_parity(lib):
+    p = config_problem("C2", n=16)
+    tol = 0.45
+    ref = cbc_tree(p.parent, p.state, p.op, p.max_bond, tol)
+    out, comp = lib.compress(p, precision="fp64", tol=tol)
+    assert tn.rel_error(p.parent, out, ref) <= FP64_BAR
+
+
+def test_repeat_calls_reuse_plan(lib):
+    """Two calls on the same buffers give the same result (plan cache, no stale state)."""
+    p = config_problem("C2", n=20)
+    ctx = lib.Context()
+    tree = lib.Tree.of(p)
+    st, so = lib.pack(p.state, "cuda")
+    op, oo = lib.pack(p.op, "cuda")
+    c = lib.Compressor(ctx, tree, p.max_bond, "fp64")
+    c.run(op, oo, st, so)
+    a = c.unpack()
+    c.run(op, oo, st, so)
+    b = c.unpack()
+    assert tn.rel_error(p.parent, a, b) <= 1e-14

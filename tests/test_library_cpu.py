@@ -1,0 +1,119 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every declared
+symbol, validates arguments before any device work, and plans the same output bond dimensions as
+the oracle produces."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2601_19650_amd import cbc
+from paper_2601_19650_amd.inputs import chain_parent, config_problem, kary_parent, random_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = []
+    for h in ("cbc.h", "cbc_testing.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(cbc_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_declared_symbols():
+    L = cbc.lib()
+    names = declared_functions()
+    assert "cbc_apply" in names and "cbc_apply_naive" in names and "cbc_query" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(cbc.EXPORTED) | set(cbc.TESTING_EXPORTED) == set(names)
+
+
+def _query(tree, max_bond=8, prec=0, method=0):
+    ctx = cbc.Context()
+    ws = ctypes.c_size_t()
+    off = np.zeros(tree.n + 1, dtype=np.int64)
+    rc = cbc.lib().cbc_query(ctx.h, ctypes.byref(tree.c), max_bond, prec, method, ctypes.byref(ws),
+                             off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return rc, int(ws.value), off
+
+
+def T(parent, phys=2, chi=None, dop=None):
+    n = len(parent)
+    chi = chi if chi is not None else [1 if p < 0 else 2 for p in parent]
+    dop = dop if dop is not None else [1 if p < 0 else 2 for p in parent]
+    return cbc.Tree(parent, [phys] * n if np.isscalar(phys) else phys, chi, dop)
+
+
+@pytest.mark.parametrize("parent", [[-1, -1, 0], [1, 2, 0], [-1, 5, 0], [-1, 1], [0, 0]])
+def test_bad_topology_rejected(parent):
+    rc, _, _ = _query(T(parent))
+    assert rc == -2
+
+
+def test_bad_dims_rejected():
+    assert _query(T([-1, 0], chi=[2, 2]))[0] == -2          # root bond must be 1
+    assert _query(T([-1, 0], chi=[1, 0]))[0] == -2
+    assert _query(T([-1, 0], phys=[2, 0]))[0] == -2
+    assert _query(T([-1, 0]), max_bond=0)[0] == -1
+    assert _query(T([-1, 0]), prec=7)[0] == -1
+    assert _query(T([-1, 0]), method=5)[0] == -1
+
+
+def test_apply_argument_errors_need_no_device():
+    p = config_problem("C1")
+    tree = cbc.Tree.of(p)
+    ctx = cbc.Context()
+    I64 = ctypes.POINTER(ctypes.c_int64)
+    off = np.zeros(p.n, dtype=np.int64)
+    sizes = [t.size for t in p.state]
+    off[1:] = np.cumsum(sizes)[:-1]
+    ooff = np.zeros(p.n, dtype=np.int64)
+    osz = [w.size for w in p.op]
+    ooff[1:] = np.cumsum(osz)[:-1]
+    rc, ws, outoff = _query(tree, p.max_bond)
+    assert rc == 0 and ws > 0
+    bond = np.zeros(p.n, dtype=np.int32)
+    ttns = cbc._Tensors(0x1000, off.ctypes.data_as(I64))
+    ttno = cbc._Tensors(0x1000, ooff.ctypes.data_as(I64))
+    out = cbc._Out(0x1000, outoff.ctypes.data_as(I64), bond.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    stats = cbc.Stats()
+    f = cbc.lib().cbc_apply
+    args = lambda tol, wsb, mb=p.max_bond: (ctx.h, ctypes.byref(ttno), ctypes.byref(ttns),
+                                            ctypes.byref(tree.c), mb, tol, 0, 0x1000, wsb,
+                                            ctypes.byref(out), None, ctypes.byref(stats))
+    assert f(*args(-1.0, ws)) == -1
+    assert f(*args(float("nan"), ws)) == -1
+    assert f(*args(float("inf"), ws)) == -1
+    assert f(*args(0.0, ws - 1)) == -3                       # workspace too small
+    assert f(*args(0.0, ws, 0)) == -1
+    assert f(ctx.h, None, ctypes.byref(ttns), ctypes.byref(tree.c), 4, 0.0, 0, 0x1000, ws,
+             ctypes.byref(out), None, None) == -1
+    # offsets that are not a packed layout are rejected
+    bad = off.copy()
+    bad[-1] += 10 ** 6
+    ttns_bad = cbc._Tensors(0x1000, bad.ctypes.data_as(I64))
+    assert f(ctx.h, ctypes.byref(ttno), ctypes.byref(ttns_bad), ctypes.byref(tree.c), 4, 0.0, 0,
+             0x1000, ws, ctypes.byref(out), None, None) == -1
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: config_problem("C1"), lambda: config_problem("C2", n=16), lambda: config_problem("C3", n=15),
+    lambda: random_problem(kary_parent(13, 3), 2, 6, 3, 5, seed=4),
+    lambda: random_problem(chain_parent(7), [3, 1, 2, 2, 1, 3, 2], 5, 4, 6, seed=5)])
+def test_planned_bonds_match_oracle(maker):
+    """The static output bond dimensions the planner fixes before any device work equal the bond
+    dimensions of the oracle's output (tol = 0)."""
+    from oracle import cbc_tree
+    p = maker()
+    tree = cbc.Tree.of(p)
+    rc, ws, off = _query(tree, p.max_bond)
+    assert rc == 0
+    ref = cbc_tree(p.parent, p.state, p.op, p.max_bond)
+    sizes = np.diff(off)
+    assert [int(s) for s in sizes] == [t.size for t in ref]
+    for prec in (0, 1):
+        assert _query(tree, p.max_bond, prec)[0] == 0
