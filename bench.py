@@ -1,0 +1,190 @@
+#!/usr/bin/env python
+"""Benchmark of the CBC hot path on one MI355X.
+
+Workload (default): the 64-site MPS of the paper's random-network benchmark shape, d=2, state bond
+chi=64, MPO bond D=8, complex Gaussian entries, target bond 64 (truncating 512 -> 64). One step is one
+complete compression (forward and backward sweeps, every truncation and QR) of that input, already
+resident in HBM. The headline value is compressions/s of the mixed form (FP32 MFMA contractions,
+FP64 Gram/eigen/Cholesky); the plain FP64 form is timed beside it on the same input.
+
+Prints one JSON line. `--gpus N` with N > 1 is refused: the library runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "fp64_alu": 78.6e12, "hbm": 8.0e12,
+}
+WORKLOADS = {
+    "C2": "MPS N=64 d=2 chi=64 D=8 max_bond=64 (truncating), complex Gaussian",
+    "C1": "MPS N=8 d=2 chi=8 D=4 max_bond=32 (exact)",
+    "C3": "binary tree 31 nodes d=2 chi=32 D=6 max_bond=32",
+}
+
+
+def timed_runs(comp, args_run, stream, steps, warmup):
+    import torch
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            comp.run(*args_run, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            comp.run(*args_run, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) / steps
+
+
+def profiled_runs(comp, args_run, stream, steps):
+    """Per-kernel-class time from HIP events the library records on its own stream."""
+    import torch
+    from paper_2601_19650_amd import cbc
+    tot = [0.0] * cbc.NCLASS
+    with torch.cuda.stream(stream):
+        for _ in range(steps):
+            comp.run(*args_run, stream=stream.cuda_stream, profile=True)
+            for k in range(cbc.NCLASS):
+                tot[k] += comp.stats.ms[k]
+    torch.cuda.synchronize()
+    return [t / steps for t in tot]
+
+
+def cpu_baseline(p, gpu_outputs, budget_s=20.0):
+    """The oracle on the host cores (all of them), bounded to ~budget_s; also the error of each GPU
+    output against the oracle's result."""
+    import numpy as np  # noqa: F401
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import cbc_tree, cbc_tt, tn
+    ncores = len(os.sched_getaffinity(0))
+    chain = all(q == i - 1 for i, q in enumerate(p.parent))
+    with threadpool_limits(limits=ncores):
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+        times = []
+        ref = None
+        t_start = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            if chain:
+                ref = tn.mps_to_tree(cbc_tt(tn.tree_to_mps(p.state), tn.tree_to_mpo(p.op), p.max_bond))
+            else:
+                ref = cbc_tree(p.parent, p.state, p.op, p.max_bond)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_start > budget_s * 0.5 or len(times) >= 20:
+                break
+    med = sorted(times)[len(times) // 2]
+    errs = {}
+    for prec, out in gpu_outputs.items():
+        errs[prec] = dict(rel_state_error=tn.rel_error(p.parent, out, ref),
+                          infidelity=1.0 - tn.fidelity(p.parent, out, ref))
+    return dict(value=1.0 / med, unit="compressions/s", cores=int(threads), kind="oracle",
+                sample=f"{len(times)} full compressions of the same workload (median "
+                       f"{med:.2f} s each, NumPy complex128, {'tensor-train' if chain else 'tree'} "
+                       f"sweep)"), errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2601_19650_amd import cbc
+    from paper_2601_19650_amd.inputs import config_problem
+
+    torch.cuda.set_device(0)
+    p = config_problem(args.workload)
+    tree = cbc.Tree.of(p)
+    st, so = cbc.pack(p.state, "cuda:0")
+    op, oo = cbc.pack(p.op, "cuda:0")
+    ctx = cbc.Context()
+    stream = torch.cuda.Stream()
+    res, outputs = {}, {}
+    precs = [args.only] if args.only else ["mixed", "fp64"]
+    for prec in precs:
+        comp = cbc.Compressor(ctx, tree, p.max_bond, prec, device="cuda:0")
+        run_args = (op, oo, st, so, 0.0)
+        sec = timed_runs(comp, run_args, stream, args.steps, args.warmup)
+        replayed = int(comp.stats.graph_replayed)
+        outputs[prec] = comp.unpack()
+        kms = profiled_runs(comp, run_args, stream, max(3, min(args.steps, 10)))
+        st_d = comp.stats.as_dict()
+        res[prec] = dict(sec=sec, kms=kms, stats=st_d, replayed=replayed,
+                         n_kernels=int(comp.stats.n_kernels))
+        print(f"[bench] {prec}: {sec * 1e3:.3f} ms/compression, kernels/call "
+              f"{comp.stats.n_kernels}, graph replay {replayed}", file=sys.stderr, flush=True)
+
+    head = precs[0]
+    r = res[head]
+    sec = r["sec"]
+    cls = cbc.CLASSES
+    # dominant kernel class by profiled time
+    kd = max(range(cbc.NCLASS), key=lambda k: r["kms"][k])
+    launches = r["stats"][cls[kd]]["launches"]
+    avg_ms = r["kms"][kd] / max(launches, 1)
+    flops_per_launch = r["stats"][cls[kd]]["flops"] / max(launches, 1)
+    if cls[kd] in ("contract",):
+        bound, peak = "mfma", PEAK["fp32_mfma"] if head == "mixed" else PEAK["fp64_mfma"]
+    elif cls[kd] in ("gram", "qrmul"):
+        bound, peak = "mfma", PEAK["fp64_mfma"]
+    else:
+        bound, peak = "alu", PEAK["fp64_alu"]
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    contraction_flops = r["stats"]["contract"]["flops"]
+    line = {
+        "metric": "CBC compressions/s (mixed FP32-MFMA contractions + FP64 Gram/eigen/Cholesky)",
+        "value": 1.0 / sec,
+        "unit": "compressions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64" if head == "mixed" else "c128",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "name": args.workload,
+                   "precision": head, "max_bond": p.max_bond, "n_nodes": p.n},
+        "contraction_tflops": contraction_flops / sec / 1e12,
+        "roofline": {"bound": bound, "kernel": cls[kd], "achieved": achieved,
+                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved * 1e12 / peak,
+                     "traffic": None, "avg_launch_ms": avg_ms,
+                     "flops_per_launch": flops_per_launch},
+        "kernel_ms_per_step": {cls[k]: r["kms"][k] for k in range(cbc.NCLASS)},
+        "kernels_per_step": r["n_kernels"],
+        "graph_replayed": r["replayed"],
+    }
+    if "fp64" in res and "mixed" in res:
+        line["fp64"] = {"value": 1.0 / res["fp64"]["sec"], "ms_per_step": res["fp64"]["sec"] * 1e3,
+                        "kernel_ms_per_step": {cls[k]: res["fp64"]["kms"][k]
+                                               for k in range(cbc.NCLASS)}}
+        line["speedup_mixed_vs_fp64"] = res["fp64"]["sec"] / res["mixed"]["sec"]
+    if not args.no_cpu_baseline:
+        cb, errs = cpu_baseline(p, outputs)
+        line["cpu_baseline"] = cb
+        line["error_vs_oracle"] = errs
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -84,21 +84,38 @@ typedef struct {
 } cbc_tensors;
 
 /* The compressed state. Node i is written at out_offset[i] (from cbc_query) with legs
- * (sigma_i, bond_parent, bond_child_1, ...) as interleaved complex128; bond[] is written on return. */
+ * (sigma_i, bond_parent, bond_child_1, ...) as interleaved complex128, packed row-major at the start
+ * of its slot; bond[] is written on return. Slots are sized for the largest bonds the call can
+ * produce, so node i may use less than out_offset[i+1] - out_offset[i] elements. */
 typedef struct {
   void* data;              /* device pointer, at least out_offset[n_nodes] elements */
   const int64_t* offset;   /* host, n_nodes + 1 entries as returned by cbc_query */
   int32_t* bond;           /* host, n_nodes entries: bond of node i to its parent (1 at the root) */
 } cbc_out;
 
-/* Per-call statistics (optional). */
+/* Kernel classes reported in cbc_stats. */
+enum {
+  CBC_K_CONTRACT = 0,  /* environment / operator contractions, projections, environment updates */
+  CBC_K_GRAM = 1,      /* FP64 Gram matrices (truncation and QR) */
+  CBC_K_QRMUL = 2,     /* Q = C^{-1} S products of the Cholesky-QR */
+  CBC_K_EIG = 3,       /* truncation eigensolves */
+  CBC_K_CHOL = 4,      /* Cholesky factorisations and triangular inverses */
+  CBC_K_OTHER = 5,     /* conversions, output writes, fills */
+  CBC_K_NCLASS = 6
+};
+
+/* Per-call statistics (optional). `profile` is an input: when nonzero the call records a HIP event
+ * pair around every kernel on the call's stream and fills ms[] (no hipGraph replay in that mode). */
 typedef struct {
-  double contraction_flops;   /* algorithmic flops of the contractions (8 per complex MAC) */
-  double gram_flops;          /* algorithmic flops of the FP64 Gram matrices (8 per complex MAC) */
-  int32_t n_eig;              /* eigensolves performed */
-  int32_t max_eig_dim;        /* largest Gram matrix that was eigensolved */
-  int32_t n_kernels;          /* kernels launched per call */
-  int32_t graph_replayed;     /* 1 if the call replayed a cached hipGraph */
+  int32_t profile;                   /* in: 1 = time every kernel class with HIP events */
+  int32_t n_kernels;                 /* out: kernels launched per call */
+  int32_t n_eig;                     /* out: eigensolves performed */
+  int32_t max_eig_dim;               /* out: largest Gram matrix that was eigensolved */
+  int32_t graph_replayed;            /* out: 1 if the call replayed a cached hipGraph */
+  int32_t launches[CBC_K_NCLASS];    /* out: launches per kernel class */
+  double flops[CBC_K_NCLASS];        /* out: algorithmic flops per class (8 per complex MAC) */
+  double bytes[CBC_K_NCLASS];        /* out: algorithmic bytes moved per class (operands + result) */
+  double ms[CBC_K_NCLASS];           /* out: summed kernel time per class (profile mode only) */
 } cbc_stats;
 
 /* Create / destroy a context. */
@@ -111,6 +128,13 @@ const char* cbc_status_str(cbc_status s);
  * `method` is 0 for cbc_apply and 1 for cbc_apply_naive. */
 cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
                      int32_t method, size_t* workspace_bytes, int64_t* out_offset);
+
+/* The output bond dimensions cbc_apply will report (host only, no device work): bond[i] for the
+ * edge from node i to its parent, 1 at the root. With tol_on = 0 they are the economy-QR bonds
+ * min(environment bond, sigma' x child bonds); with tol_on = 1 every edge keeps its planned
+ * environment bond (slices beyond the kept directions are zero). */
+cbc_status cbc_plan_bonds(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, int32_t tol_on,
+                          int32_t* bond);
 
 /* Cholesky-based compression of O|psi> (Sec. III A for chains, Sec. III B for trees).
  * max_bond >= 1 is the target bond dimension (the paper's D-bar); tol >= 0 additionally drops

@@ -39,10 +39,21 @@ class _Out(ctypes.Structure):
                 ("bond", ctypes.POINTER(ctypes.c_int32))]
 
 
+NCLASS = 6
+CLASSES = ("contract", "gram", "qrmul", "eig", "chol", "other")
+
+
 class Stats(ctypes.Structure):
-    _fields_ = [("contraction_flops", ctypes.c_double), ("gram_flops", ctypes.c_double),
+    _fields_ = [("profile", ctypes.c_int32), ("n_kernels", ctypes.c_int32),
                 ("n_eig", ctypes.c_int32), ("max_eig_dim", ctypes.c_int32),
-                ("n_kernels", ctypes.c_int32), ("graph_replayed", ctypes.c_int32)]
+                ("graph_replayed", ctypes.c_int32), ("launches", ctypes.c_int32 * NCLASS),
+                ("flops", ctypes.c_double * NCLASS), ("bytes", ctypes.c_double * NCLASS),
+                ("ms", ctypes.c_double * NCLASS)]
+
+    def as_dict(self):
+        return {c: dict(launches=int(self.launches[k]), flops=float(self.flops[k]),
+                        bytes=float(self.bytes[k]), ms=float(self.ms[k]))
+                for k, c in enumerate(CLASSES)}
 
 
 _lib = None
@@ -65,6 +76,9 @@ def lib():
                                 ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t),
                                 ctypes.POINTER(ctypes.c_int64)]
         L.cbc_query.restype = ctypes.c_int
+        L.cbc_plan_bonds.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tree), ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.cbc_plan_bonds.restype = ctypes.c_int
         for name in ("cbc_apply", "cbc_apply_naive"):
             f = getattr(L, name)
             f.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tensors), ctypes.POINTER(_Tensors),
@@ -76,8 +90,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ("cbc_create", "cbc_destroy", "cbc_status_str", "cbc_query", "cbc_apply",
-            "cbc_apply_naive")
+EXPORTED = ("cbc_create", "cbc_destroy", "cbc_status_str", "cbc_query", "cbc_plan_bonds",
+            "cbc_apply", "cbc_apply_naive")
 
 
 def _check(code, what):
@@ -163,8 +177,9 @@ class Compressor:
         self.bond = np.zeros(tree.n, dtype=np.int32)
         self.stats = Stats()
 
-    def run(self, op_buf, op_off, st_buf, st_off, tol=0.0, stream=None):
+    def run(self, op_buf, op_off, st_buf, st_off, tol=0.0, stream=None, profile=False):
         import torch
+        self.stats.profile = int(bool(profile))
         op_off = np.ascontiguousarray(op_off, dtype=np.int64)
         st_off = np.ascontiguousarray(st_off, dtype=np.int64)
         I64 = ctypes.POINTER(ctypes.c_int64)

@@ -51,6 +51,8 @@ enum OpKind : int { K_GEMM, K_EIG, K_FORM_N, K_CHOL, K_CONVERT, K_IDENT, K_WRITE
 
 struct Op {
   OpKind kind;
+  int cls = CBC_K_OTHER;     // kernel class for statistics
+  double flops = 0.0, bytes = 0.0;
   // GEMM
   TRef A, B, C;
   int M = 0, N = 0, K = 0;
@@ -81,6 +83,10 @@ struct Plan {
   std::vector<int32_t> out_bond;
   double cflops = 0.0, gflops = 0.0;
   int n_eig = 0, max_eig = 0;
+  int launches[CBC_K_NCLASS] = {0};
+  double flops[CBC_K_NCLASS] = {0.0};
+  double bytes[CBC_K_NCLASS] = {0.0};
+  std::vector<hipEvent_t> events;
   // misc device slots (persistent workspace offsets)
   int64_t logs_off = 0, ndrop_off = 0;
   int64_t state_conv_off = -1, op_conv_off = -1;
@@ -91,6 +97,7 @@ struct Plan {
   ~Plan() {
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (d_tables) (void)hipFree(d_tables);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
   }
 };
 
@@ -293,6 +300,11 @@ struct Builder {
     op.adev2 = adev2;
     op.tile = ((int64_t)op.M * op.N >= (int64_t)64 * 64 * 96) ? 1 : 0;
     const double f = 8.0 * (double)op.M * op.N * op.K;
+    op.cls = bucket == 0 ? CBC_K_CONTRACT : bucket == 1 ? CBC_K_GRAM : CBC_K_QRMUL;
+    // a Hermitian Gram counts half its complex MACs as algorithmic work
+    op.flops = bucket == 1 ? 0.5 * f : f;
+    op.bytes = (double)esz(op.ta) * op.M * op.K + (double)esz(op.tb) * op.K * op.N +
+               (double)esz(tc) * op.M * op.N;
     if (bucket == 0) P.cflops += f;
     else if (bucket == 1) P.gflops += 0.5 * f;
     else P.gflops += f;
@@ -391,6 +403,10 @@ struct Builder {
     e.kkeep = kk;
     e.invs = invs;
     e.work = work;
+    e.cls = CBC_K_EIG;
+    // Householder reduction (16/3 s^3) plus back-transformation of kmax vectors (8 s^2 kmax)
+    e.flops = 16.0 / 3.0 * (double)s * s * s + 8.0 * (double)s * s * kmax;
+    e.bytes = 16.0 * (double)s * s + 16.0 * (double)s * kmax;
     P.ops.push_back(e);
     P.n_eig++;
     P.max_eig = std::max(P.max_eig, s);
@@ -409,6 +425,7 @@ struct Builder {
       f.kmax = (int)kmax;
       f.L = L.ref;
       f.td = ct;
+      f.cls = CBC_K_OTHER;
       P.ops.push_back(f);
     }
     return L;
@@ -448,6 +465,10 @@ struct Builder {
       nd.src = S_WS;
       nd.off = P.ndrop_off;
       c.ndrop = nd;
+      c.cls = CBC_K_CHOL;
+      // Cholesky (4/3 k^3) plus triangular inverse (4/3 k^3), complex
+      c.flops = 8.0 / 3.0 * (double)k * k * k;
+      c.bytes = 32.0 * (double)k * k;
       P.ops.push_back(c);
       // Q = C^{-1} cur
       std::vector<int> qo{knew_leg};
@@ -597,11 +618,17 @@ cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc
     int64_t ns = pr.phys[i];
     for (int c : pr.ch[i]) ns *= kout[c];
     const int64_t k = B.legdim[Lpar[i].legs[0]];
-    kout[i] = (int)std::min<int64_t>(k, ns);
+    // Without a tolerance the economy QR gives min(k, ns) rows. With one, Q keeps all k rows (those
+    // beyond the row space of S are zero), because the kept count is only known on device.
+    kout[i] = tol_on ? (int)k : (int)std::min<int64_t>(k, ns);
   }
+  // Output slots are sized for the planned environment bond on every edge (the tolerance-mode
+  // shape), so the packing is the same with and without a tolerance; a node is written as a prefix
+  // of its slot with its actual bonds.
   for (int i = 0; i < n; ++i) {
-    int64_t e = pr.phys[i] * (int64_t)kout[i];
-    for (int c : pr.ch[i]) e *= kout[c];
+    const int64_t kcap_i = i == pr.root ? 1 : B.legdim[Lpar[i].legs[0]];
+    int64_t e = pr.phys[i] * kcap_i;
+    for (int c : pr.ch[i]) e *= B.legdim[Lpar[c].legs[0]];
     P.out_off[i + 1] = P.out_off[i] + e;
     P.out_bond[i] = kout[i];
   }
@@ -699,6 +726,11 @@ cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc
   }
   P.persist_bytes = B.persist;
   P.scratch_bytes = B.scratch_max;
+  for (const Op& op : P.ops) {
+    P.launches[op.cls] += 1;
+    P.flops[op.cls] += op.flops;
+    P.bytes[op.cls] += op.bytes;
+  }
   return CBC_OK;
 }
 
@@ -747,9 +779,14 @@ __global__ void k_zero_bytes(uint32_t* p, int64_t n) {
   if (i < n) p[i] = 0u;
 }
 
-hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st) {
+hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev = nullptr) {
+  size_t idx = 0;
   for (const Op& op : P.ops) {
     hipError_t e = hipSuccess;
+    if (ev) {
+      e = hipEventRecord(ev[2 * idx], st);
+      if (e != hipSuccess) return e;
+    }
     switch (op.kind) {
       case K_GEMM: {
         GemmArgs g;
@@ -829,6 +866,11 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st) {
       }
     }
     if (e != hipSuccess) return e;
+    if (ev) {
+      e = hipEventRecord(ev[2 * idx + 1], st);
+      if (e != hipSuccess) return e;
+    }
+    ++idx;
   }
   return hipSuccess;
 }
@@ -946,6 +988,24 @@ cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_p
   return CBC_OK;
 }
 
+cbc_status cbc_plan_bonds(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, int32_t tol_on,
+                          int32_t* bond) {
+  if (!ctx || !bond) return CBC_EINVAL;
+  Problem pr;
+  cbc_status s = common_checks(tree, max_bond, CBC_PREC_FP64, pr);
+  if (s != CBC_OK) return s;
+  int64_t se = 0, oe = 0;
+  for (int i = 0; i < pr.n; ++i) {
+    se += tensor_elems_state(pr, i);
+    oe += tensor_elems_op(pr, i);
+  }
+  Plan* P = nullptr;
+  s = get_plan(ctx, pr, max_bond, tol_on != 0, CBC_PREC_FP64, 0, se, oe, &P);
+  if (s != CBC_OK) return s;
+  for (int i = 0; i < pr.n; ++i) bond[i] = P->out_bond[i];
+  return CBC_OK;
+}
+
 static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
                              const cbc_tree* tree, int32_t max_bond, double tol,
                              cbc_precision prec, void* workspace, size_t workspace_bytes,
@@ -989,17 +1049,75 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   c.out_off = P->out_off.data();
   c.persist = P->persist_bytes;
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = run_ops(*P, c, st);
-  if (e != hipSuccess) return CBC_EHIP;
+  const bool profile = stats && stats->profile;
+  int replayed = 0;
+  if (profile) {
+    const size_t ne = 2 * P->ops.size();
+    while (P->events.size() < ne) {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) return CBC_EHIP;
+      P->events.push_back(ev);
+    }
+    if (run_ops(*P, c, st, P->events.data()) != hipSuccess) return CBC_EHIP;
+  } else if (st != nullptr) {
+    // replay a captured graph of the whole launch sequence when the buffers are unchanged
+    std::vector<uintptr_t> key{(uintptr_t)c.ws, (uintptr_t)c.state, (uintptr_t)c.op,
+                               (uintptr_t)c.out};
+    uint64_t tb;
+    memcpy(&tb, &tol, sizeof(tb));
+    key.push_back((uintptr_t)tb);
+    for (int i = 0; i < pr.n; ++i) {
+      key.push_back((uintptr_t)c.st_off[i]);
+      key.push_back((uintptr_t)c.op_off[i]);
+    }
+    if (!P->gexec || P->gkey != key) {
+      if (P->gexec) {
+        (void)hipGraphExecDestroy(P->gexec);
+        P->gexec = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return CBC_EHIP;
+      const hipError_t e1 = run_ops(*P, c, st);
+      const hipError_t e2 = hipStreamEndCapture(st, &g);
+      if (e1 != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return CBC_EHIP;
+      }
+      const hipError_t e3 = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e3 != hipSuccess) {
+        P->gexec = nullptr;
+        return CBC_EHIP;
+      }
+      P->gkey = key;
+    } else {
+      replayed = 1;
+    }
+    if (hipGraphLaunch(P->gexec, st) != hipSuccess) return CBC_EHIP;
+  } else {
+    if (run_ops(*P, c, st) != hipSuccess) return CBC_EHIP;
+  }
   if (hipStreamSynchronize(st) != hipSuccess) return CBC_EHIP;
   for (int i = 0; i < pr.n; ++i) out->bond[i] = P->out_bond[i];
   if (stats) {
-    stats->contraction_flops = P->cflops;
-    stats->gram_flops = P->gflops;
+    stats->n_kernels = (int32_t)P->ops.size();
     stats->n_eig = P->n_eig;
     stats->max_eig_dim = P->max_eig;
-    stats->n_kernels = (int32_t)P->ops.size();
-    stats->graph_replayed = 0;
+    stats->graph_replayed = replayed;
+    for (int k = 0; k < CBC_K_NCLASS; ++k) {
+      stats->launches[k] = P->launches[k];
+      stats->flops[k] = P->flops[k];
+      stats->bytes[k] = P->bytes[k];
+      stats->ms[k] = 0.0;
+    }
+    if (profile) {
+      for (size_t i = 0; i < P->ops.size(); ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, P->events[2 * i], P->events[2 * i + 1]) != hipSuccess)
+          return CBC_EHIP;
+        stats->ms[P->ops[i].cls] += ms;
+      }
+    }
   }
   return CBC_OK;
 }
