@@ -24,17 +24,20 @@ int cbc_test_gemm(int M, int N, int K, const void* A, int a_c128, int transA, in
 /* Truncation eigensolve (Sec. III A "compress ... for example via singular value decomposition",
  * realised on the FP64 Gram matrix): G (s x s complex128 Hermitian, overwritten) -> U (s x kmax
  * complex128, top eigenvectors as columns, zero beyond the kept count), lam (kmax doubles,
- * descending), kkeep (1 int), inv_sqrt_l0 (1 double). */
+ * descending), kkeep (1 int), inv_sqrt_l0 (1 double). tstamp: nullptr, or 8 int64 device slots that
+ * receive wall-clock stamps (100 MHz) at the phase boundaries: start, tridiagonal, eigenvalues,
+ * eigenvectors, back-transformed. */
 int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void* lam, void* kkeep,
-                 void* inv_sqrt_l0, void* stream);
+                 void* inv_sqrt_l0, void* tstamp, void* stream);
 
 /* One Cholesky + triangular inverse step of the QR on the parent leg (Sec. III A, Eq.
  * tt_cbc_qr_decomp, realised as Cholesky-QR): G (k x k complex128 Hermitian PSD, overwritten) ->
  * Cinv (k x k complex128, inverse of the lower Cholesky factor; zero rows and columns for dropped
  * pivots); shift_rel adds shift_rel * trace(G) to the diagonal first. ndrop (1 int) receives the
- * number of dropped pivots. */
+ * number of dropped pivots. tstamp: nullptr or 4 int64 device slots for wall-clock stamps (100 MHz)
+ * at: start, factorised, inverted, written (LDS-resident sizes only). */
 int cbc_test_chol_inv(void* G, int k, double shift_rel, double drop_rel, void* Cinv, void* ndrop,
-                      void* stream);
+                      void* tstamp, void* stream);
 
 #ifdef __cplusplus
 }

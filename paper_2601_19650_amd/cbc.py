@@ -228,9 +228,9 @@ def _testing_lib():
         vp, ci, cd = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
         L.cbc_test_gemm.argtypes = [ci, ci, ci, vp, ci, ci, ci, vp, ci, ci, ci, vp, ci, ci, ci, vp]
         L.cbc_test_gemm.restype = ci
-        L.cbc_test_eig.argtypes = [vp, ci, ci, cd, vp, vp, vp, vp, vp]
+        L.cbc_test_eig.argtypes = [vp, ci, ci, cd, vp, vp, vp, vp, vp, vp]
         L.cbc_test_eig.restype = ci
-        L.cbc_test_chol_inv.argtypes = [vp, ci, cd, cd, vp, vp, vp]
+        L.cbc_test_chol_inv.argtypes = [vp, ci, cd, cd, vp, vp, vp, vp]
         L.cbc_test_chol_inv.restype = ci
         L._testing_ready = True
     return L
@@ -263,8 +263,9 @@ def test_gemm(A, B, transA=False, conjA=False, transB=False, conjB=False, out_dt
     return C
 
 
-def test_eig(G, kmax, tol=0.0):
-    """Top-kmax eigenpairs of a Hermitian complex128 device matrix (G is consumed)."""
+def test_eig(G, kmax, tol=0.0, stamps=None):
+    """Top-kmax eigenpairs of a Hermitian complex128 device matrix (G is consumed). If `stamps` is a
+    list, the phase durations in microseconds are appended to it."""
     import torch
     s = G.shape[0]
     G = G.contiguous().clone()
@@ -272,19 +273,29 @@ def test_eig(G, kmax, tol=0.0):
     lam = torch.empty(kmax, dtype=torch.float64, device=G.device)
     kk = torch.empty(1, dtype=torch.int32, device=G.device)
     inv = torch.empty(1, dtype=torch.float64, device=G.device)
+    ts = torch.zeros(8, dtype=torch.int64, device=G.device)
     _check(_testing_lib().cbc_test_eig(G.data_ptr(), s, kmax, float(tol), U.data_ptr(),
-                                       lam.data_ptr(), kk.data_ptr(), inv.data_ptr(), _stream()),
+                                       lam.data_ptr(), kk.data_ptr(), inv.data_ptr(),
+                                       ts.data_ptr() if stamps is not None else None, _stream()),
            "cbc_test_eig")
+    if stamps is not None:
+        t = ts.cpu().numpy()
+        stamps.append([(t[i + 1] - t[i]) / 100.0 for i in range(4)])
     return U, lam, int(kk.item()), float(inv.item())
 
 
-def test_chol_inv(G, shift_rel=0.0, drop_rel=0.0):
+def test_chol_inv(G, shift_rel=0.0, drop_rel=0.0, stamps=None):
     import torch
     k = G.shape[0]
     G = G.contiguous().clone()
     Ci = torch.empty((k, k), dtype=torch.complex128, device=G.device)
     nd = torch.zeros(1, dtype=torch.int32, device=G.device)
+    ts = torch.zeros(4, dtype=torch.int64, device=G.device)
     _check(_testing_lib().cbc_test_chol_inv(G.data_ptr(), k, float(shift_rel), float(drop_rel),
-                                            Ci.data_ptr(), nd.data_ptr(), _stream()),
+                                            Ci.data_ptr(), nd.data_ptr(),
+                                            ts.data_ptr() if stamps is not None else None, _stream()),
            "cbc_test_chol_inv")
+    if stamps is not None:
+        t = ts.cpu().numpy()
+        stamps.append([(t[i + 1] - t[i]) / 100.0 for i in range(3)])
     return Ci, int(nd.item())

@@ -824,6 +824,7 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         a.inv_sqrt_l0 = (double*)resolve(P, c, op.invs);
         a.work = (double*)resolve(P, c, op.work);
         a.tol = op.shift_rel;  // tolerance stored per call below
+        a.tstamp = nullptr;
         e = launch_eig(a, st);
         break;
       }
@@ -842,6 +843,7 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         a.log_scale = op.logs.src == S_NONE ? nullptr : (double*)resolve(P, c, op.logs);
         a.scale = op.scale.src == S_NONE ? nullptr : (double*)resolve(P, c, op.scale);
         a.ndrop = (int*)resolve(P, c, op.ndrop);
+        a.tstamp = nullptr;
         e = launch_chol_inv(a, st);
         break;
       }

@@ -50,6 +50,7 @@ struct EigArgs {
   int* kkeep;
   double* inv_sqrt_l0;
   double* work;     // scratch, eig_work_doubles(s, kmax) doubles
+  long long* tstamp;  // optional: wall-clock stamps at phase boundaries (8 entries), or nullptr
 };
 size_t eig_work_doubles(int s, int kmax);
 hipError_t launch_eig(const EigArgs& a, hipStream_t st);
@@ -72,6 +73,7 @@ struct CholArgs {
   double* log_scale;
   double* scale;
   int* ndrop;
+  long long* tstamp;  // optional: wall-clock stamps at phase boundaries (4 entries), or nullptr
 };
 hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st);
 

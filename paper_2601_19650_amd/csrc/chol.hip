@@ -140,9 +140,141 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(CholArgs a) {
   }
 }
 
+// LDS-resident variant for k <= CHOL_LDS_MAX: the factor lives in the lower triangle of a k x k LDS
+// matrix M; the inverse X = C^{-1} is built column by column (one lane per column) with its strictly
+// lower part stored transposed in the upper triangle of M and its diagonal in xd.
+static constexpr int CHOL_LDS_MAX = 88;
+
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a) {
+  extern __shared__ double2 M[];
+  __shared__ double red[32];
+  __shared__ double sh_thresh;
+  const int k = a.k;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  const int ld = k + 1;   // odd row stride: column-wise lane accesses hit distinct banks
+  double* xd = reinterpret_cast<double*>(M + (size_t)k * ld);
+  int* dropped = reinterpret_cast<int*>(xd + k);
+  if (a.tstamp && tid == 0) a.tstamp[0] = wall_clock64();
+  for (int i = tid; i < k * k; i += blockDim.x) M[(i / k) * ld + (i % k)] = a.G[i];
+  for (int i = tid; i < k; i += blockDim.x) dropped[i] = 0;
+  __syncthreads();
+  double tr = 0.0;
+  for (int i = tid; i < k; i += blockDim.x) tr += M[i * ld + i].x;
+  tr = wsum(tr);
+  if (lane == 0) red[wave] = tr;
+  __syncthreads();
+  double trace = 0.0;
+  for (int w = 0; w < nwave; ++w) trace += red[w];
+  if (tid == 0 && a.log_scale) {
+    a.log_scale[0] = trace > 0.0 ? -0.5 * log(trace) : 0.0;
+    a.scale[0] = trace > 0.0 ? 1.0 / sqrt(trace) : 1.0;
+  }
+  const double shift = a.shift_rel * trace;
+  __syncthreads();
+  double mx = 0.0;
+  for (int i = tid; i < k; i += blockDim.x) {
+    double2 g = M[i * ld + i];
+    g.x += shift;
+    g.y = 0.0;
+    M[i * ld + i] = g;
+    mx = fmax(mx, g.x);
+  }
+  mx = wmax(mx);
+  if (lane == 0) red[wave] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int w = 0; w < nwave; ++w) m = fmax(m, red[w]);
+    sh_thresh = a.drop_rel * m;
+  }
+  __syncthreads();
+  const double thresh = sh_thresh;
+  constexpr int RGc = 8;
+  const int grp = tid / RGc, gl = tid % RGc, ngrp = blockDim.x / RGc;
+  for (int j = 0; j < k; ++j) {
+    const double djj = M[j * ld + j].x;
+    if (!(djj > thresh)) {
+      for (int i = j + tid; i < k; i += blockDim.x) M[i * ld + j] = make_double2(0.0, 0.0);
+      if (tid == 0) dropped[j] = 1;
+      __syncthreads();
+      continue;
+    }
+    const double c = sqrt(djj), ic = 1.0 / c;
+    for (int i = j + 1 + tid; i < k; i += blockDim.x) {
+      double2 g = M[i * ld + j];
+      g.x *= ic;
+      g.y *= ic;
+      M[i * ld + j] = g;
+    }
+    __syncthreads();
+    if (tid == 0) M[j * ld + j] = make_double2(c, 0.0);
+    for (int i = j + 1 + grp; i < k; i += ngrp) {
+      const double2 cij = M[i * ld + j];
+      for (int l = j + 1 + gl; l <= i; l += RGc) {
+        const double2 clj = M[l * ld + j];
+        double2 g = M[i * ld + l];
+        g.x -= cij.x * clj.x + cij.y * clj.y;
+        g.y -= cij.y * clj.x - cij.x * clj.y;
+        M[i * ld + l] = g;
+      }
+    }
+    __syncthreads();
+  }
+  if (a.tstamp && tid == 0) a.tstamp[1] = wall_clock64();
+  // inverse, one lane per column
+  for (int c = tid; c < k; c += blockDim.x) {
+    if (dropped[c]) {
+      xd[c] = 0.0;
+      for (int i = c + 1; i < k; ++i) M[c * ld + i] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double dc = 1.0 / M[c * ld + c].x;
+    xd[c] = dc;
+    for (int i = c + 1; i < k; ++i) {
+      if (dropped[i]) {
+        M[c * ld + i] = make_double2(0.0, 0.0);
+        continue;
+      }
+      const double2 cic = M[i * ld + c];
+      double sr = cic.x * dc, si = cic.y * dc;
+      for (int l = c + 1; l < i; ++l) {
+        const double2 cil = M[i * ld + l];
+        const double2 xl = M[c * ld + l];
+        sr += cil.x * xl.x - cil.y * xl.y;
+        si += cil.x * xl.y + cil.y * xl.x;
+      }
+      const double inv = -1.0 / M[i * ld + i].x;
+      M[c * ld + i] = make_double2(sr * inv, si * inv);
+    }
+  }
+  __syncthreads();
+  if (a.tstamp && tid == 0) a.tstamp[2] = wall_clock64();
+  for (int idx = tid; idx < k * k; idx += blockDim.x) {
+    const int i = idx / k, c = idx % k;
+    double2 v = make_double2(0.0, 0.0);
+    if (i == c) v = make_double2(xd[c], 0.0);
+    else if (i > c) v = M[c * ld + i];
+    a.Cinv[idx] = v;
+  }
+  if (a.ndrop && tid == 0) {
+    int nd = 0;
+    for (int j = 0; j < k; ++j) nd += dropped[j];
+    a.ndrop[0] += nd;
+  }
+  __syncthreads();
+  if (a.tstamp && tid == 0) a.tstamp[3] = wall_clock64();
+}
+
 hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st) {
   if (a.k <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CHOL_THREADS), (size_t)a.k * sizeof(int), st, a);
+  if (a.k <= CHOL_LDS_MAX) {
+    const size_t lds = (size_t)a.k * (a.k + 1) * sizeof(double2) + (size_t)a.k * (sizeof(double) + sizeof(int));
+    (void)hipFuncSetAttribute((const void*)k_chol_inv_lds,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_chol_inv_lds, dim3(1), dim3(CHOL_THREADS), lds, st, a);
+  } else {
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CHOL_THREADS), (size_t)a.k * sizeof(int), st, a);
+  }
   return hipGetLastError();
 }
 

@@ -48,7 +48,7 @@ extern "C" int cbc_test_gemm(int M, int N, int K, const void* A, int a_c128, int
 }
 
 extern "C" int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void* lam, void* kkeep,
-                            void* inv_sqrt_l0, void* stream) {
+                            void* inv_sqrt_l0, void* tstamp, void* stream) {
   if (!G || !U || !lam || !kkeep || !inv_sqrt_l0 || s < 1 || kmax < 1 || kmax > s) return CBC_EINVAL;
   double* w = nullptr;
   if (hipMalloc(&w, eig_work_doubles(s, kmax) * sizeof(double)) != hipSuccess) return CBC_ENOMEM;
@@ -56,6 +56,7 @@ extern "C" int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void*
   EigArgs a;
   a.G = (double2*)G; a.s = s; a.kmax = kmax; a.tol = tol; a.U = (double2*)U;
   a.lam = (double*)lam; a.kkeep = (int*)kkeep; a.inv_sqrt_l0 = (double*)inv_sqrt_l0; a.work = w;
+  a.tstamp = (long long*)tstamp;
   int rc = CBC_OK;
   if (launch_eig(a, st) != hipSuccess) rc = CBC_EHIP;
   else if (hipStreamSynchronize(st) != hipSuccess) rc = CBC_EHIP;
@@ -64,12 +65,13 @@ extern "C" int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void*
 }
 
 extern "C" int cbc_test_chol_inv(void* G, int k, double shift_rel, double drop_rel, void* Cinv,
-                                 void* ndrop, void* stream) {
+                                 void* ndrop, void* tstamp, void* stream) {
   if (!G || !Cinv || !ndrop || k < 1) return CBC_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   CholArgs a;
   a.G = (double2*)G; a.k = k; a.shift_rel = shift_rel; a.drop_rel = drop_rel;
   a.Cinv = (double2*)Cinv; a.log_scale = nullptr; a.scale = nullptr; a.ndrop = (int*)ndrop;
+  a.tstamp = (long long*)tstamp;
   if (launch_chol_inv(a, st) != hipSuccess) return CBC_EHIP;
   if (hipStreamSynchronize(st) != hipSuccess) return CBC_EHIP;
   return CBC_OK;
