@@ -280,7 +280,10 @@ def test_eig(G, kmax, tol=0.0, stamps=None):
            "cbc_test_eig")
     if stamps is not None:
         t = ts.cpu().numpy()
-        stamps.append([(t[i + 1] - t[i]) / 100.0 for i in range(4)])
+        # tridiagonal, eigenvalues (incl. launch), eigenvectors (incl. launch), then the
+        # tridiagonal step phases A/B/D and the number of clusters
+        stamps.append([(t[1] - t[0]) / 100.0, (t[2] - t[1]) / 100.0, (t[3] - t[2]) / 100.0,
+                       t[4] / 100.0, t[5] / 100.0, t[6] / 100.0, float(t[7])])
     return U, lam, int(kk.item()), float(inv.item())
 
 

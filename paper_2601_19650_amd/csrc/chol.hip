@@ -140,20 +140,32 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(CholArgs a) {
   }
 }
 
-// LDS-resident variant for k <= CHOL_LDS_MAX: the factor lives in the lower triangle of a k x k LDS
-// matrix M; the inverse X = C^{-1} is built column by column (one lane per column) with its strictly
-// lower part stored transposed in the upper triangle of M and its diagonal in xd.
+// LDS-resident variant for k <= CHOL_LDS_MAX, blocked by NBc = 8 columns.
+//   factor:  for each panel, wave 0 factors the 8 panel columns (wave-synchronous), then all waves
+//            apply the rank-8 update to the trailing lower triangle (two barriers per panel);
+//   inverse: the 8x8 diagonal blocks of X = C^{-1} are inverted in parallel, then block-row i of X is
+//            X_ij = -X_ii sum_{l=j}^{i-1} C_il X_lj (two barriers per block-row).
+// The factor lives in the lower triangle of M (row stride k+1, so column-wise lane accesses fall in
+// distinct banks); X's strictly lower part is stored transposed in the upper triangle, its diagonal
+// in xd.
 static constexpr int CHOL_LDS_MAX = 88;
+static constexpr int NBc = 8;
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
 
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a) {
   extern __shared__ double2 M[];
   __shared__ double red[32];
   __shared__ double sh_thresh;
   const int k = a.k;
+  const int ld = k + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-  const int ld = k + 1;   // odd row stride: column-wise lane accesses hit distinct banks
   double* xd = reinterpret_cast<double*>(M + (size_t)k * ld);
   int* dropped = reinterpret_cast<int*>(xd + k);
+  double2* T = reinterpret_cast<double2*>(dropped + ((k + 3) & ~3));   // k x NBc block-row scratch
   if (a.tstamp && tid == 0) a.tstamp[0] = wall_clock64();
   for (int i = tid; i < k * k; i += blockDim.x) M[(i / k) * ld + (i % k)] = a.G[i];
   for (int i = tid; i < k; i += blockDim.x) dropped[i] = 0;
@@ -191,63 +203,122 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a) {
   const double thresh = sh_thresh;
   constexpr int RGc = 8;
   const int grp = tid / RGc, gl = tid % RGc, ngrp = blockDim.x / RGc;
-  for (int j = 0; j < k; ++j) {
-    const double djj = M[j * ld + j].x;
-    if (!(djj > thresh)) {
-      for (int i = j + tid; i < k; i += blockDim.x) M[i * ld + j] = make_double2(0.0, 0.0);
-      if (tid == 0) dropped[j] = 1;
-      __syncthreads();
-      continue;
-    }
-    const double c = sqrt(djj), ic = 1.0 / c;
-    for (int i = j + 1 + tid; i < k; i += blockDim.x) {
-      double2 g = M[i * ld + j];
-      g.x *= ic;
-      g.y *= ic;
-      M[i * ld + j] = g;
+
+  // ---- blocked factorisation ----
+  for (int p = 0; p < k; p += NBc) {
+    const int pe = min(p + NBc, k);
+    if (wave == 0) {
+      for (int jj = p; jj < pe; ++jj) {
+        const double djj = M[jj * ld + jj].x;
+        if (!(djj > thresh)) {
+          for (int i = jj + lane; i < k; i += 64) M[i * ld + jj] = make_double2(0.0, 0.0);
+          if (lane == 0) dropped[jj] = 1;
+          wave_lds_sync();
+          continue;
+        }
+        const double c = sqrt(djj), ic = 1.0 / c;
+        for (int i = jj + 1 + lane; i < k; i += 64) {
+          double2 g = M[i * ld + jj];
+          g.x *= ic;
+          g.y *= ic;
+          M[i * ld + jj] = g;
+        }
+        if (lane == 0) M[jj * ld + jj] = make_double2(c, 0.0);
+        wave_lds_sync();
+        for (int l = jj + 1; l < pe; ++l) {
+          const double2 clj = M[l * ld + jj];
+          for (int i = l + lane; i < k; i += 64) {
+            const double2 cij = M[i * ld + jj];
+            double2 g = M[i * ld + l];
+            g.x -= cij.x * clj.x + cij.y * clj.y;
+            g.y -= cij.y * clj.x - cij.x * clj.y;
+            M[i * ld + l] = g;
+          }
+        }
+        wave_lds_sync();
+      }
     }
     __syncthreads();
-    if (tid == 0) M[j * ld + j] = make_double2(c, 0.0);
-    for (int i = j + 1 + grp; i < k; i += ngrp) {
-      const double2 cij = M[i * ld + j];
-      for (int l = j + 1 + gl; l <= i; l += RGc) {
-        const double2 clj = M[l * ld + j];
+    // trailing update: M[i][l] -= sum_{jj in panel} C[i][jj] conj(C[l][jj]), pe <= l <= i
+    for (int i = pe + grp; i < k; i += ngrp) {
+      for (int l = pe + gl; l <= i; l += RGc) {
         double2 g = M[i * ld + l];
-        g.x -= cij.x * clj.x + cij.y * clj.y;
-        g.y -= cij.y * clj.x - cij.x * clj.y;
+        for (int jj = p; jj < pe; ++jj) {
+          const double2 cij = M[i * ld + jj];
+          const double2 clj = M[l * ld + jj];
+          g.x -= cij.x * clj.x + cij.y * clj.y;
+          g.y -= cij.y * clj.x - cij.x * clj.y;
+        }
         M[i * ld + l] = g;
       }
     }
     __syncthreads();
   }
   if (a.tstamp && tid == 0) a.tstamp[1] = wall_clock64();
-  // inverse, one lane per column
-  for (int c = tid; c < k; c += blockDim.x) {
-    if (dropped[c]) {
-      xd[c] = 0.0;
-      for (int i = c + 1; i < k; ++i) M[c * ld + i] = make_double2(0.0, 0.0);
-      continue;
-    }
-    const double dc = 1.0 / M[c * ld + c].x;
-    xd[c] = dc;
-    for (int i = c + 1; i < k; ++i) {
-      if (dropped[i]) {
-        M[c * ld + i] = make_double2(0.0, 0.0);
+
+  // ---- blocked inverse ----
+  // X[r][c] (r > c) lives at M[c][r]; X[r][r] in xd.
+  auto xget = [&](int r, int c) -> double2 {
+    return r == c ? make_double2(xd[r], 0.0) : M[c * ld + r];
+  };
+  const int nblk = (k + NBc - 1) / NBc;
+  // diagonal blocks, one lane each (forward substitution inside the block)
+  for (int b = tid; b < nblk; b += blockDim.x) {
+    const int b0 = b * NBc, b1 = min(b0 + NBc, k);
+    for (int c = b0; c < b1; ++c) {
+      if (dropped[c]) {
+        xd[c] = 0.0;
+        for (int r = c + 1; r < b1; ++r) M[c * ld + r] = make_double2(0.0, 0.0);
         continue;
       }
-      const double2 cic = M[i * ld + c];
-      double sr = cic.x * dc, si = cic.y * dc;
-      for (int l = c + 1; l < i; ++l) {
-        const double2 cil = M[i * ld + l];
-        const double2 xl = M[c * ld + l];
-        sr += cil.x * xl.x - cil.y * xl.y;
-        si += cil.x * xl.y + cil.y * xl.x;
+      const double dc = 1.0 / M[c * ld + c].x;
+      xd[c] = dc;
+      for (int r = c + 1; r < b1; ++r) {
+        if (dropped[r]) { M[c * ld + r] = make_double2(0.0, 0.0); continue; }
+        const double2 crc = M[r * ld + c];
+        double sr = crc.x * dc, si = crc.y * dc;
+        for (int l = c + 1; l < r; ++l) {
+          const double2 crl = M[r * ld + l];
+          const double2 xl = M[c * ld + l];
+          sr += crl.x * xl.x - crl.y * xl.y;
+          si += crl.x * xl.y + crl.y * xl.x;
+        }
+        const double inv = -1.0 / M[r * ld + r].x;
+        M[c * ld + r] = make_double2(sr * inv, si * inv);
       }
-      const double inv = -1.0 / M[i * ld + i].x;
-      M[c * ld + i] = make_double2(sr * inv, si * inv);
     }
   }
   __syncthreads();
+  for (int bi = 1; bi < nblk; ++bi) {
+    const int i0 = bi * NBc, i1 = min(i0 + NBc, k), ni = i1 - i0;
+    // T[r][c] = sum_{l = col block start}^{i0-1} C[i0+r][l] X[l][c], for c < i0
+    for (int idx = tid; idx < ni * i0; idx += blockDim.x) {
+      const int r = idx / i0, c = idx % i0;
+      const int lstart = (c / NBc) * NBc;
+      double sr = 0.0, si = 0.0;
+      for (int l = max(lstart, c); l < i0; ++l) {
+        const double2 cl = M[(i0 + r) * ld + l];
+        const double2 x = xget(l, c);
+        sr += cl.x * x.x - cl.y * x.y;
+        si += cl.x * x.y + cl.y * x.x;
+      }
+      T[r * i0 + c] = make_double2(sr, si);
+    }
+    __syncthreads();
+    // X[i0+r][c] = -sum_{q<=r} X[i0+r][i0+q] T[q][c]
+    for (int idx = tid; idx < ni * i0; idx += blockDim.x) {
+      const int r = idx / i0, c = idx % i0;
+      double sr = 0.0, si = 0.0;
+      for (int q = 0; q <= r; ++q) {
+        const double2 x = xget(i0 + r, i0 + q);
+        const double2 t = T[q * i0 + c];
+        sr += x.x * t.x - x.y * t.y;
+        si += x.x * t.y + x.y * t.x;
+      }
+      M[c * ld + i0 + r] = make_double2(-sr, -si);
+    }
+    __syncthreads();
+  }
   if (a.tstamp && tid == 0) a.tstamp[2] = wall_clock64();
   for (int idx = tid; idx < k * k; idx += blockDim.x) {
     const int i = idx / k, c = idx % k;
@@ -268,7 +339,8 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a) {
 hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st) {
   if (a.k <= 0) return hipSuccess;
   if (a.k <= CHOL_LDS_MAX) {
-    const size_t lds = (size_t)a.k * (a.k + 1) * sizeof(double2) + (size_t)a.k * (sizeof(double) + sizeof(int));
+    const size_t lds = (size_t)a.k * (a.k + 1) * sizeof(double2) + (size_t)a.k * sizeof(double) +
+                       (size_t)((a.k + 3) & ~3) * sizeof(int) + (size_t)a.k * NBc * sizeof(double2);
     (void)hipFuncSetAttribute((const void*)k_chol_inv_lds,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_chol_inv_lds, dim3(1), dim3(CHOL_THREADS), lds, st, a);

@@ -5,18 +5,19 @@
 // FP64 Gram matrix G of that matrix: its top-k eigenvectors span the same subspace and its
 // eigenvalues are the squared singular values.
 //
-// One workgroup (16 waves) solves one G:
-//   1. Householder reduction to a real symmetric tridiagonal T = Q^H G Q (reflectors
-//      H_j = I - tau_j v_j v_j^H, real sub-diagonal). For s <= EIG_LDS_MAX the packed lower triangle
-//      lives in LDS; larger matrices are reduced in place in global memory (L2 resident). The
-//      Hermitian matrix-vector product is done by groups of 8 lanes per row and the dot product w^H v
-//      is folded into it, so a step costs three workgroup barriers.
-//   2. the top-kmax eigenvalues of T by multisection on Sturm counts: a group of lanes evaluates the
-//      inertia at several points of the current interval at once;
-//   3. eigenvectors of T: a twisted factorisation T - lambda I = N_r Delta N_r^T per eigenvalue (one
-//      lane each, no memory-carried dependency chains); eigenvalues closer than 1e-3 ||T|| to a
-//      neighbour are handled together by inverse iteration with modified Gram-Schmidt;
-//   4. back-transformation U = Q Y, one group of lanes per eigenvector with the column in registers.
+// Three launches solve one G:
+//   1. k_tridiag, one workgroup (16 waves): Householder reduction to a real symmetric tridiagonal
+//      T = Q^H G Q (reflectors H_j = I - tau_j v_j v_j^H, real sub-diagonal). For s <= EIG_LDS_MAX the
+//      packed lower triangle lives in LDS; larger matrices are reduced in place in global memory (L2
+//      resident). The Hermitian matrix-vector product is done by groups of 8 lanes per row, its
+//      reductions use DPP lane moves, and the dot product w^H v is folded into it, so a step costs
+//      three workgroup barriers. This is the only sequential part.
+//   2. k_eigvals, one wave per eigenvalue over many workgroups: the top-kmax eigenvalues of T by
+//      multisection on Sturm counts (64 points of the current interval per round).
+//   3. k_eigvecs, one wave per eigenpair over many workgroups: the eigenvector of T by a twisted
+//      factorisation T - lambda I = N_r Delta N_r^T (eigenvalues closer than 1e-3 ||T|| to a neighbour
+//      are handled together, by the wave of the first one, with inverse iteration and modified
+//      Gram-Schmidt), then the back-transformation u = Q y with the reflectors streamed from L2.
 #include <float.h>
 
 #include "cbc_internal.h"
@@ -27,14 +28,38 @@ static constexpr int EIG_THREADS = 1024;
 static constexpr int EIG_LDS_MAX = 128;   // largest s whose packed triangle stays in LDS
 static constexpr int RG = 8;              // lanes per row group in the matrix-vector product
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// ---- cross-lane reductions ---------------------------------------------------------------------
+// DPP lane moves (quad permutes and row mirrors) are single-cycle VALU operations; ds_bpermute
+// (__shfl_xor) goes through the LDS crossbar. A double is moved as two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int l2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  const int h2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(h2, l2);
+}
+// sum over aligned groups of 8 lanes, result in every lane of the group
+__device__ __forceinline__ double sum8(double v) {
+  v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);   // row_half_mirror
   return v;
 }
-__device__ __forceinline__ double group_sum(double v, int g) {
-  for (int o = g >> 1; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// sum over aligned rows of 16 lanes, result in every lane of the row
+__device__ __forceinline__ double sum16(double v) {
+  v = sum8(v);
+  v += dpp<0x140>(v);   // row_mirror
   return v;
+}
+// sum over the wave, result in every lane
+__device__ __forceinline__ double wave_sum(double v) {
+  v = sum16(v);
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  double t = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    t += __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r), __builtin_amdgcn_readlane(lo, 16 * r));
+  return t;
 }
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
@@ -64,8 +89,9 @@ struct EigWork {
   double* d;      // s
   double* e;      // s
   double2* tau;   // s
-  double2* V;     // s * s   (global path) reflector j at V[j*s + i], i > j, V[j*s+j+1] = 1
-  double* Y;      // kmax * s   eigenvector t of T at Y[t*s + i]
+  double* bounds; // 8: lo, hi, tnorm, pivmin
+  double2* V;     // s * s   reflector j at V[j*s + i], i > j, V[j*s+j+1] = 1
+  double* Y;      // kmax * s   cluster eigenvectors of T at Y[t*s + i]
   double* lu;     // kmax * 5 * s
 };
 __host__ __device__ inline EigWork eig_layout(double* w, int s, int kmax) {
@@ -73,13 +99,14 @@ __host__ __device__ inline EigWork eig_layout(double* w, int s, int kmax) {
   L.d = w;
   L.e = w + s;
   L.tau = reinterpret_cast<double2*>(w + 2 * (size_t)s);
-  L.V = reinterpret_cast<double2*>(w + 4 * (size_t)s);
-  L.Y = w + 4 * (size_t)s + 2 * (size_t)s * s;
+  L.bounds = w + 4 * (size_t)s;
+  L.V = reinterpret_cast<double2*>(w + 4 * (size_t)s + 8);
+  L.Y = w + 4 * (size_t)s + 8 + 2 * (size_t)s * s;
   L.lu = L.Y + (size_t)kmax * s;
   return L;
 }
 size_t eig_work_doubles(int s, int kmax) {
-  return 4 * (size_t)s + 2 * (size_t)s * s + (size_t)kmax * s + 5 * (size_t)kmax * s + 64;
+  return 4 * (size_t)s + 8 + 2 * (size_t)s * s + (size_t)kmax * s + 5 * (size_t)kmax * s + 64;
 }
 
 __device__ int sturm_count(const double* dd, const double* ee2, int s, double x, double pivmin) {
@@ -94,16 +121,14 @@ __device__ int sturm_count(const double* dd, const double* ee2, int s, double x,
   return c;
 }
 
-struct Shared {
-  double2 tau, a2;
-  double lo, hi, pivmin, tnorm;
+struct TriShared {
+  double2 tau;
   double dotr, doti;
-  int keep;
 };
 
-// Householder vector of column j from x = A[j+1.., j]; called by wave 0 only.
-// Writes tau, beta into sh/W and returns the scaling 1/(alpha - beta) applied to x[1..].
-__device__ inline double2 householder(double2 alpha, double xn2, int j, double a_jj, Shared& sh,
+// Householder vector of column j from x = A[j+1.., j]; wave 0. Returns the scaling 1/(alpha - beta)
+// that maps x[1..] to the reflector.
+__device__ inline double2 householder(double2 alpha, double xn2, int j, double a_jj, TriShared& sh,
                                       EigWork& W, int lane) {
   double2 t = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
   double beta = alpha.x;
@@ -126,188 +151,143 @@ __device__ inline double2 householder(double2 alpha, double xn2, int j, double a
   return scal;
 }
 
-// ---- reduction with the packed lower triangle in LDS -------------------------------------------
-__device__ void tridiag_lds(double2* P, double2* vv, double2* ww, const double2* G, int s, Shared& sh,
-                            EigWork& W) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nthr = blockDim.x;
-  for (int idx = tid; idx < tri(s); idx += nthr) {
-    // row r of the packed triangle from G (row-major, both triangles valid)
-    int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-    while (tri(r + 1) <= idx) ++r;
-    while (tri(r) > idx) --r;
-    const int c = idx - tri(r);
-    P[idx] = G[(size_t)r * s + c];
+// Hermitian matrix-vector product row p_r = tau sum_c A[r][c] v[c] for one row group, plus the
+// row's contribution to w^H v.
+template <typename AFn>
+__device__ __forceinline__ void matvec_row(int r, int nj, int gl, const double2* vv, double2 t,
+                                           AFn aget, double2* ww, double& dr_acc, double& di_acc) {
+  double pr = 0.0, pi = 0.0;
+  for (int c = gl; c < nj; c += RG) {
+    const double2 a = aget(r, c);
+    const double2 v = vv[c];
+    pr += a.x * v.x - a.y * v.y;
+    pi += a.x * v.y + a.y * v.x;
   }
-  __syncthreads();
-  const int grp = tid / RG, gl = tid % RG, ngrp = nthr / RG;
-  for (int j = 0; j < s - 1; ++j) {
-    const int nj = s - j - 1;
-    if (wave == 0) {
-      const double2 alpha = P[tri(j + 1) + j];
-      double xn2 = 0.0;
-      for (int i = j + 2 + lane; i < s; i += 64) {
-        const double2 x = P[tri(i) + j];
-        xn2 += x.x * x.x + x.y * x.y;
-      }
-      xn2 = wave_sum(xn2);
-      const double2 scal = householder(alpha, xn2, j, P[tri(j) + j].x, sh, W, lane);
-      if (lane == 0) vv[0] = make_double2(1.0, 0.0);
-      for (int i = 1 + lane; i < nj; i += 64) {
-        const double2 v = cmul(P[tri(j + 1 + i) + j], scal);
-        vv[i] = v;
-        P[tri(j + 1 + i) + j] = v;   // reflector kept below the sub-diagonal for the back-transform
-      }
-    }
-    __syncthreads();
-    const double2 t = sh.tau;
-    if (t.x == 0.0 && t.y == 0.0) continue;
-    // p = tau A_sub v by row groups; w = p; partial w^H v accumulated in LDS
-    double dacc_r = 0.0, dacc_i = 0.0;
-    for (int r = grp; r < nj; r += ngrp) {
-      const int R = j + 1 + r;
-      double pr = 0.0, pi = 0.0;
-      for (int c = gl; c < nj; c += RG) {
-        const int C = j + 1 + c;
-        const double2 a = (c <= r) ? P[tri(R) + C] : cconj(P[tri(C) + R]);
-        const double2 v = vv[c];
-        pr += a.x * v.x - a.y * v.y;
-        pi += a.x * v.y + a.y * v.x;
-      }
-      pr = group_sum(pr, RG);
-      pi = group_sum(pi, RG);
-      if (gl == 0) {
-        const double2 w = cmul(t, make_double2(pr, pi));
-        ww[r] = w;
-        const double2 v = vv[r];
-        dacc_r += w.x * v.x + w.y * v.y;
-        dacc_i += w.x * v.y - w.y * v.x;
-      }
-    }
-    // w^H v: reduce the row-group leaders' partials across the wave, one LDS atomic per wave
-    dacc_r = wave_sum(dacc_r);
-    dacc_i = wave_sum(dacc_i);
-    if (lane == 0) {
-      atomicAdd(&sh.dotr, dacc_r);
-      atomicAdd(&sh.doti, dacc_i);
-    }
-    __syncthreads();
-    const double2 q = cmul(t, make_double2(sh.dotr, sh.doti));
-    const double2 a2 = make_double2(-0.5 * q.x, -0.5 * q.y);
-    // lower-triangle update A_sub -= v w'^H + w' v^H, w' = w + a2 v
-    for (int r = grp; r < nj; r += ngrp) {
-      const int R = j + 1 + r;
-      const double2 vr = vv[r];
-      const double2 wr = make_double2(ww[r].x + a2.x * vr.x - a2.y * vr.y,
-                                      ww[r].y + a2.x * vr.y + a2.y * vr.x);
-      for (int c = gl; c <= r; c += RG) {
-        const double2 vc = vv[c];
-        const double2 wc = make_double2(ww[c].x + a2.x * vc.x - a2.y * vc.y,
-                                        ww[c].y + a2.x * vc.y + a2.y * vc.x);
-        double2 x = P[tri(R) + j + 1 + c];
-        x.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
-        x.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
-        P[tri(R) + j + 1 + c] = x;
-      }
-    }
-    __syncthreads();
+  pr = sum8(pr);
+  pi = sum8(pi);
+  if (gl == 0) {
+    const double2 w = cmul(t, make_double2(pr, pi));
+    ww[r] = w;
+    const double2 v = vv[r];
+    dr_acc += w.x * v.x + w.y * v.y;
+    di_acc += w.x * v.y - w.y * v.x;
   }
-  if (tid == 0) W.d[s - 1] = P[tri(s - 1) + s - 1].x;
-  __syncthreads();
 }
 
-// ---- reduction in global memory (both triangles kept) -------------------------------------------
-__device__ void tridiag_global(double2* A, double2* vv, double2* ww, int s, Shared& sh, EigWork& W) {
+template <bool IN_LDS>
+__global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a) {
+  extern __shared__ double smem[];
+  __shared__ TriShared sh;
+  const int s = a.s;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nthr = blockDim.x;
+  double2* P = reinterpret_cast<double2*>(smem);
+  double2* vv = IN_LDS ? P + tri(s) : P;
+  double2* ww = vv + s;
+  double2* A = a.G;
+  EigWork W = eig_layout(a.work, s, a.kmax);
+  if (a.tstamp && tid == 0) a.tstamp[0] = wall_clock64();
+  if (IN_LDS) {
+    for (int idx = tid; idx < tri(s); idx += nthr) {
+      int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+      while (tri(r + 1) <= idx) ++r;
+      while (tri(r) > idx) --r;
+      const int c = idx - tri(r);
+      P[idx] = A[(size_t)r * s + c];
+    }
+  }
+  __syncthreads();
   const int grp = tid / RG, gl = tid % RG, ngrp = nthr / RG;
+  long long tA = 0, tB = 0, tD = 0, t0 = 0;
+  const bool stamp = a.tstamp && tid == 0;
   for (int j = 0; j < s - 1; ++j) {
     const int nj = s - j - 1;
+    if (stamp) t0 = wall_clock64();
     if (wave == 0) {
-      const double2 alpha = A[(size_t)(j + 1) * s + j];
+      const double2 alpha = IN_LDS ? P[tri(j + 1) + j] : A[(size_t)(j + 1) * s + j];
       double xn2 = 0.0;
       for (int i = j + 2 + lane; i < s; i += 64) {
-        const double2 x = A[(size_t)i * s + j];
+        const double2 x = IN_LDS ? P[tri(i) + j] : A[(size_t)i * s + j];
         xn2 += x.x * x.x + x.y * x.y;
       }
       xn2 = wave_sum(xn2);
-      const double2 scal = householder(alpha, xn2, j, A[(size_t)j * s + j].x, sh, W, lane);
+      const double ajj = IN_LDS ? P[tri(j) + j].x : A[(size_t)j * s + j].x;
+      const double2 scal = householder(alpha, xn2, j, ajj, sh, W, lane);
       if (lane == 0) {
         vv[0] = make_double2(1.0, 0.0);
         W.V[(size_t)j * s + j + 1] = make_double2(1.0, 0.0);
       }
       for (int i = 1 + lane; i < nj; i += 64) {
-        const double2 v = cmul(A[(size_t)(j + 1 + i) * s + j], scal);
+        const double2 x = IN_LDS ? P[tri(j + 1 + i) + j] : A[(size_t)(j + 1 + i) * s + j];
+        const double2 v = cmul(x, scal);
         vv[i] = v;
         W.V[(size_t)j * s + j + 1 + i] = v;
       }
     }
     __syncthreads();
+    if (stamp) { const long long t1 = wall_clock64(); tA += t1 - t0; t0 = t1; }
     const double2 t = sh.tau;
     if (t.x == 0.0 && t.y == 0.0) continue;
-    double dacc_r = 0.0, dacc_i = 0.0;
+    double dr_acc = 0.0, di_acc = 0.0;
     for (int r = grp; r < nj; r += ngrp) {
-      const double2* row = A + (size_t)(j + 1 + r) * s + (j + 1);
-      double pr = 0.0, pi = 0.0;
-      for (int c = gl; c < nj; c += RG) {
-        const double2 a = row[c];
-        const double2 v = vv[c];
-        pr += a.x * v.x - a.y * v.y;
-        pi += a.x * v.y + a.y * v.x;
-      }
-      pr = group_sum(pr, RG);
-      pi = group_sum(pi, RG);
-      if (gl == 0) {
-        const double2 w = cmul(t, make_double2(pr, pi));
-        ww[r] = w;
-        const double2 v = vv[r];
-        dacc_r += w.x * v.x + w.y * v.y;
-        dacc_i += w.x * v.y - w.y * v.x;
+      const int R = j + 1 + r;
+      if (IN_LDS) {
+        matvec_row(r, nj, gl, vv, t, [&](int rr, int c) {
+          const int C = j + 1 + c;
+          return (c <= rr) ? P[tri(R) + C] : cconj(P[tri(C) + R]);
+        }, ww, dr_acc, di_acc);
+      } else {
+        const double2* row = A + (size_t)R * s + (j + 1);
+        matvec_row(r, nj, gl, vv, t, [&](int, int c) { return row[c]; }, ww, dr_acc, di_acc);
       }
     }
-    // w^H v: reduce the row-group leaders' partials across the wave, one LDS atomic per wave
-    dacc_r = wave_sum(dacc_r);
-    dacc_i = wave_sum(dacc_i);
+    dr_acc = wave_sum(dr_acc);
+    di_acc = wave_sum(di_acc);
     if (lane == 0) {
-      atomicAdd(&sh.dotr, dacc_r);
-      atomicAdd(&sh.doti, dacc_i);
+      atomicAdd(&sh.dotr, dr_acc);
+      atomicAdd(&sh.doti, di_acc);
     }
     __syncthreads();
+    if (stamp) { const long long t1 = wall_clock64(); tB += t1 - t0; t0 = t1; }
     const double2 q = cmul(t, make_double2(sh.dotr, sh.doti));
     const double2 a2 = make_double2(-0.5 * q.x, -0.5 * q.y);
-    for (int r = wave; r < nj; r += nthr / 64) {
+    // A_sub -= v w'^H + w' v^H with w' = w + a2 v (lower triangle in LDS, full rows in global)
+    for (int r = grp; r < nj; r += ngrp) {
+      const int R = j + 1 + r;
       const double2 vr = vv[r];
       const double2 wr = make_double2(ww[r].x + a2.x * vr.x - a2.y * vr.y,
                                       ww[r].y + a2.x * vr.y + a2.y * vr.x);
-      double2* row = A + (size_t)(j + 1 + r) * s + (j + 1);
-      for (int c = lane; c < nj; c += 64) {
+      const int cend = IN_LDS ? r : nj - 1;
+      double2* rowp = IN_LDS ? P + tri(R) + (j + 1) : A + (size_t)R * s + (j + 1);
+      for (int c = gl; c <= cend; c += RG) {
         const double2 vc = vv[c];
         const double2 wc = make_double2(ww[c].x + a2.x * vc.x - a2.y * vc.y,
                                         ww[c].y + a2.x * vc.y + a2.y * vc.x);
-        double2 x = row[c];
+        double2 x = rowp[c];
         x.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
         x.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
-        row[c] = x;
+        rowp[c] = x;
       }
     }
     __syncthreads();
+    if (stamp) tD += wall_clock64() - t0;
   }
-  if (tid == 0) W.d[s - 1] = A[(size_t)(s - 1) * s + (s - 1)].x;
+  if (stamp) {
+    a.tstamp[4] = tA;
+    a.tstamp[5] = tB;
+    a.tstamp[6] = tD;
+  }
+  // last diagonal entry and the Gershgorin interval of T (used by the two later kernels)
+  if (tid == 0) W.d[s - 1] = IN_LDS ? P[tri(s - 1) + s - 1].x : A[(size_t)(s - 1) * s + (s - 1)].x;
   __syncthreads();
-}
-
-// ---- eigenvalues: multisection --------------------------------------------------------------------
-__device__ void eigenvalues(const double* dd, const double* ee2, const double* e, int s, int kmax,
-                            double* lam, Shared& sh) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if (wave == 0) {
     double lo = DBL_MAX, hi = -DBL_MAX, emax = 0.0;
     for (int i = lane; i < s; i += 64) {
-      const double el = i > 0 ? fabs(e[i - 1]) : 0.0;
-      const double er = i < s - 1 ? fabs(e[i]) : 0.0;
-      lo = fmin(lo, dd[i] - el - er);
-      hi = fmax(hi, dd[i] + el + er);
-      emax = fmax(emax, ee2[i]);
+      const double el = i > 0 ? fabs(W.e[i - 1]) : 0.0;
+      const double er = i < s - 1 ? fabs(W.e[i]) : 0.0;
+      lo = fmin(lo, W.d[i] - el - er);
+      hi = fmax(hi, W.d[i] + el + er);
+      emax = fmax(emax, er * er);
     }
     lo = wave_min(lo);
     hi = wave_max(hi);
@@ -315,49 +295,52 @@ __device__ void eigenvalues(const double* dd, const double* ee2, const double* e
     if (lane == 0) {
       const double tn = fmax(fabs(lo), fabs(hi));
       const double pad = 2.0 * DBL_EPSILON * tn * s + DBL_MIN;
-      sh.lo = lo - pad;
-      sh.hi = hi + pad;
-      sh.tnorm = tn;
-      sh.pivmin = DBL_MIN * fmax(1.0, emax);
+      W.bounds[0] = lo - pad;
+      W.bounds[1] = hi + pad;
+      W.bounds[2] = tn;
+      W.bounds[3] = DBL_MIN * fmax(1.0, emax);
+      if (a.tstamp) a.tstamp[1] = wall_clock64();
     }
   }
-  __syncthreads();
-  int G = 64;
-  while (G > 1 && (EIG_THREADS / G) < kmax) G >>= 1;
-  const int ngroups = EIG_THREADS / G;
-  const int grp = tid / G;
-  const int gl = tid % G;
-  const int goff = (lane / G) * G;
-  const unsigned long long gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-  const double pivmin = sh.pivmin;
-  const double target = 2.0 * DBL_EPSILON * sh.tnorm + 4.0 * pivmin;
-  int rounds = 1;
-  {
-    double w = sh.hi - sh.lo;
-    while (w > target && rounds < 200) { w /= (G + 1); ++rounds; }
-  }
-  for (int t0 = 0; t0 < kmax; t0 += ngroups) {
-    const int t = t0 + grp;
-    const bool act = t < kmax;
-    const int jidx = s - 1 - (act ? t : 0);
-    double lo = sh.lo, hi = sh.hi;
-    for (int rd = 0; rd < rounds; ++rd) {
-      const double x = lo + (hi - lo) * double(gl + 1) / double(G + 1);
-      const int c = sturm_count(dd, ee2, s, x, pivmin);
-      const unsigned long long m = __ballot(c <= jidx);
-      const int b = __popcll((m >> goff) & gmask);
-      const double xlo = lo + (hi - lo) * double(b) / double(G + 1);
-      const double xhi = lo + (hi - lo) * double(b + 1) / double(G + 1);
-      lo = xlo;
-      hi = xhi;
-    }
-    if (act && gl == 0) lam[t] = 0.5 * (lo + hi);
-  }
-  __syncthreads();
 }
 
-// ---- eigenvectors of T ----------------------------------------------------------------------------
-// Twisted factorisation for an isolated eigenvalue x: y gets the unit eigenvector.
+// ---- eigenvalues: one wave per eigenvalue -------------------------------------------------------
+static constexpr int EV_WAVES = 4;
+
+__global__ __launch_bounds__(64 * EV_WAVES) void k_eigvals(EigArgs a) {
+  extern __shared__ double smem[];
+  const int s = a.s, kmax = a.kmax;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* dd = smem;
+  double* ee2 = dd + s;
+  EigWork W = eig_layout(a.work, s, kmax);
+  for (int i = tid; i < s; i += blockDim.x) {
+    dd[i] = W.d[i];
+    ee2[i] = i < s - 1 ? W.e[i] * W.e[i] : 0.0;
+  }
+  __syncthreads();
+  const int t = blockIdx.x * EV_WAVES + wave;
+  if (t >= kmax) return;
+  const double pivmin = W.bounds[3];
+  const double target = 2.0 * DBL_EPSILON * W.bounds[2] + 4.0 * pivmin;
+  const int jidx = s - 1 - t;   // ascending index of the t-th largest eigenvalue
+  double lo = W.bounds[0], hi = W.bounds[1];
+  for (int rd = 0; rd < 40 && hi - lo > target; ++rd) {
+    const double x = lo + (hi - lo) * double(lane + 1) / 65.0;
+    const int c = sturm_count(dd, ee2, s, x, pivmin);
+    const int b = __popcll(__ballot(c <= jidx));
+    const double xlo = lo + (hi - lo) * double(b) / 65.0;
+    const double xhi = lo + (hi - lo) * double(b + 1) / 65.0;
+    lo = xlo;
+    hi = xhi;
+  }
+  if (lane == 0) a.lam[t] = 0.5 * (lo + hi);
+  if (a.tstamp && lane == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 2), (unsigned long long)wall_clock64());
+}
+
+// ---- eigenvectors of T and back-transformation: one wave per eigenpair ---------------------------
+// Twisted factorisation for an isolated eigenvalue x; y gets the unit eigenvector. Single lane.
 __device__ void twisted_vector(const double* dd, const double* e, int s, double x, double pivmin,
                                double* y, double* lp, double* dp, double* um) {
   double d = dd[0] - x;
@@ -369,7 +352,6 @@ __device__ void twisted_vector(const double* dd, const double* e, int s, double 
     d = dd[i + 1] - x - l * e[i];
     dp[i + 1] = d;
   }
-  // backward factorisation and twist index r = argmin |gamma_r|
   double dm = dd[s - 1] - x;
   int r = s - 1;
   double gbest = fabs(dp[s - 1]);
@@ -399,6 +381,7 @@ __device__ void twisted_vector(const double* dd, const double* e, int s, double 
 }
 
 // Inverse iteration for the members [cs, ce) of a cluster, re-orthogonalised within the cluster.
+// Single lane; vectors to Y[u*s ..].
 __device__ void cluster_vectors(const double* dd, const double* e, int s, const double* lam, int cs,
                                 int ce, double tnorm, double* Y, double* scratch) {
   const double eps3 = 10.0 * DBL_EPSILON * fmax(tnorm, DBL_MIN);
@@ -474,197 +457,207 @@ __device__ void cluster_vectors(const double* dd, const double* e, int s, const 
   }
 }
 
-__device__ void eigenvectors(const double* dd, const double* e, int s, int kmax, const double* lam,
-                             int* cnext, Shared& sh, EigWork& W) {
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    // clusters of non-negligible eigenvalues closer than 1e-3 ||T|| (negligible ones, at the
-    // rounding level of ||T||, are computed one by one: they carry no weight)
-    const double ortol = 1e-3 * sh.tnorm;
-    const double tiny = 64.0 * DBL_EPSILON * sh.tnorm;
-    int start = 0;
-    for (int t = 1; t <= kmax; ++t) {
-      const bool split = t == kmax || lam[t - 1] - lam[t] > ortol || lam[t] <= tiny;
-      if (split) {
-        for (int u = start; u < t; ++u) cnext[u] = (u == start) ? t : -1;
-        start = t;
-      }
+// u = Q y for one column (wave-cooperative), y real in `yin`, result to U[:, t] (or zero).
+__device__ void back_transform_col(const EigArgs& a, const EigWork& W, int s, int kmax, int t,
+                                   bool kept, const double* yin, double2* u) {
+  const int lane = threadIdx.x & 63;
+  for (int i = lane; i < s; i += 64) u[i] = make_double2(yin[i], 0.0);
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  for (int j = s - 2; j >= 0; --j) {
+    const double2 tj = W.tau[j];
+    if (tj.x == 0.0 && tj.y == 0.0) continue;
+    const double2* vj = W.V + (size_t)j * s;
+    double dr = 0.0, di = 0.0;
+    for (int i = j + 1 + lane; i < s; i += 64) {
+      const double2 v = vj[i];
+      const double2 x = u[i];
+      dr += v.x * x.x + v.y * x.y;
+      di += v.x * x.y - v.y * x.x;
+    }
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const double2 f = cmul(tj, make_double2(dr, di));
+    for (int i = j + 1 + lane; i < s; i += 64) {
+      const double2 v = vj[i];
+      double2 x = u[i];
+      x.x -= v.x * f.x - v.y * f.y;
+      x.y -= v.x * f.y + v.y * f.x;
+      u[i] = x;
     }
   }
-  __syncthreads();
-  for (int cs = tid; cs < kmax; cs += blockDim.x) {
-    const int ce = cnext[cs];
-    if (ce < 0) continue;
-    double* scratch = W.lu + (size_t)cs * 5 * s;
-    if (ce == cs + 1) {
-      twisted_vector(dd, e, s, lam[cs], sh.pivmin, W.Y + (size_t)cs * s, scratch, scratch + s,
-                     scratch + 2 * s);
-    } else {
-      cluster_vectors(dd, e, s, lam, cs, ce, sh.tnorm, W.Y, scratch);
-    }
-  }
-  __syncthreads();
+  for (int i = lane; i < s; i += 64)
+    a.U[(size_t)i * kmax + t] = kept ? u[i] : make_double2(0.0, 0.0);
 }
 
-// ---- rank selection and back-transformation -------------------------------------------------------
-__device__ void select_rank(const EigArgs& a, const double* lam, int kmax, Shared& sh) {
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    int keep = kmax;
-    if (a.tol > 0.0) {
-      const double cut = a.tol * a.tol * lam[0];
-      keep = 0;
-      for (int t = 0; t < kmax; ++t) keep += lam[t] > cut;
-    }
-    if (keep < 1) keep = 1;
-    sh.keep = keep;
-    a.kkeep[0] = keep;
-    a.inv_sqrt_l0[0] = lam[0] > 0.0 ? 1.0 / sqrt(lam[0]) : 1.0;
+// Register-resident variant for s <= 64 R: lane l holds rows l + 64 q; the next reflector and its tau
+// are loaded while the current one is reduced.
+template <int R>
+__device__ void back_transform_reg(const EigArgs& a, const EigWork& W, int s, int kmax, int t,
+                                   bool kept, const double* yin) {
+  const int lane = threadIdx.x & 63;
+  double2 ur[R], vn[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = lane + 64 * q;
+    ur[q] = make_double2(i < s ? yin[i] : 0.0, 0.0);
   }
-  for (int t = tid; t < kmax; t += blockDim.x) a.lam[t] = lam[t];
-  __syncthreads();
-}
-
-// VFn(j, i) returns component i (> j) of reflector j.
-template <typename VFn>
-__device__ void back_transform(const EigArgs& a, int s, int kmax, int keep, EigWork& W,
-                               const double2* taus, VFn vget) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-  constexpr int RR = 8;   // rows of the column held by each lane
-  int G2 = 1;
-  while (G2 < 64 && G2 * RR < s) G2 <<= 1;
-  const int cols_per_wave = 64 / G2;
-  const int gl = lane % G2;
-  const int wcol = lane / G2;
-  if (G2 * RR >= s) {
-    for (int t = wave * cols_per_wave + wcol; t < kmax; t += nwave * cols_per_wave) {
-      double ur[RR], ui[RR];
-      const double* y = W.Y + (size_t)t * s;
+  int j = s - 2;
+  double2 taun = j >= 0 ? W.tau[j] : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int r = 0; r < RR; ++r) {
-        const int i = gl + r * G2;
-        ur[r] = (i < s) ? y[i] : 0.0;
-        ui[r] = 0.0;
-      }
-      for (int j = s - 2; j >= 0; --j) {
-        const double2 tj = taus[j];
-        if (tj.x == 0.0 && tj.y == 0.0) continue;
-        double dr = 0.0, di = 0.0;
+  for (int q = 0; q < R; ++q) {
+    const int i = lane + 64 * q;
+    vn[q] = (j >= 0 && i > j && i < s) ? W.V[(size_t)j * s + i] : make_double2(0.0, 0.0);
+  }
+  for (; j >= 0; --j) {
+    double2 vc[R];
 #pragma unroll
-        for (int r = 0; r < RR; ++r) {
-          const int i = gl + r * G2;
-          if (i > j && i < s) {
-            const double2 v = vget(j, i);
-            dr += v.x * ur[r] + v.y * ui[r];
-            di += v.x * ui[r] - v.y * ur[r];
-          }
-        }
-        dr = group_sum(dr, G2);
-        di = group_sum(di, G2);
-        const double2 f = cmul(tj, make_double2(dr, di));
+    for (int q = 0; q < R; ++q) vc[q] = vn[q];
+    const double2 tc = taun;
+    if (j > 0) {
+      taun = W.tau[j - 1];
 #pragma unroll
-        for (int r = 0; r < RR; ++r) {
-          const int i = gl + r * G2;
-          if (i > j && i < s) {
-            const double2 v = vget(j, i);
-            ur[r] -= v.x * f.x - v.y * f.y;
-            ui[r] -= v.x * f.y + v.y * f.x;
-          }
-        }
-      }
-      const bool kept = t < keep;
-#pragma unroll
-      for (int r = 0; r < RR; ++r) {
-        const int i = gl + r * G2;
-        if (i < s) a.U[(size_t)i * kmax + t] = kept ? make_double2(ur[r], ui[r]) : make_double2(0.0, 0.0);
+      for (int q = 0; q < R; ++q) {
+        const int i = lane + 64 * q;
+        vn[q] = (i > j - 1 && i < s) ? W.V[(size_t)(j - 1) * s + i] : make_double2(0.0, 0.0);
       }
     }
-  } else {
-    for (int t = wave; t < kmax; t += nwave) {
-      const double* y = W.Y + (size_t)t * s;
-      for (int i = lane; i < s; i += 64) a.U[(size_t)i * kmax + t] = make_double2(y[i], 0.0);
-      for (int j = s - 2; j >= 0; --j) {
-        const double2 tj = taus[j];
-        if (tj.x == 0.0 && tj.y == 0.0) continue;
-        double dr = 0.0, di = 0.0;
-        for (int i = j + 1 + lane; i < s; i += 64) {
-          const double2 v = vget(j, i);
-          const double2 u = a.U[(size_t)i * kmax + t];
-          dr += v.x * u.x + v.y * u.y;
-          di += v.x * u.y - v.y * u.x;
-        }
-        dr = wave_sum(dr);
-        di = wave_sum(di);
-        const double2 f = cmul(tj, make_double2(dr, di));
-        for (int i = j + 1 + lane; i < s; i += 64) {
-          const double2 v = vget(j, i);
-          double2 u = a.U[(size_t)i * kmax + t];
-          u.x -= v.x * f.x - v.y * f.y;
-          u.y -= v.x * f.y + v.y * f.x;
-          a.U[(size_t)i * kmax + t] = u;
-        }
-      }
-      if (t >= keep)
-        for (int i = lane; i < s; i += 64) a.U[(size_t)i * kmax + t] = make_double2(0.0, 0.0);
+    if (tc.x == 0.0 && tc.y == 0.0) continue;
+    double dr = 0.0, di = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      dr += vc[q].x * ur[q].x + vc[q].y * ur[q].y;
+      di += vc[q].x * ur[q].y - vc[q].y * ur[q].x;
     }
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const double2 f = cmul(tc, make_double2(dr, di));
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      ur[q].x -= vc[q].x * f.x - vc[q].y * f.y;
+      ur[q].y -= vc[q].x * f.y + vc[q].y * f.x;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int i = lane + 64 * q;
+    if (i < s) a.U[(size_t)i * kmax + t] = kept ? ur[q] : make_double2(0.0, 0.0);
   }
 }
 
-// LDS layout: [packed triangle (lds path only)] vv ww (s complex each) dd ee2 e (s doubles each)
-// lam (kmax doubles) tau (s complex) cnext (kmax ints)
-template <bool IN_LDS>
-__global__ __launch_bounds__(EIG_THREADS) void k_eig(EigArgs a) {
+__device__ void back_transform_any(const EigArgs& a, const EigWork& W, int s, int kmax, int t,
+                                   bool kept, const double* yin, double2* u) {
+  if (s <= 64) back_transform_reg<1>(a, W, s, kmax, t, kept, yin);
+  else if (s <= 128) back_transform_reg<2>(a, W, s, kmax, t, kept, yin);
+  else if (s <= 256) back_transform_reg<4>(a, W, s, kmax, t, kept, yin);
+  else back_transform_col(a, W, s, kmax, t, kept, yin, u);
+}
+
+__global__ __launch_bounds__(256) void k_eigvecs(EigArgs a) {
   extern __shared__ double smem[];
-  __shared__ Shared sh;
-  const int s = a.s, kmax = a.kmax, tid = threadIdx.x;
-  double2* P = reinterpret_cast<double2*>(smem);
-  double2* vv = IN_LDS ? P + tri(s) : P;
-  double2* ww = vv + s;
-  double* dd = reinterpret_cast<double*>(ww + s);
-  double* ee2 = dd + s;
-  double* el = ee2 + s;
-  double* lam = el + s;
-  double2* taus = reinterpret_cast<double2*>(lam + kmax);
-  int* cnext = reinterpret_cast<int*>(taus + s);
+  const int s = a.s, kmax = a.kmax;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = blockDim.x >> 6;
+  double* dd = smem;
+  double* el = dd + s;
+  double* region = el + s + 4 * (size_t)s * wave;   // per wave: lp | dp (y later) | um | y
   EigWork W = eig_layout(a.work, s, kmax);
-  long long* ts = a.tstamp;
-  if (tid == 0) {
-    sh.dotr = 0.0;
-    sh.doti = 0.0;
-    if (ts) ts[0] = wall_clock64();
-  }
-  __syncthreads();
-  if (IN_LDS) tridiag_lds(P, vv, ww, a.G, s, sh, W);
-  else tridiag_global(a.G, vv, ww, s, sh, W);
-  if (ts && tid == 0) ts[1] = wall_clock64();
   for (int i = tid; i < s; i += blockDim.x) {
     dd[i] = W.d[i];
     el[i] = i < s - 1 ? W.e[i] : 0.0;
-    ee2[i] = el[i] * el[i];
-    taus[i] = i < s - 1 ? W.tau[i] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  eigenvalues(dd, ee2, el, s, kmax, lam, sh);
-  if (ts && tid == 0) ts[2] = wall_clock64();
-  eigenvectors(dd, el, s, kmax, lam, cnext, sh, W);
-  if (ts && tid == 0) ts[3] = wall_clock64();
-  select_rank(a, lam, kmax, sh);
-  const int keep = sh.keep;
-  if (IN_LDS) {
-    back_transform(a, s, kmax, keep, W, taus, [&](int j, int i) {
-      return i == j + 1 ? make_double2(1.0, 0.0) : P[tri(i) + j];
-    });
+  const int t = blockIdx.x * nw + wave;
+  if (t >= kmax) return;
+  const double tnorm = W.bounds[2], pivmin = W.bounds[3];
+  const double* lam = a.lam;
+  // rank selection: keep lam_t > tol^2 lam_0 (descending order), always the first
+  int keep = kmax;
+  if (a.tol > 0.0) {
+    const double cut = a.tol * a.tol * lam[0];
+    int c = 0;
+    for (int u = lane; u < kmax; u += 64) c += lam[u] > cut;
+    c = (int)wave_sum((double)c);
+    keep = c < 1 ? 1 : c;
+  }
+  if (t == 0 && lane == 0) {
+    a.kkeep[0] = keep;
+    a.inv_sqrt_l0[0] = lam[0] > 0.0 ? 1.0 / sqrt(lam[0]) : 1.0;
+  }
+  // clusters of non-negligible eigenvalues closer than 1e-3 ||T||; negligible ones (at the rounding
+  // level of ||T||) carry no weight and are computed one by one
+  const double ortol = 1e-3 * tnorm, tiny = 64.0 * DBL_EPSILON * tnorm;
+  auto starts = [&](int u) {
+    return u == 0 || u == kmax || lam[u - 1] - lam[u] > ortol || lam[u] <= tiny;
+  };
+  if (!starts(t)) {   // computed by the wave of the cluster's first member
+    if (a.tstamp && lane == 0)
+      atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 3), (unsigned long long)wall_clock64());
+    return;
+  }
+  int ce = t + 1;
+  while (ce < kmax && !starts(ce)) ++ce;
+  double* lp = region;
+  double* dp = region + s;
+  double* um = region + 2 * s;
+  double* y = region + 3 * s;
+  double2* u = reinterpret_cast<double2*>(region);   // reuses lp|dp after the twisted solve
+  auto wave_sync = [&]() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  };
+  if (ce == t + 1) {
+    if (lane == 0) twisted_vector(dd, el, s, lam[t], pivmin, y, lp, dp, um);
+    wave_sync();
+    back_transform_any(a, W, s, kmax, t, t < keep, y, u);
   } else {
-    const double2* V = W.V;
-    back_transform(a, s, kmax, keep, W, taus, [&](int j, int i) { return V[(size_t)j * s + i]; });
+    // a cluster: if its members are distinct at the rounding level, twisted vectors are accurate up
+    // to mixing inside the cluster, so modified Gram-Schmidt over the members gives an orthonormal
+    // basis of the cluster's invariant subspace; near-exact degeneracies use inverse iteration.
+    double mingap = DBL_MAX;
+    for (int m = t + 1; m < ce; ++m) mingap = fmin(mingap, lam[m - 1] - lam[m]);
+    if (mingap > 1e-12 * tnorm) {
+      double* Yc = W.Y;
+      for (int m = t; m < ce; ++m) {
+        double* ym = Yc + (size_t)m * s;
+        if (lane == 0) twisted_vector(dd, el, s, lam[m], pivmin, y, lp, dp, um);
+        wave_sync();
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int q = t; q < m; ++q) {
+            const double* yq = Yc + (size_t)q * s;
+            double dot = 0.0;
+            for (int i = lane; i < s; i += 64) dot += yq[i] * y[i];
+            dot = wave_sum(dot);
+            for (int i = lane; i < s; i += 64) y[i] -= dot * yq[i];
+            wave_sync();
+          }
+        }
+        double nrm = 0.0;
+        for (int i = lane; i < s; i += 64) nrm += y[i] * y[i];
+        nrm = wave_sum(nrm);
+        const double inv = 1.0 / sqrt(nrm);
+        for (int i = lane; i < s; i += 64) ym[i] = y[i] * inv;
+        __threadfence_block();
+        wave_sync();
+      }
+    } else if (lane == 0) {
+      cluster_vectors(dd, el, s, lam, t, ce, tnorm, W.Y, W.lu + (size_t)t * 5 * s);
+    }
+    wave_sync();
+    for (int m = t; m < ce; ++m) {
+      back_transform_any(a, W, s, kmax, m, m < keep, W.Y + (size_t)m * s, u);
+      wave_sync();
+    }
   }
-  __syncthreads();
-  if (ts && tid == 0) ts[4] = wall_clock64();
+  if (a.tstamp && lane == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 3), (unsigned long long)wall_clock64());
+  if (a.tstamp && lane == 0 && ce > t + 1) atomicAdd(reinterpret_cast<unsigned long long*>(a.tstamp + 7), 1ull);
 }
 
 size_t eig_lds_bytes(int s, int kmax, bool in_lds) {
-  return (in_lds ? (size_t)16 * (s * (size_t)(s + 1) / 2) : 0) + (size_t)s * (3 * 16 + 3 * 8) +
-         (size_t)kmax * (8 + 4) + 64;
+  (void)kmax;
+  return (in_lds ? (size_t)16 * (s * (size_t)(s + 1) / 2) : 0) + (size_t)s * (2 * 16) + 64;
 }
 
 hipError_t launch_eig(const EigArgs& a, hipStream_t st) {
@@ -673,14 +666,27 @@ hipError_t launch_eig(const EigArgs& a, hipStream_t st) {
   const size_t lds = eig_lds_bytes(a.s, a.kmax, in_lds);
   if (lds > 160 * 1024 - 512) return hipErrorInvalidValue;
   if (in_lds) {
-    (void)hipFuncSetAttribute((const void*)k_eig<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    hipLaunchKernelGGL(k_eig<true>, dim3(1), dim3(EIG_THREADS), lds, st, a);
+    (void)hipFuncSetAttribute((const void*)k_tridiag<true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_tridiag<true>, dim3(1), dim3(EIG_THREADS), lds, st, a);
   } else {
-    (void)hipFuncSetAttribute((const void*)k_eig<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    hipLaunchKernelGGL(k_eig<false>, dim3(1), dim3(EIG_THREADS), lds, st, a);
+    (void)hipFuncSetAttribute((const void*)k_tridiag<false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_tridiag<false>, dim3(1), dim3(EIG_THREADS), lds, st, a);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t lds2 = (size_t)16 * a.s;
+  hipLaunchKernelGGL(k_eigvals, dim3((a.kmax + EV_WAVES - 1) / EV_WAVES), dim3(64 * EV_WAVES),
+                     lds2, st, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int nw = a.s <= 1000 ? 4 : (a.s <= 1900 ? 2 : 1);
+  const size_t lds3 = (size_t)a.s * (2 * 8 + (size_t)nw * 4 * 8) + 64;
+  if (lds3 > 160 * 1024 - 512) return hipErrorInvalidValue;
+  (void)hipFuncSetAttribute((const void*)k_eigvecs, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds3);
+  hipLaunchKernelGGL(k_eigvecs, dim3((a.kmax + nw - 1) / nw), dim3(64 * nw), lds3, st, a);
   return hipGetLastError();
 }
 
