@@ -93,6 +93,27 @@ def cpu_baseline(p, gpu_outputs, budget_s=20.0):
                        f"sweep)"), errs
 
 
+def batched_run(args, cbc, p, stream):
+    """Throughput of `batch` independent instances of the workload's shape in one launch sequence
+    (mixed precision), inputs resident in HBM."""
+    import torch
+    from paper_2601_19650_amd.inputs import config_problem
+    probs = [p] + [config_problem(args.workload, seed=1000 + b) for b in range(1, args.batch)]
+    tree = cbc.Tree.of(p)
+    st, so = cbc.pack_batch([q.state for q in probs], "cuda:0")
+    op, oo = cbc.pack_batch([q.op for q in probs], "cuda:0")
+    ctx = cbc.Context()
+    comp = cbc.Compressor(ctx, tree, p.max_bond, "mixed", device="cuda:0", batch=args.batch)
+    steps = max(2, args.steps // 4)
+    sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, 1)
+    print(f"[bench] batched x{args.batch}: {sec * 1e3:.3f} ms per launch sequence", file=sys.stderr,
+          flush=True)
+    return {"batch": args.batch, "value": args.batch / sec, "unit": "compressions/s",
+            "ms_per_step": sec * 1e3, "steps": steps, "precision": "mixed",
+            "contraction_tflops": args.batch * comp.stats.flops[0] / sec / 1e12,
+            "workspace_gb": comp.ws_bytes / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +122,8 @@ def main():
     ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    ap.add_argument("--batch", type=int, default=64,
+                    help="instances per launch sequence for the batched measurement (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1",
@@ -179,6 +202,8 @@ def main():
                         "kernel_ms_per_step": {cls[k]: res["fp64"]["kms"][k]
                                                for k in range(cbc.NCLASS)}}
         line["speedup_mixed_vs_fp64"] = res["fp64"]["sec"] / res["mixed"]["sec"]
+    if args.batch > 1:
+        line["batched"] = batched_run(args, cbc, p, stream)
     if not args.no_cpu_baseline:
         cb, errs = cpu_baseline(p, outputs)
         line["cpu_baseline"] = cb

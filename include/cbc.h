@@ -145,6 +145,18 @@ cbc_status cbc_apply(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* t
                      void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
                      cbc_stats* stats);
 
+/* A batch of `batch` independent compressions of the same shape (same tree, dimensions, max_bond,
+ * tol and precision) in one launch sequence: every kernel runs all instances at once. Instance b's
+ * node i is at element b * T + offset[i] of each input buffer, where T is the network's total
+ * element count (sum of node sizes), and at b * out_offset[n_nodes] + out_offset[i] of the output;
+ * the workspace must hold batch times cbc_query's workspace_bytes. bond[] is shared by all
+ * instances. Otherwise as cbc_apply. */
+cbc_status cbc_apply_batched(cbc_ctx* ctx, int32_t batch, const cbc_tensors* ttno,
+                             const cbc_tensors* ttns, const cbc_tree* tree, int32_t max_bond,
+                             double tol, cbc_precision prec, void* workspace,
+                             size_t workspace_bytes, cbc_out* out, void* stream,
+                             cbc_stats* stats);
+
 /* Naive baseline (Sec. III C, "direct"): contract O|psi> exactly (bonds chi*D), bring it into
  * canonical form toward the root with Cholesky-QR, then truncate every bond with the top-k
  * eigenspace of its Gram matrix in a depth-first sweep from the root. Same arguments as cbc_apply. */

@@ -86,12 +86,18 @@ def lib():
                           ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(_Out), ctypes.c_void_p,
                           ctypes.POINTER(Stats)]
             f.restype = ctypes.c_int
+        L.cbc_apply_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_Tensors),
+                                        ctypes.POINTER(_Tensors), ctypes.POINTER(_Tree),
+                                        ctypes.c_int32, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(_Out),
+                                        ctypes.c_void_p, ctypes.POINTER(Stats)]
+        L.cbc_apply_batched.restype = ctypes.c_int
         _lib = L
     return _lib
 
 
 EXPORTED = ("cbc_create", "cbc_destroy", "cbc_status_str", "cbc_query", "cbc_plan_bonds",
-            "cbc_apply", "cbc_apply_naive")
+            "cbc_apply", "cbc_apply_batched", "cbc_apply_naive")
 
 
 def _check(code, what):
@@ -149,11 +155,17 @@ class Tree:
 
 def pack(tensors, device):
     """Pack node tensors (numpy complex128) into one device buffer; returns (buffer, offsets)."""
+    return pack_batch([tensors], device)
+
+
+def pack_batch(networks, device):
+    """Pack several networks of the same shape back to back (instance b at b * total elements)."""
     import torch
-    sizes = [int(np.prod(t.shape)) for t in tensors]
-    off = np.zeros(len(tensors), dtype=np.int64)
+    sizes = [int(np.prod(t.shape)) for t in networks[0]]
+    off = np.zeros(len(sizes), dtype=np.int64)
     off[1:] = np.cumsum(sizes)[:-1]
-    flat = np.concatenate([np.ascontiguousarray(t, dtype=np.complex128).reshape(-1) for t in tensors])
+    flat = np.concatenate([np.ascontiguousarray(t, dtype=np.complex128).reshape(-1)
+                           for net in networks for t in net])
     return torch.from_numpy(flat).to(device), off
 
 
@@ -161,9 +173,10 @@ class Compressor:
     """One problem shape: queries sizes once, owns workspace and output buffers, and runs the
     compression (``method`` "cbc" or "naive", ``precision`` "fp64" or "mixed")."""
 
-    def __init__(self, ctx, tree, max_bond, precision="fp64", method="cbc", device="cuda"):
+    def __init__(self, ctx, tree, max_bond, precision="fp64", method="cbc", device="cuda", batch=1):
         import torch
         self.ctx, self.tree, self.max_bond = ctx, tree, int(max_bond)
+        self.batch = int(batch)
         self.prec = PRECISIONS[precision]
         self.method = METHODS[method]
         ws = ctypes.c_size_t()
@@ -171,9 +184,10 @@ class Compressor:
         _check(lib().cbc_query(ctx.h, ctypes.byref(tree.c), self.max_bond, self.prec, self.method,
                                ctypes.byref(ws), self.out_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
                "cbc_query")
-        self.ws_bytes = int(ws.value)
+        self.ws_bytes = int(ws.value) * self.batch
         self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
-        self.out = torch.zeros(int(self.out_off[-1]), dtype=torch.complex128, device=device)
+        self.out = torch.zeros(int(self.out_off[-1]) * self.batch, dtype=torch.complex128,
+                               device=device)
         self.bond = np.zeros(tree.n, dtype=np.int32)
         self.stats = Stats()
 
@@ -189,6 +203,13 @@ class Compressor:
                    self.bond.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
+        if self.batch > 1:
+            _check(lib().cbc_apply_batched(self.ctx.h, self.batch, ctypes.byref(ttno), ctypes.byref(ttns),
+                                           ctypes.byref(self.tree.c), self.max_bond, float(tol),
+                                           self.prec, self.workspace.data_ptr(), self.ws_bytes,
+                                           ctypes.byref(out), ctypes.c_void_p(stream),
+                                           ctypes.byref(self.stats)), "cbc_apply_batched")
+            return self.out, self.bond
         fn = lib().cbc_apply if self.method == 0 else lib().cbc_apply_naive
         _check(fn(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns), ctypes.byref(self.tree.c),
                   self.max_bond, float(tol), self.prec, self.workspace.data_ptr(), self.ws_bytes,
@@ -196,9 +217,10 @@ class Compressor:
                "cbc_apply" if self.method == 0 else "cbc_apply_naive")
         return self.out, self.bond
 
-    def unpack(self):
+    def unpack(self, instance=0):
         """Output node tensors as numpy complex128 arrays (sigma', parent bond, child bonds...)."""
-        host = self.out.cpu().numpy()
+        total = int(self.out_off[-1])
+        host = self.out[instance * total:(instance + 1) * total].cpu().numpy()
         res = []
         for i in range(self.tree.n):
             shape = (int(self.tree.phys[i]), int(self.bond[i])) + tuple(

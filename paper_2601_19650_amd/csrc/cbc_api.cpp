@@ -746,6 +746,9 @@ struct Call {
   const int64_t* op_off;
   const int64_t* out_off;
   size_t persist;
+  // batch: instance b uses every buffer advanced by b times its per-instance byte stride
+  int batch = 1;
+  int64_t ws_inst = 0, st_inst = 0, op_inst = 0, out_inst = 0;
 };
 
 }  // namespace
@@ -774,9 +777,15 @@ void* resolve(const Plan& P, const Call& c, const TRef& r) {
   }
 }
 
-__global__ void k_zero_bytes(uint32_t* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
+int64_t stride_of(const Plan& P, const Call& c, const TRef& r) {
+  switch (r.src) {
+    case S_WS:
+    case S_SCR: return c.ws_inst;
+    case S_STATE: return (r.off >= 0 && P.state_conv_off >= 0) ? c.ws_inst : c.st_inst;
+    case S_OP: return (r.off >= 0 && P.op_conv_off >= 0) ? c.ws_inst : c.op_inst;
+    case S_OUT: return c.out_inst;
+    default: return 0;
+  }
 }
 
 hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev = nullptr) {
@@ -809,6 +818,12 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         g.alpha_dev = op.adev.src == S_NONE ? nullptr : (const double*)resolve(P, c, op.adev);
         g.alpha_dev2 = op.adev2.src == S_NONE ? nullptr : (const double*)resolve(P, c, op.adev2);
         g.alpha = op.alpha;
+        g.batch = c.batch;
+        g.bsA = stride_of(P, c, op.A);
+        g.bsB = stride_of(P, c, op.B);
+        g.bsC = stride_of(P, c, op.C);
+        g.bsAlpha = stride_of(P, c, op.adev);
+        g.bsAlpha2 = stride_of(P, c, op.adev2);
         e = launch_gemm(g, op.ta, op.tb, op.tc, op.acc, op.tile, st);
         break;
       }
@@ -825,13 +840,15 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         a.work = (double*)resolve(P, c, op.work);
         a.tol = op.shift_rel;  // tolerance stored per call below
         a.tstamp = nullptr;
+        a.batch = c.batch;
+        a.bs = c.ws_inst;
         e = launch_eig(a, st);
         break;
       }
       case K_FORM_N:
         e = launch_form_l_nside((const double2*)resolve(P, c, op.U), (const double*)resolve(P, c, op.lam),
                                 (const int*)resolve(P, c, op.kkeep), op.n, op.kmax,
-                                resolve(P, c, op.L), op.td, st);
+                                resolve(P, c, op.L), op.td, c.batch, c.ws_inst, st);
         break;
       case K_CHOL: {
         CholArgs a;
@@ -844,28 +861,29 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         a.scale = op.scale.src == S_NONE ? nullptr : (double*)resolve(P, c, op.scale);
         a.ndrop = (int*)resolve(P, c, op.ndrop);
         a.tstamp = nullptr;
+        a.batch = c.batch;
+        a.bs = c.ws_inst;
         e = launch_chol_inv(a, st);
         break;
       }
       case K_CONVERT:
-        e = launch_convert(resolve(P, c, op.src), op.ts, resolve(P, c, op.dst), op.td, op.count, st);
+        e = launch_convert(resolve(P, c, op.src), op.ts, resolve(P, c, op.dst), op.td, op.count,
+                           c.batch, stride_of(P, c, op.src), stride_of(P, c, op.dst), st);
         break;
       case K_IDENT:
-        e = launch_fill_identity(resolve(P, c, op.dst), op.td, op.a, op.b, st);
+        e = launch_fill_identity(resolve(P, c, op.dst), op.td, op.a, op.b, c.batch,
+                                 stride_of(P, c, op.dst), st);
         break;
       case K_WRITE:
         e = launch_write_out(resolve(P, c, op.src), op.ts, op.a, op.b, op.rest,
                              (double2*)resolve(P, c, op.dst),
                              op.logs.src == S_NONE ? nullptr : (const double*)resolve(P, c, op.logs),
-                             op.nlogs, st);
+                             op.nlogs, c.batch, stride_of(P, c, op.src), stride_of(P, c, op.dst),
+                             stride_of(P, c, op.logs), st);
         break;
-      case K_ZERO: {
-        const int64_t nw = (op.count + 3) / 4;
-        hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st,
-                           (uint32_t*)resolve(P, c, op.dst), nw);
-        e = hipGetLastError();
+      case K_ZERO:
+        e = launch_zero(resolve(P, c, op.dst), op.count, c.batch, stride_of(P, c, op.dst), st);
         break;
-      }
     }
     if (e != hipSuccess) return e;
     if (ev) {
@@ -1011,7 +1029,9 @@ cbc_status cbc_plan_bonds(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, 
 static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
                              const cbc_tree* tree, int32_t max_bond, double tol,
                              cbc_precision prec, void* workspace, size_t workspace_bytes,
-                             cbc_out* out, void* stream, cbc_stats* stats, int method) {
+                             cbc_out* out, void* stream, cbc_stats* stats, int method,
+                             int32_t batch = 1) {
+  if (batch < 1 || batch > 65535) return CBC_EINVAL;
   if (!ctx || !ttno || !ttns || !out || !ttno->data || !ttns->data || !ttno->offset ||
       !ttns->offset || !out->data || !out->offset || !out->bond)
     return CBC_EINVAL;
@@ -1033,7 +1053,8 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   Plan* P = nullptr;
   s = get_plan(ctx, pr, max_bond, tol > 0.0, prec, method, se, oe, &P);
   if (s != CBC_OK) return s;
-  if (!workspace || workspace_bytes < P->persist_bytes + P->scratch_bytes) return CBC_ENOMEM;
+  const size_t ws_inst = P->persist_bytes + P->scratch_bytes;
+  if (!workspace || workspace_bytes / (size_t)batch < ws_inst) return CBC_ENOMEM;
   for (int i = 0; i <= pr.n; ++i)
     if (out->offset[i] != P->out_off[i]) return CBC_EINVAL;
   s = upload_tables(P);
@@ -1050,6 +1071,11 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   c.op_off = ttno->offset;
   c.out_off = P->out_off.data();
   c.persist = P->persist_bytes;
+  c.batch = batch;
+  c.ws_inst = (int64_t)ws_inst;
+  c.st_inst = 16 * se;
+  c.op_inst = 16 * oe;
+  c.out_inst = 16 * P->out_off[pr.n];
   hipStream_t st = (hipStream_t)stream;
   const bool profile = stats && stats->profile;
   int replayed = 0;
@@ -1064,7 +1090,7 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   } else if (st != nullptr) {
     // replay a captured graph of the whole launch sequence when the buffers are unchanged
     std::vector<uintptr_t> key{(uintptr_t)c.ws, (uintptr_t)c.state, (uintptr_t)c.op,
-                               (uintptr_t)c.out};
+                               (uintptr_t)c.out, (uintptr_t)batch};
     uint64_t tb;
     memcpy(&tb, &tol, sizeof(tb));
     key.push_back((uintptr_t)tb);
@@ -1130,6 +1156,15 @@ cbc_status cbc_apply(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* t
                      cbc_stats* stats) {
   return apply_impl(ctx, ttno, ttns, tree, max_bond, tol, prec, workspace, workspace_bytes, out,
                     stream, stats, 0);
+}
+
+cbc_status cbc_apply_batched(cbc_ctx* ctx, int32_t batch, const cbc_tensors* ttno,
+                             const cbc_tensors* ttns, const cbc_tree* tree, int32_t max_bond,
+                             double tol, cbc_precision prec, void* workspace,
+                             size_t workspace_bytes, cbc_out* out, void* stream,
+                             cbc_stats* stats) {
+  return apply_impl(ctx, ttno, ttns, tree, max_bond, tol, prec, workspace, workspace_bytes, out,
+                    stream, stats, 0, batch);
 }
 
 cbc_status cbc_apply_naive(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,

@@ -30,7 +30,17 @@ struct GemmArgs {
   const double* alpha_dev;  // optional device scalar multiplier (nullptr: none)
   const double* alpha_dev2; // optional second device scalar multiplier (nullptr: none)
   double alpha;             // host scalar multiplier
+  // batch: instance z (blockIdx.z) uses every pointer advanced by z times its byte stride
+  int batch;
+  int64_t bsA, bsB, bsC, bsAlpha, bsAlpha2;
 };
+// pointer of instance b for a per-instance byte stride
+template <typename T>
+__host__ __device__ inline T* inst_ptr(T* p, int64_t stride, int b) {
+  return p ? reinterpret_cast<T*>(reinterpret_cast<char*>(const_cast<void*>(
+                 reinterpret_cast<const void*>(p))) + stride * (int64_t)b)
+           : p;
+}
 
 // Launch a GEMM. acc: DT_C64 -> FP32 MFMA, DT_C128 -> FP64 MFMA. tile: 0 = 32x32, 1 = 64x64.
 hipError_t launch_gemm(const GemmArgs& a, DType ta, DType tb, DType tc, DType acc, int tile,
@@ -51,6 +61,8 @@ struct EigArgs {
   double* inv_sqrt_l0;
   double* work;     // scratch, eig_work_doubles(s, kmax) doubles
   long long* tstamp;  // optional: wall-clock stamps at phase boundaries (8 entries), or nullptr
+  int batch;          // instances; every pointer above (except tstamp) advances by bs bytes
+  int64_t bs;
 };
 size_t eig_work_doubles(int s, int kmax);
 hipError_t launch_eig(const EigArgs& a, hipStream_t st);
@@ -58,7 +70,7 @@ hipError_t launch_eig(const EigArgs& a, hipStream_t st);
 // n-side truncation output: L[j, c] = sqrt(max(lam_j, 0)) / sqrt(lam_0) * conj(V[c, j]) for j < kkeep,
 // zero for kkeep <= j < kmax. L is kmax x n, written in the contraction precision.
 hipError_t launch_form_l_nside(const double2* V, const double* lam, const int* kkeep, int n,
-                               int kmax, void* L, DType tl, hipStream_t st);
+                               int kmax, void* L, DType tl, int batch, int64_t bs, hipStream_t st);
 
 // Cholesky of a Hermitian PSD Gram G (k x k, FP64, overwritten) with an optional diagonal shift of
 // shift_rel * trace(G); pivots below drop_rel * max pivot are dropped. Writes Cinv = C^{-1} (k x k,
@@ -74,15 +86,22 @@ struct CholArgs {
   double* scale;
   int* ndrop;
   long long* tstamp;  // optional: wall-clock stamps at phase boundaries (4 entries), or nullptr
+  int batch;          // instances; every pointer above (except tstamp) advances by bs bytes
+  int64_t bs;
 };
 hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st);
 
 // Elementwise helpers.
-hipError_t launch_convert(const void* src, DType ts, void* dst, DType td, int64_t n, hipStream_t st);
-hipError_t launch_fill_identity(void* dst, DType t, int rows, int cols, hipStream_t st);
+// Batched elementwise helpers: instance b uses src + b * ss and dst + b * ds (bytes).
+hipError_t launch_convert(const void* src, DType ts, void* dst, DType td, int64_t n, int batch,
+                          int64_t ss, int64_t ds, hipStream_t st);
+hipError_t launch_fill_identity(void* dst, DType t, int rows, int cols, int batch, int64_t ds,
+                                hipStream_t st);
+hipError_t launch_zero(void* dst, int64_t bytes, int batch, int64_t ds, hipStream_t st);
 // Output writer: src is a (a x b x rest) tensor in type ts; writes dst[(b, a, rest)] as complex128
 // (swap of the two leading legs), multiplied by exp(-sum(logs[0..nlogs))) if logs != nullptr.
 hipError_t launch_write_out(const void* src, DType ts, int a, int b, int64_t rest, double2* dst,
-                            const double* logs, int nlogs, hipStream_t st);
+                            const double* logs, int nlogs, int batch, int64_t ss, int64_t ds,
+                            int64_t ls, hipStream_t st);
 
 }  // namespace cbc

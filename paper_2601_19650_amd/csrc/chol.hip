@@ -27,7 +27,18 @@ __device__ __forceinline__ double wmax(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(CholArgs a) {
+__device__ inline CholArgs chol_inst(const CholArgs& a0, int b) {
+  CholArgs a = a0;
+  a.G = inst_ptr(a0.G, a0.bs, b);
+  a.Cinv = inst_ptr(a0.Cinv, a0.bs, b);
+  a.log_scale = inst_ptr(a0.log_scale, a0.bs, b);
+  a.scale = inst_ptr(a0.scale, a0.bs, b);
+  a.ndrop = inst_ptr(a0.ndrop, a0.bs, b);
+  return a;
+}
+
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(CholArgs a0) {
+  const CholArgs a = chol_inst(a0, blockIdx.x);
   extern __shared__ int dropped[];
   __shared__ double red[32];
   __shared__ double sh_trace, sh_thresh;
@@ -156,7 +167,8 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-__global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a) {
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
+  const CholArgs a = chol_inst(a0, blockIdx.x);
   extern __shared__ double2 M[];
   __shared__ double red[32];
   __shared__ double sh_thresh;
@@ -337,15 +349,16 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a) {
 }
 
 hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st) {
-  if (a.k <= 0) return hipSuccess;
+  if (a.k <= 0 || a.batch <= 0) return hipSuccess;
   if (a.k <= CHOL_LDS_MAX) {
     const size_t lds = (size_t)a.k * (a.k + 1) * sizeof(double2) + (size_t)a.k * sizeof(double) +
                        (size_t)((a.k + 3) & ~3) * sizeof(int) + (size_t)a.k * NBc * sizeof(double2);
     (void)hipFuncSetAttribute((const void*)k_chol_inv_lds,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_chol_inv_lds, dim3(1), dim3(CHOL_THREADS), lds, st, a);
+    hipLaunchKernelGGL(k_chol_inv_lds, dim3(a.batch), dim3(CHOL_THREADS), lds, st, a);
   } else {
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(CHOL_THREADS), (size_t)a.k * sizeof(int), st, a);
+    hipLaunchKernelGGL(k_chol_inv, dim3(a.batch), dim3(CHOL_THREADS), (size_t)a.k * sizeof(int), st,
+                       a);
   }
   return hipGetLastError();
 }
@@ -353,7 +366,11 @@ hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st) {
 // ------------------------------------------------------------------------------------------------
 // elementwise helpers
 
-__global__ void k_convert(const void* src, int ts, void* dst, int td, int64_t n) {
+__global__ void k_convert(const void* src, int ts, void* dst, int td, int64_t n, int64_t ss,
+                          int64_t ds) {
+  const int b = blockIdx.y;
+  src = inst_ptr(src, ss, b);
+  dst = inst_ptr(dst, ds, b);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double2 v;
@@ -366,15 +383,16 @@ __global__ void k_convert(const void* src, int ts, void* dst, int td, int64_t n)
   else reinterpret_cast<float2*>(dst)[i] = make_float2((float)v.x, (float)v.y);
 }
 
-hipError_t launch_convert(const void* src, DType ts, void* dst, DType td, int64_t n,
-                          hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_convert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, (int)ts,
-                     dst, (int)td, n);
+hipError_t launch_convert(const void* src, DType ts, void* dst, DType td, int64_t n, int batch,
+                          int64_t ss, int64_t ds, hipStream_t st) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_convert, dim3((unsigned)((n + 255) / 256), batch), dim3(256), 0, st, src,
+                     (int)ts, dst, (int)td, n, ss, ds);
   return hipGetLastError();
 }
 
-__global__ void k_fill_identity(void* dst, int t, int rows, int cols) {
+__global__ void k_fill_identity(void* dst, int t, int rows, int cols, int64_t ds) {
+  dst = inst_ptr(dst, ds, blockIdx.y);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)rows * cols) return;
   const int r = (int)(i / cols), c = (int)(i % cols);
@@ -383,17 +401,36 @@ __global__ void k_fill_identity(void* dst, int t, int rows, int cols) {
   else reinterpret_cast<float2*>(dst)[i] = make_float2((float)v, 0.0f);
 }
 
-hipError_t launch_fill_identity(void* dst, DType t, int rows, int cols, hipStream_t st) {
+hipError_t launch_fill_identity(void* dst, DType t, int rows, int cols, int batch, int64_t ds,
+                                hipStream_t st) {
   const int64_t n = (int64_t)rows * cols;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_identity, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dst,
-                     (int)t, rows, cols);
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_identity, dim3((unsigned)((n + 255) / 256), batch), dim3(256), 0, st,
+                     dst, (int)t, rows, cols, ds);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_words(uint32_t* p, int64_t n, int64_t ds) {
+  p = inst_ptr(p, ds, blockIdx.y);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero(void* dst, int64_t bytes, int batch, int64_t ds, hipStream_t st) {
+  const int64_t nw = (bytes + 3) / 4;
+  if (nw <= 0 || batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((nw + 255) / 256), batch), dim3(256), 0, st,
+                     reinterpret_cast<uint32_t*>(dst), nw, ds);
   return hipGetLastError();
 }
 
 // dst[(b, a, r)] = src[(a, b, r)] * exp(-sum logs)
 __global__ void k_write_out(const void* src, int ts, int a, int b, int64_t rest, double2* dst,
-                            const double* logs, int nlogs) {
+                            const double* logs, int nlogs, int64_t ss, int64_t ds, int64_t ls) {
+  const int inst = blockIdx.y;
+  src = inst_ptr(src, ss, inst);
+  dst = inst_ptr(dst, ds, inst);
+  logs = inst_ptr(logs, ls, inst);
   __shared__ double sh_f;
   if (threadIdx.x == 0) {
     double l = 0.0;
@@ -420,11 +457,12 @@ __global__ void k_write_out(const void* src, int ts, int a, int b, int64_t rest,
 }
 
 hipError_t launch_write_out(const void* src, DType ts, int a, int b, int64_t rest, double2* dst,
-                            const double* logs, int nlogs, hipStream_t st) {
+                            const double* logs, int nlogs, int batch, int64_t ss, int64_t ds,
+                            int64_t ls, hipStream_t st) {
   const int64_t n = (int64_t)a * b * rest;
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_write_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src,
-                     (int)ts, a, b, rest, dst, logs, nlogs);
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_write_out, dim3((unsigned)((n + 255) / 256), batch), dim3(256), 0, st, src,
+                     (int)ts, a, b, rest, dst, logs, nlogs, ss, ds, ls);
   return hipGetLastError();
 }
 

@@ -109,6 +109,18 @@ size_t eig_work_doubles(int s, int kmax) {
   return 4 * (size_t)s + 8 + 2 * (size_t)s * s + (size_t)kmax * s + 5 * (size_t)kmax * s + 64;
 }
 
+// EigArgs of instance b (every pointer except the time stamps advances by a.bs bytes)
+__device__ inline EigArgs eig_inst(const EigArgs& a0, int b) {
+  EigArgs a = a0;
+  a.G = inst_ptr(a0.G, a0.bs, b);
+  a.U = inst_ptr(a0.U, a0.bs, b);
+  a.lam = inst_ptr(a0.lam, a0.bs, b);
+  a.kkeep = inst_ptr(a0.kkeep, a0.bs, b);
+  a.inv_sqrt_l0 = inst_ptr(a0.inv_sqrt_l0, a0.bs, b);
+  a.work = inst_ptr(a0.work, a0.bs, b);
+  return a;
+}
+
 __device__ int sturm_count(const double* dd, const double* ee2, int s, double x, double pivmin) {
   double q = dd[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
@@ -175,7 +187,8 @@ __device__ __forceinline__ void matvec_row(int r, int nj, int gl, const double2*
 }
 
 template <bool IN_LDS>
-__global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a) {
+__global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
+  const EigArgs a = eig_inst(a0, blockIdx.x);
   extern __shared__ double smem[];
   __shared__ TriShared sh;
   const int s = a.s;
@@ -307,7 +320,8 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a) {
 // ---- eigenvalues: one wave per eigenvalue -------------------------------------------------------
 static constexpr int EV_WAVES = 4;
 
-__global__ __launch_bounds__(64 * EV_WAVES) void k_eigvals(EigArgs a) {
+__global__ __launch_bounds__(64 * EV_WAVES) void k_eigvals(EigArgs a0) {
+  const EigArgs a = eig_inst(a0, blockIdx.y);
   extern __shared__ double smem[];
   const int s = a.s, kmax = a.kmax;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -553,7 +567,8 @@ __device__ void back_transform_any(const EigArgs& a, const EigWork& W, int s, in
   else back_transform_col(a, W, s, kmax, t, kept, yin, u);
 }
 
-__global__ __launch_bounds__(256) void k_eigvecs(EigArgs a) {
+__global__ __launch_bounds__(256) void k_eigvecs(EigArgs a0) {
+  const EigArgs a = eig_inst(a0, blockIdx.y);
   extern __shared__ double smem[];
   const int s = a.s, kmax = a.kmax;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -661,24 +676,24 @@ size_t eig_lds_bytes(int s, int kmax, bool in_lds) {
 }
 
 hipError_t launch_eig(const EigArgs& a, hipStream_t st) {
-  if (a.s <= 0 || a.kmax <= 0 || a.kmax > a.s) return hipErrorInvalidValue;
+  if (a.s <= 0 || a.kmax <= 0 || a.kmax > a.s || a.batch <= 0) return hipErrorInvalidValue;
   const bool in_lds = a.s <= EIG_LDS_MAX;
   const size_t lds = eig_lds_bytes(a.s, a.kmax, in_lds);
   if (lds > 160 * 1024 - 512) return hipErrorInvalidValue;
   if (in_lds) {
     (void)hipFuncSetAttribute((const void*)k_tridiag<true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_tridiag<true>, dim3(1), dim3(EIG_THREADS), lds, st, a);
+    hipLaunchKernelGGL(k_tridiag<true>, dim3(a.batch), dim3(EIG_THREADS), lds, st, a);
   } else {
     (void)hipFuncSetAttribute((const void*)k_tridiag<false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_tridiag<false>, dim3(1), dim3(EIG_THREADS), lds, st, a);
+    hipLaunchKernelGGL(k_tridiag<false>, dim3(a.batch), dim3(EIG_THREADS), lds, st, a);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds2 = (size_t)16 * a.s;
-  hipLaunchKernelGGL(k_eigvals, dim3((a.kmax + EV_WAVES - 1) / EV_WAVES), dim3(64 * EV_WAVES),
-                     lds2, st, a);
+  hipLaunchKernelGGL(k_eigvals, dim3((a.kmax + EV_WAVES - 1) / EV_WAVES, a.batch),
+                     dim3(64 * EV_WAVES), lds2, st, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nw = a.s <= 1000 ? 4 : (a.s <= 1900 ? 2 : 1);
@@ -686,13 +701,18 @@ hipError_t launch_eig(const EigArgs& a, hipStream_t st) {
   if (lds3 > 160 * 1024 - 512) return hipErrorInvalidValue;
   (void)hipFuncSetAttribute((const void*)k_eigvecs, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds3);
-  hipLaunchKernelGGL(k_eigvecs, dim3((a.kmax + nw - 1) / nw), dim3(64 * nw), lds3, st, a);
+  hipLaunchKernelGGL(k_eigvecs, dim3((a.kmax + nw - 1) / nw, a.batch), dim3(64 * nw), lds3, st, a);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------------
 __global__ void k_form_l_nside(const double2* V, const double* lam, const int* kkeep, int n,
-                               int kmax, void* L, int tl) {
+                               int kmax, void* L, int tl, int64_t bs) {
+  const int b = blockIdx.y;
+  V = inst_ptr(V, bs, b);
+  lam = inst_ptr(lam, bs, b);
+  kkeep = inst_ptr(kkeep, bs, b);
+  L = inst_ptr(L, bs, b);
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)kmax * n) return;
   const int j = (int)(idx / n);
@@ -708,11 +728,11 @@ __global__ void k_form_l_nside(const double2* V, const double* lam, const int* k
 }
 
 hipError_t launch_form_l_nside(const double2* V, const double* lam, const int* kkeep, int n,
-                               int kmax, void* L, DType tl, hipStream_t st) {
+                               int kmax, void* L, DType tl, int batch, int64_t bs, hipStream_t st) {
   const int64_t tot = (int64_t)kmax * n;
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_form_l_nside, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, V, lam,
-                     kkeep, n, kmax, L, (int)tl);
+  if (tot == 0 || batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_form_l_nside, dim3((unsigned)((tot + 255) / 256), batch), dim3(256), 0, st,
+                     V, lam, kkeep, n, kmax, L, (int)tl, bs);
   return hipGetLastError();
 }
 

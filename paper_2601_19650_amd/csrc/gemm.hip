@@ -55,8 +55,9 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
   const int m0 = blockIdx.y * BM;
   const int n0 = blockIdx.x * BN;
   const int M = g.M, N = g.N, K = g.K;
-  const CA* __restrict__ A = reinterpret_cast<const CA*>(g.A);
-  const CB* __restrict__ B = reinterpret_cast<const CB*>(g.B);
+  const int bz = blockIdx.z;
+  const CA* __restrict__ A = reinterpret_cast<const CA*>(inst_ptr(g.A, g.bsA, bz));
+  const CB* __restrict__ B = reinterpret_cast<const CB*>(inst_ptr(g.B, g.bsB, bz));
   const ACC sa = g.conjA ? ACC(-1) : ACC(1);
   const ACC sb = g.conjB ? ACC(-1) : ACC(1);
 
@@ -125,9 +126,9 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
   }
 
   double alpha = g.alpha;
-  if (g.alpha_dev) alpha *= g.alpha_dev[0];
-  if (g.alpha_dev2) alpha *= g.alpha_dev2[0];
-  CC* __restrict__ C = reinterpret_cast<CC*>(g.C);
+  if (g.alpha_dev) alpha *= inst_ptr(g.alpha_dev, g.bsAlpha, bz)[0];
+  if (g.alpha_dev2) alpha *= inst_ptr(g.alpha_dev2, g.bsAlpha2, bz)[0];
+  CC* __restrict__ C = reinterpret_cast<CC*>(inst_ptr(g.C, g.bsC, bz));
 #pragma unroll
   for (int i = 0; i < MB; ++i)
 #pragma unroll
@@ -153,12 +154,12 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
 
 template <typename TA, typename TB, typename TC, typename ACC>
 static hipError_t launch_t(const GemmArgs& a, int tile, hipStream_t s) {
-  if (a.M <= 0 || a.N <= 0) return hipSuccess;
+  if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
   if (tile == 1) {
-    dim3 grid((a.N + 63) / 64, (a.M + 63) / 64);
+    dim3 grid((a.N + 63) / 64, (a.M + 63) / 64, a.batch);
     hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
   } else {
-    dim3 grid((a.N + 31) / 32, (a.M + 31) / 32);
+    dim3 grid((a.N + 31) / 32, (a.M + 31) / 32, a.batch);
     hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 32, 32>), grid, dim3(256), 0, s, a);
   }
   return hipGetLastError();

@@ -37,6 +37,7 @@ extern "C" int cbc_test_gemm(int M, int N, int K, const void* A, int a_c128, int
     g.conjA = conjA; g.conjB = conjB;
     g.a_kfast = !transA; g.b_kfast = transB;
     g.alpha_dev = nullptr; g.alpha_dev2 = nullptr; g.alpha = 1.0;
+    g.batch = 1; g.bsA = g.bsB = g.bsC = g.bsAlpha = g.bsAlpha2 = 0;
     if (launch_gemm(g, a_c128 ? DT_C128 : DT_C64, b_c128 ? DT_C128 : DT_C64,
                     c_c128 ? DT_C128 : DT_C64, acc_fp64 ? DT_C128 : DT_C64, tile, st) != hipSuccess)
       rc = CBC_EHIP;
@@ -57,6 +58,8 @@ extern "C" int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void*
   a.G = (double2*)G; a.s = s; a.kmax = kmax; a.tol = tol; a.U = (double2*)U;
   a.lam = (double*)lam; a.kkeep = (int*)kkeep; a.inv_sqrt_l0 = (double*)inv_sqrt_l0; a.work = w;
   a.tstamp = (long long*)tstamp;
+  a.batch = 1;
+  a.bs = 0;
   int rc = CBC_OK;
   if (launch_eig(a, st) != hipSuccess) rc = CBC_EHIP;
   else if (hipStreamSynchronize(st) != hipSuccess) rc = CBC_EHIP;
@@ -72,6 +75,8 @@ extern "C" int cbc_test_chol_inv(void* G, int k, double shift_rel, double drop_r
   a.G = (double2*)G; a.k = k; a.shift_rel = shift_rel; a.drop_rel = drop_rel;
   a.Cinv = (double2*)Cinv; a.log_scale = nullptr; a.scale = nullptr; a.ndrop = (int*)ndrop;
   a.tstamp = (long long*)tstamp;
+  a.batch = 1;
+  a.bs = 0;
   if (launch_chol_inv(a, st) != hipSuccess) return CBC_EHIP;
   if (hipStreamSynchronize(st) != hipSuccess) return CBC_EHIP;
   return CBC_OK;

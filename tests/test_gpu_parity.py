@@ -114,3 +114,30 @@ def test_graph_replay_matches_eager(lib, prec):
     if prec == "fp64":
         assert tn.rel_error(p.parent, outs[-1], ref) <= FP64_BAR
     assert sum(c.stats.ms[k] for k in range(6)) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("maker", [
+    lambda s: config_problem("C2", n=20, seed=s),
+    lambda s: random_problem(kary_parent(13, 3), 2, 6, 3, 5, seed=s),
+])
+def test_batched_matches_single(lib, maker, prec):
+    """A batch of independent instances of one shape in one launch sequence equals the instances
+    run one by one, and each matches the oracle."""
+    probs = [maker(100 + b) for b in range(3)]
+    p0 = probs[0]
+    ctx = lib.Context()
+    tree = lib.Tree.of(p0)
+    st, so = lib.pack_batch([p.state for p in probs], "cuda")
+    op, oo = lib.pack_batch([p.op for p in probs], "cuda")
+    cb = lib.Compressor(ctx, tree, p0.max_bond, prec, batch=len(probs))
+    cb.run(op, oo, st, so)
+    for b, p in enumerate(probs):
+        single, _ = lib.compress(p, precision=prec, ctx=ctx)
+        got = cb.unpack(b)
+        assert tn.rel_error(p.parent, got, single) <= 1e-13
+        ref = cbc_tree(p.parent, p.state, p.op, p.max_bond)
+        if prec == "fp64":
+            assert tn.rel_error(p.parent, got, ref) <= FP64_BAR
+        else:
+            assert 1.0 - tn.fidelity(p.parent, got, ref) <= MIXED_BAR
