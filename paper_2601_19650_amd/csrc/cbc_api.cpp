@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -300,14 +301,15 @@ struct Builder {
     op.adev2 = adev2;
     op.tile = ((int64_t)op.M * op.N >= (int64_t)64 * 64 * 96) ? 1 : 0;
     const double f = 8.0 * (double)op.M * op.N * op.K;
-    op.cls = bucket == 0 ? CBC_K_CONTRACT : bucket == 1 ? CBC_K_GRAM : CBC_K_QRMUL;
-    // a Hermitian Gram counts half its complex MACs as algorithmic work
-    op.flops = bucket == 1 ? 0.5 * f : f;
+    op.cls = bucket == 0 ? CBC_K_CONTRACT : bucket == 1 ? CBC_K_GRAM : bucket == 2 ? CBC_K_QRMUL
+                                                                              : CBC_K_OTHER;
+    // a Hermitian Gram counts half its complex MACs as algorithmic work; layout copies count none
+    op.flops = bucket == 1 ? 0.5 * f : bucket == 3 ? 0.0 : f;
     op.bytes = (double)esz(op.ta) * op.M * op.K + (double)esz(op.tb) * op.K * op.N +
                (double)esz(tc) * op.M * op.N;
     if (bucket == 0) P.cflops += f;
     else if (bucket == 1) P.gflops += 0.5 * f;
-    else P.gflops += f;
+    else if (bucket == 2) P.gflops += f;
     P.ops.push_back(op);
     Ten r;
     r.ref = Cref;
@@ -429,6 +431,95 @@ struct Builder {
       P.ops.push_back(f);
     }
     return L;
+  }
+
+  // Top-kmax eigenvectors of a Hermitian FP64 Gram G (s x s, row-major): U (s x kmax) with legs
+  // [row legs..., nl] (persistent if asked).
+  Ten eig_op(const TRef& G, int s, int kmax, const std::vector<int>& rowlegs, int nl, bool persistent,
+             TRef* lam_out = nullptr, TRef* kk_out = nullptr) {
+    std::vector<int> ul = rowlegs;
+    ul.push_back(nl);
+    Ten U = alloc(ul, DT_C128, persistent);
+    TRef lam = scr(sizeof(double) * kmax, DT_C128);
+    TRef kk = scr(256, DT_C128);
+    TRef invs = scr(256, DT_C128);
+    TRef work = scr(sizeof(double) * eig_work_doubles(s, kmax), DT_C128);
+    Op e;
+    e.kind = K_EIG;
+    e.G = G;
+    e.s = s;
+    e.kmax = kmax;
+    e.U = U.ref;
+    e.lam = lam;
+    e.kkeep = kk;
+    e.invs = invs;
+    e.work = work;
+    e.cls = CBC_K_EIG;
+    e.flops = 16.0 / 3.0 * (double)s * s * s + 8.0 * (double)s * s * kmax;
+    e.bytes = 16.0 * (double)s * s + 16.0 * (double)s * kmax;
+    P.ops.push_back(e);
+    P.n_eig++;
+    P.max_eig = std::max(P.max_eig, s);
+    if (lam_out) *lam_out = lam;
+    if (kk_out) *kk_out = kk;
+    return U;
+  }
+
+  static std::vector<int> without(const std::vector<int>& v, int x) {
+    std::vector<int> r;
+    for (int l : v)
+      if (l != x) r.push_back(l);
+    return r;
+  }
+  static std::vector<int> replaced(const std::vector<int>& v, int x, int y) {
+    std::vector<int> r = v;
+    for (int& l : r)
+      if (l == x) l = y;
+    return r;
+  }
+
+  // Orthonormal columns: X with legs (rows..., col somewhere) -> Q with legs (rows..., qcol) spanning
+  // the column space of X over `col` (three Cholesky-QR passes, the first shifted; complex128).
+  Ten cholqr_cols(const Ten& X, int col, int qcol, bool persistent) {
+    const std::vector<int> rows = without(X.legs, col);
+    const int64_t k = legdim[col];
+    const int64_t mrows = elems(rows);
+    const double u = 1.1102230246251565e-16;
+    Ten cur = X;
+    int cur_col = col;
+    for (int pass = 0; pass < 3; ++pass) {
+      const int c2 = leg(k);
+      Ten curb{cur.ref, replaced(cur.legs, cur_col, c2)};
+      Ten G = alloc({cur_col, c2}, DT_C128, false);
+      contract(cur, true, curb, false, {cur_col, c2}, G.ref, DT_C128, DT_C128, 1);
+      Ten Ci = alloc({qcol, cur_col}, DT_C128, false);
+      Op c;
+      c.kind = K_CHOL;
+      c.G = G.ref;
+      c.s = (int)k;
+      c.shift_rel = pass == 0 ? 11.0 * ((double)mrows * k + (double)k * (k + 1)) * u : 0.0;
+      c.drop_rel = pass == 0 ? 0.0 : 1e-13;
+      c.Cinv = Ci.ref;
+      TRef nd;
+      nd.src = S_WS;
+      nd.off = P.ndrop_off;
+      c.ndrop = nd;
+      c.cls = CBC_K_CHOL;
+      c.flops = 8.0 / 3.0 * (double)k * k * k;
+      c.bytes = 32.0 * (double)k * k;
+      P.ops.push_back(c);
+      std::vector<int> qo = rows;
+      qo.push_back(qcol);
+      Ten Q = alloc(qo, DT_C128, persistent && pass == 2);
+      contract(cur, false, Ci, true, qo, Q.ref, DT_C128, DT_C128, 2);
+      if (pass == 2) return Q;
+      const int nc = leg(k);
+      std::vector<int> nl = rows;
+      nl.push_back(nc);
+      cur = Ten{Q.ref, nl};
+      cur_col = nc;
+    }
+    return cur;
   }
 
   // Q-factor of S [k, rest...] on its first leg: returns Q [k_new, rest...] (scratch, complex128)
@@ -735,6 +826,230 @@ cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc
 }
 
 // ------------------------------------------------------------------------------------------------
+// the naive method of Sec. III C ("direct"): exact product, canonical form, truncated-SVD sweep
+
+void plan_prologue(Builder& B, Plan& P, cbc_precision prec, int n) {
+  P.logs_off = (int64_t)B.persist;
+  B.persist += Builder::al(sizeof(double) * n);
+  P.ndrop_off = (int64_t)B.persist;
+  B.persist += 256;
+  Op z;
+  z.kind = K_ZERO;
+  z.dst.src = S_WS;
+  z.dst.off = P.logs_off;
+  z.count = (int64_t)(P.ndrop_off + 256 - P.logs_off);
+  P.ops.push_back(z);
+  if (prec == CBC_PREC_MIXED) {
+    P.state_conv_off = (int64_t)B.persist;
+    B.persist += Builder::al(8 * (size_t)P.state_elems);
+    P.op_conv_off = (int64_t)B.persist;
+    B.persist += Builder::al(8 * (size_t)P.op_elems);
+    Op c1;
+    c1.kind = K_CONVERT;
+    c1.src.src = S_STATE;
+    c1.src.off = -1;
+    c1.ts = DT_C128;
+    c1.dst.src = S_WS;
+    c1.dst.off = P.state_conv_off;
+    c1.td = DT_C64;
+    c1.count = P.state_elems;
+    P.ops.push_back(c1);
+    Op c2 = c1;
+    c2.src.src = S_OP;
+    c2.dst.off = P.op_conv_off;
+    c2.count = P.op_elems;
+    P.ops.push_back(c2);
+  }
+}
+
+cbc_status build_plan_naive(Plan& P, const Problem& pr, int max_bond, bool tol_on,
+                            cbc_precision prec) {
+  Builder B(P, pr, max_bond, tol_on, prec);
+  const int n = pr.n;
+  B.sig.resize(n);
+  B.sigp.resize(n);
+  B.ealpha.assign(n, -1);
+  B.ebeta.assign(n, -1);
+  for (int i = 0; i < n; ++i) {
+    B.sig[i] = B.leg(pr.phys[i]);
+    B.sigp[i] = B.leg(pr.phys[i]);
+    if (pr.parent[i] >= 0) {
+      B.ealpha[i] = B.leg(pr.chi[i]);
+      B.ebeta[i] = B.leg(pr.dop[i]);
+    }
+  }
+  B.rootA = B.leg(1);
+  B.rootB = B.leg(1);
+  plan_prologue(B, P, prec, n);
+  const DType ct = B.ct;
+
+  // fused product bonds, one leg per edge (the root's trivial leg included)
+  std::vector<int> edge(n);
+  for (int i = 0; i < n; ++i)
+    edge[i] = B.leg(pr.parent[i] >= 0 ? (int64_t)pr.chi[i] * pr.dop[i] : 1);
+  // 1. product node tensors P_i[sigma', (a_p b_p), (a_c b_c)...] = sum_sigma W T
+  std::vector<Ten> node(n);
+  for (int i = 0; i < n; ++i) {
+    B.reset_scratch();
+    const auto sa = B.slot_alpha(i), sb = B.slot_beta(i);
+    Ten T{B.node_ref(S_STATE, i), {B.sig[i]}};
+    for (int l : sa) T.legs.push_back(l);
+    Ten W{B.node_ref(S_OP, i), {B.sigp[i], B.sig[i]}};
+    for (int l : sb) W.legs.push_back(l);
+    std::vector<int> out{B.sigp[i]};
+    for (size_t j = 0; j < sa.size(); ++j) {
+      out.push_back(sa[j]);
+      out.push_back(sb[j]);
+    }
+    Ten X = B.alloc(out, ct, true);
+    B.contract(T, false, W, false, out, X.ref, ct, B.cacc, 0);
+    std::vector<int> fused{B.sigp[i], edge[i]};
+    for (int c : pr.ch[i]) fused.push_back(edge[c]);
+    node[i] = Ten{X.ref, fused};
+  }
+  // Economy QR of node `ch` on its bond `col` to node `par`, R absorbed by `par`; returns the new bond
+  // leg (dimension min(rest, dim col) as in an economy QR).
+  TRef one = B.wsp(256, DT_C128);
+  {
+    Op f;
+    f.kind = K_IDENT;
+    f.dst = one;
+    f.td = DT_C128;
+    f.a = 1;
+    f.b = 1;
+    P.ops.push_back(f);
+  }
+  auto qr_toward = [&](int ch, int par, int col) -> int {
+    const std::vector<int> rows = Builder::without(node[ch].legs, col);
+    const int64_t rest = B.elems(rows), pd = B.legdim[col];
+    if (rest <= pd) {
+      // Q = identity on the joined leg, R = the node itself: the parent absorbs the node and the
+      // node's remaining legs become the (fused) bond
+      const int nl = B.leg(rest);
+      std::vector<int> il = rows;
+      il.push_back(nl);
+      Ten I = B.alloc(il, DT_C128, true);
+      Op f;
+      f.kind = K_IDENT;
+      f.dst = I.ref;
+      f.td = DT_C128;
+      f.a = (int)rest;
+      f.b = (int)rest;
+      P.ops.push_back(f);
+      std::vector<int> pl, pv;
+      for (int l : node[par].legs) {
+        if (l == col) {
+          pl.insert(pl.end(), rows.begin(), rows.end());
+          pv.push_back(nl);
+        } else {
+          pl.push_back(l);
+          pv.push_back(l);
+        }
+      }
+      Ten Pn = B.alloc(pl, ct, true);
+      B.contract(node[par], false, node[ch], false, pl, Pn.ref, ct, B.cacc, 0);
+      node[par] = Ten{Pn.ref, pv};
+      node[ch] = Ten{I.ref, il};
+      return nl;
+    }
+    const int nl = B.leg(pd);
+    Ten Q = B.cholqr_cols(node[ch], col, nl, true);
+    Ten R = B.alloc({nl, col}, DT_C128, false);
+    B.contract(Q, true, node[ch], false, {nl, col}, R.ref, DT_C128, DT_C128, 0);
+    const auto pl = Builder::replaced(node[par].legs, col, nl);
+    Ten Pn = B.alloc(pl, ct, true);
+    B.contract(node[par], false, R, false, pl, Pn.ref, ct, B.cacc, 0);
+    node[par] = Pn;
+    node[ch] = Q;
+    return nl;
+  };
+  // 2. canonical form toward the root
+  for (int i : pr.post) {
+    if (i == pr.root) continue;
+    B.reset_scratch();
+    edge[i] = qr_toward(i, pr.parent[i], edge[i]);
+  }
+  // 3. truncated-SVD sweep, depth first from the root, moving the orthogonality centre
+  std::function<void(int)> visit = [&](int i) {
+    for (int c : pr.ch[i]) {
+      B.reset_scratch();
+      const Ten M = node[i];
+      const int col = edge[c];
+      const std::vector<int> rows = Builder::without(M.legs, col);
+      const int64_t m = B.elems(rows), nn = B.legdim[col];
+      const int kmax = (int)std::min<int64_t>({(int64_t)max_bond, m, nn});
+      int K = B.leg(kmax);
+      Ten U;
+      if (m <= nn) {
+        std::vector<int> rows2;
+        for (int l : rows) rows2.push_back(B.leg(B.legdim[l]));
+        Ten M2{M.ref, M.legs};
+        for (size_t j = 0; j < rows.size(); ++j) M2.legs = Builder::replaced(M2.legs, rows[j], rows2[j]);
+        std::vector<int> gl = rows;
+        gl.insert(gl.end(), rows2.begin(), rows2.end());
+        Ten G = B.alloc(gl, DT_C128, false);
+        B.contract(M, false, M2, true, gl, G.ref, DT_C128, DT_C128, 1);
+        U = B.eig_op(G.ref, (int)m, kmax, rows, K, true);
+      } else {
+        const int col2 = B.leg(nn);
+        Ten M2{M.ref, Builder::replaced(M.legs, col, col2)};
+        Ten G = B.alloc({col, col2}, DT_C128, false);
+        B.contract(M, true, M2, false, {col, col2}, G.ref, DT_C128, DT_C128, 1);
+        Ten V = B.eig_op(G.ref, (int)nn, kmax, {col}, K, false);
+        std::vector<int> wl = rows;
+        wl.push_back(K);
+        Ten Wt = B.alloc(wl, DT_C128, false);
+        B.contract(M, false, V, false, wl, Wt.ref, DT_C128, DT_C128, 0);
+        const int K2 = B.leg(kmax);
+        U = B.cholqr_cols(Wt, K, K2, true);
+        K = K2;
+      }
+      // the child absorbs U^H M on the truncated bond
+      Ten Y = B.alloc({K, col}, DT_C128, false);
+      B.contract(U, true, M, false, {K, col}, Y.ref, DT_C128, DT_C128, 0);
+      const auto cl = Builder::replaced(node[c].legs, col, K);
+      Ten Cn = B.alloc(cl, ct, true);
+      B.contract(Y, false, node[c], false, cl, Cn.ref, ct, B.cacc, 0);
+      node[i] = U;
+      node[c] = Cn;
+      edge[c] = K;
+      visit(c);
+      // move the centre back: child = Q R on its parent bond, R absorbed by node i
+      B.reset_scratch();
+      edge[c] = qr_toward(c, i, edge[c]);
+    }
+  };
+  visit(pr.root);
+  // 4. outputs in the (sigma', parent, children...) layout, complex128
+  P.out_off.assign(n + 1, 0);
+  P.out_bond.assign(n, 1);
+  for (int i = 0; i < n; ++i) {
+    int64_t e = pr.phys[i] * B.legdim[edge[i]];
+    for (int c : pr.ch[i]) e *= B.legdim[edge[c]];
+    P.out_off[i + 1] = P.out_off[i] + e;
+    P.out_bond[i] = (int)B.legdim[edge[i]];
+  }
+  for (int i = 0; i < n; ++i) {
+    B.reset_scratch();
+    std::vector<int> ol{B.sigp[i], edge[i]};
+    for (int c : pr.ch[i]) ol.push_back(edge[c]);
+    TRef dst;
+    dst.src = S_OUT;
+    dst.off = i;
+    dst.dt = DT_C128;
+    B.contract(node[i], false, Ten{one, {}}, false, ol, dst, DT_C128, DT_C128, 3);
+  }
+  P.persist_bytes = B.persist;
+  P.scratch_bytes = B.scratch_max;
+  for (const Op& op : P.ops) {
+    P.launches[op.cls] += 1;
+    P.flops[op.cls] += op.flops;
+    P.bytes[op.cls] += op.bytes;
+  }
+  return CBC_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
 // context and execution
 
 struct Call {
@@ -929,8 +1244,8 @@ cbc_status get_plan(cbc_ctx* ctx, const Problem& pr, int max_bond, bool tol_on, 
   auto P = std::make_unique<Plan>();
   P->state_elems = state_span;
   P->op_elems = op_span;
-  if (method != 0) return CBC_EUNSUP;
-  cbc_status s = build_plan(*P, pr, max_bond, tol_on, prec);
+  cbc_status s = method == 0 ? build_plan(*P, pr, max_bond, tol_on, prec)
+                              : build_plan_naive(*P, pr, max_bond, tol_on, prec);
   if (s != CBC_OK) return s;
   *out = P.get();
   ctx->plans[key] = std::move(P);
@@ -1171,9 +1486,8 @@ cbc_status cbc_apply_naive(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tens
                            const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
                            void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
                            cbc_stats* stats) {
-  (void)ctx; (void)ttno; (void)ttns; (void)tree; (void)max_bond; (void)tol; (void)prec;
-  (void)workspace; (void)workspace_bytes; (void)out; (void)stream; (void)stats;
-  return CBC_EUNSUP;
+  return apply_impl(ctx, ttno, ttns, tree, max_bond, tol, prec, workspace, workspace_bytes, out,
+                    stream, stats, 1);
 }
 
 }  // extern "C"

@@ -10,8 +10,9 @@
 //      T = Q^H G Q (reflectors H_j = I - tau_j v_j v_j^H, real sub-diagonal). For s <= EIG_LDS_MAX the
 //      packed lower triangle lives in LDS; larger matrices are reduced in place in global memory (L2
 //      resident). The Hermitian matrix-vector product is done by groups of 8 lanes per row, its
-//      reductions use DPP lane moves, and the dot product w^H v is folded into it, so a step costs
-//      three workgroup barriers. This is the only sequential part.
+//      reductions use DPP lane moves, and the dot product w^H v is folded into it (per-wave partials
+//      added in a fixed order, so results are bitwise reproducible), so a step costs three
+//      workgroup barriers. This is the only sequential part.
 //   2. k_eigvals, one wave per eigenvalue over many workgroups: the top-kmax eigenvalues of T by
 //      multisection on Sturm counts (64 points of the current interval per round).
 //   3. k_eigvecs, one wave per eigenpair over many workgroups: the eigenvector of T by a twisted
@@ -136,6 +137,7 @@ __device__ int sturm_count(const double* dd, const double* ee2, int s, double x,
 struct TriShared {
   double2 tau;
   double dotr, doti;
+  double2 part[EIG_THREADS / 64];   // per-wave partial sums of w^H v, added in a fixed order
 };
 
 // Householder vector of column j from x = A[j+1.., j]; wave 0. Returns the scaling 1/(alpha - beta)
@@ -256,13 +258,15 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     }
     dr_acc = wave_sum(dr_acc);
     di_acc = wave_sum(di_acc);
-    if (lane == 0) {
-      atomicAdd(&sh.dotr, dr_acc);
-      atomicAdd(&sh.doti, di_acc);
-    }
+    if (lane == 0) sh.part[wave] = make_double2(dr_acc, di_acc);
     __syncthreads();
     if (stamp) { const long long t1 = wall_clock64(); tB += t1 - t0; t0 = t1; }
-    const double2 q = cmul(t, make_double2(sh.dotr, sh.doti));
+    double dsum_r = 0.0, dsum_i = 0.0;
+    for (int w = 0; w < (nthr >> 6); ++w) {
+      dsum_r += sh.part[w].x;
+      dsum_i += sh.part[w].y;
+    }
+    const double2 q = cmul(t, make_double2(dsum_r, dsum_i));
     const double2 a2 = make_double2(-0.5 * q.x, -0.5 * q.y);
     // A_sub -= v w'^H + w' v^H with w' = w + a2 v (lower triangle in LDS, full rows in global)
     for (int r = grp; r < nj; r += ngrp) {

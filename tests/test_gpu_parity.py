@@ -141,3 +141,30 @@ def test_batched_matches_single(lib, maker, prec):
             assert tn.rel_error(p.parent, got, ref) <= FP64_BAR
         else:
             assert 1.0 - tn.fidelity(p.parent, got, ref) <= MIXED_BAR
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("maker", [
+    lambda: config_problem("C1"),
+    lambda: config_problem("C2", n=16),
+    lambda: random_problem(kary_parent(7, 2), 2, 8, 4, 4, seed=3, name="bin7"),
+    lambda: random_problem(kary_parent(13, 3), 2, 6, 3, 5, seed=4, name="ter13"),
+])
+def test_naive_baseline_parity(lib, maker, prec):
+    """cbc_apply_naive (contract, canonicalise, truncated-SVD sweep) against the oracle's naive
+    method; in the exact case (C1) both equal O|psi>."""
+    p = maker()
+    print(f"naive {p.name} prec={prec}", flush=True)
+    ref = tn.naive_compress(p.parent, p.op, p.state, p.max_bond)
+    out, comp = lib.compress(p, precision=prec, method="naive")
+    if prec == "fp64":
+        assert tn.rel_error(p.parent, out, ref) <= FP64_BAR
+    else:
+        assert 1.0 - tn.fidelity(p.parent, out, ref) <= MIXED_BAR
+    # the paper finds CBC slightly less accurate than the direct method at a given bond dimension
+    phi = tn.product_ttn(p.parent, p.op, p.state)
+    cbc_out, _ = lib.compress(p, precision="fp64")
+    e_cbc = tn.rel_error(p.parent, cbc_out, phi)
+    e_naive = tn.rel_error(p.parent, out, phi)
+    if prec == "fp64" and e_naive > 1e-8:
+        assert 0.5 <= e_cbc / e_naive <= 5.0

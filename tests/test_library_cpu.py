@@ -130,3 +130,17 @@ def test_planned_bonds_match_oracle(maker):
     assert bonds == [t.shape[1] for t in ref]
     for prec in (0, 1):
         assert _query(tree, p.max_bond, prec)[0] == 0
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: config_problem("C1"), lambda: config_problem("C2", n=12),
+    lambda: random_problem(kary_parent(7, 2), 2, 8, 4, 4, seed=3),
+    lambda: random_problem(kary_parent(13, 3), 2, 6, 3, 5, seed=4)])
+def test_naive_plan_sizes_match_oracle(maker):
+    """The naive baseline's planned output node sizes equal those of the oracle's naive method."""
+    from oracle import tn
+    p = maker()
+    rc, ws, off = _query(cbc.Tree.of(p), p.max_bond, 0, 1)
+    assert rc == 0 and ws > 0
+    ref = tn.naive_compress(p.parent, p.op, p.state, p.max_bond)
+    assert [int(s) for s in np.diff(off)] == [t.size for t in ref]
