@@ -114,6 +114,30 @@ def batched_run(args, cbc, p, stream):
             "workspace_gb": comp.ws_bytes / 1e9}
 
 
+def uneven_run(count, stream_count=8):
+    """Throughput of an uneven batch: `count` instances drawn as tensor trains, binary and ternary
+    trees with N in [16, 64], d in {2, 4}, D in [4, 12], max_bond = chi, mixed precision, launched over
+    several streams. The bond range is reduced to chi in [16, 48] (ternary chi <= 16): with the full
+    [16, 128] draw single node steps of binary and ternary instances need intermediates of 1e9
+    elements."""
+    import torch
+    from paper_2601_19650_amd import cbc
+    from paper_2601_19650_amd.inputs import batch_problems
+    probs = batch_problems(count=count, seed=5, chi_range=(16, 48), ternary_chi_cap=16)
+    ub = cbc.UnevenBatch(probs, precision="mixed", nstreams=stream_count, device="cuda:0")
+    ub.run()                      # capture every instance's graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ub.run()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    print(f"[bench] uneven batch of {count}: {sec * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return {"instances": count, "value": count / sec, "unit": "compressions/s", "seconds": sec,
+            "contraction_tflops": ub.flops() / sec / 1e12, "streams": stream_count,
+            "recipe": "uneven draw (seed 5): MPS/binary/ternary, N 16-64, d 2|4, D 4-12, chi 16-48 "
+                      "(ternary <= 16), first instances of the sequence"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +148,8 @@ def main():
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
     ap.add_argument("--batch", type=int, default=64,
                     help="instances per launch sequence for the batched measurement (0: skip)")
+    ap.add_argument("--uneven", type=int, default=0,
+                    help="instances of the uneven batch workload to time (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1",
@@ -204,6 +230,8 @@ def main():
         line["speedup_mixed_vs_fp64"] = res["fp64"]["sec"] / res["mixed"]["sec"]
     if args.batch > 1:
         line["batched"] = batched_run(args, cbc, p, stream)
+    if args.uneven > 0:
+        line["uneven_batch"] = uneven_run(args.uneven)
     if not args.no_cpu_baseline:
         cb, errs = cpu_baseline(p, outputs)
         line["cpu_baseline"] = cb

@@ -37,8 +37,12 @@
  * caller memory. A context owns only its plan cache (device offset tables, captured graphs), which is
  * released by cbc_destroy. One context per host thread; a context must not be used concurrently.
  *
- * Streams: calls are stream-ordered on the given hipStream_t (passed as void*; NULL = null stream).
- * cbc_apply synchronises the stream once at the end to return the output bond dimensions.
+ * Streams: calls are stream-ordered and asynchronous on the given hipStream_t (passed as void*;
+ * NULL = null stream): every shape is fixed by max_bond before device work, so the output bond
+ * dimensions are returned at once and the output tensors are ready when the stream reaches the end
+ * of the call. Only the profiling mode (cbc_stats.profile) synchronises the stream. The first call
+ * with a given set of buffers on a non-null stream captures the launch sequence into a hipGraph;
+ * later calls with the same buffers replay it.
  *
  * Errors: every entry point returns a cbc_status; nothing aborts or throws across the ABI. All
  * argument validation happens on the host before any device work is queued.

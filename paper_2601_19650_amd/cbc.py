@@ -218,7 +218,10 @@ class Compressor:
         return self.out, self.bond
 
     def unpack(self, instance=0):
-        """Output node tensors as numpy complex128 arrays (sigma', parent bond, child bonds...)."""
+        """Output node tensors as numpy complex128 arrays (sigma', parent bond, child bonds...).
+        Synchronises the device (the library's calls are asynchronous)."""
+        import torch
+        torch.cuda.synchronize()
         total = int(self.out_off[-1])
         host = self.out[instance * total:(instance + 1) * total].cpu().numpy()
         res = []
@@ -228,6 +231,33 @@ class Compressor:
             a, b = int(self.out_off[i]), int(self.out_off[i]) + int(np.prod(shape))
             res.append(host[a:b].reshape(shape))
         return res
+
+
+class UnevenBatch:
+    """Many instances of different shapes: one Compressor (plan, workspace, captured graph) per
+    instance, launched round-robin over `nstreams` side streams so that instances overlap on the
+    GPU. Inputs are packed once and stay resident."""
+
+    def __init__(self, problems, precision="mixed", nstreams=8, device="cuda"):
+        import torch
+        self.ctx = Context()
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(nstreams)]
+        self.items = []
+        for p in problems:
+            tree = Tree.of(p)
+            st, so = pack(p.state, device)
+            op, oo = pack(p.op, device)
+            comp = Compressor(self.ctx, tree, p.max_bond, precision, device=device)
+            self.items.append((comp, (op, oo, st, so, p.tol)))
+
+    def run(self):
+        """Launch every instance (asynchronous); call torch.cuda.synchronize() to wait."""
+        for k, (comp, args) in enumerate(self.items):
+            s = self.streams[k % len(self.streams)]
+            comp.run(*args, stream=s.cuda_stream)
+
+    def flops(self):
+        return sum(c.stats.flops[0] for c, _ in self.items)
 
 
 def compress(problem, precision="fp64", method="cbc", tol=None, ctx=None, device="cuda"):

@@ -33,6 +33,7 @@ struct GemmArgs {
   // batch: instance z (blockIdx.z) uses every pointer advanced by z times its byte stride
   int batch;
   int64_t bsA, bsB, bsC, bsAlpha, bsAlpha2;
+  int mbase;   // first row of this launch (the launcher splits very tall problems into row chunks)
 };
 // pointer of instance b for a per-instance byte stride
 template <typename T>

@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int m0 = blockIdx.y * BM;
+  const int m0 = g.mbase + blockIdx.y * BM;
   const int n0 = blockIdx.x * BN;
   const int M = g.M, N = g.N, K = g.K;
   const int bz = blockIdx.z;
@@ -153,16 +153,25 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
 }
 
 template <typename TA, typename TB, typename TC, typename ACC>
-static hipError_t launch_t(const GemmArgs& a, int tile, hipStream_t s) {
-  if (a.M <= 0 || a.N <= 0 || a.batch <= 0) return hipSuccess;
-  if (tile == 1) {
-    dim3 grid((a.N + 63) / 64, (a.M + 63) / 64, a.batch);
-    hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
-  } else {
-    dim3 grid((a.N + 31) / 32, (a.M + 31) / 32, a.batch);
-    hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 32, 32>), grid, dim3(256), 0, s, a);
+static hipError_t launch_t(const GemmArgs& a0, int tile, hipStream_t s) {
+  if (a0.M <= 0 || a0.N <= 0 || a0.batch <= 0) return hipSuccess;
+  const int BMt = tile == 1 ? 64 : 32;
+  const int max_rows = 65535 * BMt;   // grid y limit per launch
+  for (int mb = 0; mb < a0.M; mb += max_rows) {
+    GemmArgs a = a0;
+    a.mbase = mb;
+    const int rows = a0.M - mb < max_rows ? a0.M - mb : max_rows;
+    if (tile == 1) {
+      dim3 grid((a.N + 63) / 64, (rows + 63) / 64, a.batch);
+      hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
+    } else {
+      dim3 grid((a.N + 31) / 32, (rows + 31) / 32, a.batch);
+      hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 32, 32>), grid, dim3(256), 0, s, a);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 template <typename ACC>

@@ -38,6 +38,7 @@ extern "C" int cbc_test_gemm(int M, int N, int K, const void* A, int a_c128, int
     g.a_kfast = !transA; g.b_kfast = transB;
     g.alpha_dev = nullptr; g.alpha_dev2 = nullptr; g.alpha = 1.0;
     g.batch = 1; g.bsA = g.bsB = g.bsC = g.bsAlpha = g.bsAlpha2 = 0;
+    g.mbase = 0;
     if (launch_gemm(g, a_c128 ? DT_C128 : DT_C64, b_c128 ? DT_C128 : DT_C64,
                     c_c128 ? DT_C128 : DT_C64, acc_fp64 ? DT_C128 : DT_C64, tile, st) != hipSuccess)
       rc = CBC_EHIP;

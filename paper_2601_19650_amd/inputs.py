@@ -221,12 +221,13 @@ def config_problem(name, **over):
                           tol=c.get("tol", 0.0), dist=c.get("dist", "gauss"), name=name)
 
 
-def batch_problems(count=256, seed=5, ternary_chi_cap=32, n_range=(16, 64)):
+def batch_problems(count=256, seed=5, ternary_chi_cap=32, n_range=(16, 64), chi_range=(16, 128)):
     """The uneven batch workload: per instance a tensor train, binary or ternary tree with
-    N in n_range, d in {2,4}, chi in [16,128], D in [4,12], max_bond = chi.
+    N in n_range, d in {2,4}, chi in chi_range, D in [4,12], max_bond = chi.
 
     Ternary trees have their chi clamped to ``ternary_chi_cap`` (their nodes carry four virtual
-    legs, so an unclamped draw is dominated by a handful of ternary instances).
+    legs, so an unclamped draw is dominated by a handful of ternary instances). The same sequence of
+    random draws is used whatever the ranges, so instance j keeps its kind, N, d and D.
     """
     seeds = np.random.SeedSequence(seed).spawn(count)
     out = []
@@ -235,7 +236,7 @@ def batch_problems(count=256, seed=5, ternary_chi_cap=32, n_range=(16, 64)):
         kind = ["mps", "binary", "ternary"][int(rng.integers(0, 3))]
         n = int(rng.integers(n_range[0], n_range[1] + 1))
         d = int([2, 4][int(rng.integers(0, 2))])
-        chi = int(rng.integers(16, 129))
+        chi = int(chi_range[0] + rng.integers(0, 113) * (chi_range[1] - chi_range[0]) // 112)
         D = int(rng.integers(4, 13))
         if kind == "ternary":
             chi = min(chi, ternary_chi_cap)

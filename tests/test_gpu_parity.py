@@ -168,3 +168,28 @@ def test_naive_baseline_parity(lib, maker, prec):
     e_naive = tn.rel_error(p.parent, out, phi)
     if prec == "fp64" and e_naive > 1e-8:
         assert 0.5 <= e_cbc / e_naive <= 5.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_uneven_batch(lib, prec):
+    """Instances of different kinds and shapes launched together over several streams (each with its
+    own captured graph); every instance matches the oracle."""
+    probs = [
+        random_problem(chain_parent(10), 4, 16, 4, 12, seed=1, name="mps10d4"),
+        random_problem(kary_parent(9, 2), 2, 12, 5, 10, seed=2, name="bin9"),
+        random_problem(kary_parent(10, 3), 2, 8, 4, 6, seed=3, name="ter10"),
+        random_problem(chain_parent(14), 2, 24, 6, 16, seed=4, name="mps14"),
+        random_problem(kary_parent(7, 2), 4, 10, 6, 8, seed=5, name="bin7d4"),
+        random_problem(chain_parent(6), 3, 9, 3, 5, seed=6, name="mps6d3"),
+    ]
+    ub = lib.UnevenBatch(probs, precision=prec, nstreams=3)
+    for _ in range(2):          # capture, then replay
+        ub.run()
+    torch.cuda.synchronize()
+    for (comp, _), p in zip(ub.items, probs):
+        got = comp.unpack()
+        ref = cbc_tree(p.parent, p.state, p.op, p.max_bond)
+        if prec == "fp64":
+            assert tn.rel_error(p.parent, got, ref) <= FP64_BAR, p.name
+        else:
+            assert 1.0 - tn.fidelity(p.parent, got, ref) <= MIXED_BAR, p.name
