@@ -31,6 +31,26 @@ WORKLOADS = {
 }
 
 
+def recorded_traffic(workload, precision, op):
+    """HBM bytes per launch of `op` from a committed counter summary (profiles/*_hbm_counters.md),
+    or None when there is none for this workload, or a kernel source changed since it was taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_hbm_counters.md"))):
+        text = open(path).read()
+        if "```json" not in text:
+            continue
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        if (rec.get("workload"), rec.get("precision"), rec.get("op")) != (workload, precision, op):
+            continue
+        for src, sha in rec.get("sources_sha256", {}).items():
+            with open(os.path.join(ROOT, src), "rb") as fh:
+                if hashlib.sha256(fh.read()).hexdigest() != sha:
+                    return None
+        return float(rec["hbm_bytes_per_launch"])
+    return None
+
+
 def timed_runs(comp, args_run, stream, steps, warmup):
     import torch
     with torch.cuda.stream(stream):
@@ -150,6 +170,9 @@ def main():
                     help="instances per launch sequence for the batched measurement (0: skip)")
     ap.add_argument("--uneven", type=int, default=0,
                     help="instances of the uneven batch workload to time (0: skip)")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (5 times) and exit; used to "
+                         "scale the HBM byte counters of a profiler run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1",
@@ -161,6 +184,16 @@ def main():
     from paper_2601_19650_amd.inputs import config_problem
 
     torch.cuda.set_device(0)
+    if args.copy_calibration_mb > 0:
+        n = args.copy_calibration_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4,
+                                               "launches": 5}}))
+        return
     p = config_problem(args.workload)
     tree = cbc.Tree.of(p)
     st, so = cbc.pack(p.state, "cuda:0")
@@ -217,7 +250,7 @@ def main():
         "contraction_tflops": contraction_flops / sec / 1e12,
         "roofline": {"bound": bound, "kernel": cls[kd], "achieved": achieved,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved * 1e12 / peak,
-                     "traffic": None, "avg_launch_ms": avg_ms,
+                     "traffic": recorded_traffic(args.workload, head, cls[kd]), "avg_launch_ms": avg_ms,
                      "flops_per_launch": flops_per_launch},
         "kernel_ms_per_step": {cls[k]: r["kms"][k] for k in range(cbc.NCLASS)},
         "kernels_per_step": r["n_kernels"],
