@@ -28,7 +28,96 @@ WORKLOADS = {
     "C2": "MPS N=64 d=2 chi=64 D=8 max_bond=64 (truncating), complex Gaussian",
     "C1": "MPS N=8 d=2 chi=8 D=4 max_bond=32 (exact)",
     "C3": "binary tree 31 nodes d=2 chi=32 D=6 max_bond=32",
+    "C4": "MPS N=128 d=4 chi=256 D=16 max_bond=256 (large bond), complex Gaussian",
 }
+
+
+def measure(cbc, p, precs, steps, warmup, stream):
+    """Time `steps` compressions of problem p per precision (after `warmup`), then the same number
+    with per-op HIP events for the kernel-class times. Returns per-precision results and outputs."""
+    import torch  # noqa: F401
+    tree = cbc.Tree.of(p)
+    st, so = cbc.pack(p.state, "cuda:0")
+    op, oo = cbc.pack(p.op, "cuda:0")
+    ctx = cbc.Context()
+    res, outputs = {}, {}
+    for prec in precs:
+        comp = cbc.Compressor(ctx, tree, p.max_bond, prec, device="cuda:0")
+        run_args = (op, oo, st, so, 0.0)
+        sec = timed_runs(comp, run_args, stream, steps, warmup)
+        replayed = int(comp.stats.graph_replayed)
+        outputs[prec] = comp.unpack()
+        kms = profiled_runs(comp, run_args, stream, max(2, min(steps, 10)))
+        st_d = comp.stats.as_dict()
+        res[prec] = dict(sec=sec, kms=kms, stats=st_d, replayed=replayed,
+                         n_kernels=int(comp.stats.n_kernels))
+        print(f"[bench] {p.name} {prec}: {sec * 1e3:.3f} ms/compression, kernels/call "
+              f"{comp.stats.n_kernels}, graph replay {replayed}", file=sys.stderr, flush=True)
+        del comp
+    return res, outputs
+
+
+def contraction_roofline(r, prec, cls):
+    """Contraction kernels (the MFMA GEMMs of the sweeps) against the MFMA peak of their type:
+    algorithmic flops per compression over their event-timed kernel time per compression."""
+    k = cls.index("contract")
+    flops = r["stats"]["contract"]["flops"]
+    ms = r["kms"][k]
+    peak = PEAK["fp32_mfma"] if prec == "mixed" else PEAK["fp64_mfma"]
+    achieved = flops / (ms * 1e-3) if ms > 0 else 0.0
+    return {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "kernel_ms_per_step": ms,
+            "launches_per_step": r["stats"]["contract"]["launches"],
+            "flops_per_step": flops}
+
+
+def large_run(cbc, stream, steps):
+    """The large-bond workload (MPS N=128, d=4, chi=256, D=16, max_bond=256): both precisions,
+    compressions/s, contraction throughput against the MFMA peaks, and the mixed result against the
+    FP64 result (both from the GPU; the oracle needs minutes here)."""
+    from paper_2601_19650_amd.inputs import config_problem
+    p = config_problem("C4")
+    res, outputs = measure(cbc, p, ["mixed", "fp64"], steps, 1, stream)
+    cls = cbc.CLASSES
+    out = {"workload": WORKLOADS["C4"], "steps": steps}
+    for prec in ("mixed", "fp64"):
+        r = res[prec]
+        out[prec] = {"value": 1.0 / r["sec"], "unit": "compressions/s", "ms_per_step": r["sec"] * 1e3,
+                     "contraction_tflops_wall": r["stats"]["contract"]["flops"] / r["sec"] / 1e12,
+                     "contraction_roofline": contraction_roofline(r, prec, cls),
+                     "kernel_ms_per_step": {cls[k]: r["kms"][k] for k in range(cbc.NCLASS)},
+                     "kernels_per_step": r["n_kernels"]}
+    out["speedup_mixed_vs_fp64"] = res["fp64"]["sec"] / res["mixed"]["sec"]
+    # At 128 sites the compressed state is ill-conditioned (a rounding-level input change grows by
+    # ~1.4x per site), so mixed and FP64 results are compared by the weight they capture; the
+    # non-root nodes are isometries, so ||psi'||^2 is the root's squared norm.
+    w = {k: float(sum(abs(x) ** 2 for x in v[0].reshape(-1))) for k, v in outputs.items()}
+    out["captured_weight"] = w
+    out["captured_weight_ratio_mixed_vs_fp64"] = w["mixed"] / w["fp64"]
+    out["mixed_fidelity_vs_fp64"] = _chain_fidelity(outputs["mixed"], outputs["fp64"])
+    return out
+
+
+def _chain_fidelity(a, b):
+    """|<a|b>|^2 / (<a|a><b|b>) of two tensor trains (nodes (sigma, left, right), site 0 the root),
+    by transfer matrices on the device (plain torch; a measurement helper of this script)."""
+    import torch
+
+    def overlap(x, y):
+        e = torch.ones((1, 1), dtype=torch.complex128, device="cuda:0")
+        for i in range(len(x) - 1, -1, -1):
+            xi = torch.from_numpy(x[i]).to("cuda:0")
+            yi = torch.from_numpy(y[i]).to("cuda:0")
+            if xi.dim() == 2:
+                xi, yi = xi.unsqueeze(-1), yi.unsqueeze(-1)
+            t = torch.tensordot(yi, e, dims=([2], [1]))          # sigma, pb, ca
+            xa = xi.permute(1, 0, 2).reshape(xi.shape[1], -1).conj().contiguous()
+            tb = t.permute(1, 0, 2).reshape(t.shape[1], -1).transpose(0, 1).contiguous()
+            e = xa @ tb
+        return complex(e.reshape(-1)[0].item())
+
+    ab = overlap(a, b)
+    return abs(ab) ** 2 / (overlap(a, a).real * overlap(b, b).real)
 
 
 def recorded_traffic(workload, precision, op):
@@ -170,6 +259,9 @@ def main():
                     help="instances per launch sequence for the batched measurement (0: skip)")
     ap.add_argument("--uneven", type=int, default=0,
                     help="instances of the uneven batch workload to time (0: skip)")
+    ap.add_argument("--large-steps", type=int, default=0,
+                    help="also time the large-bond workload (MPS N=128, d=4, chi=256) for this many "
+                         "steps per precision (0: skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times) and exit; used to "
                          "scale the HBM byte counters of a profiler run")
@@ -195,25 +287,9 @@ def main():
                                                "launches": 5}}))
         return
     p = config_problem(args.workload)
-    tree = cbc.Tree.of(p)
-    st, so = cbc.pack(p.state, "cuda:0")
-    op, oo = cbc.pack(p.op, "cuda:0")
-    ctx = cbc.Context()
     stream = torch.cuda.Stream()
-    res, outputs = {}, {}
     precs = [args.only] if args.only else ["mixed", "fp64"]
-    for prec in precs:
-        comp = cbc.Compressor(ctx, tree, p.max_bond, prec, device="cuda:0")
-        run_args = (op, oo, st, so, 0.0)
-        sec = timed_runs(comp, run_args, stream, args.steps, args.warmup)
-        replayed = int(comp.stats.graph_replayed)
-        outputs[prec] = comp.unpack()
-        kms = profiled_runs(comp, run_args, stream, max(3, min(args.steps, 10)))
-        st_d = comp.stats.as_dict()
-        res[prec] = dict(sec=sec, kms=kms, stats=st_d, replayed=replayed,
-                         n_kernels=int(comp.stats.n_kernels))
-        print(f"[bench] {prec}: {sec * 1e3:.3f} ms/compression, kernels/call "
-              f"{comp.stats.n_kernels}, graph replay {replayed}", file=sys.stderr, flush=True)
+    res, outputs = measure(cbc, p, precs, args.steps, args.warmup, stream)
 
     head = precs[0]
     r = res[head]
@@ -252,6 +328,7 @@ def main():
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved * 1e12 / peak,
                      "traffic": recorded_traffic(args.workload, head, cls[kd]), "avg_launch_ms": avg_ms,
                      "flops_per_launch": flops_per_launch},
+        "contraction_roofline": contraction_roofline(r, head, cls),
         "kernel_ms_per_step": {cls[k]: r["kms"][k] for k in range(cbc.NCLASS)},
         "kernels_per_step": r["n_kernels"],
         "graph_replayed": r["replayed"],
@@ -265,6 +342,8 @@ def main():
         line["batched"] = batched_run(args, cbc, p, stream)
     if args.uneven > 0:
         line["uneven_batch"] = uneven_run(args.uneven)
+    if args.large_steps > 0 and args.workload != "C4":
+        line["large_bond"] = large_run(cbc, stream, args.large_steps)
     if not args.no_cpu_baseline:
         cb, errs = cpu_baseline(p, outputs)
         line["cpu_baseline"] = cb

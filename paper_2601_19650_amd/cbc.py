@@ -260,6 +260,16 @@ class UnevenBatch:
         return sum(c.stats.flops[0] for c, _ in self.items)
 
 
+def plan_bonds(tree, max_bond, tol_on=False, ctx=None):
+    """Output bond to the parent of every node as planned for `max_bond` (host only, no device)."""
+    ctx = ctx or Context()
+    bond = np.zeros(tree.n, dtype=np.int32)
+    _check(lib().cbc_plan_bonds(ctx.h, ctypes.byref(tree.c), int(max_bond), int(bool(tol_on)),
+                                bond.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+           "cbc_plan_bonds")
+    return [int(b) for b in bond]
+
+
 def compress(problem, precision="fp64", method="cbc", tol=None, ctx=None, device="cuda"):
     """Convenience wrapper: one compression of a Problem from paper_2601_19650_amd.inputs."""
     ctx = ctx or Context()

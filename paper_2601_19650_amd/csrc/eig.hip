@@ -86,6 +86,7 @@ __device__ __forceinline__ double qdiv(double a, double b) {
 }
 
 // Layout of the scratch buffer (doubles).
+static constexpr int MW_MAX_WG = 256;     // workgroups of the multi-workgroup reduction, at most
 struct EigWork {
   double* d;      // s
   double* e;      // s
@@ -94,6 +95,11 @@ struct EigWork {
   double2* V;     // s * s   reflector j at V[j*s + i], i > j, V[j*s+j+1] = 1
   double* Y;      // kmax * s   cluster eigenvectors of T at Y[t*s + i]
   double* lu;     // kmax * 5 * s
+  // multi-workgroup reduction only (each double-buffered by the parity of the column)
+  double2* ybuf;  // 2 * s       products A v of the current column
+  double2* part;  // 2 * MW_MAX_WG  per-workgroup partial sums of v^H A v
+  double2* prow;  // 2 * s       next pivot row, published by its owner
+  unsigned* sync; // MW_MAX_WG + 16 words: last barrier reached per workgroup, then a time-out flag
 };
 __host__ __device__ inline EigWork eig_layout(double* w, int s, int kmax) {
   EigWork L;
@@ -104,10 +110,16 @@ __host__ __device__ inline EigWork eig_layout(double* w, int s, int kmax) {
   L.V = reinterpret_cast<double2*>(w + 4 * (size_t)s + 8);
   L.Y = w + 4 * (size_t)s + 8 + 2 * (size_t)s * s;
   L.lu = L.Y + (size_t)kmax * s;
+  L.ybuf = reinterpret_cast<double2*>(L.lu + 5 * (size_t)kmax * s);
+  L.part = L.ybuf + 2 * (size_t)s;
+  L.prow = L.part + 2 * MW_MAX_WG;
+  L.sync = reinterpret_cast<unsigned*>(L.prow + 2 * (size_t)s);
   return L;
 }
+static constexpr int MW_SYNC_BYTES = 4 * (MW_MAX_WG + 16);
 size_t eig_work_doubles(int s, int kmax) {
-  return 4 * (size_t)s + 8 + 2 * (size_t)s * s + (size_t)kmax * s + 5 * (size_t)kmax * s + 64;
+  return 4 * (size_t)s + 8 + 2 * (size_t)s * s + (size_t)kmax * s + 5 * (size_t)kmax * s +
+         4 * (size_t)s + 4 * MW_MAX_WG + 4 * (size_t)s + MW_SYNC_BYTES / 8 + 64;
 }
 
 // EigArgs of instance b (every pointer except the time stamps advances by a.bs bytes)
@@ -187,6 +199,8 @@ __device__ __forceinline__ void matvec_row(int r, int nj, int gl, const double2*
     di_acc += w.x * v.y - w.y * v.x;
   }
 }
+
+__device__ void tri_bounds(EigWork& W, int s, long long* tstamp);
 
 template <bool IN_LDS>
 __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
@@ -297,7 +311,13 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
   // last diagonal entry and the Gershgorin interval of T (used by the two later kernels)
   if (tid == 0) W.d[s - 1] = IN_LDS ? P[tri(s - 1) + s - 1].x : A[(size_t)(s - 1) * s + (s - 1)].x;
   __syncthreads();
-  if (wave == 0) {
+  if (wave == 0) tri_bounds(W, s, a.tstamp);
+}
+
+// Gershgorin interval of T and the pivot floor of the Sturm counts; one wave.
+__device__ void tri_bounds(EigWork& W, int s, long long* tstamp) {
+  const int lane = threadIdx.x & 63;
+  {
     double lo = DBL_MAX, hi = -DBL_MAX, emax = 0.0;
     for (int i = lane; i < s; i += 64) {
       const double el = i > 0 ? fabs(W.e[i - 1]) : 0.0;
@@ -316,8 +336,291 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
       W.bounds[1] = hi + pad;
       W.bounds[2] = tn;
       W.bounds[3] = DBL_MIN * fmax(1.0, emax);
-      if (a.tstamp) a.tstamp[1] = wall_clock64();
+      if (tstamp) tstamp[1] = wall_clock64();
     }
+  }
+}
+
+// ---- multi-workgroup Householder reduction (s > EIG_LDS_MAX) ------------------------------------
+// The rows of G are dealt cyclically to nwg workgroups (row r to workgroup r mod nwg) and stay in
+// their LDS for the whole reduction. Column j costs one grid-wide barrier:
+//   (1) every workgroup forms y = A v_j on its rows, and its share of v_j^H y;
+//   (2) barrier: each workgroup publishes its arrival in a flag of its own (no shared counter) and
+//       one wave polls all flags;
+//   (3) every workgroup forms w_j = tau y - |tau|^2/2 (y^H v_j)^* v_j from all of y, applies the rank-2
+//       update A -= v_j w_j^H + w_j v_j^H to its rows (the owner of row j+2 publishes that row), and
+//       builds row j+1 of the updated matrix from the row its owner published one column earlier, so
+//       that the next reflector is formed by every workgroup, identically, without another barrier.
+// Reductions are summed in a fixed order, so every workgroup holds bitwise the same v and w.
+// The barrier waits are bounded: after MW_TIMEOUT_TICKS of the 100 MHz wall clock a workgroup
+// raises a flag, every workgroup leaves at its next barrier, and d[0] is set to NaN.
+static constexpr int MW_THREADS = 1024;
+static constexpr int MW_WAVES = MW_THREADS / 64;
+static constexpr int MW_EPT = 2;                    // vector elements per thread: s <= 2048
+static constexpr size_t MW_LDS_BUDGET = 160 * 1024 - 2048;
+static constexpr long long MW_TIMEOUT_TICKS = 200000000LL;   // 2 s at 100 MHz
+
+struct MwShape {
+  int nwg, rows;
+};
+// Workgroup count: enough for the rows to fit in LDS beside v and w, and at least one workgroup per
+// 16 rows (up to 32) so that small matrices still spread their work.
+__host__ __device__ inline MwShape mw_shape(int s) {
+  int fit = (int)(MW_LDS_BUDGET / (16 * (size_t)s)) - 2;
+  if (fit < 1) fit = 1;
+  int nwg = (s + fit - 1) / fit;
+  const int want = (s + 15) / 16 < 32 ? (s + 15) / 16 : 32;
+  if (nwg < want) nwg = want;
+  MwShape m;
+  m.nwg = nwg;
+  m.rows = (s + nwg - 1) / nwg;
+  return m;
+}
+size_t mw_lds_bytes(int s) { return (size_t)(mw_shape(s).rows + 2) * s * 16; }
+
+// Barrier number `it` (sync[q] = last barrier workgroup q reached; sync[MW_MAX_WG] = time-out flag).
+__device__ bool mw_sync(unsigned* sync, int nwg, unsigned it, int* ok_sh) {
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (tid < 64) {
+    if (tid == 0)
+      __hip_atomic_store(&sync[blockIdx.x], it, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    const long long t0 = wall_clock64();
+    for (;;) {
+      int done = 1;
+      for (int q = tid; q < nwg; q += 64)
+        done &= __hip_atomic_load(&sync[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= it;
+      if (__all(done)) break;
+      const int err =
+          __hip_atomic_load(&sync[MW_MAX_WG], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+      if (__any(err) || wall_clock64() - t0 > MW_TIMEOUT_TICKS) {
+        if (tid == 0) __hip_atomic_store(&sync[MW_MAX_WG], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (tid == 0) *ok_sh = ok;
+  }
+  __syncthreads();
+  return *ok_sh != 0;
+}
+
+// block-wide sum of a complex value in a fixed order; result in every thread
+__device__ inline double2 mw_block_sum(double re, double im, double2* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  re = wave_sum(re);
+  im = wave_sum(im);
+  if (lane == 0) red[wave] = make_double2(re, im);
+  __syncthreads();
+  double2 t = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < MW_WAVES; ++q) {
+    t.x += red[q].x;
+    t.y += red[q].y;
+  }
+  __syncthreads();
+  return t;
+}
+
+// Reflector j from the pivot row x (row j of the partly reduced matrix, valid from column j): the
+// column below the diagonal is conj(x[j+1..]). Writes v_j to v (zero up to j, 1 at j+1) and returns
+// tau_j; the writer stores d_j, e_j, tau_j and v_j. For j = s-1 only d_j is stored.
+__device__ double2 mw_reflector(int j, int s, const double2* x, double2* v, EigWork& W, bool writer,
+                                double2* red) {
+  const int tid = threadIdx.x;
+  if (j >= s - 1) {
+    if (writer && tid == 0) W.d[j] = x[j].x;
+    return make_double2(0.0, 0.0);
+  }
+  double xn2 = 0.0;
+  for (int c = j + 2 + tid; c < s; c += MW_THREADS) xn2 += x[c].x * x[c].x + x[c].y * x[c].y;
+  xn2 = mw_block_sum(xn2, 0.0, red).x;
+  const double2 alpha = cconj(x[j + 1]);
+  double2 t = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
+  double beta = alpha.x;
+  if (!(xn2 == 0.0 && alpha.y == 0.0)) {
+    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+    beta = alpha.x >= 0.0 ? -nrm : nrm;
+    t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+    const double ar = alpha.x - beta, ai = alpha.y;
+    const double den = ar * ar + ai * ai;
+    scal = make_double2(ar / den, -ai / den);
+  }
+  const double djj = x[j].x;
+  for (int c = tid; c < s; c += MW_THREADS) {
+    double2 val = make_double2(0.0, 0.0);
+    if (c == j + 1) val = make_double2(1.0, 0.0);
+    else if (c > j + 1) val = cmul(cconj(x[c]), scal);
+    v[c] = val;
+    if (writer && c > j) W.V[(size_t)j * s + c] = val;
+  }
+  if (writer && tid == 0) {
+    W.tau[j] = t;
+    W.e[j] = beta;
+    W.d[j] = djj;
+  }
+  __syncthreads();
+  return t;
+}
+
+__global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) {
+  const EigArgs a = eig_inst(a0, blockIdx.y);
+  const int wg = blockIdx.x;
+  const int s = a.s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rows = (s + nwg - 1) / nwg;
+  const int nr = wg < s ? (s - wg + nwg - 1) / nwg : 0;   // rows owned: wg, wg + nwg, ...
+  // waves per owned row (a row's columns are split over its waves), rows per round
+  const int wpr = nr >= MW_WAVES ? 1 : MW_WAVES / nr;
+  const int rstep = MW_WAVES / wpr;
+  const int sub = wave % wpr;
+  extern __shared__ double smem[];
+  double2* Ar = reinterpret_cast<double2*>(smem);   // rows x s
+  double2* v = Ar + (size_t)rows * s;               // s
+  double2* w = v + s;                               // s
+  __shared__ double2 red[MW_WAVES];
+  __shared__ double2 rowred[MW_WAVES];
+  __shared__ int ok_sh;
+  EigWork W = eig_layout(a.work, s, a.kmax);
+  const bool writer = wg == 0;
+  if (a.tstamp && writer && tid == 0) a.tstamp[0] = wall_clock64();
+  for (int q = 0; q < nr; ++q) {
+    const double2* src = a.G + (size_t)(wg + (size_t)q * nwg) * s;
+    for (int c = tid; c < s; c += MW_THREADS) Ar[(size_t)q * s + c] = src[c];
+  }
+  for (int c = tid; c < s; c += MW_THREADS) w[c] = a.G[c];
+  __syncthreads();
+  double2 t = mw_reflector(0, s, w, v, W, writer, red);
+  const bool stamp = a.tstamp && writer && tid == 0;
+  long long tA = 0, tB = 0, tD = 0, t0 = 0;
+  for (int j = 0; j < s - 1; ++j) {
+    if (stamp) t0 = wall_clock64();
+    // (1) y = A v_j on the owned rows r > j; share of v_j^H y
+    double2* ybuf = W.ybuf + (size_t)(j & 1) * s;
+    double pr = 0.0, pi = 0.0;
+    auto row_dot = [&](int q, int r, double& yr, double& yi) {
+      yr = 0.0;
+      yi = 0.0;
+      if (r > j) {
+        const double2* row = Ar + (size_t)q * s;
+        for (int c = j + 1 + sub * 64 + lane; c < s; c += 64 * wpr) {
+          const double2 av = row[c], vv = v[c];
+          yr += av.x * vv.x - av.y * vv.y;
+          yi += av.x * vv.y + av.y * vv.x;
+        }
+      }
+      yr = wave_sum(yr);
+      yi = wave_sum(yi);
+    };
+    auto take = [&](int r, double yr, double yi) {
+      ybuf[r] = make_double2(yr, yi);
+      const double2 vr = v[r];
+      pr += vr.x * yr + vr.y * yi;
+      pi += vr.x * yi - vr.y * yr;
+    };
+    if (wpr > 1) {
+      // fewer rows than waves: each row's columns are split over wpr waves (one round)
+      const int q = wave / wpr;
+      const int r = wg + q * nwg;
+      double yr = 0.0, yi = 0.0;
+      if (q < nr) row_dot(q, r, yr, yi);
+      if (lane == 0) rowred[wave] = make_double2(yr, yi);
+      __syncthreads();
+      if (q < nr && r > j && sub == 0 && lane == 0) {
+        yr = 0.0;
+        yi = 0.0;
+        for (int u = 0; u < wpr; ++u) {
+          yr += rowred[q * wpr + u].x;
+          yi += rowred[q * wpr + u].y;
+        }
+        take(r, yr, yi);
+      }
+    } else {
+      for (int q = wave; q < nr; q += MW_WAVES) {
+        const int r = wg + q * nwg;
+        double yr, yi;
+        row_dot(q, r, yr, yi);
+        if (r > j && lane == 0) take(r, yr, yi);
+      }
+    }
+    const double2 ps = mw_block_sum(pr, pi, red);
+    if (tid == 0) W.part[(size_t)(j & 1) * MW_MAX_WG + wg] = ps;
+    if (stamp) { const long long t1 = wall_clock64(); tA += t1 - t0; t0 = t1; }
+    // (2)
+    if (!mw_sync(W.sync, nwg, (unsigned)(j + 1), &ok_sh)) {
+      if (writer && tid == 0) W.d[0] = __builtin_nan("");
+      return;
+    }
+    if (stamp) { const long long t1 = wall_clock64(); tB += t1 - t0; t0 = t1; }
+    // (3) everything published for this column is fetched at once
+    const double2* prev = j == 0 ? a.G + s : W.prow + (size_t)(j & 1) * s;
+    double2 yv[MW_EPT], pv[MW_EPT];
+#pragma unroll
+    for (int e = 0; e < MW_EPT; ++e) {
+      const int c = j + 1 + tid + e * MW_THREADS;
+      yv[e] = c < s ? ybuf[c] : make_double2(0.0, 0.0);
+      pv[e] = c < s ? prev[c] : make_double2(0.0, 0.0);
+    }
+    const double2 pp = tid < nwg ? W.part[(size_t)(j & 1) * MW_MAX_WG + tid] : make_double2(0.0, 0.0);
+    const double2 cs = mw_block_sum(pp.x, pp.y, red);
+    // a2 = -|tau|^2 / 2 * conj(v^H y)
+    const double tt = t.x * t.x + t.y * t.y;
+    const double2 a2 = make_double2(-0.5 * tt * cs.x, 0.5 * tt * cs.y);
+#pragma unroll
+    for (int e = 0; e < MW_EPT; ++e) {
+      const int c = j + 1 + tid + e * MW_THREADS;
+      if (c < s) {
+        const double2 vc = v[c];
+        const double2 ty = cmul(t, yv[e]);
+        w[c] = make_double2(ty.x + a2.x * vc.x - a2.y * vc.y, ty.y + a2.x * vc.y + a2.y * vc.x);
+      }
+    }
+    __syncthreads();
+    // rank-2 update of the owned rows r > j+1 on the columns > j+1; the owner of row j+2 publishes it
+    double2* pnext = W.prow + (size_t)((j + 1) & 1) * s;
+    for (int q = wave / wpr; q < nr; q += rstep) {
+      const int r = wg + q * nwg;
+      if (r <= j + 1) continue;
+      double2* row = Ar + (size_t)q * s;
+      const double2 vr = v[r], wr = w[r];
+      for (int c = j + 2 + sub * 64 + lane; c < s; c += 64 * wpr) {
+        const double2 vc = v[c], wc = w[c];
+        double2 x = row[c];
+        x.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
+        x.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
+        row[c] = x;
+        if (r == j + 2) pnext[c] = x;
+      }
+    }
+    // row j+1 of the updated matrix from its published predecessor
+    const double2 v1 = v[j + 1], w1 = w[j + 1];
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < MW_EPT; ++e) {
+      const int c = j + 1 + tid + e * MW_THREADS;
+      if (c < s) {
+        const double2 vc = v[c], wc = w[c];
+        double2 x = pv[e];
+        x.x -= (v1.x * wc.x + v1.y * wc.y) + (w1.x * vc.x + w1.y * vc.y);
+        x.y -= (v1.y * wc.x - v1.x * wc.y) + (w1.y * vc.x - w1.x * vc.y);
+        w[c] = x;
+      }
+    }
+    __syncthreads();
+    t = mw_reflector(j + 1, s, w, v, W, writer, red);
+    if (stamp) tD += wall_clock64() - t0;
+  }
+  if (stamp) {
+    a.tstamp[4] = tA;
+    a.tstamp[5] = tB;
+    a.tstamp[6] = tD;
+  }
+  if (writer) {
+    __syncthreads();
+    if (wave == 0) tri_bounds(W, s, a.tstamp);
   }
 }
 
@@ -674,6 +977,133 @@ __global__ __launch_bounds__(256) void k_eigvecs(EigArgs a0) {
   if (a.tstamp && lane == 0 && ce > t + 1) atomicAdd(reinterpret_cast<unsigned long long*>(a.tstamp + 7), 1ull);
 }
 
+// ---- eigenvectors for s > EIG_SPLIT_MIN: three launches -------------------------------------------
+// (A) one wave per eigenpair: the twisted-factorisation eigenvector of T, to Y;
+// (B) one wave per cluster of close eigenvalues: modified Gram-Schmidt of the members in order
+//     (or inverse iteration for near-exact degeneracies), in place in Y;
+// (C) one wave per eigenpair: back-transformation u = Q y with the vector held in registers.
+// Separating (A) and (C) from (B) keeps the expensive back-transformation parallel over all
+// eigenpairs even where the spectrum is dense enough for many eigenvalues to fall into clusters.
+static constexpr int EIG_SPLIT_MIN = 256;
+
+__device__ inline int keep_count(const EigArgs& a) {
+  int keep = a.kmax;
+  if (a.tol > 0.0) {
+    const double cut = a.tol * a.tol * a.lam[0];
+    int c = 0;
+    for (int u = threadIdx.x & 63; u < a.kmax; u += 64) c += a.lam[u] > cut;
+    c = (int)wave_sum((double)c);
+    keep = c < 1 ? 1 : c;
+  }
+  return keep;
+}
+// u starts a cluster: its gap to the previous eigenvalue exceeds 1e-3 ||T||, or it is negligible
+__device__ inline bool cluster_start(const double* lam, int u, int kmax, double tnorm) {
+  const double ortol = 1e-3 * tnorm, tiny = 64.0 * DBL_EPSILON * tnorm;
+  return u == 0 || u == kmax || lam[u - 1] - lam[u] > ortol || lam[u] <= tiny;
+}
+
+__global__ __launch_bounds__(256) void k_eigvecs_twisted(EigArgs a0) {
+  const EigArgs a = eig_inst(a0, blockIdx.y);
+  extern __shared__ double smem[];
+  const int s = a.s, kmax = a.kmax;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = blockDim.x >> 6;
+  double* dd = smem;
+  double* el = dd + s;
+  double* region = el + s + 4 * (size_t)s * wave;   // per wave: lp | dp | um | y
+  EigWork W = eig_layout(a.work, s, kmax);
+  for (int i = tid; i < s; i += blockDim.x) {
+    dd[i] = W.d[i];
+    el[i] = i < s - 1 ? W.e[i] : 0.0;
+  }
+  __syncthreads();
+  const int t = blockIdx.x * nw + wave;
+  if (t >= kmax) return;
+  const int keep = keep_count(a);
+  if (t == 0 && lane == 0) {
+    a.kkeep[0] = keep;
+    a.inv_sqrt_l0[0] = a.lam[0] > 0.0 ? 1.0 / sqrt(a.lam[0]) : 1.0;
+  }
+  double* y = region + 3 * (size_t)s;
+  if (lane == 0) twisted_vector(dd, el, s, a.lam[t], W.bounds[3], y, region, region + s, region + 2 * s);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  double* yo = W.Y + (size_t)t * s;
+  for (int i = lane; i < s; i += 64) yo[i] = y[i];
+}
+
+__global__ __launch_bounds__(256) void k_eigvecs_clusters(EigArgs a0) {
+  const EigArgs a = eig_inst(a0, blockIdx.y);
+  extern __shared__ double smem[];
+  const int s = a.s, kmax = a.kmax;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int nw = blockDim.x >> 6;
+  EigWork W = eig_layout(a.work, s, kmax);
+  const int t = blockIdx.x * nw + wave;
+  if (t >= kmax) return;
+  const double tnorm = W.bounds[2];
+  const double* lam = a.lam;
+  if (!cluster_start(lam, t, kmax, tnorm)) return;
+  int ce = t + 1;
+  while (ce < kmax && !cluster_start(lam, ce, kmax, tnorm)) ++ce;
+  if (ce == t + 1) return;
+  if (a.tstamp && lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(a.tstamp + 7), 1ull);
+  double mingap = DBL_MAX;
+  for (int m = t + 1; m < ce; ++m) mingap = fmin(mingap, lam[m - 1] - lam[m]);
+  if (mingap > 1e-12 * tnorm) {
+    // twisted vectors are accurate up to mixing inside the cluster: two passes of modified
+    // Gram-Schmidt over the members in order give an orthonormal basis of its invariant subspace
+    for (int m = t + 1; m < ce; ++m) {
+      double* ym = W.Y + (size_t)m * s;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int q = t; q < m; ++q) {
+          const double* yq = W.Y + (size_t)q * s;
+          double dot = 0.0;
+          for (int i = lane; i < s; i += 64) dot += yq[i] * ym[i];
+          dot = wave_sum(dot);
+          for (int i = lane; i < s; i += 64) ym[i] -= dot * yq[i];
+        }
+      }
+      double nrm = 0.0;
+      for (int i = lane; i < s; i += 64) nrm += ym[i] * ym[i];
+      nrm = wave_sum(nrm);
+      const double inv = 1.0 / sqrt(nrm);
+      for (int i = lane; i < s; i += 64) ym[i] *= inv;
+    }
+  } else {
+    double* dd = smem + 2 * (size_t)s * wave;
+    double* el = dd + s;
+    for (int i = lane; i < s; i += 64) {
+      dd[i] = W.d[i];
+      el[i] = i < s - 1 ? W.e[i] : 0.0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (lane == 0) cluster_vectors(dd, el, s, lam, t, ce, tnorm, W.Y, W.lu + (size_t)t * 5 * s);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_backtransform(EigArgs a0) {
+  const EigArgs a = eig_inst(a0, blockIdx.y);
+  extern __shared__ double smem[];
+  const int s = a.s, kmax = a.kmax;
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  EigWork W = eig_layout(a.work, s, kmax);
+  const int t = blockIdx.x * nw + wave;
+  if (t >= kmax) return;
+  const bool kept = t < a.kkeep[0];
+  const double* y = W.Y + (size_t)t * s;
+  if (s <= 512) back_transform_reg<8>(a, W, s, kmax, t, kept, y);
+  else if (s <= 1024) back_transform_reg<16>(a, W, s, kmax, t, kept, y);
+  else back_transform_col(a, W, s, kmax, t, kept, y, reinterpret_cast<double2*>(smem) + (size_t)s * wave);
+  if (a.tstamp && (threadIdx.x & 63) == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 3), (unsigned long long)wall_clock64());
+}
+
 size_t eig_lds_bytes(int s, int kmax, bool in_lds) {
   (void)kmax;
   return (in_lds ? (size_t)16 * (s * (size_t)(s + 1) / 2) : 0) + (size_t)s * (2 * 16) + 64;
@@ -681,17 +1111,23 @@ size_t eig_lds_bytes(int s, int kmax, bool in_lds) {
 
 hipError_t launch_eig(const EigArgs& a, hipStream_t st) {
   if (a.s <= 0 || a.kmax <= 0 || a.kmax > a.s || a.batch <= 0) return hipErrorInvalidValue;
-  const bool in_lds = a.s <= EIG_LDS_MAX;
-  const size_t lds = eig_lds_bytes(a.s, a.kmax, in_lds);
-  if (lds > 160 * 1024 - 512) return hipErrorInvalidValue;
-  if (in_lds) {
+  if (a.s <= EIG_LDS_MAX) {
+    const size_t lds = eig_lds_bytes(a.s, a.kmax, true);
     (void)hipFuncSetAttribute((const void*)k_tridiag<true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_tridiag<true>, dim3(a.batch), dim3(EIG_THREADS), lds, st, a);
   } else {
-    (void)hipFuncSetAttribute((const void*)k_tridiag<false>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_tridiag<false>, dim3(a.batch), dim3(EIG_THREADS), lds, st, a);
+    const MwShape m = mw_shape(a.s);
+    const size_t lds = mw_lds_bytes(a.s);
+    if (m.nwg > MW_MAX_WG || lds > MW_LDS_BUDGET || a.s > MW_EPT * MW_THREADS)
+      return hipErrorInvalidValue;
+    // the barrier words start at zero for every call
+    EigWork W = eig_layout(a.work, a.s, a.kmax);
+    hipError_t z = launch_zero(W.sync, MW_SYNC_BYTES, a.batch, a.bs, st);
+    if (z != hipSuccess) return z;
+    (void)hipFuncSetAttribute((const void*)k_tridiag_mw, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL(k_tridiag_mw, dim3(m.nwg, a.batch), dim3(MW_THREADS), lds, st, a, m.nwg);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -703,9 +1139,31 @@ hipError_t launch_eig(const EigArgs& a, hipStream_t st) {
   const int nw = a.s <= 1000 ? 4 : (a.s <= 1900 ? 2 : 1);
   const size_t lds3 = (size_t)a.s * (2 * 8 + (size_t)nw * 4 * 8) + 64;
   if (lds3 > 160 * 1024 - 512) return hipErrorInvalidValue;
-  (void)hipFuncSetAttribute((const void*)k_eigvecs, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds3);
-  hipLaunchKernelGGL(k_eigvecs, dim3((a.kmax + nw - 1) / nw, a.batch), dim3(64 * nw), lds3, st, a);
+  const dim3 g3((a.kmax + nw - 1) / nw, a.batch);
+  if (a.s <= EIG_SPLIT_MIN) {
+    (void)hipFuncSetAttribute((const void*)k_eigvecs, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds3);
+    hipLaunchKernelGGL(k_eigvecs, g3, dim3(64 * nw), lds3, st, a);
+    return hipGetLastError();
+  }
+  (void)hipFuncSetAttribute((const void*)k_eigvecs_twisted,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds3);
+  hipLaunchKernelGGL(k_eigvecs_twisted, g3, dim3(64 * nw), lds3, st, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t ldsc = (size_t)a.s * 2 * 8 * 4;
+  if (ldsc > 160 * 1024 - 512) return hipErrorInvalidValue;
+  (void)hipFuncSetAttribute((const void*)k_eigvecs_clusters,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsc);
+  hipLaunchKernelGGL(k_eigvecs_clusters, dim3((a.kmax + 3) / 4, a.batch), dim3(256), ldsc, st, a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t ldsb = a.s > 1024 ? (size_t)a.s * 16 * 4 : 0;
+  if (ldsb > 160 * 1024 - 512) return hipErrorInvalidValue;
+  if (ldsb > 0)
+    (void)hipFuncSetAttribute((const void*)k_backtransform,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsb);
+  hipLaunchKernelGGL(k_backtransform, dim3((a.kmax + 3) / 4, a.batch), dim3(256), ldsb, st, a);
   return hipGetLastError();
 }
 

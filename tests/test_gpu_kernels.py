@@ -62,7 +62,7 @@ def herm_psd(rng, s, rank=None, n=None):
 
 
 @pytest.mark.parametrize("s,kmax", [(1, 1), (2, 1), (2, 2), (7, 3), (64, 32), (128, 64), (200, 100),
-                                    (96, 96)])
+                                    (96, 96), (129, 64), (300, 300), (520, 128), (1024, 256)])
 def test_eig_topk(lib, s, kmax):
     print(f"eig s={s} kmax={kmax}", flush=True)
     rng = np.random.default_rng(s)
@@ -104,10 +104,10 @@ def test_eig_rank_deficient_and_tol(lib):
     assert np.abs(U2.cpu().numpy()[:, 10:]).max() == 0.0
 
 
-def test_eig_degenerate_cluster(lib):
+@pytest.mark.parametrize("s", [50, 260])
+def test_eig_degenerate_cluster(lib, s):
     """Exactly repeated eigenvalues: the returned vectors must stay orthonormal."""
     rng = np.random.default_rng(11)
-    s = 50
     q, _ = np.linalg.qr(crand(rng, s, s))
     w = np.concatenate([[5.0] * 6, np.linspace(3.0, 0.1, s - 6)])
     g = (q * w) @ q.conj().T

@@ -12,7 +12,7 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-from oracle import cbc_tree, tn  # noqa: E402
+from oracle import cbc_tree, cbc_tt, tn  # noqa: E402
 from paper_2601_19650_amd.inputs import (chain_parent, config_problem, kary_parent,  # noqa: E402
                                          random_problem)
 
@@ -73,6 +73,54 @@ def test_c2_parity(lib, prec):
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_c3_parity(lib, prec):
     check(lib, config_problem("C3"), prec)
+
+
+@pytest.fixture(scope="module")
+def c4_small():
+    """The large-bond workload's shape (d=4, chi=256, D=16, max_bond=256) on 10 sites: three bulk
+    sites reach bond 256, so the truncation Grams are 1024 x 1024 and the QR Grams 256 x 256."""
+    p = config_problem("C4", n=10)
+    ref = tn.mps_to_tree(cbc_tt(tn.tree_to_mps(p.state), tn.tree_to_mpo(p.op), p.max_bond))
+    return p, ref
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c4_reduced_parity(lib, c4_small, prec):
+    p, ref = c4_small
+    out, comp = check(lib, p, prec, oracle_out=ref)
+    assert comp.stats.max_eig_dim == 1024
+
+
+def test_c4_full_size_properties(lib):
+    """The full 128-site large-bond workload, as the benchmark runs it.
+
+    At this size the compressed state is not a well-conditioned function of the input: every site
+    keeps about 60 % of the weight, and a rounding-level change of the input grows by about 1.4x per
+    site (the oracle's own output moves by 3e-13 at 16 sites and 5e-12 at 24 sites when its input is
+    multiplied by 1 + 1e-15 noise), so no two implementations agree beyond the captured weight at
+    128 sites. Oracle parity is therefore checked at reduced size (above); here the checks are the
+    properties that hold at any size: bonds as planned, every non-root node an isometry, FP64 runs
+    bitwise reproducible, and the captured weight ||psi'||^2 of the mixed result within 5 % of the
+    FP64 one."""
+    p = config_problem("C4")
+    planned = lib.plan_bonds(lib.Tree.of(p), p.max_bond)
+    weight = {}
+    first = None
+    for prec in ("fp64", "fp64", "mixed"):
+        print(f"C4 full size {prec}", flush=True)
+        out, comp = lib.compress(p, precision=prec)
+        for i, t in enumerate(out):
+            assert np.all(np.isfinite(t))
+            if i != 0:
+                assert tn.isometry_error(t) <= 1e-12
+            assert t.shape[1] == planned[i]
+        if prec == "fp64" and first is not None:
+            assert all(np.array_equal(a, b) for a, b in zip(first, out))
+        if prec == "fp64":
+            first = out
+        # non-root nodes are isometries, so the state's norm is the root's
+        weight[prec] = float(np.linalg.norm(out[0]) ** 2)
+    assert abs(weight["mixed"] / weight["fp64"] - 1.0) <= 0.05, weight
 
 
 def test_tolerance_parity(lib):
