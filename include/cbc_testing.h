@@ -16,10 +16,18 @@ extern "C" {
 
 /* C (M x N) = op(A) op(B), op(X) = X, X^T, conj(X) or X^H by (trans, conj). A is stored M x K (or
  * K x M if transA), B is K x N (or N x K if transB). acc_fp64 selects FP64 MFMA accumulation,
- * otherwise FP32 MFMA. tile: 0 = 32x32, 1 = 64x64. This is the contraction kernel of every sweep. */
+ * otherwise FP32 MFMA. tile: -1 = the compression's policy (tile by shape, split reduction where it
+ * would split), 0 = 32x32, 1 = 64x64, 2 = pipelined 64x64 (FP32 accumulation only; FP64 falls back
+ * to 1); other values are rejected. This is the contraction kernel of every sweep. */
 int cbc_test_gemm(int M, int N, int K, const void* A, int a_c128, int transA, int conjA,
                   const void* B, int b_c128, int transB, int conjB, void* C, int c_c128,
                   int acc_fp64, int tile, void* stream);
+
+/* Timing of the same kernel on a plain row-major M x K by K x N product with buffers it allocates
+ * itself (zero-filled): one untimed launch, then `reps` launches between two HIP events on the null
+ * stream; *ms (host) receives the average milliseconds per launch. */
+int cbc_test_gemm_time(int M, int N, int K, int a_c128, int b_c128, int c_c128, int acc_fp64,
+                       int tile, int reps, float* ms);
 
 /* Truncation eigensolve (Sec. III A "compress ... for example via singular value decomposition",
  * realised on the FP64 Gram matrix): G (s x s complex128 Hermitian, overwritten) -> U (s x kmax

@@ -294,11 +294,14 @@ def _testing_lib():
         L.cbc_test_eig.restype = ci
         L.cbc_test_chol_inv.argtypes = [vp, ci, cd, cd, vp, vp, vp, vp]
         L.cbc_test_chol_inv.restype = ci
+        L.cbc_test_gemm_time.argtypes = [ci, ci, ci, ci, ci, ci, ci, ci, ci,
+                                         ctypes.POINTER(ctypes.c_float)]
+        L.cbc_test_gemm_time.restype = ci
         L._testing_ready = True
     return L
 
 
-TESTING_EXPORTED = ("cbc_test_gemm", "cbc_test_eig", "cbc_test_chol_inv")
+TESTING_EXPORTED = ("cbc_test_gemm", "cbc_test_gemm_time", "cbc_test_eig", "cbc_test_chol_inv")
 
 
 def _stream():
@@ -323,6 +326,16 @@ def test_gemm(A, B, transA=False, conjA=False, transB=False, conjB=False, out_dt
                                         C.data_ptr(), int(out_dtype == torch.complex128),
                                         int(acc_fp64), int(tile), _stream()), "cbc_test_gemm")
     return C
+
+
+def test_gemm_time(M, N, K, a_c128=False, b_c128=False, c_c128=False, acc_fp64=False, tile=-1,
+                   reps=10):
+    """Average milliseconds per launch of the contraction kernel on a plain M x N x K product."""
+    ms = ctypes.c_float()
+    _check(_testing_lib().cbc_test_gemm_time(M, N, K, int(a_c128), int(b_c128), int(c_c128),
+                                             int(acc_fp64), int(tile), int(reps), ctypes.byref(ms)),
+           "cbc_test_gemm_time")
+    return float(ms.value)
 
 
 def test_eig(G, kmax, tol=0.0, stamps=None):

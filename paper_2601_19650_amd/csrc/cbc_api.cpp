@@ -58,7 +58,8 @@ struct Op {
   TRef A, B, C;
   int M = 0, N = 0, K = 0;
   int64_t tAm = 0, tAk = 0, tBk = 0, tBn = 0, tCm = 0, tCn = 0;
-  int conjA = 0, conjB = 0, akf = 0, bkf = 0, tile = 0;
+  int conjA = 0, conjB = 0, akf = 0, bkf = 0, tile = 0, ksplit = 1;
+  TRef part;   // split-K chunk sums (scratch)
   DType ta = DT_C128, tb = DT_C128, tc = DT_C128, acc = DT_C128;
   double alpha = 1.0;
   TRef adev, adev2;
@@ -299,7 +300,19 @@ struct Builder {
     op.alpha = alpha;
     op.adev = adev;
     op.adev2 = adev2;
-    op.tile = ((int64_t)op.M * op.N >= (int64_t)64 * 64 * 96) ? 1 : 0;
+    // tile chosen at launch (it depends on the batch); a split reduction needs scratch, so it is
+    // decided here, for one instance
+    op.tile = GEMM_AUTO;
+    {
+      const bool f64 = acc == DT_C128;
+      const int t1 = gemm_pick_tile(op.M, op.N, op.K, 1, f64);
+      const int ks = gemm_pick_ksplit(op.M, op.N, op.K, 1, t1);
+      if (ks > 1) {
+        op.tile = t1;
+        op.ksplit = ks;
+        op.part = scr((size_t)ks * op.M * op.N * (f64 ? 16 : 8), acc);
+      }
+    }
     const double f = 8.0 * (double)op.M * op.N * op.K;
     op.cls = bucket == 0 ? CBC_K_CONTRACT : bucket == 1 ? CBC_K_GRAM : bucket == 2 ? CBC_K_QRMUL
                                                                               : CBC_K_OTHER;
@@ -1140,6 +1153,10 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         g.bsAlpha = stride_of(P, c, op.adev);
         g.bsAlpha2 = stride_of(P, c, op.adev2);
         g.mbase = 0;
+        g.ksplit = op.ksplit;
+        g.kchunk = ((op.K + op.ksplit - 1) / op.ksplit + 15) / 16 * 16;
+        g.part = op.ksplit > 1 ? resolve(P, c, op.part) : nullptr;
+        g.bsPart = op.ksplit > 1 ? stride_of(P, c, op.part) : 0;
         e = launch_gemm(g, op.ta, op.tb, op.tc, op.acc, op.tile, st);
         break;
       }

@@ -33,7 +33,14 @@ struct GemmArgs {
   // batch: instance z (blockIdx.z) uses every pointer advanced by z times its byte stride
   int batch;
   int64_t bsA, bsB, bsC, bsAlpha, bsAlpha2;
-  int mbase;   // first row of this launch (the launcher splits very tall problems into row chunks)
+  int mbase = 0;   // first row of this launch (the launcher splits very tall problems into row chunks)
+  // split-K: the reduction range is cut into ksplit chunks of kchunk (a multiple of 16); chunk z of
+  // instance b writes its raw sums to part_b[(z * M + m) * N + n] (accumulator type, part_b = part +
+  // b * bsPart bytes), and a second kernel adds the chunks in order and applies alpha and C offsets
+  int ksplit = 1;
+  int kchunk = 0;
+  void* part = nullptr;
+  int64_t bsPart = 0;   // per-instance byte stride of part
 };
 // pointer of instance b for a per-instance byte stride
 template <typename T>
@@ -43,7 +50,13 @@ __host__ __device__ inline T* inst_ptr(T* p, int64_t stride, int b) {
            : p;
 }
 
-// Launch a GEMM. acc: DT_C64 -> FP32 MFMA, DT_C128 -> FP64 MFMA. tile: 0 = 32x32, 1 = 64x64.
+// Tile configurations of the contraction GEMM: table-driven 32x32 / 64x64 tiles, or (FP32
+// accumulation only) the pipelined kernel with 64x64 tiles; GEMM_AUTO picks by shape.
+enum GemmTile : int { GEMM_AUTO = -1, GEMM_TILE32 = 0, GEMM_TILE64 = 1, GEMM_PIPE64 = 2 };
+int gemm_pick_tile(int M, int N, int K, int batch, bool fp64_acc);
+// number of K chunks for a table-driven 32x32 launch with too few output tiles (1: no split)
+int gemm_pick_ksplit(int M, int N, int K, int batch, int tile);
+// Launch a GEMM. acc: DT_C64 -> FP32 MFMA, DT_C128 -> FP64 MFMA.
 hipError_t launch_gemm(const GemmArgs& a, DType ta, DType tb, DType tc, DType acc, int tile,
                        hipStream_t s);
 

@@ -54,8 +54,10 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
   const int wr = wave >> 1, wc = wave & 1;
   const int m0 = g.mbase + blockIdx.y * BM;
   const int n0 = blockIdx.x * BN;
-  const int M = g.M, N = g.N, K = g.K;
-  const int bz = blockIdx.z;
+  const int M = g.M, N = g.N;
+  const int bz = blockIdx.z / g.ksplit, kz = blockIdx.z % g.ksplit;
+  const int kbeg = g.ksplit > 1 ? kz * g.kchunk : 0;
+  const int K = g.ksplit > 1 ? min(g.K, kbeg + g.kchunk) : g.K;
   const CA* __restrict__ A = reinterpret_cast<const CA*>(inst_ptr(g.A, g.bsA, bz));
   const CB* __restrict__ B = reinterpret_cast<const CB*>(inst_ptr(g.B, g.bsB, bz));
   const ACC sa = g.conjA ? ACC(-1) : ACC(1);
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
       acci[i][j] = V4{0, 0, 0, 0};
     }
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < K; k0 += BK) {
     for (int e = tid; e < BM * BK; e += 256) {
       int r, kk;
       if (g.a_kfast) { kk = e % BK; r = e / BK; } else { r = e % BM; kk = e / BM; }
@@ -112,19 +114,45 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
         br[j] = sBr[kr][wc * WN + j * 16 + (lane & 15)];
         bi[j] = sBi[kr][wc * WN + j * 16 + (lane & 15)];
       }
+      // the two products into each accumulator are issued a full sweep apart, so dependent MFMAs
+      // never follow each other
 #pragma unroll
       for (int i = 0; i < MB; ++i)
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
           accr[i][j] = mfma16(ar[i], br[j], accr[i][j]);
-          accr[i][j] = mfma16(-ai[i], bi[j], accr[i][j]);
           acci[i][j] = mfma16(ar[i], bi[j], acci[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          accr[i][j] = mfma16(-ai[i], bi[j], accr[i][j]);
           acci[i][j] = mfma16(ai[i], br[j], acci[i][j]);
         }
     }
     __syncthreads();
   }
 
+  if (g.ksplit > 1) {
+    // raw chunk sums, row-major M x N per (instance, chunk)
+    using CP = typename Cplx<ACC>::type;
+    CP* __restrict__ P = reinterpret_cast<CP*>(inst_ptr(g.part, g.bsPart, bz)) + (int64_t)kz * M * N;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int n = n0 + wc * WN + j * 16 + (lane & 15);
+        if (n >= N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rb = sizeof(ACC) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+          const int m = m0 + wr * WM + i * 16 + rb;
+          if (m < M) P[(int64_t)m * N + n] = CP{accr[i][j][r], acci[i][j][r]};
+        }
+      }
+    return;
+  }
   double alpha = g.alpha;
   if (g.alpha_dev) alpha *= inst_ptr(g.alpha_dev, g.bsAlpha, bz)[0];
   if (g.alpha_dev2) alpha *= inst_ptr(g.alpha_dev2, g.bsAlpha2, bz)[0];
@@ -152,24 +180,241 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
     }
 }
 
+// Second pass of a split-K GEMM: C = alpha * sum over the chunks, in chunk order.
+template <typename TC, typename ACC>
+__global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
+  using CP = typename Cplx<ACC>::type;
+  using CC = typename Cplx<TC>::type;
+  const int b = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mn = (int64_t)g.M * g.N;
+  if (idx >= mn) return;
+  const CP* P = reinterpret_cast<const CP*>(inst_ptr(g.part, g.bsPart, b)) + idx;
+  double re = 0.0, im = 0.0;
+  for (int z = 0; z < g.ksplit; ++z) {
+    const CP v = P[(int64_t)z * mn];
+    re += double(v.x);
+    im += double(v.y);
+  }
+  double alpha = g.alpha;
+  if (g.alpha_dev) alpha *= inst_ptr(g.alpha_dev, g.bsAlpha, b)[0];
+  if (g.alpha_dev2) alpha *= inst_ptr(g.alpha_dev2, g.bsAlpha2, b)[0];
+  CC* C = reinterpret_cast<CC*>(inst_ptr(g.C, g.bsC, b));
+  const int m = (int)(idx / g.N), n = (int)(idx % g.N);
+  CC out;
+  out.x = TC(re * alpha);
+  out.y = TC(im * alpha);
+  C[(int64_t)g.offCm[m] + g.offCn[n]] = out;
+}
+
+// Pipelined variant for FP32 accumulation and large tiles (BM x BN = 128 x 128 or 64 x 64, BK = 16):
+// the row / column offsets of the tile are read once into registers, the next k-tile is fetched
+// from global memory into registers while the MFMAs consume the current one from LDS, and the LDS
+// tiles are double-buffered so each k-tile costs one barrier.
+template <typename TA, typename TB, typename TC, int BM, int BN>
+__global__ __launch_bounds__(256) void k_cgemm_pipe(GemmArgs g) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int MB = WM / 16, NB = WN / 16;
+  constexpr int PAD = 4;
+  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;   // elements per thread and k-tile
+  using CA = typename Cplx<TA>::type;
+  using CB = typename Cplx<TB>::type;
+  using CC = typename Cplx<TC>::type;
+
+  __shared__ float sAr[2][BK][BM + PAD];
+  __shared__ float sAi[2][BK][BM + PAD];
+  __shared__ float sBr[2][BK][BN + PAD];
+  __shared__ float sBi[2][BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int m0 = g.mbase + blockIdx.y * BM;
+  const int n0 = blockIdx.x * BN;
+  const int M = g.M, N = g.N, K = g.K;
+  const int bz = blockIdx.z;
+  const CA* __restrict__ A = reinterpret_cast<const CA*>(inst_ptr(g.A, g.bsA, bz));
+  const CB* __restrict__ B = reinterpret_cast<const CB*>(inst_ptr(g.B, g.bsB, bz));
+  const float sa = g.conjA ? -1.0f : 1.0f;
+  const float sb = g.conjB ? -1.0f : 1.0f;
+  const bool akf = g.a_kfast, bkf = g.b_kfast;
+
+  // this thread's load slots: element u of a k-tile is (row ra(u), k ka(u)) of A, (k kb(u), col cb(u)) of B
+  auto ra = [&](int u) { return akf ? tid / BK + (256 / BK) * u : tid % BM; };
+  auto ka = [&](int u) { return akf ? tid % BK : tid / BM + (256 / BM) * u; };
+  auto cb = [&](int u) { return bkf ? tid / BK + (256 / BK) * u : tid % BN; };
+  auto kb = [&](int u) { return bkf ? tid % BK : tid / BN + (256 / BN) * u; };
+  int offm[EA], offn[EB];
+#pragma unroll
+  for (int u = 0; u < EA; ++u) {
+    const int m = m0 + ra(u);
+    offm[u] = m < M ? g.offAm[m] : -1;
+  }
+#pragma unroll
+  for (int u = 0; u < EB; ++u) {
+    const int n = n0 + cb(u);
+    offn[u] = n < N ? g.offBn[n] : -1;
+  }
+  CA ra_v[EA];
+  CB rb_v[EB];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      const int k = k0 + ka(u);
+      ra_v[u] = (offm[u] >= 0 && k < K) ? A[(int64_t)offm[u] + g.offAk[k]] : CA{0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int k = k0 + kb(u);
+      rb_v[u] = (offn[u] >= 0 && k < K) ? B[(int64_t)g.offBk[k] + offn[u]] : CB{0, 0};
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      sAr[buf][ka(u)][ra(u)] = float(ra_v[u].x);
+      sAi[buf][ka(u)][ra(u)] = sa * float(ra_v[u].y);
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      sBr[buf][kb(u)][cb(u)] = float(rb_v[u].x);
+      sBi[buf][kb(u)][cb(u)] = sb * float(rb_v[u].y);
+    }
+  };
+
+  f4v accr[MB][NB], acci[MB][NB];
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      accr[i][j] = f4v{0, 0, 0, 0};
+      acci[i][j] = f4v{0, 0, 0, 0};
+    }
+
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    const bool more = k0 + BK < K;
+    if (more) fetch(k0 + BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      float ar[MB], ai[MB], br[NB], bi[NB];
+#pragma unroll
+      for (int i = 0; i < MB; ++i) {
+        ar[i] = sAr[buf][kr][wr * WM + i * 16 + (lane & 15)];
+        ai[i] = sAi[buf][kr][wr * WM + i * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        br[j] = sBr[buf][kr][wc * WN + j * 16 + (lane & 15)];
+        bi[j] = sBi[buf][kr][wc * WN + j * 16 + (lane & 15)];
+      }
+      // the two products into each accumulator are issued a full sweep apart, so dependent MFMAs
+      // never follow each other
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          accr[i][j] = mfma16(ar[i], br[j], accr[i][j]);
+          acci[i][j] = mfma16(ar[i], bi[j], acci[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          accr[i][j] = mfma16(-ai[i], bi[j], accr[i][j]);
+          acci[i][j] = mfma16(ai[i], br[j], acci[i][j]);
+        }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  double alpha = g.alpha;
+  if (g.alpha_dev) alpha *= inst_ptr(g.alpha_dev, g.bsAlpha, bz)[0];
+  if (g.alpha_dev2) alpha *= inst_ptr(g.alpha_dev2, g.bsAlpha2, bz)[0];
+  CC* __restrict__ C = reinterpret_cast<CC*>(inst_ptr(g.C, g.bsC, bz));
+#pragma unroll
+  for (int i = 0; i < MB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int n = n0 + wc * WN + j * 16 + (lane & 15);
+      if (n >= N) continue;
+      const int32_t cn = g.offCn[n];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wr * WM + i * 16 + 4 * (lane >> 4) + r;
+        if (m < M) {
+          CC out;
+          out.x = TC(double(accr[i][j][r]) * alpha);
+          out.y = TC(double(acci[i][j][r]) * alpha);
+          C[(int64_t)g.offCm[m] + cn] = out;
+        }
+      }
+    }
+}
+
+// Tile choice by shape (measured on MI355X): the pipelined 64x64 kernel when there are enough
+// 64x64 output tiles to give every compute unit two; otherwise, and for FP64 accumulation, the
+// table-driven 32x32 kernel, whose many small workgroups hide latency best.
+int gemm_pick_tile(int M, int N, int K, int batch, bool fp64_acc) {
+  const int64_t t64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64) * batch;
+  if (!fp64_acc && M >= 64 && N >= 64 && K >= 16 && t64 >= 512) return GEMM_PIPE64;
+  return GEMM_TILE32;
+}
+
+// Split-K for 32x32 launches with fewer than 512 output tiles and a long reduction: chunks of at
+// least 256 until there are about 1024 workgroups.
+int gemm_pick_ksplit(int M, int N, int K, int batch, int tile) {
+  if (tile != GEMM_TILE32 || K < 512) return 1;
+  const int64_t t32 = (int64_t)((M + 31) / 32) * ((N + 31) / 32) * batch;
+  if (t32 >= 512) return 1;
+  int64_t ks = (1024 + t32 - 1) / t32;
+  const int64_t kmax = K / 256;
+  if (ks > kmax) ks = kmax;
+  if (ks > 64) ks = 64;
+  return ks < 2 ? 1 : (int)ks;
+}
+
 template <typename TA, typename TB, typename TC, typename ACC>
 static hipError_t launch_t(const GemmArgs& a0, int tile, hipStream_t s) {
   if (a0.M <= 0 || a0.N <= 0 || a0.batch <= 0) return hipSuccess;
-  const int BMt = tile == 1 ? 64 : 32;
+  if (tile == GEMM_AUTO) tile = gemm_pick_tile(a0.M, a0.N, a0.K, a0.batch, sizeof(ACC) == 8);
+  if (tile != GEMM_TILE32 && tile != GEMM_TILE64 && tile != GEMM_PIPE64) return hipErrorInvalidValue;
+  if (sizeof(ACC) == 8 && tile == GEMM_PIPE64) tile = GEMM_TILE64;   // pipelined: FP32 only
+  const bool split = a0.ksplit > 1;
+  if (split && (tile != GEMM_TILE32 || !a0.part || a0.kchunk % 16 != 0 ||
+                (int64_t)a0.kchunk * a0.ksplit < a0.K))
+    return hipErrorInvalidValue;
+  if ((int64_t)a0.batch * a0.ksplit > 65535) return hipErrorInvalidValue;
+  const int BMt = tile == GEMM_TILE32 ? 32 : 64;
   const int max_rows = 65535 * BMt;   // grid y limit per launch
+  if (split && a0.M > max_rows) return hipErrorInvalidValue;
   for (int mb = 0; mb < a0.M; mb += max_rows) {
     GemmArgs a = a0;
     a.mbase = mb;
     const int rows = a0.M - mb < max_rows ? a0.M - mb : max_rows;
-    if (tile == 1) {
-      dim3 grid((a.N + 63) / 64, (rows + 63) / 64, a.batch);
+    const dim3 grid((a.N + BMt - 1) / BMt, (rows + BMt - 1) / BMt, a.batch * a.ksplit);
+    if (tile == GEMM_PIPE64)
+      hipLaunchKernelGGL((k_cgemm_pipe<TA, TB, TC, 64, 64>), grid, dim3(256), 0, s, a);
+    else if (tile == GEMM_TILE64)
       hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
-    } else {
-      dim3 grid((a.N + 31) / 32, (rows + 31) / 32, a.batch);
+    else
       hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 32, 32>), grid, dim3(256), 0, s, a);
-    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+  }
+  if (split) {
+    const int64_t mn = (int64_t)a0.M * a0.N;
+    hipLaunchKernelGGL((k_splitk_reduce<TC, ACC>), dim3((unsigned)((mn + 255) / 256), a0.batch),
+                       dim3(256), 0, s, a0);
+    return hipGetLastError();
   }
   return hipSuccess;
 }

@@ -39,13 +39,99 @@ extern "C" int cbc_test_gemm(int M, int N, int K, const void* A, int a_c128, int
     g.alpha_dev = nullptr; g.alpha_dev2 = nullptr; g.alpha = 1.0;
     g.batch = 1; g.bsA = g.bsB = g.bsC = g.bsAlpha = g.bsAlpha2 = 0;
     g.mbase = 0;
-    if (launch_gemm(g, a_c128 ? DT_C128 : DT_C64, b_c128 ? DT_C128 : DT_C64,
+    void* part = nullptr;
+    if (tile == GEMM_AUTO) {
+      // the compression's policy: split-K where it would split, the tile chosen at launch
+      const int t1 = gemm_pick_tile(M, N, K, 1, acc_fp64 != 0);
+      const int ks = gemm_pick_ksplit(M, N, K, 1, t1);
+      if (ks > 1) {
+        tile = t1;
+        g.ksplit = ks;
+        g.kchunk = ((K + ks - 1) / ks + 15) / 16 * 16;
+        if (hipMalloc(&part, (size_t)ks * M * N * (acc_fp64 ? 16 : 8)) != hipSuccess) rc = CBC_ENOMEM;
+        g.part = part;
+      }
+    }
+    if (rc == CBC_OK &&
+        launch_gemm(g, a_c128 ? DT_C128 : DT_C64, b_c128 ? DT_C128 : DT_C64,
                     c_c128 ? DT_C128 : DT_C64, acc_fp64 ? DT_C128 : DT_C64, tile, st) != hipSuccess)
       rc = CBC_EHIP;
-    else if (hipStreamSynchronize(st) != hipSuccess)
+    else if (rc == CBC_OK && hipStreamSynchronize(st) != hipSuccess)
       rc = CBC_EHIP;
+    if (part) (void)hipFree(part);
   }
   (void)hipFree(d);
+  return rc;
+}
+
+extern "C" int cbc_test_gemm_time(int M, int N, int K, int a_c128, int b_c128, int c_c128,
+                                  int acc_fp64, int tile, int reps, float* ms) {
+  if (M < 1 || N < 1 || K < 1 || reps < 1 || !ms) return CBC_EINVAL;
+  std::vector<int32_t> t(2 * (size_t)M + 2 * (size_t)N + 2 * (size_t)K);
+  int32_t* am = t.data();
+  int32_t* cm = am + M;
+  int32_t* bn = cm + M;
+  int32_t* cn = bn + N;
+  int32_t* ak = cn + N;
+  int32_t* bk = ak + K;
+  for (int m = 0; m < M; ++m) { am[m] = m * K; cm[m] = m * N; }
+  for (int n = 0; n < N; ++n) { bn[n] = n; cn[n] = n; }
+  for (int k = 0; k < K; ++k) { ak[k] = k; bk[k] = k * N; }
+  const size_t ea = a_c128 ? 16 : 8, eb = b_c128 ? 16 : 8, ec = c_c128 ? 16 : 8;
+  int32_t* d = nullptr;
+  void *A = nullptr, *B = nullptr, *C = nullptr, *part = nullptr;
+  int rc = CBC_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMalloc(&d, t.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMalloc(&A, ea * M * K) != hipSuccess || hipMalloc(&B, eb * K * N) != hipSuccess ||
+      hipMalloc(&C, ec * M * N) != hipSuccess) {
+    rc = CBC_ENOMEM;
+  } else if (hipMemcpy(d, t.data(), t.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemset(A, 0, ea * M * K) != hipSuccess || hipMemset(B, 0, eb * K * N) != hipSuccess ||
+             hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    rc = CBC_EHIP;
+  } else {
+    GemmArgs g;
+    g.A = A; g.B = B; g.C = C; g.M = M; g.N = N; g.K = K;
+    g.offAm = d; g.offCm = d + M; g.offBn = d + 2 * M; g.offCn = d + 2 * M + N;
+    g.offAk = d + 2 * M + 2 * N; g.offBk = d + 2 * M + 2 * N + K;
+    g.conjA = 0; g.conjB = 0; g.a_kfast = 1; g.b_kfast = 0;
+    g.alpha_dev = nullptr; g.alpha_dev2 = nullptr; g.alpha = 1.0;
+    g.batch = 1; g.bsA = g.bsB = g.bsC = g.bsAlpha = g.bsAlpha2 = 0;
+    g.mbase = 0;
+    const DType ta = a_c128 ? DT_C128 : DT_C64, tb = b_c128 ? DT_C128 : DT_C64;
+    const DType tc = c_c128 ? DT_C128 : DT_C64, tacc = acc_fp64 ? DT_C128 : DT_C64;
+    if (tile == GEMM_AUTO) {
+      const int t1 = gemm_pick_tile(M, N, K, 1, acc_fp64 != 0);
+      const int ks = gemm_pick_ksplit(M, N, K, 1, t1);
+      if (ks > 1) {
+        tile = t1;
+        g.ksplit = ks;
+        g.kchunk = ((K + ks - 1) / ks + 15) / 16 * 16;
+        if (hipMalloc(&part, (size_t)ks * M * N * (acc_fp64 ? 16 : 8)) != hipSuccess) rc = CBC_ENOMEM;
+        g.part = part;
+      }
+    }
+    if (rc == CBC_OK && launch_gemm(g, ta, tb, tc, tacc, tile, nullptr) != hipSuccess) rc = CBC_EHIP;
+    (void)hipEventRecord(e0, nullptr);
+    for (int r = 0; r < reps && rc == CBC_OK; ++r)
+      if (launch_gemm(g, ta, tb, tc, tacc, tile, nullptr) != hipSuccess) rc = CBC_EHIP;
+    (void)hipEventRecord(e1, nullptr);
+    if (rc == CBC_OK && hipEventSynchronize(e1) == hipSuccess) {
+      float t_ms = 0.0f;
+      (void)hipEventElapsedTime(&t_ms, e0, e1);
+      *ms = t_ms / reps;
+    } else {
+      rc = CBC_EHIP;
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipFree(d);
+  (void)hipFree(part);
+  (void)hipFree(A);
+  (void)hipFree(B);
+  (void)hipFree(C);
   return rc;
 }
 

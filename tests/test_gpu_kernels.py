@@ -26,9 +26,12 @@ def test_gemm_fp64(lib, M, N, K, tile):
 
 
 @pytest.mark.parametrize("tA,cA,tB,cB", [(1, 1, 0, 0), (0, 0, 1, 1), (1, 0, 1, 0), (0, 1, 0, 1)])
-def test_gemm_transpose_conj(lib, tA, cA, tB, cB):
+@pytest.mark.parametrize("M,N,K,tile", [(45, 33, 70, 0), (200, 150, 70, 2), (1700, 2100, 37, 1),
+                                        (1700, 2100, 37, -1)])
+def test_gemm_transpose_conj(lib, tA, cA, tB, cB, M, N, K, tile):
+    """Every operand layout (k fastest or not) through both tile sizes of the table-driven kernel
+    and the pipelined FP32 kernel (FP64 accumulation falls back to the table-driven 64 x 64 tiles)."""
     rng = np.random.default_rng(7)
-    M, N, K = 45, 33, 70
     a = crand(rng, K, M) if tA else crand(rng, M, K)
     b = crand(rng, N, K) if tB else crand(rng, K, N)
     opa = a.T if tA else a
@@ -39,20 +42,38 @@ def test_gemm_transpose_conj(lib, tA, cA, tB, cB):
         dt = torch.complex128 if acc else torch.complex64
         C = lib.test_gemm(torch.from_numpy(a).to(dt).cuda(), torch.from_numpy(b).to(dt).cuda(),
                           transA=bool(tA), conjA=bool(cA), transB=bool(tB), conjB=bool(cB),
-                          acc_fp64=acc).cpu().numpy()
+                          acc_fp64=acc, tile=tile).cpu().numpy()
         ref = opa @ opb
         tol = 1e-13 if acc else 2e-5
         assert np.abs(C - ref).max() <= tol * np.sqrt(K) * 4, (acc, np.abs(C - ref).max())
 
 
-@pytest.mark.parametrize("M,N,K", [(32, 32, 16), (100, 200, 300), (257, 65, 64)])
-def test_gemm_fp32(lib, M, N, K):
+@pytest.mark.parametrize("tile", [-1, 0, 1, 2])
+@pytest.mark.parametrize("M,N,K", [(32, 32, 16), (100, 200, 300), (257, 65, 64), (64, 64, 16),
+                                   (2049, 1793, 100), (4096, 1024, 256)])
+def test_gemm_fp32(lib, M, N, K, tile):
     rng = np.random.default_rng(M + N + K)
     a, b = crand(rng, M, K).astype(np.complex64), crand(rng, K, N).astype(np.complex64)
     C = lib.test_gemm(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), acc_fp64=False,
-                      tile=1).cpu().numpy()
+                      tile=tile).cpu().numpy()
     ref = a.astype(np.complex128) @ b.astype(np.complex128)
     assert np.abs(C - ref).max() <= 1e-5 * np.sqrt(K) * 4
+
+
+@pytest.mark.parametrize("acc", [True, False])
+@pytest.mark.parametrize("M,N,K", [(64, 96, 1000), (70, 50, 1500), (256, 1024, 4096)])
+def test_gemm_split_k(lib, M, N, K, acc):
+    """Few output tiles and a long reduction: the reduction is split into chunks whose sums are added
+    in order by a second kernel (the compression's own policy, tile = -1)."""
+    rng = np.random.default_rng(M + N + K)
+    dt = np.complex128 if acc else np.complex64
+    a, b = crand(rng, M, K).astype(dt), crand(rng, K, N).astype(dt)
+    C = lib.test_gemm(torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda(), acc_fp64=acc,
+                      tile=-1).cpu().numpy()
+    ref = a.astype(np.complex128) @ b.astype(np.complex128)
+    tol = 1e-13 if acc else 2e-6
+    assert np.abs(C - ref).max() <= tol * np.sqrt(K) * 4 * np.abs(ref).max() / np.sqrt(K), \
+        np.abs(C - ref).max()
 
 
 def herm_psd(rng, s, rank=None, n=None):
