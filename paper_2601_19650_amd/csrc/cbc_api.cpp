@@ -518,6 +518,7 @@ struct Builder {
       nd.off = P.ndrop_off;
       c.ndrop = nd;
       c.cls = CBC_K_CHOL;
+      if (k > CHOL_LDS_MAX) c.work = scr(sizeof(double) * chol_work_doubles((int)k), DT_C128);
       c.flops = 8.0 / 3.0 * (double)k * k * k;
       c.bytes = 32.0 * (double)k * k;
       P.ops.push_back(c);
@@ -570,6 +571,7 @@ struct Builder {
       nd.off = P.ndrop_off;
       c.ndrop = nd;
       c.cls = CBC_K_CHOL;
+      if (k > CHOL_LDS_MAX) c.work = scr(sizeof(double) * chol_work_doubles((int)k), DT_C128);
       // Cholesky (4/3 k^3) plus triangular inverse (4/3 k^3), complex
       c.flops = 8.0 / 3.0 * (double)k * k * k;
       c.bytes = 32.0 * (double)k * k;
@@ -1196,6 +1198,7 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         a.tstamp = nullptr;
         a.batch = c.batch;
         a.bs = c.ws_inst;
+        a.work = op.work.src == S_NONE ? nullptr : (double2*)resolve(P, c, op.work);
         e = launch_chol_inv(a, st);
         break;
       }

@@ -41,6 +41,10 @@ struct GemmArgs {
   int kchunk = 0;
   void* part = nullptr;
   int64_t bsPart = 0;   // per-instance byte stride of part
+  // dense mode (offAm == nullptr): element offsets are m * sAm + k * sAk, k * sBk + n * sBn and
+  // m * sCm + n * sCn instead of table lookups
+  int64_t sAm = 0, sAk = 0, sBk = 0, sBn = 0, sCm = 0, sCn = 0;
+  int accum = 0;        // 1: C += alpha * op(A) op(B)
 };
 // pointer of instance b for a per-instance byte stride
 template <typename T>
@@ -102,7 +106,15 @@ struct CholArgs {
   long long* tstamp;  // optional: wall-clock stamps at phase boundaries (4 entries), or nullptr
   int batch;          // instances; every pointer above (except tstamp) advances by bs bytes
   int64_t bs;
+  double2* work = nullptr;   // k > CHOL_LDS_MAX: chol_work_doubles(k) doubles of scratch
+  // internal (diagonal blocks of the blocked factorisation): row stride of G and Cinv, and an
+  // absolute pivot threshold read from the device (the shift is then already applied)
+  int ld = 0;
+  const double* thresh_dev = nullptr;
 };
+// largest k factorised by one LDS-resident workgroup; larger ones are blocked and need `work`
+constexpr int CHOL_LDS_MAX = 88;
+size_t chol_work_doubles(int k);
 hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st);
 
 // Elementwise helpers.

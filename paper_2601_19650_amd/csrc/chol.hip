@@ -34,121 +34,9 @@ __device__ inline CholArgs chol_inst(const CholArgs& a0, int b) {
   a.log_scale = inst_ptr(a0.log_scale, a0.bs, b);
   a.scale = inst_ptr(a0.scale, a0.bs, b);
   a.ndrop = inst_ptr(a0.ndrop, a0.bs, b);
+  a.work = inst_ptr(a0.work, a0.bs, b);
+  a.thresh_dev = inst_ptr(a0.thresh_dev, a0.bs, b);
   return a;
-}
-
-__global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(CholArgs a0) {
-  const CholArgs a = chol_inst(a0, blockIdx.x);
-  extern __shared__ int dropped[];
-  __shared__ double red[32];
-  __shared__ double sh_trace, sh_thresh;
-  const int k = a.k;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
-  double2* G = a.G;
-
-  // trace and shift
-  double tr = 0.0;
-  for (int i = tid; i < k; i += blockDim.x) tr += G[(size_t)i * k + i].x;
-  tr = wsum(tr);
-  if (lane == 0) red[wave] = tr;
-  __syncthreads();
-  if (tid == 0) {
-    double t = 0.0;
-    for (int w = 0; w < nwave; ++w) t += red[w];
-    sh_trace = t;
-    if (a.log_scale) {
-      a.log_scale[0] = t > 0.0 ? -0.5 * log(t) : 0.0;
-      a.scale[0] = t > 0.0 ? 1.0 / sqrt(t) : 1.0;
-    }
-  }
-  __syncthreads();
-  const double trace = sh_trace;
-  const double shift = a.shift_rel * trace;
-  double mx = 0.0;
-  for (int i = tid; i < k; i += blockDim.x) {
-    double2 g = G[(size_t)i * k + i];
-    g.x += shift;
-    g.y = 0.0;
-    G[(size_t)i * k + i] = g;
-    mx = fmax(mx, g.x);
-    dropped[i] = 0;
-  }
-  mx = wmax(mx);
-  if (lane == 0) red[wave] = mx;
-  __syncthreads();
-  if (tid == 0) {
-    double m = 0.0;
-    for (int w = 0; w < nwave; ++w) m = fmax(m, red[w]);
-    sh_thresh = a.drop_rel * m;
-  }
-  __syncthreads();
-  const double thresh = sh_thresh;
-
-  // right-looking Cholesky, lower triangle
-  for (int j = 0; j < k; ++j) {
-    const double djj = G[(size_t)j * k + j].x;
-    if (!(djj > thresh)) {
-      if (tid == 0) dropped[j] = 1;
-      for (int i = j + tid; i < k; i += blockDim.x) G[(size_t)i * k + j] = make_double2(0.0, 0.0);
-      __syncthreads();
-      continue;
-    }
-    const double c = sqrt(djj);
-    const double ic = 1.0 / c;
-    for (int i = j + 1 + tid; i < k; i += blockDim.x) {
-      double2 g = G[(size_t)i * k + j];
-      g.x *= ic;
-      g.y *= ic;
-      G[(size_t)i * k + j] = g;
-    }
-    __syncthreads();
-    if (tid == 0) G[(size_t)j * k + j] = make_double2(c, 0.0);
-    // trailing update of the lower triangle: G[i][l] -= C[i][j] conj(C[l][j]), j < l <= i
-    for (int i = j + 1 + wave; i < k; i += nwave) {
-      const double2 cij = G[(size_t)i * k + j];
-      for (int l = j + 1 + lane; l <= i; l += 64) {
-        const double2 clj = G[(size_t)l * k + j];
-        double2 g = G[(size_t)i * k + l];
-        g.x -= cij.x * clj.x + cij.y * clj.y;
-        g.y -= cij.y * clj.x - cij.x * clj.y;
-        G[(size_t)i * k + l] = g;
-      }
-    }
-    __syncthreads();
-  }
-
-  // triangular inverse X = C^{-1}, one column per thread (forward substitution)
-  double2* X = a.Cinv;
-  for (int c = tid; c < k; c += blockDim.x) {
-    for (int i = 0; i < c; ++i) X[(size_t)i * k + c] = make_double2(0.0, 0.0);
-    if (dropped[c]) {
-      for (int i = c; i < k; ++i) X[(size_t)i * k + c] = make_double2(0.0, 0.0);
-      continue;
-    }
-    const double2 ccc = G[(size_t)c * k + c];
-    X[(size_t)c * k + c] = make_double2(1.0 / ccc.x, 0.0);
-    for (int i = c + 1; i < k; ++i) {
-      if (dropped[i]) {
-        X[(size_t)i * k + c] = make_double2(0.0, 0.0);
-        continue;
-      }
-      double sr = 0.0, si = 0.0;
-      for (int l = c; l < i; ++l) {
-        const double2 cil = G[(size_t)i * k + l];
-        const double2 xl = X[(size_t)l * k + c];
-        sr += cil.x * xl.x - cil.y * xl.y;
-        si += cil.x * xl.y + cil.y * xl.x;
-      }
-      const double inv = -1.0 / G[(size_t)i * k + i].x;
-      X[(size_t)i * k + c] = make_double2(sr * inv, si * inv);
-    }
-  }
-  __syncthreads();
-  if (a.ndrop && tid == 0) {
-    int nd = 0;
-    for (int j = 0; j < k; ++j) nd += dropped[j];
-    a.ndrop[0] += nd;
-  }
 }
 
 // LDS-resident variant for k <= CHOL_LDS_MAX, blocked by NBc = 8 columns.
@@ -159,7 +47,6 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv(CholArgs a0) {
 // The factor lives in the lower triangle of M (row stride k+1, so column-wise lane accesses fall in
 // distinct banks); X's strictly lower part is stored transposed in the upper triangle, its diagonal
 // in xd.
-static constexpr int CHOL_LDS_MAX = 88;
 static constexpr int NBc = 8;
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -178,10 +65,15 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
   double* xd = reinterpret_cast<double*>(M + (size_t)k * ld);
   int* dropped = reinterpret_cast<int*>(xd + k);
   double2* T = reinterpret_cast<double2*>(dropped + ((k + 3) & ~3));   // k x NBc block-row scratch
+  const int gld = a.ld > 0 ? a.ld : k;   // row stride of G and Cinv in global memory
   if (a.tstamp && tid == 0) a.tstamp[0] = wall_clock64();
-  for (int i = tid; i < k * k; i += blockDim.x) M[(i / k) * ld + (i % k)] = a.G[i];
+  for (int i = tid; i < k * k; i += blockDim.x) M[(i / k) * ld + (i % k)] = a.G[(size_t)(i / k) * gld + (i % k)];
   for (int i = tid; i < k; i += blockDim.x) dropped[i] = 0;
   __syncthreads();
+  if (a.thresh_dev) {
+    // diagonal block of the blocked factorisation: shift applied, threshold given
+    if (tid == 0) sh_thresh = a.thresh_dev[0];
+  } else {
   double tr = 0.0;
   for (int i = tid; i < k; i += blockDim.x) tr += M[i * ld + i].x;
   tr = wsum(tr);
@@ -210,6 +102,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
     double m = 0.0;
     for (int w = 0; w < nwave; ++w) m = fmax(m, red[w]);
     sh_thresh = a.drop_rel * m;
+  }
   }
   __syncthreads();
   const double thresh = sh_thresh;
@@ -337,7 +230,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
     double2 v = make_double2(0.0, 0.0);
     if (i == c) v = make_double2(xd[c], 0.0);
     else if (i > c) v = M[c * ld + i];
-    a.Cinv[idx] = v;
+    a.Cinv[(size_t)i * gld + c] = v;
   }
   if (a.ndrop && tid == 0) {
     int nd = 0;
@@ -348,19 +241,146 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
   if (a.tstamp && tid == 0) a.tstamp[3] = wall_clock64();
 }
 
+// ---- blocked factorisation for k > CHOL_LDS_MAX ------------------------------------------------
+// Right-looking, by blocks of CHOL_NB columns: the diagonal block is factorised and inverted by the
+// LDS kernel, the panel below it is C_ip = G_ip C_pp^{-H} and the trailing matrix is updated with
+// G -= C_ip C_jp^H (both on the contraction GEMM in dense mode, FP64). Block row i of the inverse is
+// then X_i,<i = -X_ii (C_i,<i X_<i,<i). Pivots are dropped against the same absolute threshold as
+// the unblocked algorithm (drop_rel times the largest shifted diagonal entry), so this is the same
+// computation in another order.
+static constexpr int CHOL_NB = 64;
+
+size_t chol_work_doubles(int k) {
+  return 2 * (size_t)k * k + 2 * (size_t)CHOL_NB * k + 16;
+}
+
+// trace -> log-scale / scale, diagonal shift, pivot threshold (one workgroup per instance)
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_prep(CholArgs a0, double* thresh_out) {
+  const CholArgs a = chol_inst(a0, blockIdx.x);
+  thresh_out = inst_ptr(thresh_out, a0.bs, blockIdx.x);
+  __shared__ double red[32];
+  __shared__ double sh_trace;
+  const int k = a.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  double tr = 0.0;
+  for (int i = tid; i < k; i += blockDim.x) tr += a.G[(size_t)i * k + i].x;
+  tr = wsum(tr);
+  if (lane == 0) red[wave] = tr;
+  __syncthreads();
+  if (tid == 0) {
+    double t = 0.0;
+    for (int w = 0; w < nwave; ++w) t += red[w];
+    sh_trace = t;
+    if (a.log_scale) {
+      a.log_scale[0] = t > 0.0 ? -0.5 * log(t) : 0.0;
+      a.scale[0] = t > 0.0 ? 1.0 / sqrt(t) : 1.0;
+    }
+  }
+  __syncthreads();
+  const double shift = a.shift_rel * sh_trace;
+  double mx = 0.0;
+  for (int i = tid; i < k; i += blockDim.x) {
+    double2 g = a.G[(size_t)i * k + i];
+    g.x += shift;
+    g.y = 0.0;
+    a.G[(size_t)i * k + i] = g;
+    mx = fmax(mx, g.x);
+  }
+  mx = wmax(mx);
+  __syncthreads();
+  if (lane == 0) red[wave] = mx;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int w = 0; w < nwave; ++w) m = fmax(m, red[w]);
+    thresh_out[0] = a.drop_rel * m;
+  }
+}
+
+static size_t chol_lds_bytes(int k) {
+  return (size_t)k * (k + 1) * sizeof(double2) + (size_t)k * sizeof(double) +
+         (size_t)((k + 3) & ~3) * sizeof(int) + (size_t)k * NBc * sizeof(double2);
+}
+
+// dense FP64 GEMM on sub-blocks (row-major strides), same batch layout as the factorisation
+static hipError_t dense_gemm(const CholArgs& a, int M, int N, int K, const double2* A, int64_t sAm,
+                             int64_t sAk, const double2* B, int64_t sBk, int64_t sBn, int conjB,
+                             double2* C, int64_t sCm, int64_t sCn, double alpha, int accum,
+                             hipStream_t st) {
+  GemmArgs g;
+  g.A = A; g.B = B; g.C = C; g.M = M; g.N = N; g.K = K;
+  g.offAm = g.offAk = g.offBk = g.offBn = g.offCm = g.offCn = nullptr;
+  g.sAm = sAm; g.sAk = sAk; g.sBk = sBk; g.sBn = sBn; g.sCm = sCm; g.sCn = sCn;
+  g.conjA = 0; g.conjB = conjB;
+  g.a_kfast = sAk == 1;
+  g.b_kfast = sBk == 1;
+  g.alpha_dev = nullptr; g.alpha_dev2 = nullptr; g.alpha = alpha;
+  g.batch = a.batch;
+  g.bsA = g.bsB = g.bsC = a.bs;
+  g.bsAlpha = g.bsAlpha2 = 0;
+  g.accum = accum;
+  return launch_gemm(g, DT_C128, DT_C128, DT_C128, DT_C128, GEMM_TILE32, st);
+}
+
 hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st) {
   if (a.k <= 0 || a.batch <= 0) return hipSuccess;
   if (a.k <= CHOL_LDS_MAX) {
-    const size_t lds = (size_t)a.k * (a.k + 1) * sizeof(double2) + (size_t)a.k * sizeof(double) +
-                       (size_t)((a.k + 3) & ~3) * sizeof(int) + (size_t)a.k * NBc * sizeof(double2);
+    const size_t lds = chol_lds_bytes(a.k);
     (void)hipFuncSetAttribute((const void*)k_chol_inv_lds,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_chol_inv_lds, dim3(a.batch), dim3(CHOL_THREADS), lds, st, a);
-  } else {
-    hipLaunchKernelGGL(k_chol_inv, dim3(a.batch), dim3(CHOL_THREADS), (size_t)a.k * sizeof(int), st,
-                       a);
+    return hipGetLastError();
   }
-  return hipGetLastError();
+  if (!a.work) return hipErrorInvalidValue;
+  const int k = a.k;
+  double2* G = a.G;
+  double2* X = a.Cinv;
+  double2* Cf = a.work;                                      // k x k factor panels
+  double2* T = a.work + (size_t)k * k;                       // CHOL_NB x k
+  double* thr = reinterpret_cast<double*>(T + (size_t)CHOL_NB * k);
+  hipLaunchKernelGGL(k_chol_prep, dim3(a.batch), dim3(CHOL_THREADS), 0, st, a, thr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_zero(X, (int64_t)16 * k * k, a.batch, a.bs, st);
+  if (e != hipSuccess) return e;
+  const size_t lds = chol_lds_bytes(CHOL_NB);
+  (void)hipFuncSetAttribute((const void*)k_chol_inv_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  for (int o = 0; o < k; o += CHOL_NB) {
+    const int bp = k - o < CHOL_NB ? k - o : CHOL_NB;
+    CholArgs d = a;
+    d.G = G + (size_t)o * k + o;
+    d.Cinv = X + (size_t)o * k + o;
+    d.k = bp;
+    d.ld = k;
+    d.thresh_dev = thr;
+    d.log_scale = nullptr;
+    d.scale = nullptr;
+    d.work = nullptr;
+    d.tstamp = nullptr;
+    hipLaunchKernelGGL(k_chol_inv_lds, dim3(a.batch), dim3(CHOL_THREADS), lds, st, d);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int r0 = o + bp, rows = k - r0;
+    if (rows <= 0) break;
+    // panel: Cf[r, c] = sum_l G[r, l] conj(X_pp[c, l])
+    e = dense_gemm(a, rows, bp, bp, G + (size_t)r0 * k + o, k, 1, X + (size_t)o * k + o, 1, k, 1,
+                   Cf + (size_t)r0 * k + o, k, 1, 1.0, 0, st);
+    if (e != hipSuccess) return e;
+    // trailing: G[r, r'] -= sum_c Cf[r, c] conj(Cf[r', c])
+    e = dense_gemm(a, rows, rows, bp, Cf + (size_t)r0 * k + o, k, 1, Cf + (size_t)r0 * k + o, 1, k, 1,
+                   G + (size_t)r0 * k + r0, k, 1, -1.0, 1, st);
+    if (e != hipSuccess) return e;
+  }
+  // inverse, block rows i >= 1: T = Cf[i, <i] X[<i, <i]; X[i, <i] = -X_ii T
+  for (int oi = CHOL_NB; oi < k; oi += CHOL_NB) {
+    const int bi = k - oi < CHOL_NB ? k - oi : CHOL_NB;
+    e = dense_gemm(a, bi, oi, oi, Cf + (size_t)oi * k, k, 1, X, k, 1, 0, T, k, 1, 1.0, 0, st);
+    if (e != hipSuccess) return e;
+    e = dense_gemm(a, bi, oi, bi, X + (size_t)oi * k + oi, k, 1, T, k, 1, 0, X + (size_t)oi * k, k, 1,
+                   -1.0, 0, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // ------------------------------------------------------------------------------------------------

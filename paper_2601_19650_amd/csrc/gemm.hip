@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
       const int m = m0 + r, k = k0 + kk;
       ACC re = 0, im = 0;
       if (m < M && k < K) {
-        const CA v = A[(int64_t)g.offAm[m] + g.offAk[k]];
+        const CA v = A[g.offAm ? (int64_t)g.offAm[m] + g.offAk[k] : m * g.sAm + k * g.sAk];
         re = ACC(v.x);
         im = sa * ACC(v.y);
       }
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
       const int n = n0 + c, k = k0 + kk;
       ACC re = 0, im = 0;
       if (n < N && k < K) {
-        const CB v = B[(int64_t)g.offBk[k] + g.offBn[n]];
+        const CB v = B[g.offAm ? (int64_t)g.offBk[k] + g.offBn[n] : k * g.sBk + n * g.sBn];
         re = ACC(v.x);
         im = sb * ACC(v.y);
       }
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
     for (int j = 0; j < NB; ++j) {
       const int n = n0 + wc * WN + j * 16 + (lane & 15);
       if (n >= N) continue;
-      const int32_t cn = g.offCn[n];
+      const int64_t cn = g.offAm ? (int64_t)g.offCn[n] : n * g.sCn;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         // output rows of a 16x16 block: FP32 MFMA lane l, register r -> row 4*(l/16) + r;
@@ -171,10 +171,17 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
         const int rb = sizeof(ACC) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
         const int m = m0 + wr * WM + i * 16 + rb;
         if (m < M) {
+          const int64_t ci = (g.offAm ? (int64_t)g.offCm[m] : m * g.sCm) + cn;
+          double xr = double(accr[i][j][r]) * alpha, xi = double(acci[i][j][r]) * alpha;
+          if (g.accum) {
+            const CC old = C[ci];
+            xr += double(old.x);
+            xi += double(old.y);
+          }
           CC out;
-          out.x = TC(double(accr[i][j][r]) * alpha);
-          out.y = TC(double(acci[i][j][r]) * alpha);
-          C[(int64_t)g.offCm[m] + cn] = out;
+          out.x = TC(xr);
+          out.y = TC(xi);
+          C[ci] = out;
         }
       }
     }
@@ -201,10 +208,17 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
   if (g.alpha_dev2) alpha *= inst_ptr(g.alpha_dev2, g.bsAlpha2, b)[0];
   CC* C = reinterpret_cast<CC*>(inst_ptr(g.C, g.bsC, b));
   const int m = (int)(idx / g.N), n = (int)(idx % g.N);
+  const int64_t ci = g.offAm ? (int64_t)g.offCm[m] + g.offCn[n] : m * g.sCm + n * g.sCn;
+  double xr = re * alpha, xi = im * alpha;
+  if (g.accum) {
+    const CC old = C[ci];
+    xr += double(old.x);
+    xi += double(old.y);
+  }
   CC out;
-  out.x = TC(re * alpha);
-  out.y = TC(im * alpha);
-  C[(int64_t)g.offCm[m] + g.offCn[n]] = out;
+  out.x = TC(xr);
+  out.y = TC(xi);
+  C[ci] = out;
 }
 
 // Pipelined variant for FP32 accumulation and large tiles (BM x BN = 128 x 128 or 64 x 64, BK = 16):
@@ -387,7 +401,8 @@ static hipError_t launch_t(const GemmArgs& a0, int tile, hipStream_t s) {
   if (a0.M <= 0 || a0.N <= 0 || a0.batch <= 0) return hipSuccess;
   if (tile == GEMM_AUTO) tile = gemm_pick_tile(a0.M, a0.N, a0.K, a0.batch, sizeof(ACC) == 8);
   if (tile != GEMM_TILE32 && tile != GEMM_TILE64 && tile != GEMM_PIPE64) return hipErrorInvalidValue;
-  if (sizeof(ACC) == 8 && tile == GEMM_PIPE64) tile = GEMM_TILE64;   // pipelined: FP32 only
+  // the pipelined kernel: FP32 accumulation, offset tables, no accumulation into C
+  if (tile == GEMM_PIPE64 && (sizeof(ACC) == 8 || !a0.offAm || a0.accum)) tile = GEMM_TILE64;
   const bool split = a0.ksplit > 1;
   if (split && (tile != GEMM_TILE32 || !a0.part || a0.kchunk % 16 != 0 ||
                 (int64_t)a0.kchunk * a0.ksplit < a0.K))

@@ -161,10 +161,17 @@ extern "C" int cbc_test_chol_inv(void* G, int k, double shift_rel, double drop_r
   CholArgs a;
   a.G = (double2*)G; a.k = k; a.shift_rel = shift_rel; a.drop_rel = drop_rel;
   a.Cinv = (double2*)Cinv; a.log_scale = nullptr; a.scale = nullptr; a.ndrop = (int*)ndrop;
-  a.tstamp = (long long*)tstamp;
+  a.tstamp = k <= CHOL_LDS_MAX ? (long long*)tstamp : nullptr;
   a.batch = 1;
   a.bs = 0;
-  if (launch_chol_inv(a, st) != hipSuccess) return CBC_EHIP;
-  if (hipStreamSynchronize(st) != hipSuccess) return CBC_EHIP;
-  return CBC_OK;
+  double2* w = nullptr;
+  if (k > CHOL_LDS_MAX) {
+    if (hipMalloc(&w, chol_work_doubles(k) * sizeof(double)) != hipSuccess) return CBC_ENOMEM;
+    a.work = w;
+  }
+  int rc = CBC_OK;
+  if (launch_chol_inv(a, st) != hipSuccess) rc = CBC_EHIP;
+  else if (hipStreamSynchronize(st) != hipSuccess) rc = CBC_EHIP;
+  if (w) (void)hipFree(w);
+  return rc;
 }

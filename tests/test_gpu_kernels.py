@@ -138,8 +138,9 @@ def test_eig_degenerate_cluster(lib, s):
     assert np.abs(g @ U - U * lam.cpu().numpy()[None, :]).max() <= 1e-11 * 5
 
 
-@pytest.mark.parametrize("k", [1, 5, 64, 130])
+@pytest.mark.parametrize("k", [1, 5, 64, 88, 89, 130, 256, 300])
 def test_chol_inv(lib, k):
+    """LDS-resident sizes (k <= 88) and the blocked factorisation above them."""
     rng = np.random.default_rng(k)
     g = herm_psd(rng, k)
     Ci, nd = lib.test_chol_inv(torch.from_numpy(g).cuda())
@@ -150,11 +151,11 @@ def test_chol_inv(lib, k):
     assert np.abs(np.triu(Ci, 1)).max() == 0.0
 
 
-def test_chol_inv_drops_zero_pivots(lib):
+@pytest.mark.parametrize("k,r", [(24, 15), (200, 130)])
+def test_chol_inv_drops_zero_pivots(lib, k, r):
     rng = np.random.default_rng(2)
-    k, r = 24, 15
-    s = crand(rng, r, 40)
-    s = np.concatenate([s, np.zeros((k - r, 40))])
+    s = crand(rng, r, max(40, 2 * r))
+    s = np.concatenate([s, np.zeros((k - r, s.shape[1]))])
     perm = rng.permutation(k)
     s = s[perm]
     g = s @ s.conj().T
