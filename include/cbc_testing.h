@@ -32,9 +32,10 @@ int cbc_test_gemm_time(int M, int N, int K, int a_c128, int b_c128, int c_c128, 
 /* Truncation eigensolve (Sec. III A "compress ... for example via singular value decomposition",
  * realised on the FP64 Gram matrix): G (s x s complex128 Hermitian, overwritten) -> U (s x kmax
  * complex128, top eigenvectors as columns, zero beyond the kept count), lam (kmax doubles,
- * descending), kkeep (1 int), inv_sqrt_l0 (1 double). tstamp: nullptr, or 8 int64 device slots that
- * receive wall-clock stamps (100 MHz) at the phase boundaries: start, tridiagonal, eigenvalues,
- * eigenvectors, back-transformed. */
+ * descending), kkeep (1 int), inv_sqrt_l0 (1 double). tstamp: nullptr, or 16 int64 device slots:
+ * wall-clock stamps (100 MHz) of the start [0] and the ends of the tridiagonal reduction [1], the
+ * eigenvalues [2] and the eigenvectors [3]; accumulated durations of the reduction's phases [4..6]
+ * (and, for s > 128, [8..12]); the number of eigenvalue clusters [7]. */
 int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void* lam, void* kkeep,
                  void* inv_sqrt_l0, void* tstamp, void* stream);
 

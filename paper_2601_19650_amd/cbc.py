@@ -348,7 +348,7 @@ def test_eig(G, kmax, tol=0.0, stamps=None):
     lam = torch.empty(kmax, dtype=torch.float64, device=G.device)
     kk = torch.empty(1, dtype=torch.int32, device=G.device)
     inv = torch.empty(1, dtype=torch.float64, device=G.device)
-    ts = torch.zeros(8, dtype=torch.int64, device=G.device)
+    ts = torch.zeros(16, dtype=torch.int64, device=G.device)
     _check(_testing_lib().cbc_test_eig(G.data_ptr(), s, kmax, float(tol), U.data_ptr(),
                                        lam.data_ptr(), kk.data_ptr(), inv.data_ptr(),
                                        ts.data_ptr() if stamps is not None else None, _stream()),
@@ -358,7 +358,8 @@ def test_eig(G, kmax, tol=0.0, stamps=None):
         # tridiagonal, eigenvalues (incl. launch), eigenvectors (incl. launch), then the
         # tridiagonal step phases A/B/D and the number of clusters
         stamps.append([(t[1] - t[0]) / 100.0, (t[2] - t[1]) / 100.0, (t[3] - t[2]) / 100.0,
-                       t[4] / 100.0, t[5] / 100.0, t[6] / 100.0, float(t[7])])
+                       t[4] / 100.0, t[5] / 100.0, t[6] / 100.0, float(t[7])] +
+                      [x / 100.0 for x in t[8:13]])
     return U, lam, int(kk.item()), float(inv.item())
 
 

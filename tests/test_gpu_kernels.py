@@ -107,6 +107,22 @@ def test_eig_topk(lib, s, kmax):
         assert np.abs(p_gpu - p_ref).max() <= 1e-13 / gap * s
 
 
+def test_eig_multi_workgroup_repeatable(lib):
+    """The multi-workgroup reduction (s > 128) sums in a fixed order: repeated solves of the same
+    matrix are bitwise identical and match the reference."""
+    rng = np.random.default_rng(21)
+    s, kmax = 700, 200
+    g = herm_psd(rng, s)
+    G = torch.from_numpy(g).cuda()
+    runs = [lib.test_eig(G, kmax) for _ in range(4)]
+    U0, l0 = runs[0][0].cpu().numpy(), runs[0][1].cpu().numpy()
+    for U, lam, _, _ in runs[1:]:
+        assert np.array_equal(U.cpu().numpy(), U0) and np.array_equal(lam.cpu().numpy(), l0)
+    w = np.linalg.eigvalsh(g)[::-1]
+    assert np.abs(l0 - w[:kmax]).max() <= 1e-12 * w[0] * s
+    assert np.abs(g @ U0 - U0 * l0[None, :]).max() <= 1e-11 * w[0]
+
+
 def test_eig_rank_deficient_and_tol(lib):
     rng = np.random.default_rng(3)
     s, r = 60, 20
