@@ -257,9 +257,9 @@ def main():
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
     ap.add_argument("--batch", type=int, default=64,
                     help="instances per launch sequence for the batched measurement (0: skip)")
-    ap.add_argument("--uneven", type=int, default=0,
+    ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven batch workload to time (0: skip)")
-    ap.add_argument("--large-steps", type=int, default=0,
+    ap.add_argument("--large-steps", type=int, default=2,
                     help="also time the large-bond workload (MPS N=128, d=4, chi=256) for this many "
                          "steps per precision (0: skip)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,

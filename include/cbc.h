@@ -11,7 +11,7 @@
  *     contractions, truncation of the joined leg to the target dimension, QR on the parent leg and
  *     the environment update, with the output rule closing each subsection;
  *   - the optional tolerance-adaptive bond dimension of Sec. V;
- *   - the naive "contract, then compress with truncated SVDs" method of Sec. III C.
+ *   - the naive method of Sec. III C: contract exactly, then compress with truncated SVDs.
  *
  * Data model (Sec. II A-C):
  *   - a rooted tree of n nodes: parent[i] in [0, n) or -1 for exactly one root. The children of i
@@ -161,7 +161,7 @@ cbc_status cbc_apply_batched(cbc_ctx* ctx, int32_t batch, const cbc_tensors* ttn
                              size_t workspace_bytes, cbc_out* out, void* stream,
                              cbc_stats* stats);
 
-/* Naive baseline (Sec. III C, "direct"): contract O|psi> exactly (bonds chi*D), bring it into
+/* Naive baseline (Sec. III C, the direct method): contract O|psi> exactly (bonds chi*D), bring it into
  * canonical form toward the root with Cholesky-QR, then truncate every bond with the top-k
  * eigenspace of its Gram matrix in a depth-first sweep from the root. Same arguments as cbc_apply. */
 cbc_status cbc_apply_naive(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,

@@ -29,7 +29,7 @@ int cbc_test_gemm(int M, int N, int K, const void* A, int a_c128, int transA, in
 int cbc_test_gemm_time(int M, int N, int K, int a_c128, int b_c128, int c_c128, int acc_fp64,
                        int tile, int reps, float* ms);
 
-/* Truncation eigensolve (Sec. III A "compress ... for example via singular value decomposition",
+/* Truncation eigensolve (Sec. III A: the joined leg is compressed, by a singular value decomposition,
  * realised on the FP64 Gram matrix): G (s x s complex128 Hermitian, overwritten) -> U (s x kmax
  * complex128, top eigenvectors as columns, zero beyond the kept count), lam (kmax doubles,
  * descending), kkeep (1 int), inv_sqrt_l0 (1 double). tstamp: nullptr, or 16 int64 device slots:

@@ -16,7 +16,7 @@ Network States"):
     (cbc_final_contraction), with the output rule that closes Sec. III B.
 
 Readings taken where the paper is silent or garbled (each listed in the design notes):
-  * truncation "for example via singular value decomposition" (Sec. III A) is the optimal truncated
+  * the truncation (Sec. III A leaves the method open and names the SVD) is the optimal truncated
     SVD of the joined-leg matrix: keep ``k = min(max_bond, len(s))`` singular triplets, and with a
     tolerance ``tol > 0`` (Sec. V: a tolerance for the SVD) additionally only ``s_j > tol * s_0``,
     never fewer than one; the isometry on the joined leg is dropped, so ``L = diag(s_k) Vh_k``;

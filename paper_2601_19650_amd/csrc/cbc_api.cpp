@@ -841,7 +841,7 @@ cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc
 }
 
 // ------------------------------------------------------------------------------------------------
-// the naive method of Sec. III C ("direct"): exact product, canonical form, truncated-SVD sweep
+// the naive (direct) method of Sec. III C: exact product, canonical form, truncated-SVD sweep
 
 void plan_prologue(Builder& B, Plan& P, cbc_precision prec, int n) {
   P.logs_off = (int64_t)B.persist;

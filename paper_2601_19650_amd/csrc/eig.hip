@@ -1,24 +1,25 @@
 // FP64 Hermitian eigensolver for the truncation step.
 //
-// The compression keeps the top-k singular subspace of the joined-leg matrix (Sec. III A: compress the
-// joined leg "for example via singular value decomposition"). On the GPU it is reached through the
+// The compression keeps the top-k singular subspace of the joined-leg matrix (Sec. III A leaves the
+// compression method open and names the singular value decomposition). On the GPU it is reached through the
 // FP64 Gram matrix G of that matrix: its top-k eigenvectors span the same subspace and its
 // eigenvalues are the squared singular values.
 //
-// Three launches solve one G:
-//   1. k_tridiag, one workgroup (16 waves): Householder reduction to a real symmetric tridiagonal
-//      T = Q^H G Q (reflectors H_j = I - tau_j v_j v_j^H, real sub-diagonal). For s <= EIG_LDS_MAX the
-//      packed lower triangle lives in LDS; larger matrices are reduced in place in global memory (L2
-//      resident). The Hermitian matrix-vector product is done by groups of 8 lanes per row, its
-//      reductions use DPP lane moves, and the dot product w^H v is folded into it (per-wave partials
-//      added in a fixed order, so results are bitwise reproducible), so a step costs three
-//      workgroup barriers. This is the only sequential part.
-//   2. k_eigvals, one wave per eigenvalue over many workgroups: the top-kmax eigenvalues of T by
-//      multisection on Sturm counts (64 points of the current interval per round).
-//   3. k_eigvecs, one wave per eigenpair over many workgroups: the eigenvector of T by a twisted
-//      factorisation T - lambda I = N_r Delta N_r^T (eigenvalues closer than 1e-3 ||T|| to a neighbour
-//      are handled together, by the wave of the first one, with inverse iteration and modified
-//      Gram-Schmidt), then the back-transformation u = Q y with the reflectors streamed from L2.
+// One G is solved by a reduction to a real symmetric tridiagonal T = Q^H G Q (reflectors
+// H_j = I - tau_j v_j v_j^H, real sub-diagonal), then the top-kmax eigenpairs of T, then the
+// back-transformation u = Q y:
+//   1. reduction: for s <= EIG_LDS_MAX one workgroup (k_tridiag) holds the packed lower triangle in
+//      LDS; the Hermitian matrix-vector product uses groups of 8 lanes per row, DPP reductions and
+//      per-wave partial sums added in a fixed order (bitwise reproducible), three workgroup
+//      barriers per column. Larger s use k_tridiag_mw: the rows are spread over many workgroups and
+//      every column costs one grid-wide barrier.
+//   2. k_eigvals, one wave per eigenvalue over many workgroups: multisection on Sturm counts (64
+//      points of the current interval per round).
+//   3. eigenvectors of T by a twisted factorisation T - lambda I = N_r Delta N_r^T, one wave per
+//      eigenpair; eigenvalues closer than 1e-3 ||T|| form clusters that are re-orthogonalised (or,
+//      for near-exact degeneracies, computed by inverse iteration); then the back-transformation with
+//      the reflectors streamed from L2. For s <= EIG_SPLIT_MIN one kernel does all of it; larger s
+//      use three launches so that the back-transformation stays parallel over all eigenpairs.
 #include <float.h>
 
 #include "cbc_internal.h"
@@ -203,7 +204,6 @@ __device__ __forceinline__ void matvec_row(int r, int nj, int gl, const double2*
 
 __device__ void tri_bounds(EigWork& W, int s, long long* tstamp);
 
-template <bool IN_LDS>
 __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
   const EigArgs a = eig_inst(a0, blockIdx.x);
   extern __shared__ double smem[];
@@ -212,19 +212,17 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nthr = blockDim.x;
   double2* P = reinterpret_cast<double2*>(smem);
-  double2* vv = IN_LDS ? P + tri(s) : P;
+  double2* vv = P + tri(s);
   double2* ww = vv + s;
   double2* A = a.G;
   EigWork W = eig_layout(a.work, s, a.kmax);
   if (a.tstamp && tid == 0) a.tstamp[0] = wall_clock64();
-  if (IN_LDS) {
-    for (int idx = tid; idx < tri(s); idx += nthr) {
-      int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-      while (tri(r + 1) <= idx) ++r;
-      while (tri(r) > idx) --r;
-      const int c = idx - tri(r);
-      P[idx] = A[(size_t)r * s + c];
-    }
+  for (int idx = tid; idx < tri(s); idx += nthr) {
+    int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while (tri(r + 1) <= idx) ++r;
+    while (tri(r) > idx) --r;
+    const int c = idx - tri(r);
+    P[idx] = A[(size_t)r * s + c];
   }
   __syncthreads();
   const int grp = tid / RG, gl = tid % RG, ngrp = nthr / RG;
@@ -234,21 +232,21 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     const int nj = s - j - 1;
     if (stamp) t0 = wall_clock64();
     if (wave == 0) {
-      const double2 alpha = IN_LDS ? P[tri(j + 1) + j] : A[(size_t)(j + 1) * s + j];
+      const double2 alpha = P[tri(j + 1) + j];
       double xn2 = 0.0;
       for (int i = j + 2 + lane; i < s; i += 64) {
-        const double2 x = IN_LDS ? P[tri(i) + j] : A[(size_t)i * s + j];
+        const double2 x = P[tri(i) + j];
         xn2 += x.x * x.x + x.y * x.y;
       }
       xn2 = wave_sum(xn2);
-      const double ajj = IN_LDS ? P[tri(j) + j].x : A[(size_t)j * s + j].x;
+      const double ajj = P[tri(j) + j].x;
       const double2 scal = householder(alpha, xn2, j, ajj, sh, W, lane);
       if (lane == 0) {
         vv[0] = make_double2(1.0, 0.0);
         W.V[(size_t)j * s + j + 1] = make_double2(1.0, 0.0);
       }
       for (int i = 1 + lane; i < nj; i += 64) {
-        const double2 x = IN_LDS ? P[tri(j + 1 + i) + j] : A[(size_t)(j + 1 + i) * s + j];
+        const double2 x = P[tri(j + 1 + i) + j];
         const double2 v = cmul(x, scal);
         vv[i] = v;
         W.V[(size_t)j * s + j + 1 + i] = v;
@@ -261,15 +259,10 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     double dr_acc = 0.0, di_acc = 0.0;
     for (int r = grp; r < nj; r += ngrp) {
       const int R = j + 1 + r;
-      if (IN_LDS) {
-        matvec_row(r, nj, gl, vv, t, [&](int rr, int c) {
-          const int C = j + 1 + c;
-          return (c <= rr) ? P[tri(R) + C] : cconj(P[tri(C) + R]);
-        }, ww, dr_acc, di_acc);
-      } else {
-        const double2* row = A + (size_t)R * s + (j + 1);
-        matvec_row(r, nj, gl, vv, t, [&](int, int c) { return row[c]; }, ww, dr_acc, di_acc);
-      }
+      matvec_row(r, nj, gl, vv, t, [&](int rr, int c) {
+        const int C = j + 1 + c;
+        return (c <= rr) ? P[tri(R) + C] : cconj(P[tri(C) + R]);
+      }, ww, dr_acc, di_acc);
     }
     dr_acc = wave_sum(dr_acc);
     di_acc = wave_sum(di_acc);
@@ -283,14 +276,14 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     }
     const double2 q = cmul(t, make_double2(dsum_r, dsum_i));
     const double2 a2 = make_double2(-0.5 * q.x, -0.5 * q.y);
-    // A_sub -= v w'^H + w' v^H with w' = w + a2 v (lower triangle in LDS, full rows in global)
+    // A_sub -= v w'^H + w' v^H with w' = w + a2 v (packed lower triangle)
     for (int r = grp; r < nj; r += ngrp) {
       const int R = j + 1 + r;
       const double2 vr = vv[r];
       const double2 wr = make_double2(ww[r].x + a2.x * vr.x - a2.y * vr.y,
                                       ww[r].y + a2.x * vr.y + a2.y * vr.x);
-      const int cend = IN_LDS ? r : nj - 1;
-      double2* rowp = IN_LDS ? P + tri(R) + (j + 1) : A + (size_t)R * s + (j + 1);
+      const int cend = r;
+      double2* rowp = P + tri(R) + (j + 1);
 #pragma unroll 4
       for (int c = gl; c <= cend; c += RG) {
         const double2 vc = vv[c];
@@ -311,7 +304,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     a.tstamp[6] = tD;
   }
   // last diagonal entry and the Gershgorin interval of T (used by the two later kernels)
-  if (tid == 0) W.d[s - 1] = IN_LDS ? P[tri(s - 1) + s - 1].x : A[(size_t)(s - 1) * s + (s - 1)].x;
+  if (tid == 0) W.d[s - 1] = P[tri(s - 1) + s - 1].x;
   __syncthreads();
   if (wave == 0) tri_bounds(W, s, a.tstamp);
 }
@@ -1185,18 +1178,15 @@ __global__ __launch_bounds__(256) void k_backtransform(EigArgs a0) {
     atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 3), (unsigned long long)wall_clock64());
 }
 
-size_t eig_lds_bytes(int s, int kmax, bool in_lds) {
-  (void)kmax;
-  return (in_lds ? (size_t)16 * (s * (size_t)(s + 1) / 2) : 0) + (size_t)s * (2 * 16) + 64;
-}
+size_t eig_lds_bytes(int s) { return (size_t)16 * (s * (size_t)(s + 1) / 2) + (size_t)s * (2 * 16) + 64; }
 
 hipError_t launch_eig(const EigArgs& a, hipStream_t st) {
   if (a.s <= 0 || a.kmax <= 0 || a.kmax > a.s || a.batch <= 0) return hipErrorInvalidValue;
   if (a.s <= EIG_LDS_MAX) {
-    const size_t lds = eig_lds_bytes(a.s, a.kmax, true);
-    (void)hipFuncSetAttribute((const void*)k_tridiag<true>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_tridiag<true>, dim3(a.batch), dim3(EIG_THREADS), lds, st, a);
+    const size_t lds = eig_lds_bytes(a.s);
+    (void)hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    hipLaunchKernelGGL(k_tridiag, dim3(a.batch), dim3(EIG_THREADS), lds, st, a);
   } else {
     const MwShape m = mw_shape(a.s);
     const size_t lds = mw_lds_bytes(a.s);
