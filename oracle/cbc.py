@@ -15,21 +15,22 @@ Network States"):
     and the final leaves-to-root sweep of Eqs. (cbc_tree_third_contraction), (cbc_tree_qr) and
     (cbc_final_contraction), with the output rule that closes Sec. III B.
 
-Readings taken where the paper is silent or garbled (each listed in the design notes):
+Readings taken where the paper is silent or garbled:
   * the truncation (Sec. III A leaves the method open and names the SVD) is the optimal truncated
     SVD of the joined-leg matrix: keep ``k = min(max_bond, len(s))`` singular triplets, and with a
     tolerance ``tol > 0`` (Sec. V: a tolerance for the SVD) additionally only ``s_j > tol * s_0``,
     never fewer than one; the isometry on the joined leg is dropped, so ``L = diag(s_k) Vh_k``;
-  * the QR "on leg chi_{i-1}" is an economy LQ: ``S = R Q`` with Q's rows orthonormal, new bond
+  * the QR on the leg chi_{i-1} is an economy LQ: ``S = R Q`` with Q's rows orthonormal, new bond
     ``min(dim chi_{i-1}, rest)``;
   * in Eq. (cbc_final_contraction) Q enters complex-conjugated, as in the tensor-train update;
-  * the output case "i = 0" of Sec. III A is the root site (the first site);
+  * the output case for i = 0 in Sec. III A is the root site (the first site);
   * legs are identified by name; storage order is (sigma, parent, children...) for states and
     (sigma', sigma, parent, children...) for operators.
 
 Parity pins: tests/test_oracle_pins.py checks this module against dense contraction, the projection
 and isometry invariants, the Eckart-Young bound, an N=2 closed form, gauge and scalar covariances,
-special cases and an independent dense reformulation of the tensor-train sweep.
+special cases and an independent dense reformulation of the tensor-train sweep;
+tests/test_oracle_mutations.py shows that plausible mistakes planted in this module fail them.
 """
 from __future__ import annotations
 

@@ -1,0 +1,89 @@
+"""The oracle's pins catch plausible mistakes in the oracle.
+
+Each case edits the oracle's source the way a plausible mistake would (a dropped term, a wrong sign
+or conjugate, transposed legs, an off-by-one bond), executes the edited module, and runs a set of
+the pins of test_oracle_pins against it: at least one must fail. The unedited oracle must pass them
+all. CPU only.
+"""
+import importlib.util
+import os
+import types
+
+import pytest
+
+import oracle.cbc as ocbc
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ORACLE_SRC = open(ocbc.__file__).read()
+
+
+def _load_pins():
+    spec = importlib.util.spec_from_file_location("pins_for_mutation", os.path.join(HERE, "test_oracle_pins.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+PINS = _load_pins()
+
+CHECKS = [
+    ("exact 8-site chain vs dense", lambda: PINS.test_c1_exact_dense()),
+    ("exact binary tree vs dense", lambda: PINS.test_exact_trees_dense("binary", 7, 2, 4, 3)),
+    ("chain = tree formulation", lambda: PINS.test_tt_formulation_equals_tree_formulation()),
+    ("projection invariants", lambda: PINS.test_projection_property_dense("binary", 7, 2, 8, 4, 4)),
+    ("two-site closed form", lambda: PINS.test_two_site_closed_form()),
+    ("dense reformulation", lambda: PINS.test_dense_reformulation_chain(6, 2, 4, 3, 3)),
+    ("truncation identities", lambda: PINS.test_truncation_step_identities()),
+    ("LQ step", lambda: PINS.test_lq_step()),
+]
+
+MUTATIONS = [
+    ("LQ without the final conjugate", "return qh.conj().T", "return qh.T"),
+    ("truncation drops diag(s)", "lmat = s[:k, None] * vh[:k]", "lmat = vh[:k]"),
+    ("truncation keeps one direction too few", "k = max(k, 1)", "k = max(k - 1, 1)"),
+    ("tree R update without conj(Q)", "_r_update(state[i], op[i], qt.conj(),", "_r_update(state[i], op[i], qt,"),
+    ("chain R update without conj(Q)", 'r = np.einsum("ztx,uab,tupq,xbq->zap", q3.conj(),', 'r = np.einsum("ztx,uab,tupq,xbq->zap", q3,'),
+    ("operator legs transposed in the node contraction", "    terms.append((w, [sigp, sig] + beta))\n    if open_leg", "    terms.append((w, [sig, sigp] + beta))\n    if open_leg"),
+    ("operator legs transposed in the chain forward sweep", '"xap,tupq,uab->xtbq"', '"xap,utpq,uab->xtbq"'),
+    ("operator legs transposed in the tree R update", "    terms.append((w, [sigp, sig] + beta))\n    terms.append((qc", "    terms.append((w, [sig, sigp] + beta))\n    terms.append((qc"),
+    ("sweep 2 keeps the target child's own environment", "                if c != k:", "                if True:"),
+]
+
+
+def _with_oracle(src):
+    mod = types.ModuleType("oracle_mutant")
+    exec(compile(src, "oracle_mutant", "exec"), mod.__dict__)
+    saved = {k: getattr(PINS, k) for k in ("cbc_tree", "cbc_tt", "truncate_joined", "lq")}
+    for k in saved:
+        setattr(PINS, k, getattr(mod, k))
+    return saved
+
+
+def _restore(saved):
+    for k, v in saved.items():
+        setattr(PINS, k, v)
+
+
+def _failing_checks(src):
+    saved = _with_oracle(src)
+    failed = []
+    try:
+        for name, fn in CHECKS:
+            try:
+                fn()
+            except Exception:   # an assertion or a shape error: the pin rejects the mutant
+                failed.append(name)
+    finally:
+        _restore(saved)
+    return failed
+
+
+def test_unmutated_oracle_passes_every_check():
+    assert _failing_checks(ORACLE_SRC) == []
+
+
+@pytest.mark.parametrize("name,old,new", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_mutation_is_caught(name, old, new):
+    assert ORACLE_SRC.count(old) == 1, f"mutation site not unique: {old!r}"
+    failed = _failing_checks(ORACLE_SRC.replace(old, new))
+    assert failed, f"no pin catches: {name}"
