@@ -7,7 +7,8 @@
 // Pivots below drop_rel times the largest diagonal are dropped: their row and column of C^{-1} are
 // zero, so the matching rows of Q vanish (they carried no weight of S).
 //
-// One workgroup; G is k x k row-major in global memory (L2 resident for the sizes used).
+// A re-orthogonalisation pass (no shift) whose Gram equals the identity to rounding writes the
+// identity: its Cholesky factor and inverse are the identity to the same rounding.
 #include <float.h>
 
 #include "cbc_internal.h"
@@ -70,6 +71,30 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
   for (int i = tid; i < k * k; i += blockDim.x) M[(i / k) * ld + (i % k)] = a.G[(size_t)(i / k) * gld + (i % k)];
   for (int i = tid; i < k; i += blockDim.x) dropped[i] = 0;
   __syncthreads();
+  if (!a.thresh_dev && a.shift_rel == 0.0) {
+    // a re-orthogonalisation pass whose Gram is the identity to rounding (|G - I| <= 4 k u): its
+    // Cholesky factor and inverse are the identity to rounding as well, so write that and stop
+    double dev = 0.0;
+    for (int i = tid; i < k * k; i += blockDim.x) {
+      const int r = i / k, c = i % k;
+      const double2 g = M[r * ld + c];
+      dev = fmax(dev, fmax(fabs(g.x - (r == c ? 1.0 : 0.0)), fabs(g.y)));
+    }
+    dev = wmax(dev);
+    if (lane == 0) red[wave] = dev;
+    __syncthreads();
+    double m = 0.0;
+    for (int w = 0; w < nwave; ++w) m = fmax(m, red[w]);
+    if (m <= 4.0 * k * DBL_EPSILON * 0.5) {
+      for (int idx = tid; idx < k * k; idx += blockDim.x) {
+        const int i = idx / k, c = idx % k;
+        a.Cinv[(size_t)i * gld + c] = make_double2(i == c ? 1.0 : 0.0, 0.0);
+      }
+      if (a.tstamp && tid == 0) a.tstamp[1] = a.tstamp[2] = a.tstamp[3] = wall_clock64();
+      return;
+    }
+    __syncthreads();
+  }
   if (a.thresh_dev) {
     // diagonal block of the blocked factorisation: shift applied, threshold given
     if (tid == 0) sh_thresh = a.thresh_dev[0];

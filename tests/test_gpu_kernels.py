@@ -167,6 +167,24 @@ def test_chol_inv(lib, k):
     assert np.abs(np.triu(Ci, 1)).max() == 0.0
 
 
+@pytest.mark.parametrize("eps", [1e-16, 1e-9])
+def test_chol_inv_near_identity(lib, eps):
+    """A re-orthogonalisation pass (no shift) on a Gram within rounding of the identity returns the
+    identity; a larger deviation is factorised as usual. Both are the inverse Cholesky factor to
+    rounding."""
+    rng = np.random.default_rng(5)
+    k = 64
+    e = crand(rng, k, k) * eps
+    g = np.eye(k) + (e + e.conj().T) / 2
+    Ci, nd = lib.test_chol_inv(torch.from_numpy(g).cuda())
+    Ci = Ci.cpu().numpy()
+    ref = np.linalg.inv(np.linalg.cholesky(g))
+    assert nd == 0
+    assert np.abs(Ci - ref).max() <= 1e-13
+    if eps < 1e-15:
+        assert np.array_equal(Ci, np.eye(k))
+
+
 @pytest.mark.parametrize("k,r", [(24, 15), (200, 130)])
 def test_chol_inv_drops_zero_pivots(lib, k, r):
     rng = np.random.default_rng(2)
