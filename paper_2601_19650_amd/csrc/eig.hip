@@ -178,30 +178,6 @@ __device__ inline double2 householder(double2 alpha, double xn2, int j, double a
   return scal;
 }
 
-// Hermitian matrix-vector product row p_r = tau sum_c A[r][c] v[c] for one row group, plus the
-// row's contribution to w^H v.
-template <typename AFn>
-__device__ __forceinline__ void matvec_row(int r, int nj, int gl, const double2* vv, double2 t,
-                                           AFn aget, double2* ww, double& dr_acc, double& di_acc) {
-  double pr = 0.0, pi = 0.0;
-#pragma unroll 4
-  for (int c = gl; c < nj; c += RG) {
-    const double2 a = aget(r, c);
-    const double2 v = vv[c];
-    pr += a.x * v.x - a.y * v.y;
-    pi += a.x * v.y + a.y * v.x;
-  }
-  pr = sum8(pr);
-  pi = sum8(pi);
-  if (gl == 0) {
-    const double2 w = cmul(t, make_double2(pr, pi));
-    ww[r] = w;
-    const double2 v = vv[r];
-    dr_acc += w.x * v.x + w.y * v.y;
-    di_acc += w.x * v.y - w.y * v.x;
-  }
-}
-
 __device__ void tri_bounds(EigWork& W, int s, long long* tstamp);
 
 __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
@@ -259,10 +235,34 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     double dr_acc = 0.0, di_acc = 0.0;
     for (int r = grp; r < nj; r += ngrp) {
       const int R = j + 1 + r;
-      matvec_row(r, nj, gl, vv, t, [&](int rr, int c) {
-        const int C = j + 1 + c;
-        return (c <= rr) ? P[tri(R) + C] : cconj(P[tri(C) + R]);
-      }, ww, dr_acc, di_acc);
+      // row part (stored, contiguous) then column part (conjugated, addressed incrementally:
+      // tri(C + RG) = tri(C) + RG C + RG (RG + 1) / 2)
+      const double2* rowp = P + tri(R) + (j + 1);
+      double pr = 0.0, pi = 0.0;
+      for (int c = gl; c <= r; c += RG) {
+        const double2 a = rowp[c], v = vv[c];
+        pr += a.x * v.x - a.y * v.y;
+        pi += a.x * v.y + a.y * v.x;
+      }
+      int c = r + 1 + (((gl - r - 1) % RG) + RG) % RG;
+      int C = j + 1 + c;
+      int idx = tri(C) + R;
+      for (; c < nj; c += RG) {
+        const double2 a = P[idx], v = vv[c];
+        pr += a.x * v.x + a.y * v.y;
+        pi += a.x * v.y - a.y * v.x;
+        idx += RG * C + RG * (RG + 1) / 2;
+        C += RG;
+      }
+      pr = sum8(pr);
+      pi = sum8(pi);
+      if (gl == 0) {
+        const double2 w = cmul(t, make_double2(pr, pi));
+        ww[r] = w;
+        const double2 v = vv[r];
+        dr_acc += w.x * v.x + w.y * v.y;
+        di_acc += w.x * v.y - w.y * v.x;
+      }
     }
     dr_acc = wave_sum(dr_acc);
     di_acc = wave_sum(di_acc);
@@ -276,19 +276,23 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     }
     const double2 q = cmul(t, make_double2(dsum_r, dsum_i));
     const double2 a2 = make_double2(-0.5 * q.x, -0.5 * q.y);
-    // A_sub -= v w'^H + w' v^H with w' = w + a2 v (packed lower triangle)
+    // w' = w + a2 v, formed once
+    for (int r = tid; r < nj; r += nthr) {
+      const double2 vr = vv[r], wr = ww[r];
+      ww[r] = make_double2(wr.x + a2.x * vr.x - a2.y * vr.y, wr.y + a2.x * vr.y + a2.y * vr.x);
+    }
+    __syncthreads();
+    // A_sub -= v w'^H + w' v^H (packed lower triangle)
     for (int r = grp; r < nj; r += ngrp) {
       const int R = j + 1 + r;
       const double2 vr = vv[r];
-      const double2 wr = make_double2(ww[r].x + a2.x * vr.x - a2.y * vr.y,
-                                      ww[r].y + a2.x * vr.y + a2.y * vr.x);
+      const double2 wr = ww[r];
       const int cend = r;
       double2* rowp = P + tri(R) + (j + 1);
 #pragma unroll 4
       for (int c = gl; c <= cend; c += RG) {
         const double2 vc = vv[c];
-        const double2 wc = make_double2(ww[c].x + a2.x * vc.x - a2.y * vc.y,
-                                        ww[c].y + a2.x * vc.y + a2.y * vc.x);
+        const double2 wc = ww[c];
         double2 x = rowp[c];
         x.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
         x.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
