@@ -55,10 +55,11 @@ __host__ __device__ inline T* inst_ptr(T* p, int64_t stride, int b) {
 }
 
 // Tile configurations of the contraction GEMM: table-driven 32x32 / 64x64 tiles, or (FP32
-// accumulation only) the pipelined kernel with 64x64 tiles; GEMM_AUTO picks by shape.
+// accumulation only) the pipelined kernel with 64x64 tiles; GEMM_AUTO picks by shape. Split-K
+// works with the 32x32 and the pipelined tiles.
 enum GemmTile : int { GEMM_AUTO = -1, GEMM_TILE32 = 0, GEMM_TILE64 = 1, GEMM_PIPE64 = 2 };
 int gemm_pick_tile(int M, int N, int K, int batch, bool fp64_acc);
-// number of K chunks for a table-driven 32x32 launch with too few output tiles (1: no split)
+// number of K chunks for a launch with too few output tiles for its tile size (1: no split)
 int gemm_pick_ksplit(int M, int N, int K, int batch, int tile);
 // Launch a GEMM. acc: DT_C64 -> FP32 MFMA, DT_C128 -> FP64 MFMA.
 hipError_t launch_gemm(const GemmArgs& a, DType ta, DType tb, DType tc, DType acc, int tile,

@@ -247,8 +247,10 @@ __global__ __launch_bounds__(256) void k_cgemm_pipe(GemmArgs g) {
   const int wr = wave >> 1, wc = wave & 1;
   const int m0 = g.mbase + blockIdx.y * BM;
   const int n0 = blockIdx.x * BN;
-  const int M = g.M, N = g.N, K = g.K;
-  const int bz = blockIdx.z;
+  const int M = g.M, N = g.N;
+  const int bz = blockIdx.z / g.ksplit, kz = blockIdx.z % g.ksplit;
+  const int kbeg = g.ksplit > 1 ? kz * g.kchunk : 0;
+  const int K = g.ksplit > 1 ? min(g.K, kbeg + g.kchunk) : g.K;
   const CA* __restrict__ A = reinterpret_cast<const CA*>(inst_ptr(g.A, g.bsA, bz));
   const CB* __restrict__ B = reinterpret_cast<const CB*>(inst_ptr(g.B, g.bsB, bz));
   const float sa = g.conjA ? -1.0f : 1.0f;
@@ -307,11 +309,11 @@ __global__ __launch_bounds__(256) void k_cgemm_pipe(GemmArgs g) {
       acci[i][j] = f4v{0, 0, 0, 0};
     }
 
-  fetch(0);
+  fetch(kbeg);
   stash(0);
   __syncthreads();
   int buf = 0;
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < K; k0 += BK) {
     const bool more = k0 + BK < K;
     if (more) fetch(k0 + BK);
 #pragma unroll
@@ -350,6 +352,23 @@ __global__ __launch_bounds__(256) void k_cgemm_pipe(GemmArgs g) {
     buf ^= 1;
   }
 
+  if (g.ksplit > 1) {
+    // raw chunk sums, row-major M x N per (instance, chunk)
+    float2* __restrict__ P = reinterpret_cast<float2*>(inst_ptr(g.part, g.bsPart, bz)) + (int64_t)kz * M * N;
+#pragma unroll
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const int n = n0 + wc * WN + j * 16 + (lane & 15);
+        if (n >= N) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wr * WM + i * 16 + 4 * (lane >> 4) + r;
+          if (m < M) P[(int64_t)m * N + n] = make_float2(accr[i][j][r], acci[i][j][r]);
+        }
+      }
+    return;
+  }
   double alpha = g.alpha;
   if (g.alpha_dev) alpha *= inst_ptr(g.alpha_dev, g.bsAlpha, bz)[0];
   if (g.alpha_dev2) alpha *= inst_ptr(g.alpha_dev2, g.bsAlpha2, bz)[0];
@@ -374,22 +393,26 @@ __global__ __launch_bounds__(256) void k_cgemm_pipe(GemmArgs g) {
     }
 }
 
-// Tile choice by shape (measured on MI355X): the pipelined 64x64 kernel when there are enough
-// 64x64 output tiles to give every compute unit two; otherwise, and for FP64 accumulation, the
-// table-driven 32x32 kernel, whose many small workgroups hide latency best.
+// Tile choice by shape (measured on MI355X): with FP32 accumulation the pipelined 64x64 kernel
+// whenever there are at least 64 such output tiles (split along K below 512 tiles, see
+// gemm_pick_ksplit); otherwise, and for FP64 accumulation, the table-driven 32x32 kernel, whose many
+// small workgroups hide latency best.
 int gemm_pick_tile(int M, int N, int K, int batch, bool fp64_acc) {
   const int64_t t64 = (int64_t)((M + 63) / 64) * ((N + 63) / 64) * batch;
-  if (!fp64_acc && M >= 64 && N >= 64 && K >= 16 && t64 >= 512) return GEMM_PIPE64;
+  if (!fp64_acc && M >= 64 && N >= 64 && K >= 16 &&
+      (t64 >= 512 || (t64 >= 64 && K >= 512)))
+    return GEMM_PIPE64;
   return GEMM_TILE32;
 }
 
-// Split-K for 32x32 launches with fewer than 512 output tiles and a long reduction: chunks of at
-// least 256 until there are about 1024 workgroups.
+// Split-K for launches with fewer than 512 output tiles and a long reduction: chunks of at least
+// 256 until there are about 1024 workgroups.
 int gemm_pick_ksplit(int M, int N, int K, int batch, int tile) {
-  if (tile != GEMM_TILE32 || K < 512) return 1;
-  const int64_t t32 = (int64_t)((M + 31) / 32) * ((N + 31) / 32) * batch;
-  if (t32 >= 512) return 1;
-  int64_t ks = (1024 + t32 - 1) / t32;
+  if (K < 512) return 1;
+  const int bm = tile == GEMM_TILE32 ? 32 : 64;
+  const int64_t tiles = (int64_t)((M + bm - 1) / bm) * ((N + bm - 1) / bm) * batch;
+  if (tiles >= 512) return 1;
+  int64_t ks = (1024 + tiles - 1) / tiles;
   const int64_t kmax = K / 256;
   if (ks > kmax) ks = kmax;
   if (ks > 64) ks = 64;
@@ -404,7 +427,7 @@ static hipError_t launch_t(const GemmArgs& a0, int tile, hipStream_t s) {
   // the pipelined kernel: FP32 accumulation, offset tables, no accumulation into C
   if (tile == GEMM_PIPE64 && (sizeof(ACC) == 8 || !a0.offAm || a0.accum)) tile = GEMM_TILE64;
   const bool split = a0.ksplit > 1;
-  if (split && (tile != GEMM_TILE32 || !a0.part || a0.kchunk % 16 != 0 ||
+  if (split && (tile == GEMM_TILE64 || !a0.part || a0.kchunk % 16 != 0 ||
                 (int64_t)a0.kchunk * a0.ksplit < a0.K))
     return hipErrorInvalidValue;
   if ((int64_t)a0.batch * a0.ksplit > 65535) return hipErrorInvalidValue;

@@ -61,10 +61,11 @@ def test_gemm_fp32(lib, M, N, K, tile):
 
 
 @pytest.mark.parametrize("acc", [True, False])
-@pytest.mark.parametrize("M,N,K", [(64, 96, 1000), (70, 50, 1500), (256, 1024, 4096)])
+@pytest.mark.parametrize("M,N,K", [(64, 96, 1000), (70, 50, 1500), (256, 1024, 4096), (512, 640, 777)])
 def test_gemm_split_k(lib, M, N, K, acc):
     """Few output tiles and a long reduction: the reduction is split into chunks whose sums are added
-    in order by a second kernel (the compression's own policy, tile = -1)."""
+    in order by a second kernel (the compression's own policy, tile = -1; with FP32 accumulation
+    the last two shapes split the pipelined kernel, the first two the table-driven one)."""
     rng = np.random.default_rng(M + N + K)
     dt = np.complex128 if acc else np.complex64
     a, b = crand(rng, M, K).astype(dt), crand(rng, K, N).astype(dt)
