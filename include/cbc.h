@@ -45,7 +45,10 @@
  * later calls with the same buffers replay it.
  *
  * Errors: every entry point returns a cbc_status; nothing aborts or throws across the ABI. All
- * argument validation happens on the host before any device work is queued.
+ * argument validation happens on the host before any device work is queued. Truncation Gram
+ * matrices of dimension above 128 are solved by up to 256 cooperating workgroups that must be
+ * resident together; their waits are bounded (2 s), so if the device is so busy that they are not,
+ * the call still completes and its output holds NaN instead of hanging.
  */
 #ifndef CBC_H
 #define CBC_H
@@ -64,7 +67,7 @@ typedef enum {
   CBC_ENOMEM = -3,     /* workspace smaller than cbc_query reported, or a context allocation failed */
   CBC_EHIP = -4,       /* a HIP runtime call failed */
   CBC_ENOTPD = -5,     /* reserved: a factorisation failed even after its fallbacks */
-  CBC_EUNSUP = -6,     /* valid input outside what this build supports (see cbc_status_str) */
+  CBC_EUNSUP = -6,     /* valid input outside this build's limits: a truncation Gram > 1272 */
   CBC_ENOTBUILT = -7   /* library built without a usable device (no gfx950 GPU visible) */
 } cbc_status;
 

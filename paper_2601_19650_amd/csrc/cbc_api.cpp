@@ -85,6 +85,7 @@ struct Plan {
   std::vector<int32_t> out_bond;
   double cflops = 0.0, gflops = 0.0;
   int n_eig = 0, max_eig = 0;
+  bool unsupported = false;   // a step exceeds this build's kernel limits
   int launches[CBC_K_NCLASS] = {0};
   double flops[CBC_K_NCLASS] = {0.0};
   double bytes[CBC_K_NCLASS] = {0.0};
@@ -425,6 +426,7 @@ struct Builder {
     P.ops.push_back(e);
     P.n_eig++;
     P.max_eig = std::max(P.max_eig, s);
+    if (!eig_size_supported(s)) P.unsupported = true;
     if (mside) {
       // L = U^H M / sqrt(lambda_0)
       Ten Uv{U.ref, {r, nl}};
@@ -473,6 +475,7 @@ struct Builder {
     P.ops.push_back(e);
     P.n_eig++;
     P.max_eig = std::max(P.max_eig, s);
+    if (!eig_size_supported(s)) P.unsupported = true;
     if (lam_out) *lam_out = lam;
     if (kk_out) *kk_out = kk;
     return U;
@@ -1268,6 +1271,7 @@ cbc_status get_plan(cbc_ctx* ctx, const Problem& pr, int max_bond, bool tol_on, 
   cbc_status s = method == 0 ? build_plan(*P, pr, max_bond, tol_on, prec)
                               : build_plan_naive(*P, pr, max_bond, tol_on, prec);
   if (s != CBC_OK) return s;
+  if (P->unsupported) return CBC_EUNSUP;
   *out = P.get();
   ctx->plans[key] = std::move(P);
   return CBC_OK;
@@ -1306,7 +1310,7 @@ const char* cbc_status_str(cbc_status s) {
     case CBC_ENOMEM: return "workspace too small or allocation failed";
     case CBC_EHIP: return "HIP runtime error";
     case CBC_ENOTPD: return "factorisation failed after fallbacks";
-    case CBC_EUNSUP: return "unsupported configuration";
+    case CBC_EUNSUP: return "unsupported configuration (a truncation Gram matrix larger than 1272)";
     case CBC_ENOTBUILT: return "no usable gfx950 device";
   }
   return "unknown status";

@@ -84,6 +84,8 @@ struct EigArgs {
   int64_t bs;
 };
 size_t eig_work_doubles(int s, int kmax);
+// largest Gram the eigensolver handles (the multi-workgroup reduction keeps its rows in LDS)
+bool eig_size_supported(int s);
 hipError_t launch_eig(const EigArgs& a, hipStream_t st);
 
 // n-side truncation output: L[j, c] = sqrt(max(lam_j, 0)) / sqrt(lam_0) * conj(V[c, j]) for j < kkeep,

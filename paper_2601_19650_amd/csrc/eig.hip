@@ -377,6 +377,11 @@ __host__ __device__ inline MwShape mw_shape(int s) {
 }
 size_t mw_lds_bytes(int s) { return (size_t)(mw_shape(s).rows + 2) * s * 16; }
 
+bool eig_size_supported(int s) {
+  if (s <= EIG_LDS_MAX) return s >= 1;
+  return s <= MW_EPT * MW_THREADS && mw_shape(s).nwg <= MW_MAX_WG && mw_lds_bytes(s) <= MW_LDS_BUDGET;
+}
+
 // Data exchanged between the workgroups (products, partial sums, pivot rows) is written and read
 // with device-coherent atomic accesses, which go to the point of coherence without caching in the
 // per-XCD L2. The barrier then only has to order them against the arrival flags (each workgroup

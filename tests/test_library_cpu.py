@@ -63,6 +63,15 @@ def test_bad_dims_rejected():
     assert _query(T([-1, 0]), method=5)[0] == -1
 
 
+def test_oversized_truncation_is_unsupported():
+    """A truncation Gram above the eigensolver's limit (1272) is reported at query time, on the
+    host, as CBC_EUNSUP; the largest-bond workload (Grams of 1024) is accepted."""
+    # two-site chain: the first site's joined leg is d * 1 = 1400 wide against chi * D = 1400
+    big = T([-1, 0], phys=1400, chi=[1, 1400], dop=[1, 1])
+    assert _query(big, max_bond=64)[0] == -6
+    assert _query(cbc.Tree.of(config_problem("C4", n=10)), max_bond=256)[0] == 0
+
+
 def test_apply_argument_errors_need_no_device():
     p = config_problem("C1")
     tree = cbc.Tree.of(p)
