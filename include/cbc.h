@@ -42,7 +42,9 @@
  * dimensions are returned at once and the output tensors are ready when the stream reaches the end
  * of the call. Only the profiling mode (cbc_stats.profile) synchronises the stream. The first call
  * with a given set of buffers on a non-null stream captures the launch sequence into a hipGraph;
- * later calls with the same buffers replay it.
+ * later calls with the same buffers replay it. If the stream is already being captured by the caller,
+ * the kernels are recorded into the caller's graph instead; a call with the same shape must have run
+ * once before (it builds the plan and uploads its tables, which a capture cannot record).
  *
  * Errors: every entry point returns a cbc_status; nothing aborts or throws across the ABI. All
  * argument validation happens on the host before any device work is queued. Truncation Gram

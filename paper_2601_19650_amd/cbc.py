@@ -252,9 +252,31 @@ class UnevenBatch:
 
     def run(self):
         """Launch every instance (asynchronous); call torch.cuda.synchronize() to wait."""
+        if getattr(self, "graph", None) is not None:
+            self.graph.replay()
+            return
         for k, (comp, args) in enumerate(self.items):
             s = self.streams[k % len(self.streams)]
             comp.run(*args, stream=s.cuda_stream)
+
+    def capture(self):
+        """Record the whole batch (every instance, forked over the streams and joined) into one
+        graph; run() then replays it with a single launch. Runs the batch once first, eagerly."""
+        import torch
+        self.graph = None
+        self.run()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        root = torch.cuda.Stream(device=self.streams[0].device)
+        with torch.cuda.graph(g, stream=root):
+            for s in self.streams:
+                s.wait_stream(root)
+            for k, (comp, args) in enumerate(self.items):
+                s = self.streams[k % len(self.streams)]
+                comp.run(*args, stream=s.cuda_stream)
+            for s in self.streams:
+                root.wait_stream(s)
+        self.graph = g
 
     def flops(self):
         return sum(c.stats.flops[0] for c, _ in self.items)

@@ -1257,6 +1257,11 @@ int64_t tensor_elems_op(const Problem& pr, int i) {
   return e;
 }
 
+bool capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
+
 cbc_status get_plan(cbc_ctx* ctx, const Problem& pr, int max_bond, bool tol_on, cbc_precision prec,
                     int method, int64_t state_span, int64_t op_span, Plan** out) {
   const auto key = plan_key(pr, max_bond, tol_on, prec, method, state_span, op_span);
@@ -1427,6 +1432,9 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
       P->events.push_back(ev);
     }
     if (run_ops(*P, c, st, P->events.data()) != hipSuccess) return CBC_EHIP;
+  } else if (st != nullptr && capturing(st)) {
+    // the caller is capturing this stream into a graph of its own: record the kernels into it
+    if (run_ops(*P, c, st) != hipSuccess) return CBC_EHIP;
   } else if (st != nullptr) {
     // replay a captured graph of the whole launch sequence when the buffers are unchanged
     std::vector<uintptr_t> key{(uintptr_t)c.ws, (uintptr_t)c.state, (uintptr_t)c.op,

@@ -241,3 +241,34 @@ def test_uneven_batch(lib, prec):
             assert tn.rel_error(p.parent, got, ref) <= FP64_BAR, p.name
         else:
             assert 1.0 - tn.fidelity(p.parent, got, ref) <= MIXED_BAR, p.name
+
+
+def test_uneven_batch_single_graph(lib):
+    """The whole uneven batch recorded into one graph (the library records into the caller's
+    capture) and replayed several times, with eager work between the replays: every replay
+    reproduces the eager result bitwise (outputs are cleared before each replay)."""
+    probs = [
+        random_problem(chain_parent(10), 4, 16, 4, 12, seed=1, name="mps10d4"),
+        random_problem(kary_parent(9, 2), 2, 12, 5, 10, seed=2, name="bin9"),
+        random_problem(kary_parent(10, 3), 2, 8, 4, 6, seed=3, name="ter10"),
+        random_problem(chain_parent(14), 2, 24, 6, 16, seed=4, name="mps14"),
+        random_problem(kary_parent(7, 2), 4, 150, 12, 140, seed=7, name="bin7big"),
+    ]
+    ub = lib.UnevenBatch(probs, precision="mixed", nstreams=3)
+    ub.run()
+    torch.cuda.synchronize()
+    eager = [comp.out.clone() for comp, _ in ub.items]
+    # the last instance's truncations use the multi-workgroup eigensolver
+    assert ub.items[-1][0].stats.max_eig_dim > 128
+    ub.capture()
+    for rep in range(3):
+        for comp, _ in ub.items:
+            comp.out.zero_()
+        x = torch.randn(1 << 20, device="cuda") * 2.0          # unrelated eager work
+        torch.cuda.synchronize()
+        ub.run()
+        y = (x * x).sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(y)
+        for (comp, _), ref, p in zip(ub.items, eager, probs):
+            assert torch.equal(comp.out, ref), (rep, p.name)
