@@ -41,8 +41,9 @@ __device__ inline CholArgs chol_inst(const CholArgs& a0, int b) {
 }
 
 // LDS-resident variant for k <= CHOL_LDS_MAX, blocked by NBc = 8 columns.
-//   factor:  for each panel, wave 0 factors the 8 panel columns (wave-synchronous), then all waves
-//            apply the rank-8 update to the trailing lower triangle (two barriers per panel);
+//   factor:  for each panel, wave 0 factors the 8 panel columns with the panel rows in registers
+//            (two rows per lane, so k <= 128), then all waves apply the rank-8 update to the trailing
+//            lower triangle (two barriers per panel);
 //   inverse: the 8x8 diagonal blocks of X = C^{-1} are inverted in parallel, then block-row i of X is
 //            X_ij = -X_ii sum_{l=j}^{i-1} C_il X_lj (two barriers per block-row).
 // The factor lives in the lower triangle of M (row stride k+1, so column-wise lane accesses fall in
@@ -50,10 +51,13 @@ __device__ inline CholArgs chol_inst(const CholArgs& a0, int b) {
 // in xd.
 static constexpr int NBc = 8;
 
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  __builtin_amdgcn_wave_barrier();
+// a double from lane `l` (uniform) of the wave
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
 }
+
+static_assert(CHOL_LDS_MAX <= 128, "the register panel holds two rows per lane");
 
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
   const CholArgs a = chol_inst(a0, blockIdx.x);
@@ -138,34 +142,54 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
   for (int p = 0; p < k; p += NBc) {
     const int pe = min(p + NBc, k);
     if (wave == 0) {
-      for (int jj = p; jj < pe; ++jj) {
-        const double djj = M[jj * ld + jj].x;
+      // the panel rows p..k-1 in registers (lane l holds rows p + l and p + l + 64); the pivot and
+      // the panel's diagonal-block entries are broadcast from their lanes
+      const int i0r = p + lane, i1r = p + 64 + lane;
+      double2 R0[NBc], R1[NBc];
+#pragma unroll
+      for (int q = 0; q < NBc; ++q) {
+        const bool inp = p + q < pe;
+        R0[q] = inp && i0r < k ? M[i0r * ld + p + q] : make_double2(0.0, 0.0);
+        R1[q] = inp && i1r < k ? M[i1r * ld + p + q] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < NBc; ++q) {
+        const int jj = p + q;
+        if (jj >= pe) break;
+        const double djj = readlane_d(R0[q].x, q);
         if (!(djj > thresh)) {
-          for (int i = jj + lane; i < k; i += 64) M[i * ld + jj] = make_double2(0.0, 0.0);
+          if (i0r >= jj) R0[q] = make_double2(0.0, 0.0);
+          R1[q] = make_double2(0.0, 0.0);
           if (lane == 0) dropped[jj] = 1;
-          wave_lds_sync();
           continue;
         }
         const double c = sqrt(djj), ic = 1.0 / c;
-        for (int i = jj + 1 + lane; i < k; i += 64) {
-          double2 g = M[i * ld + jj];
-          g.x *= ic;
-          g.y *= ic;
-          M[i * ld + jj] = g;
+        if (i0r > jj) {
+          R0[q].x *= ic;
+          R0[q].y *= ic;
+        } else if (i0r == jj) {
+          R0[q] = make_double2(c, 0.0);
         }
-        if (lane == 0) M[jj * ld + jj] = make_double2(c, 0.0);
-        wave_lds_sync();
-        for (int l = jj + 1; l < pe; ++l) {
-          const double2 clj = M[l * ld + jj];
-          for (int i = l + lane; i < k; i += 64) {
-            const double2 cij = M[i * ld + jj];
-            double2 g = M[i * ld + l];
-            g.x -= cij.x * clj.x + cij.y * clj.y;
-            g.y -= cij.y * clj.x - cij.x * clj.y;
-            M[i * ld + l] = g;
+        R1[q].x *= ic;
+        R1[q].y *= ic;
+#pragma unroll
+        for (int l = q + 1; l < NBc; ++l) {
+          if (p + l >= pe) break;
+          const double2 clj = make_double2(readlane_d(R0[q].x, l), readlane_d(R0[q].y, l));
+          if (i0r >= p + l) {
+            R0[l].x -= R0[q].x * clj.x + R0[q].y * clj.y;
+            R0[l].y -= R0[q].y * clj.x - R0[q].x * clj.y;
           }
+          R1[l].x -= R1[q].x * clj.x + R1[q].y * clj.y;
+          R1[l].y -= R1[q].y * clj.x - R1[q].x * clj.y;
         }
-        wave_lds_sync();
+      }
+#pragma unroll
+      for (int q = 0; q < NBc; ++q) {
+        if (p + q < pe) {
+          if (i0r < k && i0r >= p + q) M[i0r * ld + p + q] = R0[q];
+          if (i1r < k) M[i1r * ld + p + q] = R1[q];
+        }
       }
     }
     __syncthreads();
@@ -173,11 +197,19 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
     for (int i = pe + grp; i < k; i += ngrp) {
       for (int l = pe + gl; l <= i; l += RGc) {
         double2 g = M[i * ld + l];
-        for (int jj = p; jj < pe; ++jj) {
-          const double2 cij = M[i * ld + jj];
-          const double2 clj = M[l * ld + jj];
-          g.x -= cij.x * clj.x + cij.y * clj.y;
-          g.y -= cij.y * clj.x - cij.x * clj.y;
+        double2 ci[NBc], cl[NBc];
+#pragma unroll
+        for (int q = 0; q < NBc; ++q) {
+          const int jj = min(p + q, pe - 1);
+          ci[q] = M[i * ld + jj];
+          cl[q] = M[l * ld + jj];
+        }
+#pragma unroll
+        for (int q = 0; q < NBc; ++q) {
+          if (p + q < pe) {
+            g.x -= ci[q].x * cl[q].x + ci[q].y * cl[q].y;
+            g.y -= ci[q].y * cl[q].x - ci[q].x * cl[q].y;
+          }
         }
         M[i * ld + l] = g;
       }
@@ -207,11 +239,19 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
         if (dropped[r]) { M[c * ld + r] = make_double2(0.0, 0.0); continue; }
         const double2 crc = M[r * ld + c];
         double sr = crc.x * dc, si = crc.y * dc;
-        for (int l = c + 1; l < r; ++l) {
-          const double2 crl = M[r * ld + l];
-          const double2 xl = M[c * ld + l];
-          sr += crl.x * xl.x - crl.y * xl.y;
-          si += crl.x * xl.y + crl.y * xl.x;
+        double2 crl[NBc], xl[NBc];
+#pragma unroll
+        for (int q = 0; q < NBc - 1; ++q) {
+          const int l = min(c + 1 + q, b1 - 1);
+          crl[q] = M[r * ld + l];
+          xl[q] = M[c * ld + l];
+        }
+#pragma unroll
+        for (int q = 0; q < NBc - 1; ++q) {
+          if (c + 1 + q < r) {
+            sr += crl[q].x * xl[q].x - crl[q].y * xl[q].y;
+            si += crl[q].x * xl[q].y + crl[q].y * xl[q].x;
+          }
         }
         const double inv = -1.0 / M[r * ld + r].x;
         M[c * ld + r] = make_double2(sr * inv, si * inv);
@@ -225,12 +265,23 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
     for (int idx = tid; idx < ni * i0; idx += blockDim.x) {
       const int r = idx / i0, c = idx % i0;
       const int lstart = (c / NBc) * NBc;
+      const double2 xcc = make_double2(xd[c], 0.0);
       double sr = 0.0, si = 0.0;
-      for (int l = max(lstart, c); l < i0; ++l) {
-        const double2 cl = M[(i0 + r) * ld + l];
-        const double2 x = xget(l, c);
-        sr += cl.x * x.x - cl.y * x.y;
-        si += cl.x * x.y + cl.y * x.x;
+      for (int lb = max(lstart, c); lb < i0; lb += NBc) {
+        double2 cl[NBc], x[NBc];
+#pragma unroll
+        for (int q = 0; q < NBc; ++q) {
+          const int l = min(lb + q, i0 - 1);
+          cl[q] = M[(i0 + r) * ld + l];
+          x[q] = l == c ? xcc : M[c * ld + l];
+        }
+#pragma unroll
+        for (int q = 0; q < NBc; ++q) {
+          if (lb + q < i0) {
+            sr += cl[q].x * x[q].x - cl[q].y * x[q].y;
+            si += cl[q].x * x[q].y + cl[q].y * x[q].x;
+          }
+        }
       }
       T[r * i0 + c] = make_double2(sr, si);
     }
@@ -239,11 +290,19 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
     for (int idx = tid; idx < ni * i0; idx += blockDim.x) {
       const int r = idx / i0, c = idx % i0;
       double sr = 0.0, si = 0.0;
-      for (int q = 0; q <= r; ++q) {
-        const double2 x = xget(i0 + r, i0 + q);
-        const double2 t = T[q * i0 + c];
-        sr += x.x * t.x - x.y * t.y;
-        si += x.x * t.y + x.y * t.x;
+      double2 x[NBc], t[NBc];
+#pragma unroll
+      for (int q = 0; q < NBc; ++q) {
+        const int qq = min(q, r);
+        x[q] = xget(i0 + r, i0 + qq);
+        t[q] = T[qq * i0 + c];
+      }
+#pragma unroll
+      for (int q = 0; q < NBc; ++q) {
+        if (q <= r) {
+          sr += x[q].x * t[q].x - x[q].y * t[q].y;
+          si += x[q].x * t[q].y + x[q].y * t[q].x;
+        }
       }
       M[c * ld + i0 + r] = make_double2(-sr, -si);
     }

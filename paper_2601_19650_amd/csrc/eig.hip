@@ -29,6 +29,7 @@ namespace cbc {
 static constexpr int EIG_THREADS = 1024;
 static constexpr int EIG_LDS_MAX = 128;   // largest s whose packed triangle stays in LDS
 static constexpr int RG = 8;              // lanes per row group in the matrix-vector product
+static constexpr int TRI_U = 4;           // elements per lane whose LDS loads are issued together
 
 // ---- cross-lane reductions ---------------------------------------------------------------------
 // DPP lane moves (quad permutes and row mirrors) are single-cycle VALU operations; ds_bpermute
@@ -269,10 +270,14 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     if (lane == 0) sh.part[wave] = make_double2(dr_acc, di_acc);
     __syncthreads();
     if (stamp) { const long long t1 = wall_clock64(); tB += t1 - t0; t0 = t1; }
+    double2 pw[EIG_THREADS / 64];
+#pragma unroll
+    for (int w = 0; w < EIG_THREADS / 64; ++w) pw[w] = sh.part[w];
     double dsum_r = 0.0, dsum_i = 0.0;
-    for (int w = 0; w < (nthr >> 6); ++w) {
-      dsum_r += sh.part[w].x;
-      dsum_i += sh.part[w].y;
+#pragma unroll
+    for (int w = 0; w < EIG_THREADS / 64; ++w) {
+      dsum_r += pw[w].x;
+      dsum_i += pw[w].y;
     }
     const double2 q = cmul(t, make_double2(dsum_r, dsum_i));
     const double2 a2 = make_double2(-0.5 * q.x, -0.5 * q.y);
@@ -287,16 +292,27 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
       const int R = j + 1 + r;
       const double2 vr = vv[r];
       const double2 wr = ww[r];
-      const int cend = r;
       double2* rowp = P + tri(R) + (j + 1);
-#pragma unroll 4
-      for (int c = gl; c <= cend; c += RG) {
-        const double2 vc = vv[c];
-        const double2 wc = ww[c];
-        double2 x = rowp[c];
-        x.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
-        x.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
-        rowp[c] = x;
+      // TRI_U elements per lane loaded together, then updated and stored; an element past the row
+      // end repeats element c0 and stores the same value to it
+      for (int c0 = gl; c0 <= r; c0 += TRI_U * RG) {
+        int cc[TRI_U];
+        double2 vc[TRI_U], wc[TRI_U], x[TRI_U];
+#pragma unroll
+        for (int u = 0; u < TRI_U; ++u) {
+          const int c = c0 + u * RG;
+          cc[u] = c <= r ? c : c0;
+          vc[u] = vv[cc[u]];
+          wc[u] = ww[cc[u]];
+          x[u] = rowp[cc[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < TRI_U; ++u) {
+          x[u].x -= (vr.x * wc[u].x + vr.y * wc[u].y) + (wr.x * vc[u].x + wr.y * vc[u].y);
+          x[u].y -= (vr.y * wc[u].x - vr.x * wc[u].y) + (wr.y * vc[u].x - wr.x * vc[u].y);
+        }
+#pragma unroll
+        for (int u = 0; u < TRI_U; ++u) rowp[cc[u]] = x[u];
       }
     }
     __syncthreads();
