@@ -226,9 +226,9 @@ def batched_run(args, cbc, p, stream):
 def uneven_run(count, stream_count=8):
     """Throughput of an uneven batch: `count` instances drawn as tensor trains, binary and ternary
     trees with N in [16, 64], d in {2, 4}, D in [4, 12], max_bond = chi, mixed precision, forked over
-    several streams inside one captured graph that is replayed with a single launch. The bond range is reduced to chi in [16, 48] (ternary chi <= 16): with the full
-    [16, 128] draw single node steps of binary and ternary instances need intermediates of 1e9
-    elements."""
+    several streams inside one captured graph that is replayed with a single launch. The bond range
+    is reduced to chi in [16, 48] (ternary chi <= 16): with the full [16, 128] draw single node steps
+    of binary and ternary instances need intermediates of 1e9 elements."""
     import torch
     from paper_2601_19650_amd import cbc
     from paper_2601_19650_amd.inputs import batch_problems
