@@ -44,8 +44,9 @@ __device__ inline CholArgs chol_inst(const CholArgs& a0, int b) {
 //   factor:  for each panel, wave 0 factors the 8 panel columns with the panel rows in registers
 //            (two rows per lane, so k <= 128), then all waves apply the rank-8 update to the trailing
 //            lower triangle (two barriers per panel);
-//   inverse: the 8x8 diagonal blocks of X = C^{-1} are inverted in parallel, then block-row i of X is
-//            X_ij = -X_ii sum_{l=j}^{i-1} C_il X_lj (two barriers per block-row).
+//   inverse: the columns of the 8x8 diagonal blocks of X = C^{-1} are formed in parallel (one lane
+//            each), then block-row i of X is X_ij = -X_ii sum_{l=j}^{i-1} C_il X_lj (two barriers per
+//            block-row).
 // The factor lives in the lower triangle of M (row stride k+1, so column-wise lane accesses fall in
 // distinct banks); X's strictly lower part is stored transposed in the upper triangle, its diagonal
 // in xd.
@@ -224,38 +225,42 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
     return r == c ? make_double2(xd[r], 0.0) : M[c * ld + r];
   };
   const int nblk = (k + NBc - 1) / NBc;
-  // diagonal blocks, one lane each (forward substitution inside the block)
-  for (int b = tid; b < nblk; b += blockDim.x) {
-    const int b0 = b * NBc, b1 = min(b0 + NBc, k);
-    for (int c = b0; c < b1; ++c) {
-      if (dropped[c]) {
-        xd[c] = 0.0;
-        for (int r = c + 1; r < b1; ++r) M[c * ld + r] = make_double2(0.0, 0.0);
+  // diagonal blocks: one lane per column of a block (the columns of a triangular inverse are
+  // independent); the column is formed in registers by forward substitution
+  for (int t = tid; t < nblk * NBc; t += blockDim.x) {
+    const int b0 = (t / NBc) * NBc, cl = t % NBc, c = b0 + cl;
+    if (c >= k) continue;
+    const int b1 = min(b0 + NBc, k);
+    if (dropped[c]) {
+      xd[c] = 0.0;
+      for (int r = c + 1; r < b1; ++r) M[c * ld + r] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double dc = 1.0 / M[c * ld + c].x;
+    xd[c] = dc;
+    double2 xr[NBc];   // X[b0 + rr][c]; zero above the diagonal
+#pragma unroll
+    for (int rr = 0; rr < NBc; ++rr) xr[rr] = rr == cl ? make_double2(dc, 0.0) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int rr = 1; rr < NBc; ++rr) {
+      const int r = b0 + rr;
+      if (rr <= cl || r >= b1) continue;
+      if (dropped[r]) {
+        M[c * ld + r] = make_double2(0.0, 0.0);
         continue;
       }
-      const double dc = 1.0 / M[c * ld + c].x;
-      xd[c] = dc;
-      for (int r = c + 1; r < b1; ++r) {
-        if (dropped[r]) { M[c * ld + r] = make_double2(0.0, 0.0); continue; }
-        const double2 crc = M[r * ld + c];
-        double sr = crc.x * dc, si = crc.y * dc;
-        double2 crl[NBc], xl[NBc];
+      double2 crow[NBc - 1];
 #pragma unroll
-        for (int q = 0; q < NBc - 1; ++q) {
-          const int l = min(c + 1 + q, b1 - 1);
-          crl[q] = M[r * ld + l];
-          xl[q] = M[c * ld + l];
-        }
+      for (int ll = 0; ll < rr; ++ll) crow[ll] = M[r * ld + b0 + ll];
+      const double ninv = -1.0 / M[r * ld + r].x;
+      double sr = 0.0, si = 0.0;
 #pragma unroll
-        for (int q = 0; q < NBc - 1; ++q) {
-          if (c + 1 + q < r) {
-            sr += crl[q].x * xl[q].x - crl[q].y * xl[q].y;
-            si += crl[q].x * xl[q].y + crl[q].y * xl[q].x;
-          }
-        }
-        const double inv = -1.0 / M[r * ld + r].x;
-        M[c * ld + r] = make_double2(sr * inv, si * inv);
+      for (int ll = 0; ll < rr; ++ll) {
+        sr += crow[ll].x * xr[ll].x - crow[ll].y * xr[ll].y;
+        si += crow[ll].x * xr[ll].y + crow[ll].y * xr[ll].x;
       }
+      xr[rr] = make_double2(sr * ninv, si * ninv);
+      M[c * ld + r] = xr[rr];
     }
   }
   __syncthreads();
