@@ -560,17 +560,20 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
   for (int c = tid; c < s; c += MW_THREADS) w[c] = a.G[c];
   __syncthreads();
   double2 t = mw_reflector(0, s, w, v, W, writer, red);
+  // phase times (tests only) accumulate in LDS, so that they take no registers of the other threads
   const bool stamp = a.tstamp && writer && tid == 0;
-  long long ph[7] = {0, 0, 0, 0, 0, 0, 0}, t0 = 0;
+  __shared__ long long ph[8];
+  if (stamp)
+    for (int i = 0; i < 8; ++i) ph[i] = 0;
   auto lap = [&](int i) {
     if (stamp) {
       const long long t1 = wall_clock64();
-      ph[i] += t1 - t0;
-      t0 = t1;
+      ph[i] += t1 - ph[7];
+      ph[7] = t1;
     }
   };
   for (int j = 0; j < s - 1; ++j) {
-    if (stamp) t0 = wall_clock64();
+    if (stamp) ph[7] = wall_clock64();
     // (1) y = A v_j on the owned rows r > j; share of v_j^H y
     double2* ybuf = W.ybuf + (size_t)(j & 1) * s;
     double pr = 0.0, pi = 0.0;
@@ -679,7 +682,7 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
       if (r <= j + 1) continue;
       double2* row = Ar + (size_t)q * s;
       const double2 vr = v[r], wr = w[r];
-#pragma unroll 4
+#pragma unroll 2
       for (int c = j + 2 + sub * 64 + lane; c < s; c += 64 * wpr) {
         const double2 vc = v[c], wc = w[c];
         double2 x = row[c];
