@@ -18,8 +18,7 @@
 //   3. eigenvectors of T by a twisted factorisation T - lambda I = N_r Delta N_r^T, one wave per
 //      eigenpair; eigenvalues closer than 1e-3 ||T|| form clusters that are re-orthogonalised (or,
 //      for near-exact degeneracies, computed by inverse iteration); then the back-transformation with
-//      the reflectors streamed from L2. For s <= EIG_SPLIT_MIN one kernel does all of it; larger s
-//      use three launches so that the back-transformation stays parallel over all eigenpairs.
+//      the reflectors streamed from L2, one wave per eigenpair (three launches).
 #include <float.h>
 
 #include "cbc_internal.h"
@@ -976,117 +975,15 @@ __device__ void back_transform_any(const EigArgs& a, const EigWork& W, int s, in
   else back_transform_col(a, W, s, kmax, t, kept, yin, u);
 }
 
-__global__ __launch_bounds__(256) void k_eigvecs(EigArgs a0) {
-  const EigArgs a = eig_inst(a0, blockIdx.y);
-  extern __shared__ double smem[];
-  const int s = a.s, kmax = a.kmax;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int nw = blockDim.x >> 6;
-  double* dd = smem;
-  double* el = dd + s;
-  double* region = el + s + 4 * (size_t)s * wave;   // per wave: lp | dp (y later) | um | y
-  EigWork W = eig_layout(a.work, s, kmax);
-  for (int i = tid; i < s; i += blockDim.x) {
-    dd[i] = W.d[i];
-    el[i] = i < s - 1 ? W.e[i] : 0.0;
-  }
-  __syncthreads();
-  const int t = blockIdx.x * nw + wave;
-  if (t >= kmax) return;
-  const double tnorm = W.bounds[2], pivmin = W.bounds[3];
-  const double* lam = a.lam;
-  // rank selection: keep lam_t > tol^2 lam_0 (descending order), always the first
-  int keep = kmax;
-  if (a.tol > 0.0) {
-    const double cut = a.tol * a.tol * lam[0];
-    int c = 0;
-    for (int u = lane; u < kmax; u += 64) c += lam[u] > cut;
-    c = (int)wave_sum((double)c);
-    keep = c < 1 ? 1 : c;
-  }
-  if (t == 0 && lane == 0) {
-    a.kkeep[0] = keep;
-    a.inv_sqrt_l0[0] = lam[0] > 0.0 ? 1.0 / sqrt(lam[0]) : 1.0;
-  }
-  // clusters of non-negligible eigenvalues closer than 1e-3 ||T||; negligible ones (at the rounding
-  // level of ||T||) carry no weight and are computed one by one
-  const double ortol = 1e-3 * tnorm, tiny = 64.0 * DBL_EPSILON * tnorm;
-  auto starts = [&](int u) {
-    return u == 0 || u == kmax || lam[u - 1] - lam[u] > ortol || lam[u] <= tiny;
-  };
-  if (!starts(t)) {   // computed by the wave of the cluster's first member
-    if (a.tstamp && lane == 0)
-      atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 3), (unsigned long long)wall_clock64());
-    return;
-  }
-  int ce = t + 1;
-  while (ce < kmax && !starts(ce)) ++ce;
-  double* lp = region;
-  double* dp = region + s;
-  double* um = region + 2 * s;
-  double* y = region + 3 * s;
-  double2* u = reinterpret_cast<double2*>(region);   // reuses lp|dp after the twisted solve
-  auto wave_sync = [&]() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  };
-  if (ce == t + 1) {
-    if (lane == 0) twisted_vector(dd, el, s, lam[t], pivmin, y, lp, dp, um);
-    wave_sync();
-    back_transform_any(a, W, s, kmax, t, t < keep, y, u);
-  } else {
-    // a cluster: if its members are distinct at the rounding level, twisted vectors are accurate up
-    // to mixing inside the cluster, so modified Gram-Schmidt over the members gives an orthonormal
-    // basis of the cluster's invariant subspace; near-exact degeneracies use inverse iteration.
-    double mingap = DBL_MAX;
-    for (int m = t + 1; m < ce; ++m) mingap = fmin(mingap, lam[m - 1] - lam[m]);
-    if (mingap > 1e-12 * tnorm) {
-      double* Yc = W.Y;
-      for (int m = t; m < ce; ++m) {
-        double* ym = Yc + (size_t)m * s;
-        if (lane == 0) twisted_vector(dd, el, s, lam[m], pivmin, y, lp, dp, um);
-        wave_sync();
-        for (int pass = 0; pass < 2; ++pass) {
-          for (int q = t; q < m; ++q) {
-            const double* yq = Yc + (size_t)q * s;
-            double dot = 0.0;
-            for (int i = lane; i < s; i += 64) dot += yq[i] * y[i];
-            dot = wave_sum(dot);
-            for (int i = lane; i < s; i += 64) y[i] -= dot * yq[i];
-            wave_sync();
-          }
-        }
-        double nrm = 0.0;
-        for (int i = lane; i < s; i += 64) nrm += y[i] * y[i];
-        nrm = wave_sum(nrm);
-        const double inv = 1.0 / sqrt(nrm);
-        for (int i = lane; i < s; i += 64) ym[i] = y[i] * inv;
-        __threadfence_block();
-        wave_sync();
-      }
-    } else if (lane == 0) {
-      cluster_vectors(dd, el, s, lam, t, ce, tnorm, W.Y, W.lu + (size_t)t * 5 * s);
-    }
-    wave_sync();
-    for (int m = t; m < ce; ++m) {
-      back_transform_any(a, W, s, kmax, m, m < keep, W.Y + (size_t)m * s, u);
-      wave_sync();
-    }
-  }
-  if (a.tstamp && lane == 0)
-    atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 3), (unsigned long long)wall_clock64());
-  if (a.tstamp && lane == 0 && ce > t + 1) atomicAdd(reinterpret_cast<unsigned long long*>(a.tstamp + 7), 1ull);
-}
-
-// ---- eigenvectors for s > EIG_SPLIT_MIN: three launches -------------------------------------------
+// ---- eigenvectors: three launches ----------------------------------------------------------------
 // (A) one wave per eigenpair: the twisted-factorisation eigenvector of T, to Y;
 // (B) one wave per cluster of close eigenvalues: modified Gram-Schmidt of the members in order
 //     (or inverse iteration for near-exact degeneracies), in place in Y;
 // (C) one wave per eigenpair: back-transformation u = Q y with the vector held in registers.
-// Separating (A) and (C) from (B) keeps the expensive back-transformation parallel over all
-// eigenpairs even where the spectrum is dense enough for many eigenvalues to fall into clusters.
-static constexpr int EIG_SPLIT_MIN = 256;
+// Separating (A) and (C) from (B) keeps the twisted solves and the back-transformations parallel
+// over all eigenpairs even where eigenvalues fall into clusters (measured at s = 128: 107 us
+// without clusters, 280 us with three clusters, where one wave per cluster doing all of its
+// members' work took 1374 us).
 
 __device__ inline int keep_count(const EigArgs& a) {
   int keep = a.kmax;
@@ -1199,7 +1096,8 @@ __global__ __launch_bounds__(256) void k_backtransform(EigArgs a0) {
   if (t >= kmax) return;
   const bool kept = t < a.kkeep[0];
   const double* y = W.Y + (size_t)t * s;
-  if (s <= 512) back_transform_reg<8>(a, W, s, kmax, t, kept, y);
+  if (s <= 256) back_transform_any(a, W, s, kmax, t, kept, y, nullptr);
+  else if (s <= 512) back_transform_reg<8>(a, W, s, kmax, t, kept, y);
   else if (s <= 1024) back_transform_reg<16>(a, W, s, kmax, t, kept, y);
   else back_transform_col(a, W, s, kmax, t, kept, y, reinterpret_cast<double2*>(smem) + (size_t)s * wave);
   if (a.tstamp && (threadIdx.x & 63) == 0)
@@ -1239,12 +1137,6 @@ hipError_t launch_eig(const EigArgs& a, hipStream_t st) {
   const size_t lds3 = (size_t)a.s * (2 * 8 + (size_t)nw * 4 * 8) + 64;
   if (lds3 > 160 * 1024 - 512) return hipErrorInvalidValue;
   const dim3 g3((a.kmax + nw - 1) / nw, a.batch);
-  if (a.s <= EIG_SPLIT_MIN) {
-    (void)hipFuncSetAttribute((const void*)k_eigvecs, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds3);
-    hipLaunchKernelGGL(k_eigvecs, g3, dim3(64 * nw), lds3, st, a);
-    return hipGetLastError();
-  }
   (void)hipFuncSetAttribute((const void*)k_eigvecs_twisted,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds3);
   hipLaunchKernelGGL(k_eigvecs_twisted, g3, dim3(64 * nw), lds3, st, a);
