@@ -762,44 +762,117 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_eigvals(EigArgs a0) {
 }
 
 // ---- eigenvectors of T and back-transformation: one wave per eigenpair ---------------------------
-// Twisted factorisation for an isolated eigenvalue x; y gets the unit eigenvector. Single lane.
-__device__ void twisted_vector(const double* dd, const double* e, int s, double x, double pivmin,
-                               double* y, double* lp, double* dp, double* um) {
+// a double from lane `l` (a constant) of the wave
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Twisted factorisation T - x I = N_r Delta N_r^T for an isolated eigenvalue x, by a whole wave:
+// every lane runs the recurrences (their values are the same in every lane), the coefficients of
+// 64 consecutive steps are loaded one per lane and broadcast with readlane, and the result of step
+// i is kept by lane i mod 64 and stored after each block of 64 steps. The operations and their
+// order are those of the plain sequential recurrences. lp, dp, um, y: LDS scratch of s doubles
+// each (y gets the unnormalised vector); returns 1 / ||y||.
+__device__ double twisted_vector(const double* dd, const double* e, int s, double x, double pivmin,
+                                 double* lp, double* dp, double* um, double* y) {
+  const int lane = threadIdx.x & 63;
+  // L+ D+ L+^T from the top
   double d = dd[0] - x;
-  dp[0] = d;
-  for (int i = 0; i < s - 1; ++i) {
-    if (fabs(d) < pivmin) d = d < 0.0 ? -pivmin : pivmin;
-    const double l = qdiv(e[i], d);
-    lp[i] = l;
-    d = dd[i + 1] - x - l * e[i];
-    dp[i + 1] = d;
+  if (lane == 0) dp[0] = d;
+  for (int i0 = 0; i0 < s - 1; i0 += 64) {
+    const int il = i0 + lane;
+    const double ddl = il + 1 < s ? dd[il + 1] : 0.0;
+    const double el = il < s - 1 ? e[il] : 0.0;
+    double lpl = 0.0, dpl = 0.0;
+    const int nk = min(64, s - 1 - i0);
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+      if (k < nk) {
+        const double ddi = readlane_d(ddl, k), ei = readlane_d(el, k);
+        if (fabs(d) < pivmin) d = d < 0.0 ? -pivmin : pivmin;
+        const double l = qdiv(ei, d);
+        d = ddi - x - l * ei;
+        if (lane == k) {
+          lpl = l;
+          dpl = d;
+        }
+      }
+    }
+    if (il < s - 1) {
+      lp[il] = lpl;
+      dp[il + 1] = dpl;
+    }
   }
+  wave_lds_sync();
+  // U- D- U-^T from the bottom, and the twist index r of the smallest |gamma|
   double dm = dd[s - 1] - x;
   int r = s - 1;
   double gbest = fabs(dp[s - 1]);
-  for (int i = s - 2; i >= 0; --i) {
-    if (fabs(dm) < pivmin) dm = dm < 0.0 ? -pivmin : pivmin;
-    const double u = qdiv(e[i], dm);
-    um[i] = u;
-    dm = dd[i] - x - u * e[i];
-    const double g = fabs(dp[i] + dm - (dd[i] - x));
-    if (g < gbest) { gbest = g; r = i; }
+  for (int i1 = s - 2; i1 >= 0; i1 -= 64) {
+    const int il = i1 - lane;
+    const double ddl = il >= 0 ? dd[il] : 0.0, el = il >= 0 ? e[il] : 0.0, dpl = il >= 0 ? dp[il] : 0.0;
+    double uml = 0.0;
+    const int nk = min(64, i1 + 1);
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+      if (k < nk) {
+        const double ddi = readlane_d(ddl, k), ei = readlane_d(el, k), dpi = readlane_d(dpl, k);
+        if (fabs(dm) < pivmin) dm = dm < 0.0 ? -pivmin : pivmin;
+        const double u = qdiv(ei, dm);
+        dm = ddi - x - u * ei;
+        const double g = fabs(dpi + dm - (ddi - x));
+        if (g < gbest) {
+          gbest = g;
+          r = i1 - k;
+        }
+        if (lane == k) uml = u;
+      }
+    }
+    if (il >= 0) um[il] = uml;
   }
+  wave_lds_sync();
+  // y[r] = 1, y[i] = -lp[i] y[i+1] below r, y[i+1] = -um[i] y[i] above
   double z = 1.0, nrm = 1.0;
-  y[r] = 1.0;
-  for (int i = r - 1; i >= 0; --i) {
-    z = -lp[i] * z;
-    y[i] = z;
-    nrm += z * z;
+  if (lane == 0) y[r] = 1.0;
+  for (int i1 = r - 1; i1 >= 0; i1 -= 64) {
+    const int il = i1 - lane;
+    const double lpl = il >= 0 ? lp[il] : 0.0;
+    double yl = 0.0;
+    const int nk = min(64, i1 + 1);
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+      if (k < nk) {
+        z = -readlane_d(lpl, k) * z;
+        nrm += z * z;
+        if (lane == k) yl = z;
+      }
+    }
+    if (il >= 0) y[il] = yl;
   }
   z = 1.0;
-  for (int i = r; i < s - 1; ++i) {
-    z = -um[i] * z;
-    y[i + 1] = z;
-    nrm += z * z;
+  for (int i0 = r; i0 < s - 1; i0 += 64) {
+    const int il = i0 + lane;
+    const double uml = il < s - 1 ? um[il] : 0.0;
+    double yl = 0.0;
+    const int nk = min(64, s - 1 - i0);
+#pragma unroll
+    for (int k = 0; k < 64; ++k) {
+      if (k < nk) {
+        z = -readlane_d(uml, k) * z;
+        nrm += z * z;
+        if (lane == k) yl = z;
+      }
+    }
+    if (il < s - 1) y[il + 1] = yl;
   }
-  const double inv = 1.0 / sqrt(nrm);
-  for (int i = 0; i < s; ++i) y[i] *= inv;
+  wave_lds_sync();
+  return 1.0 / sqrt(nrm);
 }
 
 // Inverse iteration for the members [cs, ce) of a cluster, re-orthogonalised within the cluster.
@@ -912,52 +985,54 @@ __device__ void back_transform_col(const EigArgs& a, const EigWork& W, int s, in
     a.U[(size_t)i * kmax + t] = kept ? u[i] : make_double2(0.0, 0.0);
 }
 
-// Register-resident variant for s <= 64 R: lane l holds rows l + 64 q; the next reflector and its tau
-// are loaded while the current one is reduced.
-template <int R>
+// Register-resident variant for s <= 64 R: lane l holds rows l + 64 q. The next PF reflectors and
+// their tau are held in registers, loaded PF steps before their use, so that the L2 latency of a
+// reflector overlaps PF reductions.
+template <int R, int PF>
 __device__ void back_transform_reg(const EigArgs& a, const EigWork& W, int s, int kmax, int t,
                                    bool kept, const double* yin) {
   const int lane = threadIdx.x & 63;
-  double2 ur[R], vn[R];
+  double2 ur[R], vn[PF][R], tn[PF];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int i = lane + 64 * q;
     ur[q] = make_double2(i < s ? yin[i] : 0.0, 0.0);
   }
-  int j = s - 2;
-  double2 taun = j >= 0 ? W.tau[j] : make_double2(0.0, 0.0);
+  auto fetch = [&](int j, double2& tau, double2* v) {
+    tau = j >= 0 ? W.tau[j] : make_double2(0.0, 0.0);
 #pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int i = lane + 64 * q;
-    vn[q] = (j >= 0 && i > j && i < s) ? W.V[(size_t)j * s + i] : make_double2(0.0, 0.0);
-  }
-  for (; j >= 0; --j) {
-    double2 vc[R];
+    for (int q = 0; q < R; ++q) {
+      const int i = lane + 64 * q;
+      v[q] = (j >= 0 && i > j && i < s) ? W.V[(size_t)j * s + i] : make_double2(0.0, 0.0);
+    }
+  };
 #pragma unroll
-    for (int q = 0; q < R; ++q) vc[q] = vn[q];
-    const double2 tc = taun;
-    if (j > 0) {
-      taun = W.tau[j - 1];
+  for (int p = 0; p < PF; ++p) fetch(s - 2 - p, tn[p], vn[p]);
+  for (int j0 = s - 2; j0 >= 0; j0 -= PF) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      const int j = j0 - p;
+      if (j < 0) break;
+      double2 vc[R];
+#pragma unroll
+      for (int q = 0; q < R; ++q) vc[q] = vn[p][q];
+      const double2 tc = tn[p];
+      fetch(j - PF, tn[p], vn[p]);
+      if (tc.x == 0.0 && tc.y == 0.0) continue;
+      double dr = 0.0, di = 0.0;
 #pragma unroll
       for (int q = 0; q < R; ++q) {
-        const int i = lane + 64 * q;
-        vn[q] = (i > j - 1 && i < s) ? W.V[(size_t)(j - 1) * s + i] : make_double2(0.0, 0.0);
+        dr += vc[q].x * ur[q].x + vc[q].y * ur[q].y;
+        di += vc[q].x * ur[q].y - vc[q].y * ur[q].x;
       }
-    }
-    if (tc.x == 0.0 && tc.y == 0.0) continue;
-    double dr = 0.0, di = 0.0;
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const double2 f = cmul(tc, make_double2(dr, di));
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      dr += vc[q].x * ur[q].x + vc[q].y * ur[q].y;
-      di += vc[q].x * ur[q].y - vc[q].y * ur[q].x;
-    }
-    dr = wave_sum(dr);
-    di = wave_sum(di);
-    const double2 f = cmul(tc, make_double2(dr, di));
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      ur[q].x -= vc[q].x * f.x - vc[q].y * f.y;
-      ur[q].y -= vc[q].x * f.y + vc[q].y * f.x;
+      for (int q = 0; q < R; ++q) {
+        ur[q].x -= vc[q].x * f.x - vc[q].y * f.y;
+        ur[q].y -= vc[q].x * f.y + vc[q].y * f.x;
+      }
     }
   }
 #pragma unroll
@@ -965,14 +1040,6 @@ __device__ void back_transform_reg(const EigArgs& a, const EigWork& W, int s, in
     const int i = lane + 64 * q;
     if (i < s) a.U[(size_t)i * kmax + t] = kept ? ur[q] : make_double2(0.0, 0.0);
   }
-}
-
-__device__ void back_transform_any(const EigArgs& a, const EigWork& W, int s, int kmax, int t,
-                                   bool kept, const double* yin, double2* u) {
-  if (s <= 64) back_transform_reg<1>(a, W, s, kmax, t, kept, yin);
-  else if (s <= 128) back_transform_reg<2>(a, W, s, kmax, t, kept, yin);
-  else if (s <= 256) back_transform_reg<4>(a, W, s, kmax, t, kept, yin);
-  else back_transform_col(a, W, s, kmax, t, kept, yin, u);
 }
 
 // ---- eigenvectors: three launches ----------------------------------------------------------------
@@ -1025,12 +1092,9 @@ __global__ __launch_bounds__(256) void k_eigvecs_twisted(EigArgs a0) {
     a.inv_sqrt_l0[0] = a.lam[0] > 0.0 ? 1.0 / sqrt(a.lam[0]) : 1.0;
   }
   double* y = region + 3 * (size_t)s;
-  if (lane == 0) twisted_vector(dd, el, s, a.lam[t], W.bounds[3], y, region, region + s, region + 2 * s);
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const double inv = twisted_vector(dd, el, s, a.lam[t], W.bounds[3], region, region + s, region + 2 * s, y);
   double* yo = W.Y + (size_t)t * s;
-  for (int i = lane; i < s; i += 64) yo[i] = y[i];
+  for (int i = lane; i < s; i += 64) yo[i] = y[i] * inv;
 }
 
 __global__ __launch_bounds__(256) void k_eigvecs_clusters(EigArgs a0) {
@@ -1085,6 +1149,9 @@ __global__ __launch_bounds__(256) void k_eigvecs_clusters(EigArgs a0) {
   }
 }
 
+// one instantiation per size class, so that small matrices run with few registers per wave (many
+// waves per SIMD when instances are batched)
+template <int R, int PF>
 __global__ __launch_bounds__(256) void k_backtransform(EigArgs a0) {
   const EigArgs a = eig_inst(a0, blockIdx.y);
   extern __shared__ double smem[];
@@ -1096,9 +1163,7 @@ __global__ __launch_bounds__(256) void k_backtransform(EigArgs a0) {
   if (t >= kmax) return;
   const bool kept = t < a.kkeep[0];
   const double* y = W.Y + (size_t)t * s;
-  if (s <= 256) back_transform_any(a, W, s, kmax, t, kept, y, nullptr);
-  else if (s <= 512) back_transform_reg<8>(a, W, s, kmax, t, kept, y);
-  else if (s <= 1024) back_transform_reg<16>(a, W, s, kmax, t, kept, y);
+  if (R > 0) back_transform_reg<(R > 0 ? R : 1), PF>(a, W, s, kmax, t, kept, y);
   else back_transform_col(a, W, s, kmax, t, kept, y, reinterpret_cast<double2*>(smem) + (size_t)s * wave);
   if (a.tstamp && (threadIdx.x & 63) == 0)
     atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 3), (unsigned long long)wall_clock64());
@@ -1149,12 +1214,24 @@ hipError_t launch_eig(const EigArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_eigvecs_clusters, dim3((a.kmax + 3) / 4, a.batch), dim3(256), ldsc, st, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t ldsb = a.s > 1024 ? (size_t)a.s * 16 * 4 : 0;
-  if (ldsb > 160 * 1024 - 512) return hipErrorInvalidValue;
-  if (ldsb > 0)
-    (void)hipFuncSetAttribute((const void*)k_backtransform,
+  const dim3 gb((a.kmax + 3) / 4, a.batch);
+  if (a.s <= 64) {
+    hipLaunchKernelGGL((k_backtransform<1, 4>), gb, dim3(256), 0, st, a);
+  } else if (a.s <= 128) {
+    hipLaunchKernelGGL((k_backtransform<2, 4>), gb, dim3(256), 0, st, a);
+  } else if (a.s <= 256) {
+    hipLaunchKernelGGL((k_backtransform<4, 4>), gb, dim3(256), 0, st, a);
+  } else if (a.s <= 512) {
+    hipLaunchKernelGGL((k_backtransform<8, 2>), gb, dim3(256), 0, st, a);
+  } else if (a.s <= 1024) {
+    hipLaunchKernelGGL((k_backtransform<16, 1>), gb, dim3(256), 0, st, a);
+  } else {
+    const size_t ldsb = (size_t)a.s * 16 * 4;
+    if (ldsb > 160 * 1024 - 512) return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute((const void*)k_backtransform<0, 1>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsb);
-  hipLaunchKernelGGL(k_backtransform, dim3((a.kmax + 3) / 4, a.batch), dim3(256), ldsb, st, a);
+    hipLaunchKernelGGL((k_backtransform<0, 1>), gb, dim3(256), ldsb, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -84,7 +84,8 @@ def herm_psd(rng, s, rank=None, n=None):
 
 
 @pytest.mark.parametrize("s,kmax", [(1, 1), (2, 1), (2, 2), (7, 3), (64, 32), (128, 64), (200, 100),
-                                    (96, 96), (129, 64), (300, 300), (520, 128), (1024, 256)])
+                                    (96, 96), (129, 64), (300, 300), (520, 128), (1024, 256),
+                                    (1100, 64)])
 def test_eig_topk(lib, s, kmax):
     print(f"eig s={s} kmax={kmax}", flush=True)
     rng = np.random.default_rng(s)
