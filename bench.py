@@ -32,6 +32,16 @@ WORKLOADS = {
 }
 
 
+AUTOTUNE = False   # contexts tune their contractions (cbc_autotune) when set
+
+
+def new_context(cbc):
+    ctx = cbc.Context()
+    if AUTOTUNE:
+        ctx.autotune()
+    return ctx
+
+
 def measure(cbc, p, precs, steps, warmup, stream):
     """Time `steps` compressions of problem p per precision (after `warmup`), then the same number
     with per-op HIP events for the kernel-class times. Returns per-precision results and outputs."""
@@ -39,7 +49,7 @@ def measure(cbc, p, precs, steps, warmup, stream):
     tree = cbc.Tree.of(p)
     st, so = cbc.pack(p.state, "cuda:0")
     op, oo = cbc.pack(p.op, "cuda:0")
-    ctx = cbc.Context()
+    ctx = new_context(cbc)
     res, outputs = {}, {}
     for prec in precs:
         comp = cbc.Compressor(ctx, tree, p.max_bond, prec, device="cuda:0")
@@ -211,7 +221,7 @@ def batched_run(args, cbc, p, stream):
     tree = cbc.Tree.of(p)
     st, so = cbc.pack_batch([q.state for q in probs], "cuda:0")
     op, oo = cbc.pack_batch([q.op for q in probs], "cuda:0")
-    ctx = cbc.Context()
+    ctx = new_context(cbc)
     comp = cbc.Compressor(ctx, tree, p.max_bond, "mixed", device="cuda:0", batch=args.batch)
     steps = max(2, args.steps // 4)
     sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, 1)
@@ -233,7 +243,8 @@ def uneven_run(count, stream_count=8):
     from paper_2601_19650_amd import cbc
     from paper_2601_19650_amd.inputs import batch_problems
     probs = batch_problems(count=count, seed=5, chi_range=(16, 48), ternary_chi_cap=16)
-    ub = cbc.UnevenBatch(probs, precision="mixed", nstreams=stream_count, device="cuda:0")
+    ub = cbc.UnevenBatch(probs, precision="mixed", nstreams=stream_count, device="cuda:0",
+                         autotune=AUTOTUNE)
     ub.capture()                  # every instance, forked over the streams, in one graph
     ub.run()
     torch.cuda.synchronize()
@@ -264,10 +275,14 @@ def main():
     ap.add_argument("--large-steps", type=int, default=2,
                     help="also time the large-bond workload (MPS N=128, d=4, chi=256) for this many "
                          "steps per precision (0: skip)")
+    ap.add_argument("--autotune", choices=["on", "off"], default="on",
+                    help="tune the contractions' tile and split per shape before timing (cbc_autotune)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times) and exit; used to "
                          "scale the HBM byte counters of a profiler run")
     args = ap.parse_args()
+    global AUTOTUNE
+    AUTOTUNE = args.autotune == "on"
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -324,7 +339,8 @@ def main():
         "dtype": "c64+f64" if head == "mixed" else "c128",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "name": args.workload,
-                   "precision": head, "max_bond": p.max_bond, "n_nodes": p.n},
+                   "precision": head, "max_bond": p.max_bond, "n_nodes": p.n,
+                   "contraction_config": "autotuned" if AUTOTUNE else "fixed policy"},
         "contraction_tflops": contraction_flops / sec / 1e12,
         "roofline": {"bound": bound, "kernel": cls[kd], "achieved": achieved,
                      "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved * 1e12 / peak,

@@ -132,6 +132,20 @@ cbc_status cbc_create(cbc_ctx** ctx);
 void cbc_destroy(cbc_ctx* ctx);
 const char* cbc_status_str(cbc_status s);
 
+/* Autotuning of the contractions (the dense complex contractions of Sec. III: the environment,
+ * Gram, projection and QR products), per GEMM shape and batch: the tile shape of the MFMA kernel
+ * (32 x 32, 64 x 64 or the pipelined 64 x 64, which accumulates in FP32 only) and the split of the
+ * reduction into 1, 2, 4 or 8 chunks. After this call, plans built by the context reserve scratch
+ * for the split candidates (cbc_query reports the larger workspace), and the first call of a plan
+ * with a new batch times every feasible configuration of each contraction on the call's own
+ * operands (three launches each, HIP events on the call's stream, which it waits for), keeps the
+ * fastest and records it; the call then computes its result as usual. Calls recorded into a
+ * caller's graph capture are not tuned. cache_path (may be NULL or empty) names a text file of
+ * earlier choices, one "cbc-gemm" line per shape: it is read now (other lines are skipped) and new
+ * choices are appended to it. Returns CBC_EINVAL for a null ctx or a cache file that cannot be
+ * opened for appending. */
+cbc_status cbc_autotune(cbc_ctx* ctx, const char* cache_path);
+
 /* Sizes for a problem: workspace bytes and the output packing (n_nodes + 1 offsets; the last entry is
  * the total number of complex elements the output buffer must hold). Host only, no device work.
  * `method` is 0 for cbc_apply and 1 for cbc_apply_naive. */

@@ -92,12 +92,14 @@ def lib():
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(_Out),
                                         ctypes.c_void_p, ctypes.POINTER(Stats)]
         L.cbc_apply_batched.restype = ctypes.c_int
+        L.cbc_autotune.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+        L.cbc_autotune.restype = ctypes.c_int
         _lib = L
     return _lib
 
 
 EXPORTED = ("cbc_create", "cbc_destroy", "cbc_status_str", "cbc_query", "cbc_plan_bonds",
-            "cbc_apply", "cbc_apply_batched", "cbc_apply_naive")
+            "cbc_apply", "cbc_apply_batched", "cbc_apply_naive", "cbc_autotune")
 
 
 def _check(code, what):
@@ -117,6 +119,13 @@ class Context:
         h = ctypes.c_void_p()
         _check(lib().cbc_create(ctypes.byref(h)), "cbc_create")
         self.h = h
+
+    def autotune(self, cache_path=None):
+        """Tune the contractions of plans built from now on (see cbc_autotune); cache_path: text
+        file of earlier choices, read now and appended to."""
+        path = None if cache_path is None else str(cache_path).encode()
+        _check(lib().cbc_autotune(self.h, path), "cbc_autotune")
+        return self
 
     def close(self):
         if self.h:
@@ -238,9 +247,11 @@ class UnevenBatch:
     instance, launched round-robin over `nstreams` side streams so that instances overlap on the
     GPU. Inputs are packed once and stay resident."""
 
-    def __init__(self, problems, precision="mixed", nstreams=8, device="cuda"):
+    def __init__(self, problems, precision="mixed", nstreams=8, device="cuda", autotune=False):
         import torch
         self.ctx = Context()
+        if autotune:
+            self.ctx.autotune()
         self.streams = [torch.cuda.Stream(device=device) for _ in range(nstreams)]
         self.items = []
         for p in problems:

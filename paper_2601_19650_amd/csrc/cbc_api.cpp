@@ -59,6 +59,7 @@ struct Op {
   int M = 0, N = 0, K = 0;
   int64_t tAm = 0, tAk = 0, tBk = 0, tBn = 0, tCm = 0, tCn = 0;
   int conjA = 0, conjB = 0, akf = 0, bkf = 0, tile = 0, ksplit = 1;
+  int kcap = 1;   // largest split the scratch `part` has room for
   TRef part;   // split-K chunk sums (scratch)
   DType ta = DT_C128, tb = DT_C128, tc = DT_C128, acc = DT_C128;
   double alpha = 1.0;
@@ -86,6 +87,8 @@ struct Plan {
   double cflops = 0.0, gflops = 0.0;
   int n_eig = 0, max_eig = 0;
   bool unsupported = false;   // a step exceeds this build's kernel limits
+  bool tune = false;          // built for autotuning: scratch for split candidates reserved
+  int tuned_batch = 0;        // batch the contractions were last tuned for (0: not tuned)
   int launches[CBC_K_NCLASS] = {0};
   double flops[CBC_K_NCLASS] = {0.0};
   double bytes[CBC_K_NCLASS] = {0.0};
@@ -167,6 +170,8 @@ cbc_status validate_tree(const cbc_tree* t, Problem& P) {
 
 // ------------------------------------------------------------------------------------------------
 // planner
+
+static constexpr int TUNE_KS = 8;   // largest split-K the autotuner tries
 
 struct Builder {
   Plan& P;
@@ -308,11 +313,16 @@ struct Builder {
       const bool f64 = acc == DT_C128;
       const int t1 = gemm_pick_tile(op.M, op.N, op.K, 1, f64);
       const int ks = gemm_pick_ksplit(op.M, op.N, op.K, 1, t1);
+      int kcap = ks;
+      // the autotuner also tries splits of up to TUNE_KS chunks where the output is small
+      const int64_t tiles32 = (int64_t)((op.M + 31) / 32) * ((op.N + 31) / 32);
+      if (P.tune && tiles32 < 512 && op.K >= 32) kcap = std::max(kcap, TUNE_KS);
       if (ks > 1) {
         op.tile = t1;
         op.ksplit = ks;
-        op.part = scr((size_t)ks * op.M * op.N * (f64 ? 16 : 8), acc);
       }
+      op.kcap = kcap;
+      if (kcap > 1) op.part = scr((size_t)kcap * op.M * op.N * (f64 ? 16 : 8), acc);
     }
     const double f = 8.0 * (double)op.M * op.N * op.K;
     op.cls = bucket == 0 ? CBC_K_CONTRACT : bucket == 1 ? CBC_K_GRAM : bucket == 2 ? CBC_K_QRMUL
@@ -1089,6 +1099,10 @@ struct Call {
 struct cbc_ctx {
   std::map<std::vector<int64_t>, std::unique_ptr<Plan>> plans;
   int device = -1;
+  // autotuning: contraction configuration (tile, split) per GEMM key, and the cache file
+  bool tune = false;
+  std::string tune_path;
+  std::map<std::vector<int64_t>, std::pair<int, int>> tuned;
 };
 
 namespace {
@@ -1121,6 +1135,41 @@ int64_t stride_of(const Plan& P, const Call& c, const TRef& r) {
   }
 }
 
+GemmArgs gemm_args(const Plan& P, const Call& c, const Op& op) {
+  GemmArgs g;
+  g.A = resolve(P, c, op.A);
+  g.B = resolve(P, c, op.B);
+  g.C = resolve(P, c, op.C);
+  g.M = op.M;
+  g.N = op.N;
+  g.K = op.K;
+  g.offAm = P.d_tables + op.tAm;
+  g.offAk = P.d_tables + op.tAk;
+  g.offBk = P.d_tables + op.tBk;
+  g.offBn = P.d_tables + op.tBn;
+  g.offCm = P.d_tables + op.tCm;
+  g.offCn = P.d_tables + op.tCn;
+  g.conjA = op.conjA;
+  g.conjB = op.conjB;
+  g.a_kfast = op.akf;
+  g.b_kfast = op.bkf;
+  g.alpha_dev = op.adev.src == S_NONE ? nullptr : (const double*)resolve(P, c, op.adev);
+  g.alpha_dev2 = op.adev2.src == S_NONE ? nullptr : (const double*)resolve(P, c, op.adev2);
+  g.alpha = op.alpha;
+  g.batch = c.batch;
+  g.bsA = stride_of(P, c, op.A);
+  g.bsB = stride_of(P, c, op.B);
+  g.bsC = stride_of(P, c, op.C);
+  g.bsAlpha = stride_of(P, c, op.adev);
+  g.bsAlpha2 = stride_of(P, c, op.adev2);
+  g.mbase = 0;
+  g.ksplit = op.ksplit;
+  g.kchunk = ((op.K + op.ksplit - 1) / op.ksplit + 15) / 16 * 16;
+  g.part = op.ksplit > 1 ? resolve(P, c, op.part) : nullptr;
+  g.bsPart = op.ksplit > 1 ? stride_of(P, c, op.part) : 0;
+  return g;
+}
+
 hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev = nullptr) {
   size_t idx = 0;
   for (const Op& op : P.ops) {
@@ -1130,41 +1179,9 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
       if (e != hipSuccess) return e;
     }
     switch (op.kind) {
-      case K_GEMM: {
-        GemmArgs g;
-        g.A = resolve(P, c, op.A);
-        g.B = resolve(P, c, op.B);
-        g.C = resolve(P, c, op.C);
-        g.M = op.M;
-        g.N = op.N;
-        g.K = op.K;
-        g.offAm = P.d_tables + op.tAm;
-        g.offAk = P.d_tables + op.tAk;
-        g.offBk = P.d_tables + op.tBk;
-        g.offBn = P.d_tables + op.tBn;
-        g.offCm = P.d_tables + op.tCm;
-        g.offCn = P.d_tables + op.tCn;
-        g.conjA = op.conjA;
-        g.conjB = op.conjB;
-        g.a_kfast = op.akf;
-        g.b_kfast = op.bkf;
-        g.alpha_dev = op.adev.src == S_NONE ? nullptr : (const double*)resolve(P, c, op.adev);
-        g.alpha_dev2 = op.adev2.src == S_NONE ? nullptr : (const double*)resolve(P, c, op.adev2);
-        g.alpha = op.alpha;
-        g.batch = c.batch;
-        g.bsA = stride_of(P, c, op.A);
-        g.bsB = stride_of(P, c, op.B);
-        g.bsC = stride_of(P, c, op.C);
-        g.bsAlpha = stride_of(P, c, op.adev);
-        g.bsAlpha2 = stride_of(P, c, op.adev2);
-        g.mbase = 0;
-        g.ksplit = op.ksplit;
-        g.kchunk = ((op.K + op.ksplit - 1) / op.ksplit + 15) / 16 * 16;
-        g.part = op.ksplit > 1 ? resolve(P, c, op.part) : nullptr;
-        g.bsPart = op.ksplit > 1 ? stride_of(P, c, op.part) : 0;
-        e = launch_gemm(g, op.ta, op.tb, op.tc, op.acc, op.tile, st);
+      case K_GEMM:
+        e = launch_gemm(gemm_args(P, c, op), op.ta, op.tb, op.tc, op.acc, op.tile, st);
         break;
-      }
       case K_EIG: {
         EigArgs a;
         a.G = (double2*)resolve(P, c, op.G);
@@ -1262,9 +1279,93 @@ bool capturing(hipStream_t st) {
   return hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
 }
 
+// ---- autotuner -------------------------------------------------------------------------------
+std::vector<int64_t> tune_key(const Op& op, int batch) {
+  return {(int64_t)op.ta, (int64_t)op.tb, (int64_t)op.tc, (int64_t)op.acc, op.M, op.N, op.K,
+          batch, op.akf, op.bkf};
+}
+
+// Feasible (tile, split) configurations of a contraction: the three tile kernels (the pipelined one
+// accumulates in FP32 only), and splits of the reduction into 2, 4 or 8 chunks of at least 16 for
+// the kernels that take them, within the scratch the plan reserved.
+std::vector<std::pair<int, int>> tune_candidates(const Op& op, int batch) {
+  std::vector<std::pair<int, int>> cand;
+  const bool f64 = op.acc == DT_C128;
+  for (int tile : {GEMM_TILE32, GEMM_TILE64, GEMM_PIPE64}) {
+    if (tile == GEMM_PIPE64 && f64) continue;
+    for (int ks = 1; ks <= TUNE_KS; ks *= 2) {
+      if (ks > 1 && (tile == GEMM_TILE64 || ks > op.kcap)) continue;
+      const int kchunk = ((op.K + ks - 1) / ks + 15) / 16 * 16;
+      if (ks > 1 && (int64_t)kchunk * (ks - 1) >= op.K) continue;   // an empty chunk
+      if ((int64_t)batch * ks > 65535) continue;
+      cand.emplace_back(tile, ks);
+    }
+  }
+  return cand;
+}
+
+hipError_t tune_plan(cbc_ctx* ctx, Plan& P, const Call& c, hipStream_t st) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  std::FILE* f = nullptr;
+  if (e == hipSuccess && !ctx->tune_path.empty()) f = std::fopen(ctx->tune_path.c_str(), "a");
+  constexpr int reps = 3;
+  for (Op& op : P.ops) {
+    if (e != hipSuccess) break;
+    if (op.kind != K_GEMM) continue;
+    const auto key = tune_key(op, c.batch);
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end() && it->second.second <= op.kcap) {
+      op.tile = it->second.first;
+      op.ksplit = it->second.second;
+      continue;
+    }
+    std::pair<int, int> best{op.tile, op.ksplit};
+    float best_ms = 0.0f;
+    bool have = false;
+    for (const auto& cf : tune_candidates(op, c.batch)) {
+      op.tile = cf.first;
+      op.ksplit = cf.second;
+      // one launch to warm up, then the timed ones; results are recomputed by the call afterwards
+      const GemmArgs g = gemm_args(P, c, op);
+      hipError_t r = launch_gemm(g, op.ta, op.tb, op.tc, op.acc, op.tile, st);
+      if (r == hipSuccess) r = hipEventRecord(e0, st);
+      for (int i = 0; i < reps && r == hipSuccess; ++i) r = launch_gemm(g, op.ta, op.tb, op.tc, op.acc, op.tile, st);
+      if (r == hipSuccess) r = hipEventRecord(e1, st);
+      if (r == hipSuccess) r = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (r == hipSuccess) r = hipEventElapsedTime(&ms, e0, e1);
+      if (r != hipSuccess) {
+        e = r;
+        break;
+      }
+      if (!have || ms < best_ms) {
+        best = cf;
+        best_ms = ms;
+        have = true;
+      }
+    }
+    op.tile = best.first;
+    op.ksplit = best.second;
+    if (e != hipSuccess) break;
+    ctx->tuned[key] = best;
+    if (f) {
+      std::fprintf(f, "cbc-gemm");
+      for (int64_t v : key) std::fprintf(f, " %lld", (long long)v);
+      std::fprintf(f, " %d %d %.6f\n", best.first, best.second, best_ms / reps);
+    }
+  }
+  if (f) std::fclose(f);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e;
+}
+
 cbc_status get_plan(cbc_ctx* ctx, const Problem& pr, int max_bond, bool tol_on, cbc_precision prec,
                     int method, int64_t state_span, int64_t op_span, Plan** out) {
-  const auto key = plan_key(pr, max_bond, tol_on, prec, method, state_span, op_span);
+  auto key = plan_key(pr, max_bond, tol_on, prec, method, state_span, op_span);
+  key.push_back(ctx->tune ? 1 : 0);
   auto it = ctx->plans.find(key);
   if (it != ctx->plans.end()) {
     *out = it->second.get();
@@ -1273,6 +1374,7 @@ cbc_status get_plan(cbc_ctx* ctx, const Problem& pr, int max_bond, bool tol_on, 
   auto P = std::make_unique<Plan>();
   P->state_elems = state_span;
   P->op_elems = op_span;
+  P->tune = ctx->tune;
   cbc_status s = method == 0 ? build_plan(*P, pr, max_bond, tol_on, prec)
                               : build_plan_naive(*P, pr, max_bond, tol_on, prec);
   if (s != CBC_OK) return s;
@@ -1306,6 +1408,39 @@ cbc_status cbc_create(cbc_ctx** ctx) {
 }
 
 void cbc_destroy(cbc_ctx* ctx) { delete ctx; }
+
+cbc_status cbc_autotune(cbc_ctx* ctx, const char* cache_path) {
+  if (!ctx) return CBC_EINVAL;
+  ctx->tune = true;
+  if (!cache_path || !cache_path[0]) return CBC_OK;
+  ctx->tune_path = cache_path;
+  std::FILE* f = std::fopen(cache_path, "r");
+  if (!f) {
+    // a new cache: create it now, so that an unwritable path is reported here
+    f = std::fopen(cache_path, "a");
+    if (!f) return CBC_EINVAL;
+    std::fclose(f);
+    return CBC_OK;
+  }
+  // lines "cbc-gemm ta tb tc acc M N K batch akf bkf tile ksplit ms"; anything else is skipped
+  char tag[16];
+  while (std::fscanf(f, "%15s", tag) == 1) {
+    long long v[10];
+    int tile = 0, ks = 0;
+    double ms = 0.0;
+    bool ok = std::strcmp(tag, "cbc-gemm") == 0;
+    for (int i = 0; ok && i < 10; ++i) ok = std::fscanf(f, "%lld", &v[i]) == 1;
+    ok = ok && std::fscanf(f, "%d %d %lf", &tile, &ks, &ms) == 3;
+    ok = ok && (tile == GEMM_TILE32 || tile == GEMM_TILE64 || tile == GEMM_PIPE64) &&
+         (ks == 1 || ks == 2 || ks == 4 || ks == 8);
+    if (ok) ctx->tuned[std::vector<int64_t>(v, v + 10)] = {tile, ks};
+    int ch;
+    while ((ch = std::fgetc(f)) != EOF && ch != '\n') {
+    }
+  }
+  std::fclose(f);
+  return CBC_OK;
+}
 
 const char* cbc_status_str(cbc_status s) {
   switch (s) {
@@ -1424,6 +1559,16 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   hipStream_t st = (hipStream_t)stream;
   const bool profile = stats && stats->profile;
   int replayed = 0;
+  if (P->tune && ctx->tune && P->tuned_batch != batch && !(st != nullptr && capturing(st))) {
+    // the contractions' configurations change: a captured graph of the old ones is dropped
+    if (tune_plan(ctx, *P, c, st) != hipSuccess) return CBC_EHIP;
+    P->tuned_batch = batch;
+    if (P->gexec) {
+      (void)hipGraphExecDestroy(P->gexec);
+      P->gexec = nullptr;
+    }
+    P->gkey.clear();
+  }
   if (profile) {
     const size_t ne = 2 * P->ops.size();
     while (P->events.size() < ne) {

@@ -20,10 +20,10 @@ FP64_BAR = 1e-10
 MIXED_BAR = 1e-5
 
 
-def check(lib, p, prec, oracle_out=None, tol=0.0):
+def check(lib, p, prec, oracle_out=None, tol=0.0, ctx=None):
     print(f"parity {p.name or 'custom'} n={p.n} prec={prec} tol={tol}", flush=True)
     ref = oracle_out if oracle_out is not None else cbc_tree(p.parent, p.state, p.op, p.max_bond, tol)
-    out, comp = lib.compress(p, precision=prec, tol=tol)
+    out, comp = lib.compress(p, precision=prec, tol=tol, ctx=ctx)
     if prec == "fp64":
         err = tn.rel_error(p.parent, out, ref)
         assert err <= FP64_BAR, err
@@ -272,3 +272,22 @@ def test_uneven_batch_single_graph(lib):
         assert torch.isfinite(y)
         for (comp, _), ref, p in zip(ub.items, eager, probs):
             assert torch.equal(comp.out, ref), (rep, p.name)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotuned_parity_and_cache(lib, prec, tmp_path):
+    """Contractions configured by the autotuner (tile and split chosen by timing on the call's own
+    operands) keep parity with the oracle; a second context that reads the recorded choices finds
+    every shape in the cache (nothing is appended) and reproduces the result bitwise."""
+    p = config_problem("C3")
+    print(f"autotune {p.name} prec={prec}", flush=True)
+    path = tmp_path / "tune.txt"
+    ctx = lib.Context().autotune(path)
+    out = check(lib, p, prec, ctx=ctx)[0]
+    lines = [l for l in path.read_text().splitlines() if l.startswith("cbc-gemm")]
+    assert len(lines) >= 3
+    ctx2 = lib.Context().autotune(path)
+    out2, _ = lib.compress(p, precision=prec, ctx=ctx2)
+    for a, b in zip(out, out2):
+        assert np.array_equal(a, b)
+    assert len([l for l in path.read_text().splitlines() if l.startswith("cbc-gemm")]) == len(lines)

@@ -153,3 +153,39 @@ def test_naive_plan_sizes_match_oracle(maker):
     assert rc == 0 and ws > 0
     ref = tn.naive_compress(p.parent, p.op, p.state, p.max_bond)
     assert [int(s) for s in np.diff(off)] == [t.size for t in ref]
+
+
+def test_autotune_arguments_and_cache_file(tmp_path):
+    """cbc_autotune needs no device: it rejects a null context and an unwritable cache, creates a
+    new cache file, and reads a cache whose foreign, malformed or invalid lines it skips."""
+    L = cbc.lib()
+    assert L.cbc_autotune(None, None) == -1
+    path = tmp_path / "tune.txt"
+    cbc.Context().autotune(path)
+    assert path.exists()
+    path.write_text("cbc-gemm 1 1 0 0 64 64 128 1 0 1 0 4 0.010\n"
+                    "cbc-gemm 1 1 0 0 64 64 128 1 0 1 7 4 0.010\n"
+                    "some other text\n"
+                    "cbc-gemm 1 2\n")
+    ctx = cbc.Context().autotune(path)
+    assert ctx.autotune(None) is ctx
+    assert L.cbc_autotune(ctx.h, str(tmp_path / "no_such_dir" / "t.txt").encode()) == -1
+
+
+def test_autotune_reserves_split_scratch():
+    """Plans built for autotuning reserve scratch for the split candidates, so cbc_query reports a
+    larger workspace than for the fixed policy."""
+    p = config_problem("C2", n=12)
+    tree = cbc.Tree.of(p)
+    sizes = []
+    for tune in (False, True):
+        ctx = cbc.Context()
+        if tune:
+            ctx.autotune()
+        ws = ctypes.c_size_t()
+        off = np.zeros(tree.n + 1, dtype=np.int64)
+        rc = cbc.lib().cbc_query(ctx.h, ctypes.byref(tree.c), p.max_bond, 1, 0, ctypes.byref(ws),
+                                 off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        assert rc == 0
+        sizes.append(int(ws.value))
+    assert sizes[1] > sizes[0]
