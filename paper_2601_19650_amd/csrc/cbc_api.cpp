@@ -60,6 +60,7 @@ struct Op {
   int64_t tAm = 0, tAk = 0, tBk = 0, tBn = 0, tCm = 0, tCn = 0;
   int conjA = 0, conjB = 0, akf = 0, bkf = 0, tile = 0, ksplit = 1;
   int kcap = 1;   // largest split the scratch `part` has room for
+  bool tuned = false;   // tile and split set by the autotuner for the current batch
   TRef part;   // split-K chunk sums (scratch)
   DType ta = DT_C128, tb = DT_C128, tc = DT_C128, acc = DT_C128;
   double alpha = 1.0;
@@ -1135,7 +1136,16 @@ int64_t stride_of(const Plan& P, const Call& c, const TRef& r) {
   }
 }
 
-GemmArgs gemm_args(const Plan& P, const Call& c, const Op& op) {
+// Tile and split of a contraction for the call's batch: the autotuner's choice, or the fixed policy
+// (the split planned for one instance is reduced when the batch already fills the GPU; without a
+// split the tile is chosen at launch for the batch).
+std::pair<int, int> gemm_config(const Op& op, int batch) {
+  if (op.tuned || batch == 1 || op.ksplit == 1) return {op.tile, op.ksplit};
+  const int ks = std::min(op.ksplit, gemm_pick_ksplit(op.M, op.N, op.K, batch, op.tile));
+  return {ks > 1 ? op.tile : GEMM_AUTO, ks};
+}
+
+GemmArgs gemm_args(const Plan& P, const Call& c, const Op& op, int ksplit) {
   GemmArgs g;
   g.A = resolve(P, c, op.A);
   g.B = resolve(P, c, op.B);
@@ -1163,10 +1173,10 @@ GemmArgs gemm_args(const Plan& P, const Call& c, const Op& op) {
   g.bsAlpha = stride_of(P, c, op.adev);
   g.bsAlpha2 = stride_of(P, c, op.adev2);
   g.mbase = 0;
-  g.ksplit = op.ksplit;
-  g.kchunk = ((op.K + op.ksplit - 1) / op.ksplit + 15) / 16 * 16;
-  g.part = op.ksplit > 1 ? resolve(P, c, op.part) : nullptr;
-  g.bsPart = op.ksplit > 1 ? stride_of(P, c, op.part) : 0;
+  g.ksplit = ksplit;
+  g.kchunk = ((op.K + ksplit - 1) / ksplit + 15) / 16 * 16;
+  g.part = ksplit > 1 ? resolve(P, c, op.part) : nullptr;
+  g.bsPart = ksplit > 1 ? stride_of(P, c, op.part) : 0;
   return g;
 }
 
@@ -1179,9 +1189,11 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
       if (e != hipSuccess) return e;
     }
     switch (op.kind) {
-      case K_GEMM:
-        e = launch_gemm(gemm_args(P, c, op), op.ta, op.tb, op.tc, op.acc, op.tile, st);
+      case K_GEMM: {
+        const auto cf = gemm_config(op, c.batch);
+        e = launch_gemm(gemm_args(P, c, op, cf.second), op.ta, op.tb, op.tc, op.acc, cf.first, st);
         break;
+      }
       case K_EIG: {
         EigArgs a;
         a.G = (double2*)resolve(P, c, op.G);
@@ -1319,6 +1331,7 @@ hipError_t tune_plan(cbc_ctx* ctx, Plan& P, const Call& c, hipStream_t st) {
     if (it != ctx->tuned.end() && it->second.second <= op.kcap) {
       op.tile = it->second.first;
       op.ksplit = it->second.second;
+      op.tuned = true;
       continue;
     }
     std::pair<int, int> best{op.tile, op.ksplit};
@@ -1328,7 +1341,7 @@ hipError_t tune_plan(cbc_ctx* ctx, Plan& P, const Call& c, hipStream_t st) {
       op.tile = cf.first;
       op.ksplit = cf.second;
       // one launch to warm up, then the timed ones; results are recomputed by the call afterwards
-      const GemmArgs g = gemm_args(P, c, op);
+      const GemmArgs g = gemm_args(P, c, op, op.ksplit);
       hipError_t r = launch_gemm(g, op.ta, op.tb, op.tc, op.acc, op.tile, st);
       if (r == hipSuccess) r = hipEventRecord(e0, st);
       for (int i = 0; i < reps && r == hipSuccess; ++i) r = launch_gemm(g, op.ta, op.tb, op.tc, op.acc, op.tile, st);
@@ -1349,6 +1362,7 @@ hipError_t tune_plan(cbc_ctx* ctx, Plan& P, const Call& c, hipStream_t st) {
     op.tile = best.first;
     op.ksplit = best.second;
     if (e != hipSuccess) break;
+    op.tuned = true;
     ctx->tuned[key] = best;
     if (f) {
       std::fprintf(f, "cbc-gemm");
