@@ -291,3 +291,25 @@ def test_autotuned_parity_and_cache(lib, prec, tmp_path):
     for a, b in zip(out, out2):
         assert np.array_equal(a, b)
     assert len([l for l in path.read_text().splitlines() if l.startswith("cbc-gemm")]) == len(lines)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_autotuned_batched_parity(lib, prec):
+    """Contractions tuned for a batch (the tuner's key includes the batch size) keep every instance
+    of a batched call within the bars of the oracle."""
+    probs = [config_problem("C3", seed=200 + b) for b in range(3)]
+    p0 = probs[0]
+    print(f"autotune batched {p0.name} x{len(probs)} prec={prec}", flush=True)
+    ctx = lib.Context().autotune()
+    tree = lib.Tree.of(p0)
+    st, so = lib.pack_batch([p.state for p in probs], "cuda")
+    op, oo = lib.pack_batch([p.op for p in probs], "cuda")
+    cb = lib.Compressor(ctx, tree, p0.max_bond, prec, batch=len(probs))
+    cb.run(op, oo, st, so)
+    for b, p in enumerate(probs):
+        got = cb.unpack(b)
+        ref = cbc_tree(p.parent, p.state, p.op, p.max_bond)
+        if prec == "fp64":
+            assert tn.rel_error(p.parent, got, ref) <= FP64_BAR
+        else:
+            assert 1.0 - tn.fidelity(p.parent, got, ref) <= MIXED_BAR
