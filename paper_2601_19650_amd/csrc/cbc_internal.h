@@ -82,6 +82,7 @@ struct EigArgs {
   long long* tstamp;  // optional: wall-clock stamps at phase boundaries (8 entries), or nullptr
   int batch;          // instances; every pointer above (except tstamp) advances by bs bytes
   int64_t bs;
+  int spread = 1;     // set by launch_eig: grid widening of the XCD-aware launches (1 or 8)
 };
 size_t eig_work_doubles(int s, int kmax);
 // largest Gram the eigensolver handles (the multi-workgroup reduction keeps its rows in LDS)
