@@ -10,9 +10,10 @@
 // back-transformation u = Q y:
 //   1. reduction: for s <= EIG_LDS_MAX one workgroup (k_tridiag) holds the packed lower triangle in
 //      LDS; the Hermitian matrix-vector product uses groups of 8 lanes per row, DPP reductions and
-//      per-wave partial sums added in a fixed order (bitwise reproducible), three workgroup
-//      barriers per column. Larger s use k_tridiag_mw: the rows are spread over many workgroups and
-//      every column costs one grid-wide barrier.
+//      per-wave partial sums added in a fixed order (bitwise reproducible); while 15 waves apply the
+//      rank-2 update (one lane per column), wave 0 updates the next column itself and forms its
+//      reflector (look-ahead), so a column costs two workgroup barriers. Larger s use k_tridiag_mw:
+//      the rows are spread over many workgroups and every column costs one grid-wide barrier.
 //   2. k_eigvals, one wave per eigenvalue over many workgroups: multisection on Sturm counts (64
 //      points of the current interval per round).
 //   3. eigenvectors of T by a twisted factorisation T - lambda I = N_r Delta N_r^T, one wave per
@@ -148,14 +149,33 @@ __device__ int sturm_count(const double* dd, const double* ee2, int s, double x,
 }
 
 struct TriShared {
-  double2 tau;
-  double dotr, doti;
+  double2 tau[2];                   // tau of the current and of the next column (by parity)
   double2 part[EIG_THREADS / 64];   // per-wave partial sums of w^H v, added in a fixed order
 };
 
-// Householder vector of column j from x = A[j+1.., j]; wave 0. Returns the scaling 1/(alpha - beta)
-// that maps x[1..] to the reflector.
-__device__ inline double2 householder(double2 alpha, double xn2, int j, double a_jj, TriShared& sh,
+// a double from lane `l` (wave-uniform) of the wave
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ double2 readlane_z(double2 v, int l) {
+  return make_double2(readlane_d(v.x, l), readlane_d(v.y, l));
+}
+// w' = w + a2 v, the corrected product of one row (formed where it is used, identically everywhere)
+__device__ __forceinline__ double2 wprime(double2 w, double2 v, double2 a2) {
+  return make_double2(w.x + a2.x * v.x - a2.y * v.y, w.y + a2.x * v.y + a2.y * v.x);
+}
+// x - (v_r w'_c^* + w'_r v_c^*): one element of the rank-2 update
+__device__ __forceinline__ double2 rank2(double2 x, double2 vr, double2 wr, double2 vc, double2 wc) {
+  x.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
+  x.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
+  return x;
+}
+
+// Householder reflector of column C from x = A[C+1.., C] (alpha = x[0], xn2 = |x[1..]|^2); lane 0
+// records tau, beta and the diagonal a_CC. Returns the scaling 1/(alpha - beta) that maps x[1..] to
+// the reflector.
+__device__ inline double2 householder(double2 alpha, double xn2, int C, double a_cc, double2& tau,
                                       EigWork& W, int lane) {
   double2 t = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
   double beta = alpha.x;
@@ -168,14 +188,65 @@ __device__ inline double2 householder(double2 alpha, double xn2, int j, double a
     scal = make_double2(ar / den, -ai / den);
   }
   if (lane == 0) {
-    sh.tau = t;
-    W.tau[j] = t;
-    W.e[j] = beta;
-    W.d[j] = a_jj;
-    sh.dotr = 0.0;
-    sh.doti = 0.0;
+    tau = t;
+    W.tau[C] = t;
+    W.e[C] = beta;
+    W.d[C] = a_cc;
   }
   return scal;
+}
+
+// Reflector of the next column, by one wave (look-ahead). With upd, column C = j+1 of the trailing
+// matrix is first brought up to date with the rank-2 update of column j (v in vc, w' in ww; the other
+// waves update every other column of the trailing matrix meanwhile); j = -1 reads column 0 as it is. Records
+// d[C] and, below the last column, the reflector of column C into vnext, tau and the workspace.
+// Rows C + r of the column are held by lane r mod 64 (r < s - C <= 128).
+__device__ inline void next_reflector(const double2* P, int s, int j, bool upd, const double2* vc,
+                                      const double2* ww, double2* vnext, double2& tau, EigWork& W,
+                                      int lane) {
+  const int C = j + 1, n = s - C;
+  double2 v0 = make_double2(1.0, 0.0), w0 = make_double2(0.0, 0.0);
+  if (upd) {
+    v0 = vc[0];
+    w0 = ww[0];
+  }
+  double2 x[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int r = lane + 64 * k;
+    x[k] = make_double2(0.0, 0.0);
+    if (r < n) {
+      x[k] = P[tri(C + r) + C];
+      if (upd) x[k] = rank2(x[k], vc[r], ww[r], v0, w0);
+    }
+  }
+  const double acc = readlane_d(x[0].x, 0);
+  if (C == s - 1) {
+    if (lane == 0) W.d[C] = acc;
+    return;
+  }
+  const double2 alpha = readlane_z(x[0], 1);
+  double xn2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int r = lane + 64 * k;
+    if (r >= 2 && r < n) xn2 += x[k].x * x[k].x + x[k].y * x[k].y;
+  }
+  xn2 = wave_sum(xn2);
+  const double2 scal = householder(alpha, xn2, C, acc, tau, W, lane);
+  if (lane == 0) {
+    vnext[0] = make_double2(1.0, 0.0);
+    W.V[(size_t)C * s + C + 1] = make_double2(1.0, 0.0);
+  }
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int r = lane + 64 * k;
+    if (r >= 2 && r < n) {
+      const double2 v = cmul(x[k], scal);
+      vnext[r - 1] = v;
+      W.V[(size_t)C * s + C + r] = v;
+    }
+  }
 }
 
 __device__ void tri_bounds(EigWork& W, int s, long long* tstamp);
@@ -185,11 +256,12 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
   extern __shared__ double smem[];
   __shared__ TriShared sh;
   const int s = a.s;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the wave index as a scalar: the update's rows and branches are then uniform per wave
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int nthr = blockDim.x;
   double2* P = reinterpret_cast<double2*>(smem);
-  double2* vv = P + tri(s);
-  double2* ww = vv + s;
+  double2* vb = P + tri(s);     // reflectors of the current and the next column (by parity)
+  double2* ww = vb + 2 * s;
   double2* A = a.G;
   EigWork W = eig_layout(a.work, s, a.kmax);
   if (a.tstamp && tid == 0) a.tstamp[0] = wall_clock64();
@@ -201,130 +273,118 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     P[idx] = A[(size_t)r * s + c];
   }
   __syncthreads();
+  if (wave == 0)
+    next_reflector(P, s, -1, false, nullptr, nullptr, vb, sh.tau[0], W, lane);
+  __syncthreads();
   const int grp = tid / RG, gl = tid % RG, ngrp = nthr / RG;
-  long long tA = 0, tB = 0, tD = 0, t0 = 0;
+  long long tL = 0, tB = 0, tD = 0, t0 = 0;
   const bool stamp = a.tstamp && tid == 0;
   for (int j = 0; j < s - 1; ++j) {
     const int nj = s - j - 1;
+    const double2* vv = vb + (j & 1) * s;
+    double2* vn = vb + ((j + 1) & 1) * s;
     if (stamp) t0 = wall_clock64();
-    if (wave == 0) {
-      const double2 alpha = P[tri(j + 1) + j];
-      double xn2 = 0.0;
-      for (int i = j + 2 + lane; i < s; i += 64) {
-        const double2 x = P[tri(i) + j];
-        xn2 += x.x * x.x + x.y * x.y;
+    const double2 t = sh.tau[j & 1];
+    const bool upd = !(t.x == 0.0 && t.y == 0.0);
+    if (upd) {
+      // w = tau A v over the trailing rows, groups of RG lanes per row, and the per-wave partial
+      // sums of w^H v
+      double dr_acc = 0.0, di_acc = 0.0;
+      for (int r = grp; r < nj; r += ngrp) {
+        const int R = j + 1 + r;
+        // row part (stored, contiguous) then column part (conjugated, addressed incrementally:
+        // tri(C + RG) = tri(C) + RG C + RG (RG + 1) / 2)
+        const double2* rowp = P + tri(R) + (j + 1);
+        double pr = 0.0, pi = 0.0;
+        for (int c = gl; c <= r; c += RG) {
+          const double2 x = rowp[c], v = vv[c];
+          pr += x.x * v.x - x.y * v.y;
+          pi += x.x * v.y + x.y * v.x;
+        }
+        int c = r + 1 + (((gl - r - 1) % RG) + RG) % RG;
+        int C = j + 1 + c;
+        int idx = tri(C) + R;
+        for (; c < nj; c += RG) {
+          const double2 x = P[idx], v = vv[c];
+          pr += x.x * v.x + x.y * v.y;
+          pi += x.x * v.y - x.y * v.x;
+          idx += RG * C + RG * (RG + 1) / 2;
+          C += RG;
+        }
+        pr = sum8(pr);
+        pi = sum8(pi);
+        if (gl == 0) {
+          const double2 w = cmul(t, make_double2(pr, pi));
+          ww[r] = w;
+          const double2 v = vv[r];
+          dr_acc += w.x * v.x + w.y * v.y;
+          di_acc += w.x * v.y - w.y * v.x;
+        }
       }
-      xn2 = wave_sum(xn2);
-      const double ajj = P[tri(j) + j].x;
-      const double2 scal = householder(alpha, xn2, j, ajj, sh, W, lane);
-      if (lane == 0) {
-        vv[0] = make_double2(1.0, 0.0);
-        W.V[(size_t)j * s + j + 1] = make_double2(1.0, 0.0);
+      dr_acc = wave_sum(dr_acc);
+      di_acc = wave_sum(di_acc);
+      if (lane == 0) sh.part[wave] = make_double2(dr_acc, di_acc);
+      __syncthreads();
+      double dsum_r = 0.0, dsum_i = 0.0;
+#pragma unroll
+      for (int w0 = 0; w0 < EIG_THREADS / 64; w0 += 8) {
+        double2 pw[8];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) pw[w] = sh.part[w0 + w];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+          dsum_r += pw[w].x;
+          dsum_i += pw[w].y;
+        }
       }
-      for (int i = 1 + lane; i < nj; i += 64) {
-        const double2 x = P[tri(j + 1 + i) + j];
-        const double2 v = cmul(x, scal);
-        vv[i] = v;
-        W.V[(size_t)j * s + j + 1 + i] = v;
-      }
+      const double2 q = cmul(t, make_double2(dsum_r, dsum_i));
+      const double2 a2 = make_double2(-0.5 * q.x, -0.5 * q.y);
+      // w' = w + a2 v, formed once
+      for (int r = tid; r < nj; r += nthr) ww[r] = wprime(ww[r], vv[r], a2);
+      __syncthreads();
     }
-    __syncthreads();
-    if (stamp) { const long long t1 = wall_clock64(); tA += t1 - t0; t0 = t1; }
-    const double2 t = sh.tau;
-    if (t.x == 0.0 && t.y == 0.0) continue;
-    double dr_acc = 0.0, di_acc = 0.0;
-    for (int r = grp; r < nj; r += ngrp) {
-      const int R = j + 1 + r;
-      // row part (stored, contiguous) then column part (conjugated, addressed incrementally:
-      // tri(C + RG) = tri(C) + RG C + RG (RG + 1) / 2)
-      const double2* rowp = P + tri(R) + (j + 1);
-      double pr = 0.0, pi = 0.0;
-      for (int c = gl; c <= r; c += RG) {
-        const double2 a = rowp[c], v = vv[c];
-        pr += a.x * v.x - a.y * v.y;
-        pi += a.x * v.y + a.y * v.x;
-      }
-      int c = r + 1 + (((gl - r - 1) % RG) + RG) % RG;
-      int C = j + 1 + c;
-      int idx = tri(C) + R;
-      for (; c < nj; c += RG) {
-        const double2 a = P[idx], v = vv[c];
-        pr += a.x * v.x + a.y * v.y;
-        pi += a.x * v.y - a.y * v.x;
-        idx += RG * C + RG * (RG + 1) / 2;
-        C += RG;
-      }
-      pr = sum8(pr);
-      pi = sum8(pi);
-      if (gl == 0) {
-        const double2 w = cmul(t, make_double2(pr, pi));
-        ww[r] = w;
-        const double2 v = vv[r];
-        dr_acc += w.x * v.x + w.y * v.y;
-        di_acc += w.x * v.y - w.y * v.x;
-      }
-    }
-    dr_acc = wave_sum(dr_acc);
-    di_acc = wave_sum(di_acc);
-    if (lane == 0) sh.part[wave] = make_double2(dr_acc, di_acc);
-    __syncthreads();
     if (stamp) { const long long t1 = wall_clock64(); tB += t1 - t0; t0 = t1; }
-    double2 pw[EIG_THREADS / 64];
+    if (wave == 0) {
+      next_reflector(P, s, j, upd, vv, ww, vn, sh.tau[(j + 1) & 1], W, lane);
+      if (stamp) tL += wall_clock64() - t0;
+    } else if (upd) {
+      // A -= v w'^H + w' v^H on rows r >= 1 and columns 1 <= c <= r of the trailing matrix (column 0
+      // belongs to the look-ahead): groups of RG lanes per row, rows dealt to the groups of waves
+      // 1.., TRI_U elements per lane loaded together, then updated and stored; an element past the
+      // row end repeats element c0 and stores the same value to it
+      const int nug = ngrp - 64 / RG;   // row groups outside wave 0
+      for (int r = 1 + grp - 64 / RG; r < nj; r += nug) {
+        const int R = j + 1 + r;
+        const double2 vr = vv[r];
+        const double2 wr = ww[r];
+        double2* rowp = P + tri(R) + (j + 1);
+        for (int c0 = 1 + gl; c0 <= r; c0 += TRI_U * RG) {
+          int cc[TRI_U];
+          double2 vc[TRI_U], wc[TRI_U], x[TRI_U];
 #pragma unroll
-    for (int w = 0; w < EIG_THREADS / 64; ++w) pw[w] = sh.part[w];
-    double dsum_r = 0.0, dsum_i = 0.0;
+          for (int u = 0; u < TRI_U; ++u) {
+            const int c = c0 + u * RG;
+            cc[u] = c <= r ? c : c0;
+            vc[u] = vv[cc[u]];
+            wc[u] = ww[cc[u]];
+            x[u] = rowp[cc[u]];
+          }
 #pragma unroll
-    for (int w = 0; w < EIG_THREADS / 64; ++w) {
-      dsum_r += pw[w].x;
-      dsum_i += pw[w].y;
-    }
-    const double2 q = cmul(t, make_double2(dsum_r, dsum_i));
-    const double2 a2 = make_double2(-0.5 * q.x, -0.5 * q.y);
-    // w' = w + a2 v, formed once
-    for (int r = tid; r < nj; r += nthr) {
-      const double2 vr = vv[r], wr = ww[r];
-      ww[r] = make_double2(wr.x + a2.x * vr.x - a2.y * vr.y, wr.y + a2.x * vr.y + a2.y * vr.x);
-    }
-    __syncthreads();
-    // A_sub -= v w'^H + w' v^H (packed lower triangle)
-    for (int r = grp; r < nj; r += ngrp) {
-      const int R = j + 1 + r;
-      const double2 vr = vv[r];
-      const double2 wr = ww[r];
-      double2* rowp = P + tri(R) + (j + 1);
-      // TRI_U elements per lane loaded together, then updated and stored; an element past the row
-      // end repeats element c0 and stores the same value to it
-      for (int c0 = gl; c0 <= r; c0 += TRI_U * RG) {
-        int cc[TRI_U];
-        double2 vc[TRI_U], wc[TRI_U], x[TRI_U];
+          for (int u = 0; u < TRI_U; ++u) x[u] = rank2(x[u], vr, wr, vc[u], wc[u]);
 #pragma unroll
-        for (int u = 0; u < TRI_U; ++u) {
-          const int c = c0 + u * RG;
-          cc[u] = c <= r ? c : c0;
-          vc[u] = vv[cc[u]];
-          wc[u] = ww[cc[u]];
-          x[u] = rowp[cc[u]];
+          for (int u = 0; u < TRI_U; ++u) rowp[cc[u]] = x[u];
         }
-#pragma unroll
-        for (int u = 0; u < TRI_U; ++u) {
-          x[u].x -= (vr.x * wc[u].x + vr.y * wc[u].y) + (wr.x * vc[u].x + wr.y * vc[u].y);
-          x[u].y -= (vr.y * wc[u].x - vr.x * wc[u].y) + (wr.y * vc[u].x - wr.x * vc[u].y);
-        }
-#pragma unroll
-        for (int u = 0; u < TRI_U; ++u) rowp[cc[u]] = x[u];
       }
     }
     __syncthreads();
     if (stamp) tD += wall_clock64() - t0;
   }
   if (stamp) {
-    a.tstamp[4] = tA;
+    a.tstamp[4] = tL;
     a.tstamp[5] = tB;
     a.tstamp[6] = tD;
   }
-  // last diagonal entry and the Gershgorin interval of T (used by the two later kernels)
-  if (tid == 0) W.d[s - 1] = P[tri(s - 1) + s - 1].x;
-  __syncthreads();
+  // the Gershgorin interval of T (used by the two later kernels)
   if (wave == 0) tri_bounds(W, s, a.tstamp);
 }
 
@@ -777,11 +837,6 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_eigvals(EigArgs a0) {
 }
 
 // ---- eigenvectors of T and back-transformation: one wave per eigenpair ---------------------------
-// a double from lane `l` (a constant) of the wave
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -1187,7 +1242,7 @@ __global__ __launch_bounds__(256) void k_backtransform(EigArgs a0) {
     atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 3), (unsigned long long)wall_clock64());
 }
 
-size_t eig_lds_bytes(int s) { return (size_t)16 * (s * (size_t)(s + 1) / 2) + (size_t)s * (2 * 16) + 64; }
+size_t eig_lds_bytes(int s) { return (size_t)16 * (s * (size_t)(s + 1) / 2) + (size_t)s * (3 * 16) + 64; }
 
 hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
   if (a0.s <= 0 || a0.kmax <= 0 || a0.kmax > a0.s || a0.batch <= 0) return hipErrorInvalidValue;
