@@ -392,7 +392,7 @@ def test_eig(G, kmax, tol=0.0, stamps=None):
         # tridiagonal step phases A/B/D and the number of clusters
         stamps.append([(t[1] - t[0]) / 100.0, (t[2] - t[1]) / 100.0, (t[3] - t[2]) / 100.0,
                        t[4] / 100.0, t[5] / 100.0, t[6] / 100.0, float(t[7])] +
-                      [x / 100.0 for x in t[8:13]])
+                      [x / 100.0 for x in t[8:16]])
     return U, lam, int(kk.item()), float(inv.item())
 
 

@@ -149,8 +149,8 @@ __device__ int sturm_count(const double* dd, const double* ee2, int s, double x,
 }
 
 struct TriShared {
-  double2 tau[2];                   // tau of the current and of the next column (by parity)
-  double2 part[EIG_THREADS / 64];   // per-wave partial sums of w^H v, added in a fixed order
+  double2 tau[2];   // tau of the current and of the next column (by parity)
+  double2 zero;     // read in place of v past the end of a row or column
 };
 
 // a double from lane `l` (wave-uniform) of the wave
@@ -182,10 +182,11 @@ __device__ inline double2 householder(double2 alpha, double xn2, int C, double a
   if (!(xn2 == 0.0 && alpha.y == 0.0)) {
     const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
     beta = alpha.x >= 0.0 ? -nrm : nrm;
-    t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
     const double ar = alpha.x - beta, ai = alpha.y;
-    const double den = ar * ar + ai * ai;
-    scal = make_double2(ar / den, -ai / den);
+    // 1/beta and 1/|alpha - beta|^2 (both of the size of the column norm) are independent
+    const double rb = 1.0 / beta, rden = 1.0 / (ar * ar + ai * ai);
+    t = make_double2(-ar * rb, -ai * rb);
+    scal = make_double2(ar * rden, -ai * rden);
   }
   if (lane == 0) {
     tau = t;
@@ -205,20 +206,24 @@ __device__ inline void next_reflector(const double2* P, int s, int j, bool upd, 
                                       const double2* ww, double2* vnext, double2& tau, EigWork& W,
                                       int lane) {
   const int C = j + 1, n = s - C;
-  double2 v0 = make_double2(1.0, 0.0), w0 = make_double2(0.0, 0.0);
-  if (upd) {
-    v0 = vc[0];
-    w0 = ww[0];
-  }
+  // loads are unconditional, so that they are issued together: past the column end a lane repeats
+  // its last row (the value is not used)
   double2 x[2];
+  if (upd) {
+    const double2 v0 = vc[0], w0 = ww[0];
+    double2 vr[2], wr[2];
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int r = lane + 64 * k;
-    x[k] = make_double2(0.0, 0.0);
-    if (r < n) {
+    for (int k = 0; k < 2; ++k) {
+      const int r = min(lane + 64 * k, n - 1);
       x[k] = P[tri(C + r) + C];
-      if (upd) x[k] = rank2(x[k], vc[r], ww[r], v0, w0);
+      vr[k] = vc[r];
+      wr[k] = ww[r];
     }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) x[k] = rank2(x[k], vr[k], wr[k], v0, w0);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) x[k] = P[tri(C + min(lane + 64 * k, n - 1)) + C];
   }
   const double acc = readlane_d(x[0].x, 0);
   if (C == s - 1) {
@@ -265,6 +270,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
   double2* A = a.G;
   EigWork W = eig_layout(a.work, s, a.kmax);
   if (a.tstamp && tid == 0) a.tstamp[0] = wall_clock64();
+  if (tid == 0) sh.zero = make_double2(0.0, 0.0);
   for (int idx = tid; idx < tri(s); idx += nthr) {
     int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
     while (tri(r + 1) <= idx) ++r;
@@ -285,11 +291,9 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     double2* vn = vb + ((j + 1) & 1) * s;
     if (stamp) t0 = wall_clock64();
     const double2 t = sh.tau[j & 1];
-    const bool upd = !(t.x == 0.0 && t.y == 0.0);
+    const bool upd = __builtin_amdgcn_readfirstlane(!(t.x == 0.0 && t.y == 0.0));
     if (upd) {
-      // w = tau A v over the trailing rows, groups of RG lanes per row, and the per-wave partial
-      // sums of w^H v
-      double dr_acc = 0.0, di_acc = 0.0;
+      // y = A v over the trailing rows, groups of RG lanes per row; w = tau y
       for (int r = grp; r < nj; r += ngrp) {
         const int R = j + 1 + r;
         // row part (stored, contiguous) then column part (conjugated, addressed incrementally:
@@ -313,34 +317,35 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
         }
         pr = sum8(pr);
         pi = sum8(pi);
-        if (gl == 0) {
-          const double2 w = cmul(t, make_double2(pr, pi));
-          ww[r] = w;
-          const double2 v = vv[r];
-          dr_acc += w.x * v.x + w.y * v.y;
-          di_acc += w.x * v.y - w.y * v.x;
-        }
+        if (gl == 0) ww[r] = cmul(t, make_double2(pr, pi));
       }
-      dr_acc = wave_sum(dr_acc);
-      di_acc = wave_sum(di_acc);
-      if (lane == 0) sh.part[wave] = make_double2(dr_acc, di_acc);
       __syncthreads();
-      double dsum_r = 0.0, dsum_i = 0.0;
+      if (wave == 0) {
+        // w' = w + a2 v with a2 = -tau (w^H v) / 2, formed once
+        double2 wk[2], vk[2];
+        double dr = 0.0, di = 0.0;
 #pragma unroll
-      for (int w0 = 0; w0 < EIG_THREADS / 64; w0 += 8) {
-        double2 pw[8];
+        for (int k = 0; k < 2; ++k) {
+          const int r = lane + 64 * k;
+          const bool ok = r < nj;
+          wk[k] = *(ok ? ww + r : &sh.zero);
+          vk[k] = *(ok ? vv + r : &sh.zero);
+        }
 #pragma unroll
-        for (int w = 0; w < 8; ++w) pw[w] = sh.part[w0 + w];
+        for (int k = 0; k < 2; ++k) {
+          dr += wk[k].x * vk[k].x + wk[k].y * vk[k].y;
+          di += wk[k].x * vk[k].y - wk[k].y * vk[k].x;
+        }
+        dr = wave_sum(dr);
+        di = wave_sum(di);
+        const double2 q = cmul(t, make_double2(dr, di));
+        const double2 a2 = make_double2(-0.5 * q.x, -0.5 * q.y);
 #pragma unroll
-        for (int w = 0; w < 8; ++w) {
-          dsum_r += pw[w].x;
-          dsum_i += pw[w].y;
+        for (int k = 0; k < 2; ++k) {
+          const int r = lane + 64 * k;
+          if (r < nj) ww[r] = wprime(wk[k], vk[k], a2);
         }
       }
-      const double2 q = cmul(t, make_double2(dsum_r, dsum_i));
-      const double2 a2 = make_double2(-0.5 * q.x, -0.5 * q.y);
-      // w' = w + a2 v, formed once
-      for (int r = tid; r < nj; r += nthr) ww[r] = wprime(ww[r], vv[r], a2);
       __syncthreads();
     }
     if (stamp) { const long long t1 = wall_clock64(); tB += t1 - t0; t0 = t1; }
@@ -569,10 +574,11 @@ __device__ double2 mw_reflector(int j, int s, const double2* x, double2* v, EigW
   if (!(xn2 == 0.0 && alpha.y == 0.0)) {
     const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
     beta = alpha.x >= 0.0 ? -nrm : nrm;
-    t = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
     const double ar = alpha.x - beta, ai = alpha.y;
-    const double den = ar * ar + ai * ai;
-    scal = make_double2(ar / den, -ai / den);
+    // 1/beta and 1/|alpha - beta|^2 (both of the size of the column norm) are independent
+    const double rb = 1.0 / beta, rden = 1.0 / (ar * ar + ai * ai);
+    t = make_double2(-ar * rb, -ai * rb);
+    scal = make_double2(ar * rden, -ai * rden);
   }
   const double djj = x[j].x;
   for (int c = tid; c < s; c += MW_THREADS) {
