@@ -60,6 +60,57 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 
 static_assert(CHOL_LDS_MAX <= 128, "the register panel holds two rows per lane");
 
+// Factor panel columns p..pe-1 (rows p..k-1) by one wave: lane l holds row p + l and, with TWO
+// (a panel taller than 64 rows), row p + l + 64 in registers; the pivot and the panel's
+// diagonal-block entries are broadcast from their lanes. Entries above the diagonal are updated too
+// but never read or stored.
+template <bool TWO>
+__device__ inline void chol_panel(double2* M, int ld, int k, int p, int pe, double thresh,
+                                  int* dropped, int lane) {
+  const int i0r = p + lane, i1r = p + 64 + lane;
+  double2 R0[NBc], R1[NBc];
+#pragma unroll
+  for (int q = 0; q < NBc; ++q) {
+    const bool inp = p + q < pe;
+    R0[q] = inp && i0r < k ? M[i0r * ld + p + q] : make_double2(0.0, 0.0);
+    if (TWO) R1[q] = inp && i1r < k ? M[i1r * ld + p + q] : make_double2(0.0, 0.0);
+  }
+#pragma unroll
+  for (int q = 0; q < NBc; ++q) {
+    const int jj = p + q;
+    if (jj >= pe) break;
+    const double djj = readlane_d(R0[q].x, q);
+    if (!(djj > thresh)) {
+      R0[q] = make_double2(0.0, 0.0);
+      if (TWO) R1[q] = make_double2(0.0, 0.0);
+      if (lane == 0) dropped[jj] = 1;
+      continue;
+    }
+    const double ic = rsqrt(djj);
+    R0[q] = i0r == jj ? make_double2(djj * ic, 0.0) : make_double2(R0[q].x * ic, R0[q].y * ic);
+    if (TWO) R1[q] = make_double2(R1[q].x * ic, R1[q].y * ic);
+#pragma unroll
+    for (int l = q + 1; l < NBc; ++l) {
+      if (p + l >= pe) break;
+      const double2 clj = make_double2(readlane_d(R0[q].x, l), readlane_d(R0[q].y, l));
+      R0[l].x -= R0[q].x * clj.x + R0[q].y * clj.y;
+      R0[l].y -= R0[q].y * clj.x - R0[q].x * clj.y;
+      if (TWO) {
+        R1[l].x -= R1[q].x * clj.x + R1[q].y * clj.y;
+        R1[l].y -= R1[q].y * clj.x - R1[q].x * clj.y;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NBc; ++q) {
+    if (p + q < pe) {
+      if (i0r < k && i0r >= p + q) M[i0r * ld + p + q] = R0[q];
+      if (TWO && i1r < k) M[i1r * ld + p + q] = R1[q];
+    }
+  }
+}
+
+
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
   const CholArgs a = chol_inst(a0, blockIdx.x);
   extern __shared__ double2 M[];
@@ -143,68 +194,21 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
   for (int p = 0; p < k; p += NBc) {
     const int pe = min(p + NBc, k);
     if (wave == 0) {
-      // the panel rows p..k-1 in registers (lane l holds rows p + l and p + l + 64); the pivot and
-      // the panel's diagonal-block entries are broadcast from their lanes
-      const int i0r = p + lane, i1r = p + 64 + lane;
-      double2 R0[NBc], R1[NBc];
-#pragma unroll
-      for (int q = 0; q < NBc; ++q) {
-        const bool inp = p + q < pe;
-        R0[q] = inp && i0r < k ? M[i0r * ld + p + q] : make_double2(0.0, 0.0);
-        R1[q] = inp && i1r < k ? M[i1r * ld + p + q] : make_double2(0.0, 0.0);
-      }
-#pragma unroll
-      for (int q = 0; q < NBc; ++q) {
-        const int jj = p + q;
-        if (jj >= pe) break;
-        const double djj = readlane_d(R0[q].x, q);
-        if (!(djj > thresh)) {
-          if (i0r >= jj) R0[q] = make_double2(0.0, 0.0);
-          R1[q] = make_double2(0.0, 0.0);
-          if (lane == 0) dropped[jj] = 1;
-          continue;
-        }
-        const double c = sqrt(djj), ic = 1.0 / c;
-        if (i0r > jj) {
-          R0[q].x *= ic;
-          R0[q].y *= ic;
-        } else if (i0r == jj) {
-          R0[q] = make_double2(c, 0.0);
-        }
-        R1[q].x *= ic;
-        R1[q].y *= ic;
-#pragma unroll
-        for (int l = q + 1; l < NBc; ++l) {
-          if (p + l >= pe) break;
-          const double2 clj = make_double2(readlane_d(R0[q].x, l), readlane_d(R0[q].y, l));
-          if (i0r >= p + l) {
-            R0[l].x -= R0[q].x * clj.x + R0[q].y * clj.y;
-            R0[l].y -= R0[q].y * clj.x - R0[q].x * clj.y;
-          }
-          R1[l].x -= R1[q].x * clj.x + R1[q].y * clj.y;
-          R1[l].y -= R1[q].y * clj.x - R1[q].x * clj.y;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < NBc; ++q) {
-        if (p + q < pe) {
-          if (i0r < k && i0r >= p + q) M[i0r * ld + p + q] = R0[q];
-          if (i1r < k) M[i1r * ld + p + q] = R1[q];
-        }
-      }
+      if (k - p > 64) chol_panel<true>(M, ld, k, p, pe, thresh, dropped, lane);
+      else chol_panel<false>(M, ld, k, p, pe, thresh, dropped, lane);
     }
     __syncthreads();
-    // trailing update: M[i][l] -= sum_{jj in panel} C[i][jj] conj(C[l][jj]), pe <= l <= i
+    // trailing update: M[i][l] -= sum_{jj in panel} C[i][jj] conj(C[l][jj]), pe <= l <= i; the
+    // panel entries of row i are read once per row
     for (int i = pe + grp; i < k; i += ngrp) {
+      double2 ci[NBc];
+#pragma unroll
+      for (int q = 0; q < NBc; ++q) ci[q] = M[i * ld + min(p + q, pe - 1)];
       for (int l = pe + gl; l <= i; l += RGc) {
         double2 g = M[i * ld + l];
-        double2 ci[NBc], cl[NBc];
+        double2 cl[NBc];
 #pragma unroll
-        for (int q = 0; q < NBc; ++q) {
-          const int jj = min(p + q, pe - 1);
-          ci[q] = M[i * ld + jj];
-          cl[q] = M[l * ld + jj];
-        }
+        for (int q = 0; q < NBc; ++q) cl[q] = M[l * ld + min(p + q, pe - 1)];
 #pragma unroll
         for (int q = 0; q < NBc; ++q) {
           if (p + q < pe) {
