@@ -93,11 +93,15 @@ __device__ inline void chol_panel(double2* M, int ld, int k, int p, int pe, doub
     for (int l = q + 1; l < NBc; ++l) {
       if (p + l >= pe) break;
       const double2 clj = make_double2(readlane_d(R0[q].x, l), readlane_d(R0[q].y, l));
-      R0[l].x -= R0[q].x * clj.x + R0[q].y * clj.y;
-      R0[l].y -= R0[q].y * clj.x - R0[q].x * clj.y;
+      R0[l].x = fma(-R0[q].x, clj.x, R0[l].x);
+      R0[l].x = fma(-R0[q].y, clj.y, R0[l].x);
+      R0[l].y = fma(-R0[q].y, clj.x, R0[l].y);
+      R0[l].y = fma(R0[q].x, clj.y, R0[l].y);
       if (TWO) {
-        R1[l].x -= R1[q].x * clj.x + R1[q].y * clj.y;
-        R1[l].y -= R1[q].y * clj.x - R1[q].x * clj.y;
+        R1[l].x = fma(-R1[q].x, clj.x, R1[l].x);
+        R1[l].x = fma(-R1[q].y, clj.y, R1[l].x);
+        R1[l].y = fma(-R1[q].y, clj.x, R1[l].y);
+        R1[l].y = fma(R1[q].x, clj.y, R1[l].y);
       }
     }
   }
@@ -212,8 +216,10 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
 #pragma unroll
         for (int q = 0; q < NBc; ++q) {
           if (p + q < pe) {
-            g.x -= ci[q].x * cl[q].x + ci[q].y * cl[q].y;
-            g.y -= ci[q].y * cl[q].x - ci[q].x * cl[q].y;
+            g.x = fma(-ci[q].x, cl[q].x, g.x);
+            g.x = fma(-ci[q].y, cl[q].y, g.x);
+            g.y = fma(-ci[q].y, cl[q].x, g.y);
+            g.y = fma(ci[q].x, cl[q].y, g.y);
           }
         }
         M[i * ld + l] = g;
@@ -287,8 +293,10 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
 #pragma unroll
         for (int q = 0; q < NBc; ++q) {
           if (lb + q < i0) {
-            sr += cl[q].x * x[q].x - cl[q].y * x[q].y;
-            si += cl[q].x * x[q].y + cl[q].y * x[q].x;
+            sr = fma(cl[q].x, x[q].x, sr);
+            sr = fma(-cl[q].y, x[q].y, sr);
+            si = fma(cl[q].x, x[q].y, si);
+            si = fma(cl[q].y, x[q].x, si);
           }
         }
       }

@@ -165,10 +165,16 @@ __device__ __forceinline__ double2 readlane_z(double2 v, int l) {
 __device__ __forceinline__ double2 wprime(double2 w, double2 v, double2 a2) {
   return make_double2(w.x + a2.x * v.x - a2.y * v.y, w.y + a2.x * v.y + a2.y * v.x);
 }
-// x - (v_r w'_c^* + w'_r v_c^*): one element of the rank-2 update
+// x - (v_r w'_c^* + w'_r v_c^*): one element of the rank-2 update, as a chain of FMAs
 __device__ __forceinline__ double2 rank2(double2 x, double2 vr, double2 wr, double2 vc, double2 wc) {
-  x.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
-  x.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
+  x.x = fma(-vr.x, wc.x, x.x);
+  x.x = fma(-vr.y, wc.y, x.x);
+  x.x = fma(-wr.x, vc.x, x.x);
+  x.x = fma(-wr.y, vc.y, x.x);
+  x.y = fma(-vr.y, wc.x, x.y);
+  x.y = fma(vr.x, wc.y, x.y);
+  x.y = fma(-wr.y, vc.x, x.y);
+  x.y = fma(wr.x, vc.y, x.y);
   return x;
 }
 
@@ -298,22 +304,27 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
         const int R = j + 1 + r;
         // row part (stored, contiguous) then column part (conjugated, addressed incrementally:
         // tri(C + RG) = tri(C) + RG C + RG (RG + 1) / 2)
-        const double2* rowp = P + tri(R) + (j + 1);
+        // (pointer-stepped loops: the fewest integer instructions per element)
+        const double2* xp = P + tri(R) + (j + 1) + gl;
+        const double2* vp = vv + gl;
         double pr = 0.0, pi = 0.0;
-        for (int c = gl; c <= r; c += RG) {
-          const double2 x = rowp[c], v = vv[c];
-          pr += x.x * v.x - x.y * v.y;
-          pi += x.x * v.y + x.y * v.x;
+        for (const double2* ve = vv + r; vp <= ve; vp += RG, xp += RG) {
+          const double2 x = *xp, v = *vp;
+          pr = fma(x.x, v.x, pr);
+          pr = fma(-x.y, v.y, pr);
+          pi = fma(x.x, v.y, pi);
+          pi = fma(x.y, v.x, pi);
         }
-        int c = r + 1 + (((gl - r - 1) % RG) + RG) % RG;
-        int C = j + 1 + c;
-        int idx = tri(C) + R;
-        for (; c < nj; c += RG) {
-          const double2 x = P[idx], v = vv[c];
-          pr += x.x * v.x + x.y * v.y;
-          pi += x.x * v.y - x.y * v.x;
-          idx += RG * C + RG * (RG + 1) / 2;
-          C += RG;
+        const int c = r + 1 + (((gl - r - 1) % RG) + RG) % RG;
+        const int C = j + 1 + c;
+        xp = P + tri(C) + R;
+        vp = vv + c;
+        for (int step = RG * C + RG * (RG + 1) / 2; vp < vv + nj; vp += RG, xp += step, step += RG * RG) {
+          const double2 x = *xp, v = *vp;
+          pr = fma(x.x, v.x, pr);
+          pr = fma(x.y, v.y, pr);
+          pi = fma(x.x, v.y, pi);
+          pi = fma(-x.y, v.x, pi);
         }
         pr = sum8(pr);
         pi = sum8(pi);
