@@ -143,6 +143,42 @@ def test_eig_rank_deficient_and_tol(lib):
     assert np.abs(U2.cpu().numpy()[:, 10:]).max() == 0.0
 
 
+@pytest.mark.parametrize("s,kind", [(5, "diagonal"), (40, "diagonal"), (128, "diagonal"),
+                                    (40, "blocks"), (128, "blocks"), (200, "blocks")])
+def test_eig_structured(lib, s, kind):
+    """Grams whose reduction meets columns with nothing below the diagonal (a reflector that is the
+    identity, tau = 0): a diagonal Gram (every column) and a block-diagonal one (the last column of
+    every block), in the single-workgroup and the multi-workgroup reductions."""
+    print(f"eig structured s={s} {kind}", flush=True)
+    rng = np.random.default_rng(40 + s)
+    if kind == "diagonal":
+        g = np.diag(rng.permutation(np.linspace(1.0, 3.0, s))).astype(np.complex128)
+    else:
+        g = np.zeros((s, s), dtype=np.complex128)
+        i0 = 0
+        for b in [9, 1, 17, 4, 30, 2, 25, 40, 64, 8]:
+            i1 = min(i0 + b, s)
+            g[i0:i1, i0:i1] = herm_psd(rng, i1 - i0)
+            i0 = i1
+            if i0 == s:
+                break
+        if i0 < s:
+            g[i0:, i0:] = herm_psd(rng, s - i0)
+    kmax = min(s, 16)
+    U, lam, kk, _ = lib.test_eig(torch.from_numpy(g).cuda(), kmax)
+    U = U.cpu().numpy()
+    lam = lam.cpu().numpy()
+    w = np.linalg.eigvalsh(g)[::-1]
+    assert kk == kmax
+    assert np.abs(lam - w[:kmax]).max() <= 1e-12 * w[0] * s
+    assert np.abs(U.conj().T @ U - np.eye(kmax)).max() <= 1e-12
+    assert np.abs(g @ U - U * lam[None, :]).max() <= 1e-11 * w[0]
+    if kind == "diagonal":
+        # distinct diagonal entries: the eigenvectors are unit vectors up to a phase
+        order = np.argsort(-np.diag(g).real)[:kmax]
+        assert np.abs(np.abs(U[order, np.arange(kmax)]) - 1.0).max() <= 1e-12
+
+
 @pytest.mark.parametrize("s", [50, 260])
 def test_eig_degenerate_cluster(lib, s):
     """Exactly repeated eigenvalues: the returned vectors must stay orthonormal."""
