@@ -42,8 +42,8 @@ __device__ inline CholArgs chol_inst(const CholArgs& a0, int b) {
 
 // LDS-resident variant for k <= CHOL_LDS_MAX, blocked by NBc = 8 columns.
 //   factor:  for each panel, wave 0 factors the 8 panel columns with the panel rows in registers
-//            (two rows per lane, so k <= 128), then all waves apply the rank-8 update to the trailing
-//            lower triangle (two barriers per panel);
+//            (one row per lane, two for panels taller than 64 rows, so k <= 128), then all waves
+//            apply the rank-8 update to the trailing lower triangle (two barriers per panel);
 //   inverse: the columns of the 8x8 diagonal blocks of X = C^{-1} are formed in parallel (one lane
 //            each), then block-row i of X is X_ij = -X_ii sum_{l=j}^{i-1} C_il X_lj (two barriers per
 //            block-row).

@@ -9,11 +9,12 @@
 // H_j = I - tau_j v_j v_j^H, real sub-diagonal), then the top-kmax eigenpairs of T, then the
 // back-transformation u = Q y:
 //   1. reduction: for s <= EIG_LDS_MAX one workgroup (k_tridiag) holds the packed lower triangle in
-//      LDS; the Hermitian matrix-vector product uses groups of 8 lanes per row, DPP reductions and
-//      per-wave partial sums added in a fixed order (bitwise reproducible); while 15 waves apply the
-//      rank-2 update (one lane per column), wave 0 updates the next column itself and forms its
-//      reflector (look-ahead), so a column costs two workgroup barriers. Larger s use k_tridiag_mw:
-//      the rows are spread over many workgroups and every column costs one grid-wide barrier.
+//      LDS; the Hermitian matrix-vector product uses groups of 8 lanes per row and DPP reductions,
+//      w^H v and w' are formed once by wave 0 (sums in a fixed order: bitwise reproducible); while
+//      15 waves apply the rank-2 update (again 8 lanes per row), wave 0 updates the next column
+//      itself and forms its reflector (look-ahead), so a column costs two workgroup barriers.
+//      Larger s use k_tridiag_mw: the rows are spread over many workgroups and every column costs
+//      one grid-wide barrier.
 //   2. k_eigvals, one wave per eigenvalue over many workgroups: multisection on Sturm counts (64
 //      points of the current interval per round).
 //   3. eigenvectors of T by a twisted factorisation T - lambda I = N_r Delta N_r^T, one wave per
@@ -150,7 +151,7 @@ __device__ int sturm_count(const double* dd, const double* ee2, int s, double x,
 
 struct TriShared {
   double2 tau[2];   // tau of the current and of the next column (by parity)
-  double2 zero;     // read in place of v past the end of a row or column
+  double2 zero;     // read in place of w and v past the trailing size
 };
 
 // a double from lane `l` (wave-uniform) of the wave
@@ -161,7 +162,7 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 __device__ __forceinline__ double2 readlane_z(double2 v, int l) {
   return make_double2(readlane_d(v.x, l), readlane_d(v.y, l));
 }
-// w' = w + a2 v, the corrected product of one row (formed where it is used, identically everywhere)
+// w' = w + a2 v, the corrected product of one row
 __device__ __forceinline__ double2 wprime(double2 w, double2 v, double2 a2) {
   return make_double2(w.x + a2.x * v.x - a2.y * v.y, w.y + a2.x * v.y + a2.y * v.x);
 }
