@@ -151,7 +151,7 @@ __device__ int sturm_count(const double* dd, const double* ee2, int s, double x,
 
 struct TriShared {
   double2 tau[2];   // tau of the current and of the next column (by parity)
-  double2 zero;     // read in place of w and v past the trailing size
+  double2 zero;     // read in place of w past the trailing size
 };
 
 // a double from lane `l` (wave-uniform) of the wave
@@ -187,11 +187,19 @@ __device__ inline double2 householder(double2 alpha, double xn2, int C, double a
   double2 t = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
   double beta = alpha.x;
   if (!(xn2 == 0.0 && alpha.y == 0.0)) {
-    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+    // |x| and 1/|x| from the hardware reciprocal square root refined by one Newton step, 1/|alpha -
+    // beta|^2 from the hardware reciprocal refined likewise (a few ulp each; the column norm is
+    // positive here)
+    const double n2 = alpha.x * alpha.x + alpha.y * alpha.y + xn2;
+    double rn = __builtin_amdgcn_rsq(n2);
+    rn = fma(0.5 * rn, fma(-n2 * rn, rn, 1.0), rn);
+    const double nrm = n2 * rn;
     beta = alpha.x >= 0.0 ? -nrm : nrm;
+    const double rb = alpha.x >= 0.0 ? -rn : rn;   // 1 / beta
     const double ar = alpha.x - beta, ai = alpha.y;
-    // 1/beta and 1/|alpha - beta|^2 (both of the size of the column norm) are independent
-    const double rb = 1.0 / beta, rden = 1.0 / (ar * ar + ai * ai);
+    const double den = ar * ar + ai * ai;
+    double rden = __builtin_amdgcn_rcp(den);
+    rden = fma(rden, fma(-den, rden, 1.0), rden);
     t = make_double2(-ar * rb, -ai * rb);
     scal = make_double2(ar * rden, -ai * rden);
   }
@@ -204,33 +212,21 @@ __device__ inline double2 householder(double2 alpha, double xn2, int C, double a
   return scal;
 }
 
-// Reflector of the next column, by one wave (look-ahead). With upd, column C = j+1 of the trailing
-// matrix is first brought up to date with the rank-2 update of column j (v in vc, w' in ww; the other
-// waves update every other column of the trailing matrix meanwhile); j = -1 reads column 0 as it is. Records
-// d[C] and, below the last column, the reflector of column C into vnext, tau and the workspace.
-// Rows C + r of the column are held by lane r mod 64 (r < s - C <= 128).
-__device__ inline void next_reflector(const double2* P, int s, int j, bool upd, const double2* vc,
-                                      const double2* ww, double2* vnext, double2& tau, EigWork& W,
-                                      int lane) {
+// Reflector of the next column, by one wave (look-ahead). xin holds column C = j + 1 of the
+// trailing matrix as it was before the rank-2 update of column j (row C + r in lane r mod 64, rows
+// past the end repeat the last one); with upd the update is applied here (v and w' of row C + r in
+// vr, wr, the same lanes), while the other waves update every other column of the trailing matrix.
+// Records d[C] and, below the last column, the reflector of column C into vnext, tau and the
+// workspace.
+__device__ inline void next_reflector(const double2 xin[2], int s, int j, bool upd,
+                                      const double2 vr[2], const double2 wr[2], double2* vnext,
+                                      double2& tau, EigWork& W, int lane) {
   const int C = j + 1, n = s - C;
-  // loads are unconditional, so that they are issued together: past the column end a lane repeats
-  // its last row (the value is not used)
-  double2 x[2];
+  double2 x[2] = {xin[0], xin[1]};
   if (upd) {
-    const double2 v0 = vc[0], w0 = ww[0];
-    double2 vr[2], wr[2];
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int r = min(lane + 64 * k, n - 1);
-      x[k] = P[tri(C + r) + C];
-      vr[k] = vc[r];
-      wr[k] = ww[r];
-    }
+    const double2 v0 = readlane_z(vr[0], 0), w0 = readlane_z(wr[0], 0);
 #pragma unroll
     for (int k = 0; k < 2; ++k) x[k] = rank2(x[k], vr[k], wr[k], v0, w0);
-  } else {
-#pragma unroll
-    for (int k = 0; k < 2; ++k) x[k] = P[tri(C + min(lane + 64 * k, n - 1)) + C];
   }
   const double acc = readlane_d(x[0].x, 0);
   if (C == s - 1) {
@@ -261,6 +257,12 @@ __device__ inline void next_reflector(const double2* P, int s, int j, bool upd, 
   }
 }
 
+// column C of the packed triangle, rows C + r in lane r mod 64 (rows past s - 1 repeat the last)
+__device__ __forceinline__ void load_column(const double2* P, int s, int C, int lane, double2 x[2]) {
+#pragma unroll
+  for (int k = 0; k < 2; ++k) x[k] = P[tri(C + min(lane + 64 * k, s - 1 - C)) + C];
+}
+
 __device__ void tri_bounds(EigWork& W, int s, long long* tstamp);
 
 __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
@@ -286,8 +288,11 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     P[idx] = A[(size_t)r * s + c];
   }
   __syncthreads();
-  if (wave == 0)
-    next_reflector(P, s, -1, false, nullptr, nullptr, vb, sh.tau[0], W, lane);
+  if (wave == 0) {
+    double2 x0[2];
+    load_column(P, s, 0, lane, x0);
+    next_reflector(x0, s, -1, false, x0, x0, vb, sh.tau[0], W, lane);
+  }
   __syncthreads();
   const int grp = tid / RG, gl = tid % RG, ngrp = nthr / RG;
   long long tL = 0, tB = 0, tD = 0, t0 = 0;
@@ -299,6 +304,13 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     if (stamp) t0 = wall_clock64();
     const double2 t = sh.tau[j & 1];
     const bool upd = __builtin_amdgcn_readfirstlane(!(t.x == 0.0 && t.y == 0.0));
+    // wave 0: column j + 1 (not written again before the look-ahead) and v of its rows, early
+    double2 xcol[2], vk[2], wk[2];
+    if (wave == 0) {
+      load_column(P, s, j + 1, lane, xcol);
+#pragma unroll
+      for (int k = 0; k < 2; ++k) vk[k] = vv[min(lane + 64 * k, nj - 1)];
+    }
     if (upd) {
       // y = A v over the trailing rows, groups of RG lanes per row; w = tau y
       for (int r = grp; r < nj; r += ngrp) {
@@ -333,15 +345,12 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
       }
       __syncthreads();
       if (wave == 0) {
-        // w' = w + a2 v with a2 = -tau (w^H v) / 2, formed once
-        double2 wk[2], vk[2];
+        // w' = w + a2 v with a2 = -tau (w^H v) / 2, formed once (kept in wk for the look-ahead)
         double dr = 0.0, di = 0.0;
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const int r = lane + 64 * k;
-          const bool ok = r < nj;
-          wk[k] = *(ok ? ww + r : &sh.zero);
-          vk[k] = *(ok ? vv + r : &sh.zero);
+          wk[k] = *(r < nj ? ww + r : &sh.zero);
         }
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
@@ -355,14 +364,15 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
           const int r = lane + 64 * k;
-          if (r < nj) ww[r] = wprime(wk[k], vk[k], a2);
+          wk[k] = wprime(wk[k], vk[k], a2);
+          if (r < nj) ww[r] = wk[k];
         }
       }
       __syncthreads();
     }
     if (stamp) { const long long t1 = wall_clock64(); tB += t1 - t0; t0 = t1; }
     if (wave == 0) {
-      next_reflector(P, s, j, upd, vv, ww, vn, sh.tau[(j + 1) & 1], W, lane);
+      next_reflector(xcol, s, j, upd, vk, wk, vn, sh.tau[(j + 1) & 1], W, lane);
       if (stamp) tL += wall_clock64() - t0;
     } else if (upd) {
       // A -= v w'^H + w' v^H on rows r >= 1 and columns 1 <= c <= r of the trailing matrix (column 0
