@@ -29,7 +29,8 @@ Readings taken where the paper is silent or garbled:
 
 Parity pins: tests/test_oracle_pins.py checks this module against dense contraction, the projection
 and isometry invariants, the Eckart-Young bound, an N=2 closed form, gauge and scalar covariances,
-special cases and an independent dense reformulation of the tensor-train sweep;
+special cases and independent dense reformulations of the tensor-train sweep and of the three tree
+sweeps (subspaces of the physical space, truncating trees with several children per node);
 tests/test_oracle_mutations.py shows that plausible mistakes planted in this module fail them.
 """
 from __future__ import annotations

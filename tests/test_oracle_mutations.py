@@ -33,6 +33,10 @@ CHECKS = [
     ("projection invariants", lambda: PINS.test_projection_property_dense("binary", 7, 2, 8, 4, 4)),
     ("two-site closed form", lambda: PINS.test_two_site_closed_form()),
     ("dense reformulation", lambda: PINS.test_dense_reformulation_chain(6, 2, 4, 3, 3)),
+    ("dense tree reformulation, binary", lambda: PINS.test_dense_reformulation_tree(
+        PINS.kary_parent(7, 2), 2, 4, 3, 3, 1)),
+    ("dense tree reformulation, ternary", lambda: PINS.test_dense_reformulation_tree(
+        PINS.kary_parent(10, 3), 2, 4, 2, 3, 2)),
     ("truncation identities", lambda: PINS.test_truncation_step_identities()),
     ("LQ step", lambda: PINS.test_lq_step()),
 ]
@@ -47,6 +51,12 @@ MUTATIONS = [
     ("operator legs transposed in the chain forward sweep", '"xap,tupq,uab->xtbq"', '"xap,utpq,uab->xtbq"'),
     ("operator legs transposed in the tree R update", "    terms.append((w, [sigp, sig] + beta))\n    terms.append((qc", "    terms.append((w, [sig, sigp] + beta))\n    terms.append((qc"),
     ("sweep 2 keeps the target child's own environment", "                if c != k:", "                if True:"),
+    ("sweep 2 omits the siblings' environments", "envs[1 + j] = lsub[c]", "pass"),
+    ("sweep 1 attaches the children's environments in reverse order",
+     "envs = {1 + j: lsub[c] for j, c in enumerate(ch[i])}",
+     "envs = {len(ch[i]) - j: lsub[c] for j, c in enumerate(ch[i])}"),
+    ("sweep 3 attaches the children's R in reverse order", "envs[1 + j] = renv[c]",
+     "envs[len(ch[i]) - j] = renv[c]"),
 ]
 
 

@@ -362,6 +362,149 @@ def test_dense_reformulation_chain(n, d, chi, D, mb):
 
 
 # ---------------------------------------------------------------------------------------------
+# P9b: independent dense formulation of tree CBC (Sec. III B) on truncating trees of up to 12
+# nodes, written with subspaces of the physical space instead of environment tensors.
+#   Cutting the edge of node i from its parent splits O|psi> = sum_{alpha beta} A_i B_i, with A_i
+#   the product network contracted over the subtree sub(i) and B_i over the rest out(i), both
+#   contracted here by brute force from the input tensors.
+#   Sweep 1 (Eq. cbc_tree_first_contraction): P_i = (1_{d_i} (x) P_c ...) U_i, an isometry into the
+#     physical space of sub(i), with U_i the top-k left singular vectors of (1 (x) P_c^H ...) A_i.
+#   Sweep 2 (Eq. cbc_tree_second_contraction): Q_k = (1_{d_i} (x) Q_i (x) P_c ..., c != k) U, an
+#     isometry into the physical space of out(k), U from (1 (x) Q_i^H (x) P_c^H ...) B_k.
+#   Sweep 3 (Eqs. cbc_tree_third_contraction, cbc_tree_qr, cbc_final_contraction): the output
+#     isometry of node i spans the column space of (1_{d_i} (x) Pi_c ...) Phi_i^T conj(Q_i), with
+#     Phi_i = O|psi> read as out(i) x sub(i) and Pi_c the children's output projectors; the root
+#     keeps (1 (x) Pi_c ...) O|psi>.
+# A leg order, conjugate or environment mistake at a node with several children changes which
+# subspace is kept, which the projection invariants alone do not see.
+
+def _ein(*args):
+    """einsum over arbitrary hashable labels: _ein(t1, labels1, t2, labels2, ..., out_labels)."""
+    *pairs, out = args
+    ids = {}
+
+    def m(ls):
+        return [ids.setdefault(l, len(ids)) for l in ls]
+
+    ops = []
+    for k in range(0, len(pairs), 2):
+        ops += [pairs[k], m(pairs[k + 1])]
+    return np.einsum(*ops, m(out), optimize="greedy")
+
+
+def _subtree(parent, i):
+    s, st = set(), [i]
+    while st:
+        j = st.pop()
+        s.add(j)
+        st += [c for c, q in enumerate(parent) if q == j]
+    return sorted(s)
+
+
+def _block(p, nodes, edge):
+    """The product network contracted over `nodes`; open legs sigma'_j (j in nodes) and, unless
+    edge is None, the state and operator legs of the edge from node `edge` to its parent."""
+    ch = [[c for c, q in enumerate(p.parent) if q == i] for i in range(p.n)]
+    args = []
+    for j in nodes:
+        up_a = ("a", j) if p.parent[j] >= 0 else ("ra",)
+        up_b = ("b", j) if p.parent[j] >= 0 else ("rb",)
+        args += [p.state[j], [("s", j), up_a] + [("a", c) for c in ch[j]]]
+        args += [p.op[j], [("sp", j), ("s", j), up_b] + [("b", c) for c in ch[j]]]
+    if p.parent.index(-1) in nodes:
+        args += [np.ones(1), [("ra",)], np.ones(1), [("rb",)]]
+    out = [("sp", j) for j in nodes] + ([] if edge is None else [("a", edge), ("b", edge)])
+    return _ein(*args, out)
+
+
+def _top_left(t, nrow, k):
+    """Top-k left singular vectors of t read as (first nrow legs) x (rest), as a tensor."""
+    u, s, _ = np.linalg.svd(t.reshape(int(np.prod(t.shape[:nrow])), -1), full_matrices=False)
+    kk = min(k, len(s))
+    return u[:, :kk].reshape(t.shape[:nrow] + (kk,))
+
+
+def _project(x, lab, w, legs, tag):
+    """Apply W W^H (W an isometry with legs `legs` + [tag]) to the legs `legs` of x."""
+    rest = [l for l in lab if l not in legs]
+    t = _ein(x, lab, w.conj(), legs + [tag], rest + [tag])
+    return _ein(t, rest + [tag], w, legs + [tag], lab)
+
+
+def _dense_cbc_tree(p, max_bond):
+    n, parent = p.n, p.parent
+    ch = [[c for c, q in enumerate(parent) if q == i] for i in range(n)]
+    root = parent.index(-1)
+    sub = {i: _subtree(parent, i) for i in range(n)}
+    out = {i: [j for j in range(n) if j not in sub[i]] for i in range(n)}
+    sp = lambda nodes: [("sp", j) for j in nodes]
+    post = tn.postorder(parent)
+    P = {}
+    for i in post:                                  # sweep 1
+        if i == root:
+            continue
+        args, rows = [_block(p, sub[i], i), sp(sub[i]) + ["a", "b"]], [("sp", i)]
+        for c in ch[i]:
+            args += [P[c].conj(), sp(sub[c]) + [("x", c)]]
+            rows.append(("x", c))
+        U = _top_left(_ein(*args, rows + ["a", "b"]), len(rows), max_bond)
+        args = [U, rows + [("x", i)]]
+        for c in ch[i]:
+            args += [P[c], sp(sub[c]) + [("x", c)]]
+        P[i] = _ein(*args, sp(sub[i]) + [("x", i)])
+    Q = {}
+    for i in reversed(post):                        # sweep 2
+        for k in ch[i]:
+            args, rows = [_block(p, out[k], k), sp(out[k]) + ["a", "b"]], [("sp", i)]
+            basis = []
+            if i != root:
+                basis.append((Q[i], sp(out[i]) + [("y", i)]))
+            basis += [(P[c], sp(sub[c]) + [("x", c)]) for c in ch[i] if c != k]
+            for t, lab in basis:
+                args += [t.conj(), lab]
+                rows.append(lab[-1])
+            U = _top_left(_ein(*args, rows + ["a", "b"]), len(rows), max_bond)
+            args = [U, rows + [("y", k)]]
+            for t, lab in basis:
+                args += [t, lab]
+            Q[k] = _ein(*args, sp(out[k]) + [("y", k)])
+    phi = _block(p, list(range(n)), None)
+    W = {}
+    for i in post:                                  # sweep 3
+        if i == root:
+            continue
+        lab = sp(sub[i]) + [("y", i)]
+        x = _ein(phi, sp(range(n)), Q[i].conj(), sp(out[i]) + [("y", i)], lab)
+        for c in ch[i]:
+            x = _project(x, lab, W[c], sp(sub[c]), ("z", c))
+        u, s, _ = np.linalg.svd(x.reshape(-1, x.shape[-1]), full_matrices=False)
+        r = int(np.count_nonzero(s > 1e-10 * s[0]))
+        rest = p.phys[i] * int(np.prod([W[c].shape[-1] for c in ch[i]]))
+        assert r == min(x.shape[-1], rest)          # generic: S has full rank
+        W[i] = u[:, :r].reshape(x.shape[:-1] + (r,))
+    res = phi
+    for c in ch[root]:
+        res = _project(res, sp(range(n)), W[c], sp(sub[c]), ("z", c))
+    return res.reshape(-1), phi.reshape(-1)
+
+
+@pytest.mark.parametrize("parent,phys,chi,D,mb,seed", [
+    (kary_parent(7, 2), 2, 4, 3, 3, 1),
+    (kary_parent(10, 3), 2, 4, 2, 3, 2),
+    (kary_parent(7, 2), [1, 1, 1, 2, 2, 2, 2], 4, 3, 3, 3),
+    ([-1, 0, 0, 1, 1, 1, 2, 2, 6], 2, 4, 3, 3, 4),
+    (kary_parent(12, 2), 2, 4, 2, 3, 5),
+    (chain_parent(7), 2, 4, 3, 3, 6)],
+    ids=["bin7", "ter10", "bin7-d1-internal", "uneven9", "bin12", "chain7"])
+def test_dense_reformulation_tree(parent, phys, chi, D, mb, seed):
+    p = random_problem(parent, phys, chi, D, mb, seed=seed)
+    got = tn.to_dense(p.parent, cbc_tree(p.parent, p.state, p.op, mb)).reshape(-1)
+    ref, phi = _dense_cbc_tree(p, mb)
+    assert np.linalg.norm(got - phi) > 1e-3 * np.linalg.norm(phi)      # really truncating
+    assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(phi)
+
+
+# ---------------------------------------------------------------------------------------------
 # metric utilities against dense forms
 
 def test_metrics_against_dense():
