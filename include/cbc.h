@@ -47,10 +47,15 @@
  * once before (it builds the plan and uploads its tables, which a capture cannot record).
  *
  * Errors: every entry point returns a cbc_status; nothing aborts or throws across the ABI. All
- * argument validation happens on the host before any device work is queued. Truncation Gram
- * matrices of dimension above 128 are solved by up to 256 cooperating workgroups that must be
- * resident together; their waits are bounded (2 s), so if the device is so busy that they are not,
- * the call still completes and its output holds NaN instead of hanging.
+ * argument validation happens on the host before any device work is queued. Failures that can only
+ * be seen on the device are recorded in a status word in the call's workspace and read, after the
+ * call has finished, with cbc_read_report: a factorisation or eigensolve that meets non-finite
+ * values (CBC_ENOTPD), or a bounded wait that expired (CBC_ETIMEOUT). Truncation Gram matrices of
+ * dimension above 128 are solved by up to 256 cooperating workgroups that must be resident
+ * together. The library orders these solves one after another on each device, across streams and
+ * contexts of the process (stream-ordered waits on one device-wide event, also inside graph
+ * captures), and their waits are bounded (2 s), so a device shared with other spinning work cannot
+ * hang the call: it ends with CBC_ETIMEOUT in the report instead.
  */
 #ifndef CBC_H
 #define CBC_H
@@ -69,8 +74,10 @@ typedef enum {
   CBC_ENOMEM = -3,     /* workspace smaller than cbc_query reported, or a context allocation failed */
   CBC_EHIP = -4,       /* a HIP runtime call failed */
   CBC_ENOTPD = -5,     /* reserved: a factorisation failed even after its fallbacks */
-  CBC_EUNSUP = -6,     /* valid input outside this build's limits: a truncation Gram > 1272 */
-  CBC_ENOTBUILT = -7   /* library built without a usable device (no gfx950 GPU visible) */
+  CBC_EUNSUP = -6,     /* valid input outside this build's limits: an eigensolve larger than the
+                          solver's limit, or a tensor of 2^31 or more elements */
+  CBC_ENOTBUILT = -7,  /* library built without a usable device (no gfx950 GPU visible) */
+  CBC_ETIMEOUT = -8    /* device side: a bounded cross-workgroup wait expired (output invalid) */
 } cbc_status;
 
 typedef enum { CBC_PREC_FP64 = 0, CBC_PREC_MIXED = 1 } cbc_precision;
@@ -126,6 +133,31 @@ typedef struct {
   double bytes[CBC_K_NCLASS];        /* out: algorithmic bytes moved per class (operands + result) */
   double ms[CBC_K_NCLASS];           /* out: summed kernel time per class (profile mode only) */
 } cbc_stats;
+
+/* One truncation of a call (Sec. III A / III B: the joined leg compressed to the target dimension),
+ * recorded on the device. */
+typedef struct {
+  int32_t node;        /* the edge from `node` to its parent is truncated */
+  int32_t sweep;       /* 1: subtree environment (Eq. cbc_tree_first_contraction); 2: environment of
+                          the rest of the tree (Eqs. tt_cbc_first_contraction,
+                          cbc_tree_second_contraction); 0: a truncation of the naive method */
+  int32_t dim;         /* dimension of the Gram matrix that was eigensolved */
+  int32_t kmax;        /* directions planned (min(max_bond, Gram dimension)) */
+  int32_t kept;        /* directions kept (fewer than kmax only with a tolerance) */
+  int32_t flags;       /* bit 0: relative gap at the cut below 1e-8 (ties, Sec. III A is silent) */
+  double discarded;    /* discarded weight sum_{j >= kept} lambda_j / sum_j lambda_j (lambda: the Gram's
+                          eigenvalues = squared singular values; absolute accuracy ~1e-15) */
+  double gap;          /* (lambda_{kept-1} - lambda_kept) / lambda_{kept-1}; 1 if nothing is cut */
+} cbc_trunc_record;
+
+/* What a finished call recorded on the device. */
+typedef struct {
+  int32_t status;          /* out: CBC_OK, CBC_ENOTPD or CBC_ETIMEOUT */
+  int32_t dropped_pivots;  /* out: Cholesky pivots dropped by the QR steps (rank-deficient S) */
+  int32_t n_trunc;         /* out: truncations the call performed */
+  int32_t capacity;        /* in: entries available in trunc (0 with trunc == NULL) */
+  cbc_trunc_record* trunc; /* in: host array; the first min(capacity, n_trunc) records are written */
+} cbc_report;
 
 /* Create / destroy a context. */
 cbc_status cbc_create(cbc_ctx** ctx);
@@ -187,6 +219,16 @@ cbc_status cbc_apply_naive(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tens
                            const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
                            void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
                            cbc_stats* stats);
+
+/* Report of the last call that used `workspace` (cbc_apply, cbc_apply_batched or cbc_apply_naive):
+ * synchronises `stream` (the call's stream),
+ * then copies the status word, the dropped-pivot count and the truncation records from the
+ * workspace. For batched calls, `instance_bytes` is the per-instance workspace size (cbc_query's
+ * workspace_bytes) and `instance` selects the instance; for single calls pass 0 and 0. Returns
+ * CBC_EINVAL for null arguments or a workspace that holds no report, CBC_EHIP if a copy fails, and
+ * otherwise the device status (CBC_OK, CBC_ENOTPD or CBC_ETIMEOUT), which is also rep->status. */
+cbc_status cbc_read_report(const void* workspace, size_t instance_bytes, int32_t instance,
+                           void* stream, cbc_report* rep);
 
 #ifdef __cplusplus
 }

@@ -39,6 +39,14 @@ int cbc_test_gemm_time(int M, int N, int K, int a_c128, int b_c128, int c_c128, 
 int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void* lam, void* kkeep,
                  void* inv_sqrt_l0, void* tstamp, void* stream);
 
+/* The same eigensolve with the call's report: status (1 int, device, must hold 0 = CBC_OK before
+ * the call) receives a failure code, rec (one cbc_trunc_record, device) the truncation record
+ * (node 7, sweep 2). force_timeout = 1 makes the first cross-workgroup wait of the multi-workgroup
+ * reduction (s > 128) give up at once, so that the time-out path runs while every workgroup exits
+ * normally: status then holds CBC_ETIMEOUT. */
+int cbc_test_eig_report(void* G, int s, int kmax, double tol, int force_timeout, void* U, void* lam,
+                        void* kkeep, void* inv_sqrt_l0, void* status, void* rec, void* stream);
+
 /* One Cholesky + triangular inverse step of the QR on the parent leg (Sec. III A, Eq.
  * tt_cbc_qr_decomp, realised as Cholesky-QR): G (k x k complex128 Hermitian PSD, overwritten) ->
  * Cinv (k x k complex128, inverse of the lower Cholesky factor; zero rows and columns for dropped

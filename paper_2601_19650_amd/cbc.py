@@ -56,6 +56,21 @@ class Stats(ctypes.Structure):
                 for k, c in enumerate(CLASSES)}
 
 
+class TruncRecord(ctypes.Structure):
+    _fields_ = [("node", ctypes.c_int32), ("sweep", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("kmax", ctypes.c_int32), ("kept", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("discarded", ctypes.c_double), ("gap", ctypes.c_double)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("dropped_pivots", ctypes.c_int32),
+                ("n_trunc", ctypes.c_int32), ("capacity", ctypes.c_int32),
+                ("trunc", ctypes.POINTER(TruncRecord))]
+
+
+STATUS = {0: "ok", -1: "einval", -2: "eshape", -3: "enomem", -4: "ehip", -5: "enotpd",
+          -6: "eunsup", -7: "enotbuilt", -8: "etimeout"}
+
 _lib = None
 
 
@@ -94,12 +109,15 @@ def lib():
         L.cbc_apply_batched.restype = ctypes.c_int
         L.cbc_autotune.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
         L.cbc_autotune.restype = ctypes.c_int
+        L.cbc_read_report.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.POINTER(Report)]
+        L.cbc_read_report.restype = ctypes.c_int
         _lib = L
     return _lib
 
 
 EXPORTED = ("cbc_create", "cbc_destroy", "cbc_status_str", "cbc_query", "cbc_plan_bonds",
-            "cbc_apply", "cbc_apply_batched", "cbc_apply_naive", "cbc_autotune")
+            "cbc_apply", "cbc_apply_batched", "cbc_apply_naive", "cbc_autotune", "cbc_read_report")
 
 
 def _check(code, what):
@@ -226,6 +244,30 @@ class Compressor:
                "cbc_apply" if self.method == 0 else "cbc_apply_naive")
         return self.out, self.bond
 
+    def report(self, instance=0, stream=None, capacity=4096):
+        """What the last call recorded on the device (waits for `stream`, default: the current
+        one): {"status", "dropped_pivots", "trunc": [record dicts]}."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        recs = (TruncRecord * capacity)()
+        rep = Report(0, 0, 0, capacity, ctypes.cast(recs, ctypes.POINTER(TruncRecord)))
+        rc = lib().cbc_read_report(self.workspace.data_ptr(), self.ws_bytes // self.batch,
+                                   int(instance), ctypes.c_void_p(stream), ctypes.byref(rep))
+        if rc not in (0, -5, -8):
+            _check(rc, "cbc_read_report")
+        trunc = [{f: getattr(recs[i], f) for f, _ in TruncRecord._fields_}
+                 for i in range(min(rep.n_trunc, capacity))]
+        return {"status": STATUS.get(rep.status, rep.status), "status_code": int(rep.status),
+                "dropped_pivots": int(rep.dropped_pivots), "trunc": trunc}
+
+    def check(self, instance=0, stream=None):
+        """Raise if the device recorded a failure (non-finite factorisation, expired wait)."""
+        r = self.report(instance, stream, capacity=0)
+        if r["status_code"] != 0:
+            _check(r["status_code"], "device")
+        return r
+
     def unpack(self, instance=0):
         """Output node tensors as numpy complex128 arrays (sigma', parent bond, child bonds...).
         Synchronises the device (the library's calls are asynchronous)."""
@@ -270,14 +312,15 @@ class UnevenBatch:
             s = self.streams[k % len(self.streams)]
             comp.run(*args, stream=s.cuda_stream)
 
-    def capture(self):
+    def capture(self, graph=None):
         """Record the whole batch (every instance, forked over the streams and joined) into one
-        graph; run() then replays it with a single launch. Runs the batch once first, eagerly."""
+        graph; run() then replays it with a single launch. Runs the batch once first, eagerly.
+        `graph`: a torch.cuda.CUDAGraph to capture into (default: a new one)."""
         import torch
         self.graph = None
         self.run()
         torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
+        g = graph if graph is not None else torch.cuda.CUDAGraph()
         root = torch.cuda.Stream(device=self.streams[0].device)
         with torch.cuda.graph(g, stream=root):
             for s in self.streams:
@@ -311,7 +354,9 @@ def compress(problem, precision="fp64", method="cbc", tol=None, ctx=None, device
     op, oo = pack(problem.op, device)
     c = Compressor(ctx, tree, problem.max_bond, precision, method, device)
     c.run(op, oo, st, so, problem.tol if tol is None else tol)
-    return c.unpack(), c
+    out = c.unpack()
+    c.check()
+    return out, c
 
 
 # ------------------------------------------------------------------------------------------------
@@ -330,11 +375,14 @@ def _testing_lib():
         L.cbc_test_gemm_time.argtypes = [ci, ci, ci, ci, ci, ci, ci, ci, ci,
                                          ctypes.POINTER(ctypes.c_float)]
         L.cbc_test_gemm_time.restype = ci
+        L.cbc_test_eig_report.argtypes = [vp, ci, ci, cd, ci, vp, vp, vp, vp, vp, vp, vp]
+        L.cbc_test_eig_report.restype = ci
         L._testing_ready = True
     return L
 
 
-TESTING_EXPORTED = ("cbc_test_gemm", "cbc_test_gemm_time", "cbc_test_eig", "cbc_test_chol_inv")
+TESTING_EXPORTED = ("cbc_test_gemm", "cbc_test_gemm_time", "cbc_test_eig", "cbc_test_chol_inv",
+                    "cbc_test_eig_report")
 
 
 def _stream():
@@ -394,6 +442,27 @@ def test_eig(G, kmax, tol=0.0, stamps=None):
                        t[4] / 100.0, t[5] / 100.0, t[6] / 100.0, float(t[7])] +
                       [x / 100.0 for x in t[8:16]])
     return U, lam, int(kk.item()), float(inv.item())
+
+
+def test_eig_report(G, kmax, tol=0.0, force_timeout=False):
+    """Eigensolve with a status word and a truncation record (see cbc_test_eig_report); returns
+    (status code, record dict, U, lam, kept)."""
+    import torch
+    s = G.shape[0]
+    G = G.contiguous().clone()
+    U = torch.empty((s, kmax), dtype=torch.complex128, device=G.device)
+    lam = torch.empty(kmax, dtype=torch.float64, device=G.device)
+    kk = torch.empty(1, dtype=torch.int32, device=G.device)
+    inv = torch.empty(1, dtype=torch.float64, device=G.device)
+    status = torch.zeros(1, dtype=torch.int32, device=G.device)
+    rec = torch.zeros(ctypes.sizeof(TruncRecord), dtype=torch.uint8, device=G.device)
+    _check(_testing_lib().cbc_test_eig_report(G.data_ptr(), s, kmax, float(tol), int(force_timeout),
+                                              U.data_ptr(), lam.data_ptr(), kk.data_ptr(),
+                                              inv.data_ptr(), status.data_ptr(), rec.data_ptr(),
+                                              _stream()), "cbc_test_eig_report")
+    r = TruncRecord.from_buffer_copy(bytes(rec.cpu().numpy()))
+    return (int(status.item()), {f: getattr(r, f) for f, _ in TruncRecord._fields_}, U, lam,
+            int(kk.item()))
 
 
 def test_chol_inv(G, shift_rel=0.0, drop_rel=0.0, stamps=None):

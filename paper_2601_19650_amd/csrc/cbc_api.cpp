@@ -48,7 +48,22 @@ struct Ten {
   std::vector<int> legs;
 };
 
-enum OpKind : int { K_GEMM, K_EIG, K_FORM_N, K_CHOL, K_CONVERT, K_IDENT, K_WRITE, K_ZERO };
+enum OpKind : int { K_GEMM, K_EIG, K_FORM_N, K_CHOL, K_CONVERT, K_IDENT, K_WRITE, K_ZERO, K_HEADER };
+
+// Start of every instance's workspace: the call's report (read by cbc_read_report). The kernels
+// store a failure code into `status` (first one wins) and add dropped pivots to `ndrop`; the
+// truncation records (cbc_trunc_record) start `rec_off` bytes into the workspace.
+struct WsHeader {
+  uint32_t magic;
+  int32_t status;
+  int32_t ndrop;
+  int32_t n_rec;
+  int64_t rec_off;
+  int64_t reserved[5];
+};
+static_assert(sizeof(WsHeader) == 64, "report header layout");
+constexpr uint32_t REPORT_MAGIC = 0x31434243u;   // "CBC1"
+constexpr int64_t HDR_STATUS = 4, HDR_NDROP = 8;
 
 struct Op {
   OpKind kind;
@@ -66,8 +81,9 @@ struct Op {
   double alpha = 1.0;
   TRef adev, adev2;
   // EIG / FORM_N / CHOL
-  TRef G, U, lam, kkeep, invs, work, Cinv, logs, scale, ndrop, L;
+  TRef G, U, lam, kkeep, invs, work, Cinv, logs, scale, ndrop, L, rec, status;
   int s = 0, kmax = 0, n = 0;
+  int rec_node = -1, rec_sweep = 0, rec_index = -1;
   double shift_rel = 0.0, drop_rel = 0.0;
   // CONVERT / IDENT / WRITE / ZERO
   TRef src, dst;
@@ -88,6 +104,9 @@ struct Plan {
   double cflops = 0.0, gflops = 0.0;
   int n_eig = 0, max_eig = 0;
   bool unsupported = false;   // a step exceeds this build's kernel limits
+  bool has_gate = false;      // some eigensolve's workgroups wait for each other (see mw_gate_*)
+  int n_rec = 0;              // truncation records
+  int64_t rec_off = 0;        // their byte offset in the workspace
   bool tune = false;          // built for autotuning: scratch for split candidates reserved
   int tuned_batch = 0;        // batch the contractions were last tuned for (0: not tuned)
   int launches[CBC_K_NCLASS] = {0};
@@ -95,14 +114,32 @@ struct Plan {
   double bytes[CBC_K_NCLASS] = {0.0};
   std::vector<hipEvent_t> events;
   // misc device slots (persistent workspace offsets)
-  int64_t logs_off = 0, ndrop_off = 0;
+  int64_t logs_off = 0;
   int64_t state_conv_off = -1, op_conv_off = -1;
   int64_t state_elems = 0, op_elems = 0;
-  // captured graph
-  hipGraphExec_t gexec = nullptr;
-  std::vector<uintptr_t> gkey;
+  // captured graphs, one per buffer set (key: buffers, offsets, batch, tol), each with an event
+  // recorded after its last launch so that it is destroyed only once it has finished
+  struct Exec {
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;
+    uint64_t used = 0;
+  };
+  std::map<std::vector<uintptr_t>, Exec> graphs;
+  uint64_t graph_clock = 0;
+  static constexpr size_t MAX_GRAPHS = 32;
+  void drop_graph(std::map<std::vector<uintptr_t>, Exec>::iterator it) {
+    if (it->second.done) {
+      (void)hipEventSynchronize(it->second.done);
+      (void)hipEventDestroy(it->second.done);
+    }
+    if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+    graphs.erase(it);
+  }
+  void drop_graphs() {
+    while (!graphs.empty()) drop_graph(graphs.begin());
+  }
   ~Plan() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
+    drop_graphs();
     if (d_tables) (void)hipFree(d_tables);
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
   }
@@ -182,6 +219,9 @@ struct Builder {
   DType ct, cacc;           // contraction storage type and accumulator
   std::vector<int64_t> legdim;
   size_t persist = 0, scratch = 0, scratch_max = 0;
+
+  bool bad = false;         // an internal planning invariant failed (reported as CBC_ESHAPE)
+  static constexpr int64_t ELEM_LIMIT = (int64_t)1 << 31;   // 32-bit element offsets
 
   Builder(Plan& p, const Problem& q, int mb, bool tol, cbc_precision prec)
       : P(p), pr(q), max_bond(mb), tol_on(tol) {
@@ -272,11 +312,21 @@ struct Builder {
     for (int l : A.legs) {
       if (pos(out, l) >= 0) ml.push_back(l);
       else if (pos(B.legs, l) >= 0) kl.push_back(l);
-      else { fprintf(stderr, "cbc: dangling leg\n"); abort(); }
+      else bad = true;   // a leg of A that is neither summed nor kept
     }
     for (int l : B.legs) {
       if (pos(out, l) >= 0) nl.push_back(l);
-      else if (pos(A.legs, l) < 0) { fprintf(stderr, "cbc: dangling leg\n"); abort(); }
+      else if (pos(A.legs, l) < 0) bad = true;
+    }
+    // the kernels address operands with 32-bit element offsets from tables
+    if (elems(A.legs) >= ELEM_LIMIT || elems(B.legs) >= ELEM_LIMIT || elems(out) >= ELEM_LIMIT)
+      P.unsupported = true;
+    if (bad || P.unsupported) {
+      Ten r;
+      r.ref = Cref;
+      r.ref.dt = tc;
+      r.legs = out;
+      return r;
     }
     const auto sA = strides(A.legs), sB = strides(B.legs), sC = strides(out);
     auto pick = [&](const std::vector<int>& legs, const std::vector<int>& of,
@@ -391,8 +441,20 @@ struct Builder {
     return contract(X, false, W, false, out, dst, ct, cacc, 0);
   }
 
-  // Truncate the joined leg of Lp (legs: row legs..., a_o, b_o) -> L [chi_new, a_o, b_o] (persistent).
-  Ten truncate(const Ten& Lp, int a_o, int b_o, bool& alias_ok) {
+  // A truncation eigensolve op: its record (node, sweep) and the status word.
+  void add_eig(Op& e, int node, int sweep) {
+    e.rec_node = node;
+    e.rec_sweep = sweep;
+    e.rec_index = P.n_rec++;
+    e.status.src = S_WS;
+    e.status.off = HDR_STATUS;
+    if (eig_needs_gate(e.s)) P.has_gate = true;
+    P.ops.push_back(e);
+  }
+
+  // Truncate the joined leg of Lp (legs: row legs..., a_o, b_o) -> L [chi_new, a_o, b_o] (persistent);
+  // the edge from `node` to its parent, in sweep `sweep`.
+  Ten truncate(const Ten& Lp, int a_o, int b_o, bool& alias_ok, int node, int sweep) {
     std::vector<int> rows(Lp.legs.begin(), Lp.legs.end() - 2);
     const int64_t m = elems(rows), n = legdim[a_o] * legdim[b_o];
     const int64_t kmax = std::min<int64_t>({(int64_t)max_bond, m, n});
@@ -434,7 +496,7 @@ struct Builder {
     // Householder reduction (16/3 s^3) plus back-transformation of kmax vectors (8 s^2 kmax)
     e.flops = 16.0 / 3.0 * (double)s * s * s + 8.0 * (double)s * s * kmax;
     e.bytes = 16.0 * (double)s * s + 16.0 * (double)s * kmax;
-    P.ops.push_back(e);
+    add_eig(e, node, sweep);
     P.n_eig++;
     P.max_eig = std::max(P.max_eig, s);
     if (!eig_size_supported(s)) P.unsupported = true;
@@ -462,7 +524,7 @@ struct Builder {
   // Top-kmax eigenvectors of a Hermitian FP64 Gram G (s x s, row-major): U (s x kmax) with legs
   // [row legs..., nl] (persistent if asked).
   Ten eig_op(const TRef& G, int s, int kmax, const std::vector<int>& rowlegs, int nl, bool persistent,
-             TRef* lam_out = nullptr, TRef* kk_out = nullptr) {
+             int node, TRef* lam_out = nullptr, TRef* kk_out = nullptr) {
     std::vector<int> ul = rowlegs;
     ul.push_back(nl);
     Ten U = alloc(ul, DT_C128, persistent);
@@ -483,7 +545,7 @@ struct Builder {
     e.cls = CBC_K_EIG;
     e.flops = 16.0 / 3.0 * (double)s * s * s + 8.0 * (double)s * s * kmax;
     e.bytes = 16.0 * (double)s * s + 16.0 * (double)s * kmax;
-    P.ops.push_back(e);
+    add_eig(e, node, 0);
     P.n_eig++;
     P.max_eig = std::max(P.max_eig, s);
     if (!eig_size_supported(s)) P.unsupported = true;
@@ -527,10 +589,10 @@ struct Builder {
       c.shift_rel = pass == 0 ? 11.0 * ((double)mrows * k + (double)k * (k + 1)) * u : 0.0;
       c.drop_rel = pass == 0 ? 0.0 : 1e-13;
       c.Cinv = Ci.ref;
-      TRef nd;
-      nd.src = S_WS;
-      nd.off = P.ndrop_off;
-      c.ndrop = nd;
+      c.ndrop.src = S_WS;
+      c.ndrop.off = HDR_NDROP;
+      c.status.src = S_WS;
+      c.status.off = HDR_STATUS;
       c.cls = CBC_K_CHOL;
       if (k > CHOL_LDS_MAX) c.work = scr(sizeof(double) * chol_work_doubles((int)k), DT_C128);
       c.flops = 8.0 / 3.0 * (double)k * k * k;
@@ -580,10 +642,10 @@ struct Builder {
         c.logs = logslot;
         c.scale = scaleslot;
       }
-      TRef nd;
-      nd.src = S_WS;
-      nd.off = P.ndrop_off;
-      c.ndrop = nd;
+      c.ndrop.src = S_WS;
+      c.ndrop.off = HDR_NDROP;
+      c.status.src = S_WS;
+      c.status.off = HDR_STATUS;
       c.cls = CBC_K_CHOL;
       if (k > CHOL_LDS_MAX) c.work = scr(sizeof(double) * chol_work_doubles((int)k), DT_C128);
       // Cholesky (4/3 k^3) plus triangular inverse (4/3 k^3), complex
@@ -607,38 +669,25 @@ struct Builder {
   }
 };
 
-cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc_precision prec) {
-  Builder B(P, pr, max_bond, tol_on, prec);
-  const int n = pr.n;
-  B.sig.resize(n);
-  B.sigp.resize(n);
-  B.ealpha.assign(n, -1);
-  B.ebeta.assign(n, -1);
-  for (int i = 0; i < n; ++i) {
-    B.sig[i] = B.leg(pr.phys[i]);
-    B.sigp[i] = B.leg(pr.phys[i]);
-    if (pr.parent[i] >= 0) {
-      B.ealpha[i] = B.leg(pr.chi[i]);
-      B.ebeta[i] = B.leg(pr.dop[i]);
-    }
-  }
-  B.rootA = B.leg(1);
-  B.rootB = B.leg(1);
-
-  // persistent device slots
+// Persistent slots every plan starts with: the report header at offset 0 (initialised by the first
+// op of every call), the per-node log-scales (zeroed), and in mixed precision the converted inputs.
+void plan_prologue(Builder& B, Plan& P, cbc_precision prec, int n) {
+  B.persist = Builder::al(sizeof(WsHeader));
   P.logs_off = (int64_t)B.persist;
   B.persist += Builder::al(sizeof(double) * n);
-  P.ndrop_off = (int64_t)B.persist;
-  B.persist += 256;
   {
+    Op h;
+    h.kind = K_HEADER;   // n_rec and rec_off are filled in by plan_epilogue
+    h.dst.src = S_WS;
+    h.dst.off = 0;
+    P.ops.push_back(h);
     Op z;
     z.kind = K_ZERO;
     z.dst.src = S_WS;
     z.dst.off = P.logs_off;
-    z.count = (int64_t)(P.ndrop_off + 256 - P.logs_off);
+    z.count = (int64_t)(B.persist - P.logs_off);
     P.ops.push_back(z);
   }
-  // mixed precision: convert inputs once
   if (prec == CBC_PREC_MIXED) {
     P.state_conv_off = (int64_t)B.persist;
     B.persist += Builder::al(8 * (size_t)P.state_elems);
@@ -660,6 +709,51 @@ cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc
     c2.count = P.op_elems;
     P.ops.push_back(c2);
   }
+}
+
+// Truncation records at the end of the persistent region; sizes and per-class totals.
+cbc_status plan_epilogue(Builder& B, Plan& P) {
+  if (B.bad) return CBC_ESHAPE;
+  P.rec_off = (int64_t)B.persist;
+  B.persist += Builder::al(sizeof(cbc_trunc_record) * (size_t)P.n_rec);
+  for (Op& op : P.ops) {
+    if (op.kind == K_HEADER) {
+      op.count = P.n_rec;
+      op.rest = P.rec_off;
+    } else if (op.kind == K_EIG) {
+      op.rec.src = S_WS;
+      op.rec.off = P.rec_off + (int64_t)sizeof(cbc_trunc_record) * op.rec_index;
+    }
+  }
+  P.persist_bytes = B.persist;
+  P.scratch_bytes = B.scratch_max;
+  for (const Op& op : P.ops) {
+    P.launches[op.cls] += 1;
+    P.flops[op.cls] += op.flops;
+    P.bytes[op.cls] += op.bytes;
+  }
+  return CBC_OK;
+}
+
+cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc_precision prec) {
+  Builder B(P, pr, max_bond, tol_on, prec);
+  const int n = pr.n;
+  B.sig.resize(n);
+  B.sigp.resize(n);
+  B.ealpha.assign(n, -1);
+  B.ebeta.assign(n, -1);
+  for (int i = 0; i < n; ++i) {
+    B.sig[i] = B.leg(pr.phys[i]);
+    B.sigp[i] = B.leg(pr.phys[i]);
+    if (pr.parent[i] >= 0) {
+      B.ealpha[i] = B.leg(pr.chi[i]);
+      B.ebeta[i] = B.leg(pr.dop[i]);
+    }
+  }
+  B.rootA = B.leg(1);
+  B.rootB = B.leg(1);
+
+  plan_prologue(B, P, prec, n);
 
   // which sweep-1 environments are consumed
   std::vector<char> need(n, 0);
@@ -690,7 +784,7 @@ cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc
     Ten Lp = B.alloc(out, B.ct, alias);
     Lp = B.node_contract(i, envs, out, Lp.ref);
     bool al;
-    Lsub[i] = B.truncate(Lp, B.ealpha[i], B.ebeta[i], al);
+    Lsub[i] = B.truncate(Lp, B.ealpha[i], B.ebeta[i], al, i, 1);
   }
   // sweep 2: root -> leaves
   {
@@ -722,7 +816,7 @@ cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc
         Ten Lp = B.alloc(out, B.ct, alias);
         Lp = B.node_contract(i, envs, out, Lp.ref);
         bool al;
-        Lpar[k] = B.truncate(Lp, B.ealpha[k], B.ebeta[k], al);
+        Lpar[k] = B.truncate(Lp, B.ealpha[k], B.ebeta[k], al, k, 2);
       }
     }
   }
@@ -844,52 +938,11 @@ cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc
     w.dst.off = i;
     P.ops.push_back(w);
   }
-  P.persist_bytes = B.persist;
-  P.scratch_bytes = B.scratch_max;
-  for (const Op& op : P.ops) {
-    P.launches[op.cls] += 1;
-    P.flops[op.cls] += op.flops;
-    P.bytes[op.cls] += op.bytes;
-  }
-  return CBC_OK;
+  return plan_epilogue(B, P);
 }
 
 // ------------------------------------------------------------------------------------------------
 // the naive (direct) method of Sec. III C: exact product, canonical form, truncated-SVD sweep
-
-void plan_prologue(Builder& B, Plan& P, cbc_precision prec, int n) {
-  P.logs_off = (int64_t)B.persist;
-  B.persist += Builder::al(sizeof(double) * n);
-  P.ndrop_off = (int64_t)B.persist;
-  B.persist += 256;
-  Op z;
-  z.kind = K_ZERO;
-  z.dst.src = S_WS;
-  z.dst.off = P.logs_off;
-  z.count = (int64_t)(P.ndrop_off + 256 - P.logs_off);
-  P.ops.push_back(z);
-  if (prec == CBC_PREC_MIXED) {
-    P.state_conv_off = (int64_t)B.persist;
-    B.persist += Builder::al(8 * (size_t)P.state_elems);
-    P.op_conv_off = (int64_t)B.persist;
-    B.persist += Builder::al(8 * (size_t)P.op_elems);
-    Op c1;
-    c1.kind = K_CONVERT;
-    c1.src.src = S_STATE;
-    c1.src.off = -1;
-    c1.ts = DT_C128;
-    c1.dst.src = S_WS;
-    c1.dst.off = P.state_conv_off;
-    c1.td = DT_C64;
-    c1.count = P.state_elems;
-    P.ops.push_back(c1);
-    Op c2 = c1;
-    c2.src.src = S_OP;
-    c2.dst.off = P.op_conv_off;
-    c2.count = P.op_elems;
-    P.ops.push_back(c2);
-  }
-}
 
 cbc_status build_plan_naive(Plan& P, const Problem& pr, int max_bond, bool tol_on,
                             cbc_precision prec) {
@@ -1018,13 +1071,13 @@ cbc_status build_plan_naive(Plan& P, const Problem& pr, int max_bond, bool tol_o
         gl.insert(gl.end(), rows2.begin(), rows2.end());
         Ten G = B.alloc(gl, DT_C128, false);
         B.contract(M, false, M2, true, gl, G.ref, DT_C128, DT_C128, 1);
-        U = B.eig_op(G.ref, (int)m, kmax, rows, K, true);
+        U = B.eig_op(G.ref, (int)m, kmax, rows, K, true, c);
       } else {
         const int col2 = B.leg(nn);
         Ten M2{M.ref, Builder::replaced(M.legs, col, col2)};
         Ten G = B.alloc({col, col2}, DT_C128, false);
         B.contract(M, true, M2, false, {col, col2}, G.ref, DT_C128, DT_C128, 1);
-        Ten V = B.eig_op(G.ref, (int)nn, kmax, {col}, K, false);
+        Ten V = B.eig_op(G.ref, (int)nn, kmax, {col}, K, false, c);
         std::vector<int> wl = rows;
         wl.push_back(K);
         Ten Wt = B.alloc(wl, DT_C128, false);
@@ -1068,14 +1121,7 @@ cbc_status build_plan_naive(Plan& P, const Problem& pr, int max_bond, bool tol_o
     dst.dt = DT_C128;
     B.contract(node[i], false, Ten{one, {}}, false, ol, dst, DT_C128, DT_C128, 3);
   }
-  P.persist_bytes = B.persist;
-  P.scratch_bytes = B.scratch_max;
-  for (const Op& op : P.ops) {
-    P.launches[op.cls] += 1;
-    P.flops[op.cls] += op.flops;
-    P.bytes[op.cls] += op.bytes;
-  }
-  return CBC_OK;
+  return plan_epilogue(B, P);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1209,6 +1255,10 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         a.tstamp = nullptr;
         a.batch = c.batch;
         a.bs = c.ws_inst;
+        a.status = (int*)resolve(P, c, op.status);
+        a.rec = (cbc_trunc_record*)resolve(P, c, op.rec);
+        a.rec_node = op.rec_node;
+        a.rec_sweep = op.rec_sweep;
         e = launch_eig(a, st);
         break;
       }
@@ -1231,6 +1281,7 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         a.batch = c.batch;
         a.bs = c.ws_inst;
         a.work = op.work.src == S_NONE ? nullptr : (double2*)resolve(P, c, op.work);
+        a.status = (int*)resolve(P, c, op.status);
         e = launch_chol_inv(a, st);
         break;
       }
@@ -1251,6 +1302,11 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         break;
       case K_ZERO:
         e = launch_zero(resolve(P, c, op.dst), op.count, c.batch, stride_of(P, c, op.dst), st);
+        break;
+      case K_HEADER:
+        e = launch_report_header(resolve(P, c, op.dst), REPORT_MAGIC, (int)op.count, op.rest,
+                                 (int64_t)sizeof(cbc_trunc_record), c.batch,
+                                 stride_of(P, c, op.dst), st);
         break;
     }
     if (e != hipSuccess) return e;
@@ -1464,8 +1520,11 @@ const char* cbc_status_str(cbc_status s) {
     case CBC_ENOMEM: return "workspace too small or allocation failed";
     case CBC_EHIP: return "HIP runtime error";
     case CBC_ENOTPD: return "factorisation failed after fallbacks";
-    case CBC_EUNSUP: return "unsupported configuration (a truncation Gram matrix larger than 1272)";
+    case CBC_EUNSUP:
+      return "unsupported configuration (an eigensolve beyond the solver's size limit, or a tensor "
+             "of 2^31 or more elements)";
     case CBC_ENOTBUILT: return "no usable gfx950 device";
+    case CBC_ETIMEOUT: return "a bounded wait between cooperating workgroups expired on the device";
   }
   return "unknown status";
 }
@@ -1577,11 +1636,7 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
     // the contractions' configurations change: a captured graph of the old ones is dropped
     if (tune_plan(ctx, *P, c, st) != hipSuccess) return CBC_EHIP;
     P->tuned_batch = batch;
-    if (P->gexec) {
-      (void)hipGraphExecDestroy(P->gexec);
-      P->gexec = nullptr;
-    }
-    P->gkey.clear();
+    P->drop_graphs();
   }
   if (profile) {
     const size_t ne = 2 * P->ops.size();
@@ -1605,11 +1660,15 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
       key.push_back((uintptr_t)c.st_off[i]);
       key.push_back((uintptr_t)c.op_off[i]);
     }
-    if (!P->gexec || P->gkey != key) {
-      if (P->gexec) {
-        (void)hipGraphExecDestroy(P->gexec);
-        P->gexec = nullptr;
+    auto it = P->graphs.find(key);
+    if (it == P->graphs.end()) {
+      if (P->graphs.size() >= Plan::MAX_GRAPHS) {
+        auto lru = P->graphs.begin();
+        for (auto g2 = P->graphs.begin(); g2 != P->graphs.end(); ++g2)
+          if (g2->second.used < lru->second.used) lru = g2;
+        P->drop_graph(lru);
       }
+      Plan::Exec ex;
       hipGraph_t g = nullptr;
       if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return CBC_EHIP;
       const hipError_t e1 = run_ops(*P, c, st);
@@ -1618,17 +1677,23 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
         if (g) (void)hipGraphDestroy(g);
         return CBC_EHIP;
       }
-      const hipError_t e3 = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0);
+      const hipError_t e3 = hipGraphInstantiate(&ex.exec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
-      if (e3 != hipSuccess) {
-        P->gexec = nullptr;
+      if (e3 != hipSuccess) return CBC_EHIP;
+      if (hipEventCreateWithFlags(&ex.done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGraphExecDestroy(ex.exec);
         return CBC_EHIP;
       }
-      P->gkey = key;
+      it = P->graphs.emplace(key, ex).first;
     } else {
       replayed = 1;
     }
-    if (hipGraphLaunch(P->gexec, st) != hipSuccess) return CBC_EHIP;
+    it->second.used = ++P->graph_clock;
+    // a graph holding a multi-workgroup eigensolve runs after the previous one on the device
+    if (P->has_gate && mw_gate_enter(st) != hipSuccess) return CBC_EHIP;
+    if (hipGraphLaunch(it->second.exec, st) != hipSuccess) return CBC_EHIP;
+    if (P->has_gate && mw_gate_leave(st) != hipSuccess) return CBC_EHIP;
+    if (hipEventRecord(it->second.done, st) != hipSuccess) return CBC_EHIP;
   } else {
     if (run_ops(*P, c, st) != hipSuccess) return CBC_EHIP;
   }
@@ -1656,6 +1721,27 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
     }
   }
   return CBC_OK;
+}
+
+cbc_status cbc_read_report(const void* workspace, size_t instance_bytes, int32_t instance,
+                           void* stream, cbc_report* rep) {
+  if (!workspace || !rep || instance < 0) return CBC_EINVAL;
+  if (rep->capacity < 0 || (rep->capacity > 0 && !rep->trunc)) return CBC_EINVAL;
+  if (instance > 0 && instance_bytes == 0) return CBC_EINVAL;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return CBC_EHIP;
+  const char* base = (const char*)workspace + instance_bytes * (size_t)instance;
+  WsHeader h;
+  if (hipMemcpy(&h, base, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return CBC_EHIP;
+  if (h.magic != REPORT_MAGIC || h.n_rec < 0 || h.rec_off < (int64_t)sizeof(WsHeader))
+    return CBC_EINVAL;
+  rep->status = h.status;
+  rep->dropped_pivots = h.ndrop;
+  rep->n_trunc = h.n_rec;
+  const int nc = std::min(rep->capacity, h.n_rec);
+  if (nc > 0 && hipMemcpy(rep->trunc, base + h.rec_off, sizeof(cbc_trunc_record) * (size_t)nc,
+                          hipMemcpyDeviceToHost) != hipSuccess)
+    return CBC_EHIP;
+  return (cbc_status)h.status;
 }
 
 cbc_status cbc_apply(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/cbc.h"
+
 namespace cbc {
 
 // Element types used for operands.
@@ -83,11 +85,32 @@ struct EigArgs {
   int batch;          // instances; every pointer above (except tstamp) advances by bs bytes
   int64_t bs;
   int spread = 1;     // set by launch_eig: grid widening of the XCD-aware launches (1 or 8)
+  // optional (advance by bs like the pointers above): the call's device status word (a failure
+  // code is stored there if it still holds 0) and the record of this truncation
+  int* status = nullptr;
+  cbc_trunc_record* rec = nullptr;
+  int rec_node = -1, rec_sweep = 0;
+  // wall-clock ticks (100 MHz) a cross-workgroup wait may take before the solve gives up; a
+  // negative value makes the first wait give up at once (tests of the status path)
+  long long timeout_ticks = 200000000LL;
 };
 size_t eig_work_doubles(int s, int kmax);
 // largest Gram the eigensolver handles (the multi-workgroup reduction keeps its rows in LDS)
 bool eig_size_supported(int s);
+// the eigensolve of an s x s Gram needs workgroups that wait for each other (must run alone)
+bool eig_needs_gate(int s);
 hipError_t launch_eig(const EigArgs& a, hipStream_t st);
+
+// Device-wide order of the solves whose workgroups wait for each other: mw_gate_enter makes `st`
+// wait for the previous such solve on the current device if that was queued on another stream
+// (eagerly, or in the same graph capture as `st`), mw_gate_leave records the solve just queued.
+hipError_t mw_gate_enter(hipStream_t st);
+hipError_t mw_gate_leave(hipStream_t st);
+
+// device status word: store `code` if the word still holds CBC_OK
+__device__ inline void raise_status(int* status, int code) {
+  if (status) atomicCAS(status, 0, code);
+}
 
 // n-side truncation output: L[j, c] = sqrt(max(lam_j, 0)) / sqrt(lam_0) * conj(V[c, j]) for j < kkeep,
 // zero for kkeep <= j < kmax. L is kmax x n, written in the contraction precision.
@@ -115,6 +138,7 @@ struct CholArgs {
   // absolute pivot threshold read from the device (the shift is then already applied)
   int ld = 0;
   const double* thresh_dev = nullptr;
+  int* status = nullptr;   // optional device status word (CBC_ENOTPD on a non-finite Gram)
 };
 // largest k factorised by one LDS-resident workgroup; larger ones are blocked and need `work`
 constexpr int CHOL_LDS_MAX = 88;
@@ -128,6 +152,11 @@ hipError_t launch_convert(const void* src, DType ts, void* dst, DType td, int64_
 hipError_t launch_fill_identity(void* dst, DType t, int rows, int cols, int batch, int64_t ds,
                                 hipStream_t st);
 hipError_t launch_zero(void* dst, int64_t bytes, int batch, int64_t ds, hipStream_t st);
+// Report header at the start of a call's workspace: 64 bytes holding magic, status 0, dropped
+// pivots 0, the record count and the records' byte offset (int64 at byte 16); the n_rec records of
+// rec_bytes each at rec_off are zeroed.
+hipError_t launch_report_header(void* ws, uint32_t magic, int n_rec, int64_t rec_off,
+                                int64_t rec_bytes, int batch, int64_t ds, hipStream_t st);
 // Output writer: src is a (a x b x rest) tensor in type ts; writes dst[(b, a, rest)] as complex128
 // (swap of the two leading legs), multiplied by exp(-sum(logs[0..nlogs))) if logs != nullptr.
 hipError_t launch_write_out(const void* src, DType ts, int a, int b, int64_t rest, double2* dst,

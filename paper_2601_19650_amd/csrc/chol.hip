@@ -11,6 +11,8 @@
 // identity: its Cholesky factor and inverse are the identity to the same rounding.
 #include <float.h>
 
+#include <algorithm>
+
 #include "cbc_internal.h"
 
 namespace cbc {
@@ -37,6 +39,7 @@ __device__ inline CholArgs chol_inst(const CholArgs& a0, int b) {
   a.ndrop = inst_ptr(a0.ndrop, a0.bs, b);
   a.work = inst_ptr(a0.work, a0.bs, b);
   a.thresh_dev = inst_ptr(a0.thresh_dev, a0.bs, b);
+  a.status = inst_ptr(a0.status, a0.bs, b);
   return a;
 }
 
@@ -170,6 +173,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
     a.log_scale[0] = trace > 0.0 ? -0.5 * log(trace) : 0.0;
     a.scale[0] = trace > 0.0 ? 1.0 / sqrt(trace) : 1.0;
   }
+  if (tid == 0 && !isfinite(trace)) raise_status(a.status, CBC_ENOTPD);
   const double shift = a.shift_rel * trace;
   __syncthreads();
   double mx = 0.0;
@@ -371,6 +375,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_prep(CholArgs a0, double*
     double t = 0.0;
     for (int w = 0; w < nwave; ++w) t += red[w];
     sh_trace = t;
+    if (!isfinite(t)) raise_status(a.status, CBC_ENOTPD);
     if (a.log_scale) {
       a.log_scale[0] = t > 0.0 ? -0.5 * log(t) : 0.0;
       a.scale[0] = t > 0.0 ? 1.0 / sqrt(t) : 1.0;
@@ -546,6 +551,35 @@ hipError_t launch_zero(void* dst, int64_t bytes, int batch, int64_t ds, hipStrea
 }
 
 // dst[(b, a, r)] = src[(a, b, r)] * exp(-sum logs)
+__global__ void k_report_header(char* ws, uint32_t magic, int n_rec, int64_t rec_off,
+                                int64_t rec_bytes, int64_t ds) {
+  ws += ds * (int64_t)blockIdx.y;
+  uint32_t* rec = reinterpret_cast<uint32_t*>(ws + rec_off);
+  const int64_t nw = (int64_t)n_rec * rec_bytes / 4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw;
+       i += (int64_t)gridDim.x * blockDim.x)
+    rec[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x < 16) {
+    uint32_t* h = reinterpret_cast<uint32_t*>(ws);
+    uint32_t v = 0u;
+    if (threadIdx.x == 0) v = magic;
+    else if (threadIdx.x == 3) v = (uint32_t)n_rec;
+    else if (threadIdx.x == 4) v = (uint32_t)(uint64_t)rec_off;
+    else if (threadIdx.x == 5) v = (uint32_t)((uint64_t)rec_off >> 32);
+    h[threadIdx.x] = v;
+  }
+}
+
+hipError_t launch_report_header(void* ws, uint32_t magic, int n_rec, int64_t rec_off,
+                                int64_t rec_bytes, int batch, int64_t ds, hipStream_t st) {
+  if (batch <= 0) return hipSuccess;
+  const int64_t nw = (int64_t)n_rec * rec_bytes / 4;
+  const int blocks = (int)std::min<int64_t>(64, std::max<int64_t>(1, (nw + 255) / 256));
+  hipLaunchKernelGGL(k_report_header, dim3(blocks, batch), dim3(256), 0, st, (char*)ws, magic,
+                     n_rec, rec_off, rec_bytes, ds);
+  return hipGetLastError();
+}
+
 __global__ void k_write_out(const void* src, int ts, int a, int b, int64_t rest, double2* dst,
                             const double* logs, int nlogs, int64_t ss, int64_t ds, int64_t ls) {
   const int inst = blockIdx.y;

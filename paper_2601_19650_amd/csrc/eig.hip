@@ -23,6 +23,8 @@
 //      the reflectors streamed from L2, one wave per eigenpair (three launches).
 #include <float.h>
 
+#include <mutex>
+
 #include "cbc_internal.h"
 
 namespace cbc {
@@ -80,8 +82,9 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 __device__ __forceinline__ int tri(int r) { return r * (r + 1) / 2; }
-// a / b through the hardware reciprocal refined by one Newton step (a few ulp; used only in the Sturm
-// count and the twisted factorisation, whose callers guard b away from zero).
+// a / b through the hardware reciprocal refined by one Newton step (relative error about the square
+// of the hardware estimate's; used only in the Sturm counts and the twisted factorisation, which
+// tolerate relative errors far above one ulp per step and whose callers guard b away from zero).
 __device__ __forceinline__ double qdiv(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
   r = fma(r, fma(-b, r, 1.0), r);
@@ -94,7 +97,7 @@ struct EigWork {
   double* d;      // s
   double* e;      // s
   double2* tau;   // s
-  double* bounds; // 8: lo, hi, tnorm, pivmin
+  double* bounds; // 8: lo, hi, tnorm, pivmin, the (kmax+1)-th largest eigenvalue
   double2* V;     // s * s   reflector j at V[j*s + i], i > j, V[j*s+j+1] = 1
   double* Y;      // kmax * s   cluster eigenvectors of T at Y[t*s + i]
   double* lu;     // kmax * 5 * s
@@ -134,6 +137,8 @@ __device__ inline EigArgs eig_inst(const EigArgs& a0, int b) {
   a.kkeep = inst_ptr(a0.kkeep, a0.bs, b);
   a.inv_sqrt_l0 = inst_ptr(a0.inv_sqrt_l0, a0.bs, b);
   a.work = inst_ptr(a0.work, a0.bs, b);
+  a.status = inst_ptr(a0.status, a0.bs, b);
+  a.rec = inst_ptr(a0.rec, a0.bs, b);
   return a;
 }
 
@@ -187,11 +192,12 @@ __device__ inline double2 householder(double2 alpha, double xn2, int C, double a
   double2 t = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
   double beta = alpha.x;
   if (!(xn2 == 0.0 && alpha.y == 0.0)) {
-    // |x| and 1/|x| from the hardware reciprocal square root refined by one Newton step, 1/|alpha -
-    // beta|^2 from the hardware reciprocal refined likewise (a few ulp each; the column norm is
-    // positive here)
+    // |x| and 1/|x| from the hardware reciprocal square root refined by two Newton steps, 1/|alpha -
+    // beta|^2 from the hardware reciprocal refined likewise (each step squares the relative error,
+    // so two leave about one ulp whatever the estimate's accuracy; the column norm is positive here)
     const double n2 = alpha.x * alpha.x + alpha.y * alpha.y + xn2;
     double rn = __builtin_amdgcn_rsq(n2);
+    rn = fma(0.5 * rn, fma(-n2 * rn, rn, 1.0), rn);
     rn = fma(0.5 * rn, fma(-n2 * rn, rn, 1.0), rn);
     const double nrm = n2 * rn;
     beta = alpha.x >= 0.0 ? -nrm : nrm;
@@ -199,6 +205,7 @@ __device__ inline double2 householder(double2 alpha, double xn2, int C, double a
     const double ar = alpha.x - beta, ai = alpha.y;
     const double den = ar * ar + ai * ai;
     double rden = __builtin_amdgcn_rcp(den);
+    rden = fma(rden, fma(-den, rden, 1.0), rden);
     rden = fma(rden, fma(-den, rden, 1.0), rden);
     t = make_double2(-ar * rb, -ai * rb);
     scal = make_double2(ar * rden, -ai * rden);
@@ -263,7 +270,7 @@ __device__ __forceinline__ void load_column(const double2* P, int s, int C, int 
   for (int k = 0; k < 2; ++k) x[k] = P[tri(C + min(lane + 64 * k, s - 1 - C)) + C];
 }
 
-__device__ void tri_bounds(EigWork& W, int s, long long* tstamp);
+__device__ void tri_bounds(EigWork& W, int s, long long* tstamp, int* status);
 
 __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
   const EigArgs a = eig_inst(a0, blockIdx.x);
@@ -412,11 +419,12 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     a.tstamp[6] = tD;
   }
   // the Gershgorin interval of T (used by the two later kernels)
-  if (wave == 0) tri_bounds(W, s, a.tstamp);
+  if (wave == 0) tri_bounds(W, s, a.tstamp, a.status);
 }
 
-// Gershgorin interval of T and the pivot floor of the Sturm counts; one wave.
-__device__ void tri_bounds(EigWork& W, int s, long long* tstamp) {
+// Gershgorin interval of T and the pivot floor of the Sturm counts; one wave. A non-finite T (a
+// Gram with NaN or infinite entries) raises CBC_ENOTPD.
+__device__ void tri_bounds(EigWork& W, int s, long long* tstamp, int* status) {
   const int lane = threadIdx.x & 63;
   {
     double lo = DBL_MAX, hi = -DBL_MAX, emax = 0.0;
@@ -431,6 +439,7 @@ __device__ void tri_bounds(EigWork& W, int s, long long* tstamp) {
     hi = wave_max(hi);
     emax = wave_max(emax);
     if (lane == 0) {
+      if (!isfinite(lo) || !isfinite(hi)) raise_status(status, CBC_ENOTPD);
       const double tn = fmax(fabs(lo), fabs(hi));
       const double pad = 2.0 * DBL_EPSILON * tn * s + DBL_MIN;
       W.bounds[0] = lo - pad;
@@ -453,13 +462,13 @@ __device__ void tri_bounds(EigWork& W, int s, long long* tstamp) {
 //       builds row j+1 of the updated matrix from the row its owner published one column earlier, so
 //       that the next reflector is formed by every workgroup, identically, without another barrier.
 // Reductions are summed in a fixed order, so every workgroup holds bitwise the same v and w.
-// The barrier waits are bounded: after MW_TIMEOUT_TICKS of the 100 MHz wall clock a workgroup
-// raises a flag, every workgroup leaves at its next barrier, and d[0] is set to NaN.
+// The barrier waits are bounded: after timeout_ticks of the 100 MHz wall clock (2 s) a workgroup
+// raises a flag, every workgroup leaves at its next barrier, d[0] is set to NaN and the call's
+// status word receives CBC_ETIMEOUT.
 static constexpr int MW_THREADS = 1024;
 static constexpr int MW_WAVES = MW_THREADS / 64;
 static constexpr int MW_EPT = 2;                    // vector elements per thread: s <= 2048
 static constexpr size_t MW_LDS_BUDGET = 160 * 1024 - 2048;
-static constexpr long long MW_TIMEOUT_TICKS = 200000000LL;   // 2 s at 100 MHz
 
 struct MwShape {
   int nwg, rows;
@@ -482,6 +491,84 @@ size_t mw_lds_bytes(int s) { return (size_t)(mw_shape(s).rows + 2) * s * 16; }
 bool eig_size_supported(int s) {
   if (s <= EIG_LDS_MAX) return s >= 1;
   return s <= MW_EPT * MW_THREADS && mw_shape(s).nwg <= MW_MAX_WG && mw_lds_bytes(s) <= MW_LDS_BUDGET;
+}
+bool eig_needs_gate(int s) { return s > EIG_LDS_MAX; }
+
+// ---- device-wide order of the multi-workgroup reductions ------------------------------------------
+// Two multi-workgroup reductions running at once on one device could each hold part of the compute
+// units while waiting for workgroups of their own that cannot be placed. Every such launch is
+// therefore ordered after the previous one on the device: eagerly queued launches through one
+// event per device, launches recorded into a graph capture through an event tagged with the
+// capture's id (so a capture never waits on work outside it, and eager launches never wait on a
+// record that only exists inside a graph).
+namespace {
+constexpr int GATE_MAX_DEV = 64;
+struct GateSide {
+  hipEvent_t ev = nullptr;
+  hipStream_t last = nullptr;
+  unsigned long long id = 0;   // capture id (0: eager)
+  bool valid = false;
+};
+struct Gate {
+  std::mutex mu;
+  GateSide eager[GATE_MAX_DEV], capture[GATE_MAX_DEV];
+};
+Gate& gate() {
+  static Gate g;
+  return g;
+}
+hipError_t gate_state(hipStream_t st, int& dev, bool& cap, unsigned long long& id) {
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= GATE_MAX_DEV) return hipErrorInvalidDevice;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  id = 0;
+  cap = false;
+  if (st != nullptr) {
+    e = hipStreamGetCaptureInfo(st, &cs, &id);
+    if (e != hipSuccess) return e;
+    cap = cs == hipStreamCaptureStatusActive;
+  }
+  if (!cap) id = 0;
+  return hipSuccess;
+}
+}  // namespace
+
+hipError_t mw_gate_enter(hipStream_t st) {
+  int dev;
+  bool cap;
+  unsigned long long id;
+  hipError_t e = gate_state(st, dev, cap, id);
+  if (e != hipSuccess) return e;
+  Gate& g = gate();
+  std::lock_guard<std::mutex> lk(g.mu);
+  GateSide& side = cap ? g.capture[dev] : g.eager[dev];
+  if (side.valid && side.last != st && side.id == id) e = hipStreamWaitEvent(st, side.ev, 0);
+  return e;
+}
+
+hipError_t mw_gate_leave(hipStream_t st) {
+  int dev;
+  bool cap;
+  unsigned long long id;
+  hipError_t e = gate_state(st, dev, cap, id);
+  if (e != hipSuccess) return e;
+  Gate& g = gate();
+  std::lock_guard<std::mutex> lk(g.mu);
+  GateSide& side = cap ? g.capture[dev] : g.eager[dev];
+  if (!side.ev) {
+    e = hipEventCreateWithFlags(&side.ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      side.ev = nullptr;
+      return e;
+    }
+  }
+  e = hipEventRecord(side.ev, st);
+  if (e != hipSuccess) return e;
+  side.last = st;
+  side.id = id;
+  side.valid = true;
+  return hipSuccess;
 }
 
 // Data exchanged between the workgroups (products, partial sums, pivot rows) is written and read
@@ -507,7 +594,7 @@ __device__ __forceinline__ double2 cload(const double2* p) {
 // MI355X: 7.1 -> 4.4 us per barrier at 147 workgroups).
 static constexpr int MW_GATHER_MIN = 64;
 
-__device__ bool mw_sync(unsigned* sync, int nwg, unsigned it, int* ok_sh) {
+__device__ bool mw_sync(unsigned* sync, int nwg, unsigned it, int* ok_sh, long long timeout) {
   // every wave's exchanged-data stores have completed before the workgroup publishes its arrival
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
   __builtin_amdgcn_s_waitcnt(0);
@@ -522,7 +609,7 @@ __device__ bool mw_sync(unsigned* sync, int nwg, unsigned it, int* ok_sh) {
     auto failed = [&]() {
       const int err =
           __hip_atomic_load(&sync[MW_MAX_WG], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-      if (__any(err) || wall_clock64() - t0 > MW_TIMEOUT_TICKS) {
+      if (__any(err) || timeout < 0 || wall_clock64() - t0 > timeout) {
         if (tid == 0) __hip_atomic_store(&sync[MW_MAX_WG], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return true;
       }
@@ -731,8 +818,9 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
     if (tid == 0) cstore(&W.part[(size_t)(j & 1) * MW_MAX_WG + wg], ps);
     lap(0);
     // (2)
-    if (!mw_sync(W.sync, nwg, (unsigned)(j + 1), &ok_sh)) {
+    if (!mw_sync(W.sync, nwg, (unsigned)(j + 1), &ok_sh, a.timeout_ticks)) {
       if (writer && tid == 0) W.d[0] = __builtin_nan("");
+      if (tid == 0) raise_status(a.status, CBC_ETIMEOUT);
       return;
     }
     lap(1);
@@ -809,7 +897,7 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
   }
   if (writer) {
     __syncthreads();
-    if (wave == 0) tri_bounds(W, s, a.tstamp);
+    if (wave == 0) tri_bounds(W, s, a.tstamp, a.status);
   }
 }
 
@@ -844,8 +932,10 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_eigvals(EigArgs a0) {
     ee2[i] = i < s - 1 ? W.e[i] * W.e[i] : 0.0;
   }
   __syncthreads();
+  // waves t < kmax: the kept candidates; t == kmax (if kmax < s): the next eigenvalue, for the gap
+  // at the cut reported in the truncation record
   const int t = (int)(blockIdx.x / a0.spread) * EV_WAVES + wave;
-  if (t >= kmax) return;
+  if (t > kmax || t >= s) return;
   const double pivmin = W.bounds[3];
   const double target = 2.0 * DBL_EPSILON * W.bounds[2] + 4.0 * pivmin;
   const int jidx = s - 1 - t;   // ascending index of the t-th largest eigenvalue
@@ -859,7 +949,10 @@ __global__ __launch_bounds__(64 * EV_WAVES) void k_eigvals(EigArgs a0) {
     lo = xlo;
     hi = xhi;
   }
-  if (lane == 0) a.lam[t] = 0.5 * (lo + hi);
+  if (lane == 0) {
+    if (t < kmax) a.lam[t] = 0.5 * (lo + hi);
+    else W.bounds[4] = 0.5 * (lo + hi);
+  }
   if (a.tstamp && lane == 0)
     atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 2), (unsigned long long)wall_clock64());
 }
@@ -1190,6 +1283,32 @@ __global__ __launch_bounds__(256) void k_eigvecs_twisted(EigArgs a0) {
     a.kkeep[0] = keep;
     a.inv_sqrt_l0[0] = a.lam[0] > 0.0 ? 1.0 / sqrt(a.lam[0]) : 1.0;
   }
+  if (t == 0 && a.rec) {
+    // the truncation record: discarded weight (trace of T minus the kept eigenvalues) and the
+    // relative gap at the cut
+    double tr = 0.0, kept = 0.0;
+    for (int i = lane; i < s; i += 64) tr += dd[i];
+    for (int u = lane; u < keep; u += 64) kept += a.lam[u];
+    tr = wave_sum(tr);
+    kept = wave_sum(kept);
+    if (lane == 0) {
+      const bool cut = keep < s;
+      const double next = keep < kmax ? a.lam[keep] : (cut ? W.bounds[4] : 0.0);
+      const double last = a.lam[keep - 1];
+      const double gap = !cut ? 1.0 : (last > 0.0 ? (last - next) / last : 0.0);
+      cbc_trunc_record r;
+      r.node = a.rec_node;
+      r.sweep = a.rec_sweep;
+      r.dim = s;
+      r.kmax = kmax;
+      r.kept = keep;
+      r.flags = gap < 1e-8 ? 1 : 0;
+      r.discarded = tr > 0.0 ? fmax(0.0, (tr - kept) / tr) : 0.0;
+      r.gap = gap;
+      *a.rec = r;
+      if (!isfinite(tr)) raise_status(a.status, CBC_ENOTPD);
+    }
+  }
   double* y = region + 3 * (size_t)s;
   const double inv = twisted_vector(dd, el, s, a.lam[t], W.bounds[3], region, region + s, region + 2 * s, y);
   double* yo = W.Y + (size_t)t * s;
@@ -1292,12 +1411,20 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
     if (z != hipSuccess) return z;
     (void)hipFuncSetAttribute((const void*)k_tridiag_mw, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
+    // its workgroups wait for each other: no other such solve may hold compute units meanwhile
+    z = mw_gate_enter(st);
+    if (z != hipSuccess) return z;
     hipLaunchKernelGGL(k_tridiag_mw, dim3(m.nwg, a.batch), dim3(MW_THREADS), lds, st, a, m.nwg);
+    z = hipGetLastError();
+    if (z != hipSuccess) return z;
+    z = mw_gate_leave(st);
+    if (z != hipSuccess) return z;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds2 = (size_t)16 * a.s;
-  hipLaunchKernelGGL(k_eigvals, dim3(a.spread * ((a.kmax + EV_WAVES - 1) / EV_WAVES), a.batch),
+  const int nev = a.kmax < a.s ? a.kmax + 1 : a.kmax;
+  hipLaunchKernelGGL(k_eigvals, dim3(a.spread * ((nev + EV_WAVES - 1) / EV_WAVES), a.batch),
                      dim3(64 * EV_WAVES), lds2, st, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -1352,7 +1479,10 @@ __global__ void k_form_l_nside(const double2* V, const double* lam, const int* k
   const int j = (int)(idx / n);
   const int c = (int)(idx % n);
   double2 out = make_double2(0.0, 0.0);
-  if (j < kkeep[0] && lam[0] > 0.0) {
+  if (!isfinite(lam[0])) {
+    // a failed eigensolve: the output must not look like a valid (zero) environment
+    out = make_double2(__builtin_nan(""), __builtin_nan(""));
+  } else if (j < kkeep[0] && lam[0] > 0.0) {
     const double f = sqrt(fmax(lam[j], 0.0) / lam[0]);
     const double2 v = V[(size_t)c * kmax + j];
     out = make_double2(f * v.x, -f * v.y);

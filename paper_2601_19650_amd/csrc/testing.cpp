@@ -175,3 +175,30 @@ extern "C" int cbc_test_chol_inv(void* G, int k, double shift_rel, double drop_r
   if (w) (void)hipFree(w);
   return rc;
 }
+
+extern "C" int cbc_test_eig_report(void* G, int s, int kmax, double tol, int force_timeout,
+                                   void* U, void* lam, void* kkeep, void* inv_sqrt_l0,
+                                   void* status, void* rec, void* stream) {
+  if (!G || !U || !lam || !kkeep || !inv_sqrt_l0 || !status || !rec || s < 1 || kmax < 1 ||
+      kmax > s)
+    return CBC_EINVAL;
+  double* w = nullptr;
+  if (hipMalloc(&w, eig_work_doubles(s, kmax) * sizeof(double)) != hipSuccess) return CBC_ENOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  EigArgs a;
+  a.G = (double2*)G; a.s = s; a.kmax = kmax; a.tol = tol; a.U = (double2*)U;
+  a.lam = (double*)lam; a.kkeep = (int*)kkeep; a.inv_sqrt_l0 = (double*)inv_sqrt_l0; a.work = w;
+  a.tstamp = nullptr;
+  a.batch = 1;
+  a.bs = 0;
+  a.status = (int*)status;
+  a.rec = (cbc_trunc_record*)rec;
+  a.rec_node = 7;
+  a.rec_sweep = 2;
+  if (force_timeout) a.timeout_ticks = -1;
+  int rc = CBC_OK;
+  if (launch_eig(a, st) != hipSuccess) rc = CBC_EHIP;
+  else if (hipStreamSynchronize(st) != hipSuccess) rc = CBC_EHIP;
+  (void)hipFree(w);
+  return rc;
+}

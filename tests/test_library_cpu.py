@@ -189,3 +189,32 @@ def test_autotune_reserves_split_scratch():
         assert rc == 0
         sizes.append(int(ws.value))
     assert sizes[1] > sizes[0]
+
+
+def test_tensors_beyond_32bit_offsets_are_unsupported():
+    """The kernels address operands with 32-bit element offsets: a plan whose contraction touches a
+    tensor of 2^31 or more elements is rejected on the host with CBC_EUNSUP (here the root's
+    operator tensor, 46341^2 x 4 elements), not truncated silently."""
+    big = cbc.Tree([-1, 0], [46341, 2], [1, 2], [1, 4])
+    assert _query(big, max_bond=4)[0] == -6
+    ok = cbc.Tree([-1, 0], [512, 2], [1, 2], [1, 4])
+    assert _query(ok, max_bond=4)[0] == 0
+
+
+def test_read_report_argument_errors_need_no_device():
+    """cbc_read_report validates its arguments before touching the device."""
+    L = cbc.lib()
+    rep = cbc.Report(0, 0, 0, 0, None)
+    assert L.cbc_read_report(None, 0, 0, None, ctypes.byref(rep)) == -1
+    assert L.cbc_read_report(ctypes.c_void_p(0x1000), 0, 0, None, None) == -1
+    assert L.cbc_read_report(ctypes.c_void_p(0x1000), 0, -1, None, ctypes.byref(rep)) == -1
+    bad = cbc.Report(0, 0, 0, 4, None)                    # capacity without an array
+    assert L.cbc_read_report(ctypes.c_void_p(0x1000), 0, 0, None, ctypes.byref(bad)) == -1
+    assert L.cbc_read_report(ctypes.c_void_p(0x1000), 0, 1, None, ctypes.byref(rep)) == -1
+
+
+def test_status_strings():
+    L = cbc.lib()
+    for code in range(-8, 1):
+        assert L.cbc_status_str(code)
+    assert b"wait" in L.cbc_status_str(-8)
