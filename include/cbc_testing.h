@@ -39,6 +39,13 @@ int cbc_test_gemm_time(int M, int N, int K, int a_c128, int b_c128, int c_c128, 
 int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void* lam, void* kkeep,
                  void* inv_sqrt_l0, void* tstamp, void* stream);
 
+/* The same eigensolve with the reduction to tridiagonal form chosen for s > 128: reduction 0 is the
+ * library's (two-stage: dense -> band of half-bandwidth 16 -> tridiagonal), 1 the one-stage
+ * multi-workgroup Householder reduction (s <= 1272), kept to compare the two; other values are
+ * rejected. */
+int cbc_test_eig_reduction(void* G, int s, int kmax, double tol, int reduction, void* U, void* lam,
+                           void* kkeep, void* inv_sqrt_l0, void* tstamp, void* stream);
+
 /* The same eigensolve with the call's report: status (1 int, device, must hold 0 = CBC_OK before
  * the call) receives a failure code, rec (one cbc_trunc_record, device) the truncation record
  * (node 7, sweep 2). force_timeout = 1 makes the first cross-workgroup wait of the multi-workgroup

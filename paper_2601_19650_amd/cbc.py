@@ -376,13 +376,15 @@ def _testing_lib():
                                          ctypes.POINTER(ctypes.c_float)]
         L.cbc_test_gemm_time.restype = ci
         L.cbc_test_eig_report.argtypes = [vp, ci, ci, cd, ci, vp, vp, vp, vp, vp, vp, vp]
+        L.cbc_test_eig_reduction.argtypes = [vp, ci, ci, cd, ci, vp, vp, vp, vp, vp, vp]
+        L.cbc_test_eig_reduction.restype = ci
         L.cbc_test_eig_report.restype = ci
         L._testing_ready = True
     return L
 
 
 TESTING_EXPORTED = ("cbc_test_gemm", "cbc_test_gemm_time", "cbc_test_eig", "cbc_test_chol_inv",
-                    "cbc_test_eig_report")
+                    "cbc_test_eig_report", "cbc_test_eig_reduction")
 
 
 def _stream():
@@ -419,9 +421,10 @@ def test_gemm_time(M, N, K, a_c128=False, b_c128=False, c_c128=False, acc_fp64=F
     return float(ms.value)
 
 
-def test_eig(G, kmax, tol=0.0, stamps=None):
+def test_eig(G, kmax, tol=0.0, stamps=None, reduction=0):
     """Top-kmax eigenpairs of a Hermitian complex128 device matrix (G is consumed). If `stamps` is a
-    list, the phase durations in microseconds are appended to it."""
+    list, the phase durations in microseconds are appended to it. `reduction` selects the reduction
+    to tridiagonal form for s > 128 (0: two-stage, 1: one-stage multi-workgroup)."""
     import torch
     s = G.shape[0]
     G = G.contiguous().clone()
@@ -430,10 +433,12 @@ def test_eig(G, kmax, tol=0.0, stamps=None):
     kk = torch.empty(1, dtype=torch.int32, device=G.device)
     inv = torch.empty(1, dtype=torch.float64, device=G.device)
     ts = torch.zeros(16, dtype=torch.int64, device=G.device)
-    _check(_testing_lib().cbc_test_eig(G.data_ptr(), s, kmax, float(tol), U.data_ptr(),
-                                       lam.data_ptr(), kk.data_ptr(), inv.data_ptr(),
-                                       ts.data_ptr() if stamps is not None else None, _stream()),
-           "cbc_test_eig")
+    _check(_testing_lib().cbc_test_eig_reduction(G.data_ptr(), s, kmax, float(tol), int(reduction),
+                                                 U.data_ptr(), lam.data_ptr(), kk.data_ptr(),
+                                                 inv.data_ptr(),
+                                                 ts.data_ptr() if stamps is not None else None,
+                                                 _stream()),
+           "cbc_test_eig_reduction")
     if stamps is not None:
         t = ts.cpu().numpy()
         # tridiagonal, eigenvalues (incl. launch), eigenvectors (incl. launch), then the

@@ -93,6 +93,9 @@ struct EigArgs {
   // wall-clock ticks (100 MHz) a cross-workgroup wait may take before the solve gives up; a
   // negative value makes the first wait give up at once (tests of the status path)
   long long timeout_ticks = 200000000LL;
+  // reduction to tridiagonal form for s > 128: 0 = two-stage (dense -> band -> tridiagonal),
+  // 1 = one-stage multi-workgroup (s <= 1272; kept for comparison)
+  int reduction = 0;
 };
 size_t eig_work_doubles(int s, int kmax);
 // largest Gram the eigensolver handles (the multi-workgroup reduction keeps its rows in LDS)

@@ -25,121 +25,12 @@
 
 #include <mutex>
 
-#include "cbc_internal.h"
+#include "eig_common.h"
 
 namespace cbc {
 
-static constexpr int EIG_THREADS = 1024;
-static constexpr int EIG_LDS_MAX = 128;   // largest s whose packed triangle stays in LDS
-static constexpr int RG = 8;              // lanes per row group in the matrix-vector product
-static constexpr int TRI_U = 4;           // elements per lane whose LDS loads are issued together
-
-// ---- cross-lane reductions ---------------------------------------------------------------------
-// DPP lane moves (quad permutes and row mirrors) are single-cycle VALU operations; ds_bpermute
-// (__shfl_xor) goes through the LDS crossbar. A double is moved as two 32-bit halves.
-template <int CTRL>
-__device__ __forceinline__ double dpp(double v) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  const int l2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
-  const int h2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
-  return __hiloint2double(h2, l2);
-}
-// sum over aligned groups of 8 lanes, result in every lane of the group
-__device__ __forceinline__ double sum8(double v) {
-  v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
-  v += dpp<0x141>(v);   // row_half_mirror
-  return v;
-}
-// sum over aligned rows of 16 lanes, result in every lane of the row
-__device__ __forceinline__ double sum16(double v) {
-  v = sum8(v);
-  v += dpp<0x140>(v);   // row_mirror
-  return v;
-}
-// sum over the wave, result in every lane
-__device__ __forceinline__ double wave_sum(double v) {
-  v = sum16(v);
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  double t = 0.0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    t += __hiloint2double(__builtin_amdgcn_readlane(hi, 16 * r), __builtin_amdgcn_readlane(lo, 16 * r));
-  return t;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ __forceinline__ int tri(int r) { return r * (r + 1) / 2; }
-// a / b through the hardware reciprocal refined by one Newton step (relative error about the square
-// of the hardware estimate's; used only in the Sturm counts and the twisted factorisation, which
-// tolerate relative errors far above one ulp per step and whose callers guard b away from zero).
-__device__ __forceinline__ double qdiv(double a, double b) {
-  double r = __builtin_amdgcn_rcp(b);
-  r = fma(r, fma(-b, r, 1.0), r);
-  return a * r;
-}
-
-// Layout of the scratch buffer (doubles).
-static constexpr int MW_MAX_WG = 256;     // workgroups of the multi-workgroup reduction, at most
-struct EigWork {
-  double* d;      // s
-  double* e;      // s
-  double2* tau;   // s
-  double* bounds; // 8: lo, hi, tnorm, pivmin, the (kmax+1)-th largest eigenvalue
-  double2* V;     // s * s   reflector j at V[j*s + i], i > j, V[j*s+j+1] = 1
-  double* Y;      // kmax * s   cluster eigenvectors of T at Y[t*s + i]
-  double* lu;     // kmax * 5 * s
-  // multi-workgroup reduction only (each double-buffered by the parity of the column)
-  double2* ybuf;  // 2 * s       products A v of the current column
-  double2* part;  // 2 * MW_MAX_WG  per-workgroup partial sums of v^H A v
-  double2* prow;  // 2 * s       next pivot row, published by its owner
-  unsigned* sync; // MW_MAX_WG + 16 words: last barrier reached per workgroup, then a time-out flag
-};
-__host__ __device__ inline EigWork eig_layout(double* w, int s, int kmax) {
-  EigWork L;
-  L.d = w;
-  L.e = w + s;
-  L.tau = reinterpret_cast<double2*>(w + 2 * (size_t)s);
-  L.bounds = w + 4 * (size_t)s;
-  L.V = reinterpret_cast<double2*>(w + 4 * (size_t)s + 8);
-  L.Y = w + 4 * (size_t)s + 8 + 2 * (size_t)s * s;
-  L.lu = L.Y + (size_t)kmax * s;
-  L.ybuf = reinterpret_cast<double2*>(L.lu + 5 * (size_t)kmax * s);
-  L.part = L.ybuf + 2 * (size_t)s;
-  L.prow = L.part + 2 * MW_MAX_WG;
-  L.sync = reinterpret_cast<unsigned*>(L.prow + 2 * (size_t)s);
-  return L;
-}
-static constexpr int MW_SYNC_BYTES = 4 * (MW_MAX_WG + 16);
 size_t eig_work_doubles(int s, int kmax) {
-  return 4 * (size_t)s + 8 + 2 * (size_t)s * s + (size_t)kmax * s + 5 * (size_t)kmax * s +
-         4 * (size_t)s + 4 * MW_MAX_WG + 4 * (size_t)s + MW_SYNC_BYTES / 8 + 64;
-}
-
-// EigArgs of instance b (every pointer except the time stamps advances by a.bs bytes)
-__device__ inline EigArgs eig_inst(const EigArgs& a0, int b) {
-  EigArgs a = a0;
-  a.G = inst_ptr(a0.G, a0.bs, b);
-  a.U = inst_ptr(a0.U, a0.bs, b);
-  a.lam = inst_ptr(a0.lam, a0.bs, b);
-  a.kkeep = inst_ptr(a0.kkeep, a0.bs, b);
-  a.inv_sqrt_l0 = inst_ptr(a0.inv_sqrt_l0, a0.bs, b);
-  a.work = inst_ptr(a0.work, a0.bs, b);
-  a.status = inst_ptr(a0.status, a0.bs, b);
-  a.rec = inst_ptr(a0.rec, a0.bs, b);
-  return a;
+  return eig_base_doubles(s, kmax) + (s > EIG_LDS_MAX ? band_work_doubles(s) : 0);
 }
 
 __device__ int sturm_count(const double* dd, const double* ee2, int s, double x, double pivmin) {
@@ -159,14 +50,6 @@ struct TriShared {
   double2 zero;     // read in place of w past the trailing size
 };
 
-// a double from lane `l` (wave-uniform) of the wave
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                          __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-__device__ __forceinline__ double2 readlane_z(double2 v, int l) {
-  return make_double2(readlane_d(v.x, l), readlane_d(v.y, l));
-}
 // w' = w + a2 v, the corrected product of one row
 __device__ __forceinline__ double2 wprime(double2 w, double2 v, double2 a2) {
   return make_double2(w.x + a2.x * v.x - a2.y * v.y, w.y + a2.x * v.y + a2.y * v.x);
@@ -270,7 +153,6 @@ __device__ __forceinline__ void load_column(const double2* P, int s, int C, int 
   for (int k = 0; k < 2; ++k) x[k] = P[tri(C + min(lane + 64 * k, s - 1 - C)) + C];
 }
 
-__device__ void tri_bounds(EigWork& W, int s, long long* tstamp, int* status);
 
 __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
   const EigArgs a = eig_inst(a0, blockIdx.x);
@@ -422,35 +304,6 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
   if (wave == 0) tri_bounds(W, s, a.tstamp, a.status);
 }
 
-// Gershgorin interval of T and the pivot floor of the Sturm counts; one wave. A non-finite T (a
-// Gram with NaN or infinite entries) raises CBC_ENOTPD.
-__device__ void tri_bounds(EigWork& W, int s, long long* tstamp, int* status) {
-  const int lane = threadIdx.x & 63;
-  {
-    double lo = DBL_MAX, hi = -DBL_MAX, emax = 0.0;
-    for (int i = lane; i < s; i += 64) {
-      const double el = i > 0 ? fabs(W.e[i - 1]) : 0.0;
-      const double er = i < s - 1 ? fabs(W.e[i]) : 0.0;
-      lo = fmin(lo, W.d[i] - el - er);
-      hi = fmax(hi, W.d[i] + el + er);
-      emax = fmax(emax, er * er);
-    }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    emax = wave_max(emax);
-    if (lane == 0) {
-      if (!isfinite(lo) || !isfinite(hi)) raise_status(status, CBC_ENOTPD);
-      const double tn = fmax(fabs(lo), fabs(hi));
-      const double pad = 2.0 * DBL_EPSILON * tn * s + DBL_MIN;
-      W.bounds[0] = lo - pad;
-      W.bounds[1] = hi + pad;
-      W.bounds[2] = tn;
-      W.bounds[3] = DBL_MIN * fmax(1.0, emax);
-      if (tstamp) tstamp[1] = wall_clock64();
-    }
-  }
-}
-
 // ---- multi-workgroup Householder reduction (s > EIG_LDS_MAX) ------------------------------------
 // The rows of G are dealt cyclically to nwg workgroups (row r to workgroup r mod nwg) and stay in
 // their LDS for the whole reduction. Column j costs one grid-wide barrier:
@@ -488,11 +341,15 @@ __host__ __device__ inline MwShape mw_shape(int s) {
 }
 size_t mw_lds_bytes(int s) { return (size_t)(mw_shape(s).rows + 2) * s * 16; }
 
-bool eig_size_supported(int s) {
-  if (s <= EIG_LDS_MAX) return s >= 1;
-  return s <= MW_EPT * MW_THREADS && mw_shape(s).nwg <= MW_MAX_WG && mw_lds_bytes(s) <= MW_LDS_BUDGET;
+// the two-stage path: panels of up to 2048 rows (two per thread of the panel kernel)
+static constexpr int EIG_MAX_S = 2048 + 16;
+bool eig_size_supported(int s) { return s >= 1 && s <= EIG_MAX_S; }
+// only the one-stage multi-workgroup reduction (selected explicitly) has cross-workgroup waits
+bool eig_needs_gate(int s) { (void)s; return false; }
+static bool mw_size_supported(int s) {
+  return s > EIG_LDS_MAX && s <= MW_EPT * MW_THREADS && mw_shape(s).nwg <= MW_MAX_WG &&
+         mw_lds_bytes(s) <= MW_LDS_BUDGET;
 }
-bool eig_needs_gate(int s) { return s > EIG_LDS_MAX; }
 
 // ---- device-wide order of the multi-workgroup reductions ------------------------------------------
 // Two multi-workgroup reductions running at once on one device could each hold part of the compute
@@ -899,20 +756,6 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
     __syncthreads();
     if (wave == 0) tri_bounds(W, s, a.tstamp, a.status);
   }
-}
-
-// ---- XCD-aware launches ------------------------------------------------------------------------
-// The kernels after the reduction read what it wrote for an instance (T, the reflectors, Y). For
-// small Grams and few instances their grids are launched a.spread = 8 times wider along x and only
-// the work-groups whose linear index is congruent to the instance modulo 8 work: work-groups are
-// placed on the 8 XCDs round-robin by linear index, so an instance's work stays on one XCD and its
-// reflectors are fetched into one L2 (measured at s = 128: 2.9 -> 0.9 MB of HBM traffic per solve;
-// the single-workgroup reduction of instance b runs on XCD b mod 8 as well). Large Grams, whose
-// back-transformation needs more than one XCD's compute units, and batches of 8 or more instances,
-// which spread over the XCDs anyway, use plain grids (spread = 1).
-static constexpr int XCD_SPREAD = 8;
-__device__ __forceinline__ bool xcd_own(int spread) {
-  return (int)(blockIdx.x % spread) == (int)(blockIdx.y % spread);
 }
 
 // ---- eigenvalues: one wave per eigenvalue -------------------------------------------------------
@@ -1395,11 +1238,17 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
   if (a0.s <= 0 || a0.kmax <= 0 || a0.kmax > a0.s || a0.batch <= 0) return hipErrorInvalidValue;
   EigArgs a = a0;
   a.spread = a.s <= 256 && a.batch < XCD_SPREAD ? XCD_SPREAD : 1;
+  if (!eig_size_supported(a.s) || (a.s > EIG_LDS_MAX && a.reduction == 1 && !mw_size_supported(a.s)))
+    return hipErrorInvalidValue;
+  const bool two_stage = a.s > EIG_LDS_MAX && a.reduction == 0;
   if (a.s <= EIG_LDS_MAX) {
     const size_t lds = eig_lds_bytes(a.s);
     (void)hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
     hipLaunchKernelGGL(k_tridiag, dim3(a.batch), dim3(EIG_THREADS), lds, st, a);
+  } else if (two_stage) {
+    const hipError_t z = launch_band_reduction(a, st);
+    if (z != hipSuccess) return z;
   } else {
     const MwShape m = mw_shape(a.s);
     const size_t lds = mw_lds_bytes(a.s);
@@ -1445,6 +1294,7 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
                      ldsc, st, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (two_stage) return launch_bt_band(a, st);
   const dim3 gb(a.spread * ((a.kmax + 3) / 4), a.batch);
   if (a.s <= 64) {
     hipLaunchKernelGGL((k_backtransform<1, 4>), gb, dim3(256), 0, st, a);

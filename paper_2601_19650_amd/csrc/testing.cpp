@@ -135,8 +135,18 @@ extern "C" int cbc_test_gemm_time(int M, int N, int K, int a_c128, int b_c128, i
   return rc;
 }
 
+extern "C" int cbc_test_eig_reduction(void* G, int s, int kmax, double tol, int reduction, void* U,
+                                      void* lam, void* kkeep, void* inv_sqrt_l0, void* tstamp,
+                                      void* stream);
 extern "C" int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void* lam, void* kkeep,
                             void* inv_sqrt_l0, void* tstamp, void* stream) {
+  return cbc_test_eig_reduction(G, s, kmax, tol, 0, U, lam, kkeep, inv_sqrt_l0, tstamp, stream);
+}
+
+extern "C" int cbc_test_eig_reduction(void* G, int s, int kmax, double tol, int reduction, void* U,
+                                      void* lam, void* kkeep, void* inv_sqrt_l0, void* tstamp,
+                                      void* stream) {
+  if (reduction != 0 && reduction != 1) return CBC_EINVAL;
   if (!G || !U || !lam || !kkeep || !inv_sqrt_l0 || s < 1 || kmax < 1 || kmax > s) return CBC_EINVAL;
   double* w = nullptr;
   if (hipMalloc(&w, eig_work_doubles(s, kmax) * sizeof(double)) != hipSuccess) return CBC_ENOMEM;
@@ -147,6 +157,7 @@ extern "C" int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void*
   a.tstamp = (long long*)tstamp;
   a.batch = 1;
   a.bs = 0;
+  a.reduction = reduction;
   int rc = CBC_OK;
   if (launch_eig(a, st) != hipSuccess) rc = CBC_EHIP;
   else if (hipStreamSynchronize(st) != hipSuccess) rc = CBC_EHIP;
@@ -195,7 +206,11 @@ extern "C" int cbc_test_eig_report(void* G, int s, int kmax, double tol, int for
   a.rec = (cbc_trunc_record*)rec;
   a.rec_node = 7;
   a.rec_sweep = 2;
-  if (force_timeout) a.timeout_ticks = -1;
+  if (force_timeout) {
+    // the time-out path exists only in the multi-workgroup reduction
+    a.timeout_ticks = -1;
+    a.reduction = 1;
+  }
   int rc = CBC_OK;
   if (launch_eig(a, st) != hipSuccess) rc = CBC_EHIP;
   else if (hipStreamSynchronize(st) != hipSuccess) rc = CBC_EHIP;

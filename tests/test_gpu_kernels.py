@@ -83,14 +83,21 @@ def herm_psd(rng, s, rank=None, n=None):
     return m @ m.conj().T
 
 
-@pytest.mark.parametrize("s,kmax", [(1, 1), (2, 1), (2, 2), (7, 3), (64, 32), (128, 64), (200, 100),
-                                    (96, 96), (129, 64), (300, 300), (520, 128), (1024, 256),
-                                    (1100, 64)])
-def test_eig_topk(lib, s, kmax):
-    print(f"eig s={s} kmax={kmax}", flush=True)
+EIG_CASES = [(1, 1), (2, 1), (2, 2), (7, 3), (64, 32), (128, 64), (200, 100), (96, 96), (129, 64),
+             (130, 130), (145, 17), (300, 300), (520, 128), (1024, 256), (1100, 64), (1040, 200),
+             (1041, 100), (1500, 256), (2064, 64)]
+
+
+@pytest.mark.parametrize("s,kmax,reduction",
+                         [(s, k, 0) for s, k in EIG_CASES] + [(200, 100, 1), (700, 200, 1)])
+def test_eig_topk(lib, s, kmax, reduction):
+    """Top-kmax eigenpairs against numpy.linalg.eigh: the single-workgroup reduction (s <= 128), the
+    two-stage reduction (above; panels of up to 1024 and up to 2048 rows, band edges) and, for
+    comparison, the one-stage multi-workgroup reduction (third parameter 1)."""
+    print(f"eig s={s} kmax={kmax} reduction={reduction}", flush=True)
     rng = np.random.default_rng(s)
     g = herm_psd(rng, s)
-    U, lam, kk, inv = lib.test_eig(torch.from_numpy(g).cuda(), kmax)
+    U, lam, kk, inv = lib.test_eig(torch.from_numpy(g).cuda(), kmax, reduction=reduction)
     U = U.cpu().numpy()
     lam = lam.cpu().numpy()
     w, v = np.linalg.eigh(g)
@@ -110,8 +117,8 @@ def test_eig_topk(lib, s, kmax):
 
 
 def test_eig_multi_workgroup_repeatable(lib):
-    """The multi-workgroup reduction (s > 128) sums in a fixed order: repeated solves of the same
-    matrix are bitwise identical and match the reference."""
+    """The two-stage reduction (s > 128) sums in a fixed order: repeated solves of the same matrix
+    are bitwise identical and match the reference."""
     rng = np.random.default_rng(21)
     s, kmax = 700, 200
     g = herm_psd(rng, s)
@@ -144,11 +151,13 @@ def test_eig_rank_deficient_and_tol(lib):
 
 
 @pytest.mark.parametrize("s,kind", [(5, "diagonal"), (40, "diagonal"), (128, "diagonal"),
-                                    (40, "blocks"), (128, "blocks"), (200, "blocks")])
+                                    (40, "blocks"), (128, "blocks"), (200, "blocks"),
+                                    (300, "diagonal"), (333, "blocks")])
 def test_eig_structured(lib, s, kind):
     """Grams whose reduction meets columns with nothing below the diagonal (a reflector that is the
     identity, tau = 0): a diagonal Gram (every column) and a block-diagonal one (the last column of
-    every block), in the single-workgroup and the multi-workgroup reductions."""
+    every block), in the single-workgroup and the two-stage reductions (zero panels and zero band
+    columns)."""
     print(f"eig structured s={s} {kind}", flush=True)
     rng = np.random.default_rng(40 + s)
     if kind == "diagonal":

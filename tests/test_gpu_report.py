@@ -29,14 +29,21 @@ def test_report_records_match_oracle(lib, prec):
     # the oracle truncates at every site of the forward sweep; the library only where the joined
     # leg exceeds max_bond (elsewhere L' is kept as it is, which discards nothing)
     cut = {i + 1: s for i, s in enumerate(rec) if len(s) > p.max_bond}
-    assert sorted(t["node"] for t in r["trunc"]) == sorted(cut)
+    # the library also factorises the smaller-side Gram where it is already no larger than max_bond
+    # (a change of basis of the new leg that discards nothing); such records keep every direction
+    nodes = sorted(t["node"] for t in r["trunc"])
+    assert set(cut) <= set(nodes) and len(set(nodes)) == len(nodes)
     tol = 1e-12 if prec == "fp64" else 1e-5
     for t in r["trunc"]:
-        s = cut[t["node"]]
+        s = rec[t["node"] - 1]
         lam = s ** 2
+        assert t["sweep"] == 2 and t["dim"] == len(s)
+        if t["node"] not in cut:
+            assert t["kmax"] == t["kept"] == t["dim"] <= p.max_bond
+            assert abs(t["discarded"]) <= tol and t["gap"] == 1.0
+            continue
         k = p.max_bond
-        assert t["sweep"] == 2 and t["kmax"] == k and t["kept"] == k
-        assert t["dim"] == len(s)
+        assert t["kmax"] == k and t["kept"] == k
         assert abs(t["discarded"] - lam[k:].sum() / lam.sum()) <= tol
         assert abs(t["gap"] - (lam[k - 1] - lam[k]) / lam[k - 1]) <= 1e3 * tol + 1e-9
         assert t["flags"] == 0
@@ -135,6 +142,8 @@ def test_multiworkgroup_solves_are_chained_in_a_capture(lib, tmp_path):
         g.debug_dump(path)
     except Exception as e:          # pragma: no cover
         pytest.skip(f"graph debug dump unavailable: {e}")
+    if not os.path.exists(path):
+        pytest.skip("torch's graph debug dump wrote no file on this ROCm build")
     text = open(path).read()
     nodes = {}
     for m in re.finditer(r'"?(\w+)"?\s*\[([^\]]*)\]', text):
