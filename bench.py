@@ -1,11 +1,13 @@
 #!/usr/bin/env python
 """Benchmark of the CBC hot path on one MI355X.
 
-Workload (default): the 64-site MPS of the paper's random-network benchmark shape, d=2, state bond
-chi=64, MPO bond D=8, complex Gaussian entries, target bond 64 (truncating 512 -> 64). One step is one
-complete compression (forward and backward sweeps, every truncation and QR) of that input, already
-resident in HBM. The headline value is compressions/s of the mixed form (FP32 MFMA contractions,
-FP64 Gram/eigen/Cholesky); the plain FP64 form is timed beside it on the same input.
+Workload (default): the large-bond MPS, N=128 sites, d=4, state bond chi=256, MPO bond D=16,
+complex Gaussian entries, target bond 256 (truncating 4096 -> 256 at every bulk site). One step is
+one complete compression (forward and backward sweeps, every truncation and QR) of that input,
+already resident in HBM. The headline value is compressions/s of the mixed form (FP32 MFMA
+contractions, FP64 Gram/eigen/Cholesky); the plain FP64 form is timed beside it on the same input.
+The smaller workloads (8-site exact chain, 64-site chain, 31-node binary tree), the naive baseline,
+batched and uneven batches are reported beside the headline.
 
 Prints one JSON line. `--gpus N` with N > 1 is refused: the library runs on one GPU.
 """
@@ -25,10 +27,10 @@ PEAK = {  # MI355X published dense peaks
     "fp32_mfma": 157.3e12, "fp64_mfma": 78.6e12, "fp64_alu": 78.6e12, "hbm": 8.0e12,
 }
 WORKLOADS = {
-    "C2": "MPS N=64 d=2 chi=64 D=8 max_bond=64 (truncating), complex Gaussian",
-    "C1": "MPS N=8 d=2 chi=8 D=4 max_bond=32 (exact)",
-    "C3": "binary tree 31 nodes d=2 chi=32 D=6 max_bond=32",
-    "C4": "MPS N=128 d=4 chi=256 D=16 max_bond=256 (large bond), complex Gaussian",
+    "C4": "MPS N=128 d=4 chi=256 D=16 max_bond=256 (large bond, truncating 4096 -> 256), complex Gaussian",
+    "C2": "MPS N=64 d=2 chi=64 D=8 max_bond=64 (truncating 512 -> 64), complex Gaussian",
+    "C1": "MPS N=8 d=2 chi=8 D=4 max_bond=32 (exact), complex Gaussian",
+    "C3": "binary tree 31 nodes d=2 chi=32 D=6 max_bond=32, complex Gaussian",
 }
 
 
@@ -81,31 +83,31 @@ def contraction_roofline(r, prec, cls):
             "flops_per_step": flops}
 
 
-def large_run(cbc, stream, steps):
-    """The large-bond workload (MPS N=128, d=4, chi=256, D=16, max_bond=256): both precisions,
-    compressions/s, contraction throughput against the MFMA peaks, and the mixed result against the
-    FP64 result (both from the GPU; the oracle needs minutes here)."""
-    from paper_2601_19650_amd.inputs import config_problem
-    p = config_problem("C4")
-    res, outputs = measure(cbc, p, ["mixed", "fp64"], steps, 1, stream)
-    cls = cbc.CLASSES
-    out = {"workload": WORKLOADS["C4"], "steps": steps}
-    for prec in ("mixed", "fp64"):
-        r = res[prec]
-        out[prec] = {"value": 1.0 / r["sec"], "unit": "compressions/s", "ms_per_step": r["sec"] * 1e3,
-                     "contraction_tflops_wall": r["stats"]["contract"]["flops"] / r["sec"] / 1e12,
-                     "contraction_roofline": contraction_roofline(r, prec, cls),
-                     "kernel_ms_per_step": {cls[k]: r["kms"][k] for k in range(cbc.NCLASS)},
-                     "kernels_per_step": r["n_kernels"]}
-    out["speedup_mixed_vs_fp64"] = res["fp64"]["sec"] / res["mixed"]["sec"]
-    # At 128 sites the compressed state is ill-conditioned (a rounding-level input change grows by
-    # ~1.4x per site), so mixed and FP64 results are compared by the weight they capture; the
-    # non-root nodes are isometries, so ||psi'||^2 is the root's squared norm.
-    w = {k: float(sum(abs(x) ** 2 for x in v[0].reshape(-1))) for k, v in outputs.items()}
-    out["captured_weight"] = w
-    out["captured_weight_ratio_mixed_vs_fp64"] = w["mixed"] / w["fp64"]
-    out["mixed_fidelity_vs_fp64"] = _chain_fidelity(outputs["mixed"], outputs["fp64"])
-    return out
+def precision_line(r, prec, cls, ncls):
+    """Compressions/s, contraction throughput and kernel-class times of one measured precision."""
+    return {"value": 1.0 / r["sec"], "unit": "compressions/s", "ms_per_step": r["sec"] * 1e3,
+            "contraction_tflops_wall": r["stats"]["contract"]["flops"] / r["sec"] / 1e12,
+            "contraction_roofline": contraction_roofline(r, prec, cls),
+            "kernel_ms_per_step": {cls[k]: r["kms"][k] for k in range(ncls)},
+            "kernels_per_step": r["n_kernels"]}
+
+
+def gpu_vs_oracle(cbc, p, ref, precs=("fp64", "mixed")):
+    """Error of each GPU precision against an oracle result `ref` of the same problem."""
+    from oracle import tn
+    errs = {}
+    for prec in precs:
+        out, _ = cbc.compress(p, precision=prec, device="cuda:0")
+        errs[prec] = dict(rel_state_error=tn.rel_error(p.parent, out, ref),
+                          infidelity=1.0 - tn.fidelity(p.parent, out, ref))
+    return errs
+
+
+def oracle_result(p):
+    from oracle import cbc_tree, cbc_tt, tn
+    if all(q == i - 1 for i, q in enumerate(p.parent)):
+        return tn.mps_to_tree(cbc_tt(tn.tree_to_mps(p.state), tn.tree_to_mpo(p.op), p.max_bond))
+    return cbc_tree(p.parent, p.state, p.op, p.max_bond)
 
 
 def _chain_fidelity(a, b):
@@ -179,37 +181,92 @@ def profiled_runs(comp, args_run, stream, steps):
     return [t / steps for t in tot]
 
 
-def cpu_baseline(p, gpu_outputs, budget_s=20.0):
-    """The oracle on the host cores (all of them), bounded to ~budget_s; also the error of each GPU
-    output against the oracle's result."""
-    import numpy as np  # noqa: F401
+def cpu_baseline_large(cbc):
+    """The oracle on the large-bond workload, timed on a bounded sample: the same chain shape cut to
+    10 and 11 sites (the 11th adds one bulk site with bonds 256 on both sides), on all host cores and
+    on one thread. The full 128-site compression is extrapolated as t(11) + 117 (t(11) - t(10)),
+    i.e. every further site at the measured bulk-site cost. The GPU results of the 10-site problem
+    are compared with the oracle's (error_vs_oracle)."""
     from threadpoolctl import threadpool_info, threadpool_limits
-    from oracle import cbc_tree, cbc_tt, tn
+    from paper_2601_19650_amd.inputs import config_problem
     ncores = len(os.sched_getaffinity(0))
-    chain = all(q == i - 1 for i, q in enumerate(p.parent))
-    with threadpool_limits(limits=ncores):
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-        times = []
-        ref = None
-        t_start = time.perf_counter()
-        while True:
-            t0 = time.perf_counter()
-            if chain:
-                ref = tn.mps_to_tree(cbc_tt(tn.tree_to_mps(p.state), tn.tree_to_mpo(p.op), p.max_bond))
-            else:
-                ref = cbc_tree(p.parent, p.state, p.op, p.max_bond)
-            times.append(time.perf_counter() - t0)
-            if time.perf_counter() - t_start > budget_s * 0.5 or len(times) >= 20:
-                break
-    med = sorted(times)[len(times) // 2]
-    errs = {}
-    for prec, out in gpu_outputs.items():
-        errs[prec] = dict(rel_state_error=tn.rel_error(p.parent, out, ref),
-                          infidelity=1.0 - tn.fidelity(p.parent, out, ref))
-    return dict(value=1.0 / med, unit="compressions/s", cores=int(threads), kind="oracle",
-                sample=f"{len(times)} full compressions of the same workload (median "
-                       f"{med:.2f} s each, NumPy complex128, {'tensor-train' if chain else 'tree'} "
-                       f"sweep)"), errs
+    legs = {}
+    refs = {}
+    for label, lim in (("all_cores", ncores), ("one_thread", 1)):
+        with threadpool_limits(limits=lim):
+            threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+            t = {}
+            for n in (10, 11):
+                p = config_problem("C4", n=n)
+                t0 = time.perf_counter()
+                refs[n] = oracle_result(p)
+                t[n] = time.perf_counter() - t0
+        site = max(t[11] - t[10], 0.0)
+        full = t[11] + (128 - 11) * site
+        legs[label] = {"value": 1.0 / full, "unit": "compressions/s", "cores": int(threads),
+                       "seconds_per_compression": full, "seconds_10_sites": t[10],
+                       "seconds_11_sites": t[11], "seconds_per_bulk_site": site}
+        print(f"[bench] oracle {label} ({threads} threads): 10 sites {t[10]:.2f} s, 11 sites "
+              f"{t[11]:.2f} s, 128 sites extrapolated {full:.0f} s", file=sys.stderr, flush=True)
+    errs = gpu_vs_oracle(cbc, config_problem("C4", n=10), refs[10])
+    a = legs["all_cores"]
+    return {"value": a["value"], "unit": "compressions/s", "cores": a["cores"], "kind": "oracle",
+            "sample": "NumPy complex128 oracle (tensor-train sweep) on the large-bond chain cut to 10 "
+                      "and 11 sites; the 128-site time extrapolated as t(11) + 117 x (t(11) - t(10)) "
+                      "(one bulk site per step)",
+            "one_thread": legs["one_thread"], "all_cores": a}, errs
+
+
+def small_workload(cbc, name, stream, steps, precs=("mixed", "fp64")):
+    """A latency-bound workload (C1, C2 or C3): compressions/s per precision and the error of each
+    GPU result against the oracle (the 8-site exact chain also against the dense product O|psi>)."""
+    from oracle import tn
+    from paper_2601_19650_amd.inputs import config_problem
+    p = config_problem(name)
+    res, outputs = measure(cbc, p, list(precs), steps, 2, stream)
+    t0 = time.perf_counter()
+    ref = oracle_result(p)
+    t_oracle = time.perf_counter() - t0
+    line = {"workload": WORKLOADS[name]}
+    for prec in precs:
+        r = res[prec]
+        line[prec] = {"value": 1.0 / r["sec"], "unit": "compressions/s",
+                      "ms_per_step": r["sec"] * 1e3,
+                      "kernel_ms_per_step": {cbc.CLASSES[k]: r["kms"][k] for k in range(cbc.NCLASS)},
+                      "kernels_per_step": r["n_kernels"],
+                      "error_vs_oracle": dict(
+                          rel_state_error=tn.rel_error(p.parent, outputs[prec], ref),
+                          infidelity=1.0 - tn.fidelity(p.parent, outputs[prec], ref))}
+    if "mixed" in res and "fp64" in res:
+        line["speedup_mixed_vs_fp64"] = res["fp64"]["sec"] / res["mixed"]["sec"]
+    line["oracle_seconds_per_compression"] = t_oracle
+    if name == "C1":
+        phi = tn.apply_dense(p.parent, p.op, tn.to_dense(p.parent, p.state))
+        for prec in precs:
+            v = tn.to_dense(p.parent, outputs[prec])
+            line[prec]["rel_error_vs_dense_product"] = float(
+                __import__("numpy").linalg.norm(v - phi) / __import__("numpy").linalg.norm(phi))
+    return line
+
+
+def naive_run(cbc, name, stream, steps):
+    """The naive contract-then-SVD baseline (Sec. III C) timed on the GPU beside CBC."""
+    from paper_2601_19650_amd.inputs import config_problem
+    p = config_problem(name)
+    tree = cbc.Tree.of(p)
+    st, so = cbc.pack(p.state, "cuda:0")
+    op, oo = cbc.pack(p.op, "cuda:0")
+    ctx = new_context(cbc)
+    out = {"workload": WORKLOADS[name]}
+    for prec in ("mixed", "fp64"):
+        comp = cbc.Compressor(ctx, tree, p.max_bond, prec, method="naive", device="cuda:0")
+        sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, 2)
+        out[prec] = {"value": 1.0 / sec, "unit": "compressions/s", "ms_per_step": sec * 1e3,
+                     "workspace_gb": comp.ws_bytes / 1e9}
+        print(f"[bench] naive {name} {prec}: {sec * 1e3:.3f} ms/compression", file=sys.stderr,
+              flush=True)
+        del comp
+    return out
 
 
 def batched_run(args, cbc, p, stream):
@@ -217,13 +274,13 @@ def batched_run(args, cbc, p, stream):
     (mixed precision), inputs resident in HBM."""
     import torch
     from paper_2601_19650_amd.inputs import config_problem
-    probs = [p] + [config_problem(args.workload, seed=1000 + b) for b in range(1, args.batch)]
+    probs = [p] + [config_problem(p.name, seed=1000 + b) for b in range(1, args.batch)]
     tree = cbc.Tree.of(p)
     st, so = cbc.pack_batch([q.state for q in probs], "cuda:0")
     op, oo = cbc.pack_batch([q.op for q in probs], "cuda:0")
     ctx = new_context(cbc)
     comp = cbc.Compressor(ctx, tree, p.max_bond, "mixed", device="cuda:0", batch=args.batch)
-    steps = max(2, args.steps // 4)
+    steps = max(2, args.small_steps // 4)
     sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, 1)
     print(f"[bench] batched x{args.batch}: {sec * 1e3:.3f} ms per launch sequence", file=sys.stderr,
           flush=True)
@@ -263,18 +320,18 @@ def uneven_run(count, stream_count=8):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--steps", type=int, default=3,
+                    help="timed compressions of the headline workload per precision")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="C4", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["mixed", "fp64"], default=None)
+    ap.add_argument("--small-steps", type=int, default=20,
+                    help="timed compressions of the 8-site, 64-site and tree workloads (0: skip)")
     ap.add_argument("--batch", type=int, default=64,
-                    help="instances per launch sequence for the batched measurement (0: skip)")
+                    help="instances of the 64-site shape per launch sequence (0: skip)")
     ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven batch workload to time (0: skip)")
-    ap.add_argument("--large-steps", type=int, default=2,
-                    help="also time the large-bond workload (MPS N=128, d=4, chi=256) for this many "
-                         "steps per precision (0: skip)")
     ap.add_argument("--autotune", choices=["on", "off"], default="on",
                     help="tune the contractions' tile and split per shape before timing (cbc_autotune)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -352,20 +409,34 @@ def main():
         "graph_replayed": r["replayed"],
     }
     if "fp64" in res and "mixed" in res:
-        line["fp64"] = {"value": 1.0 / res["fp64"]["sec"], "ms_per_step": res["fp64"]["sec"] * 1e3,
-                        "kernel_ms_per_step": {cls[k]: res["fp64"]["kms"][k]
-                                               for k in range(cbc.NCLASS)}}
+        line["fp64"] = precision_line(res["fp64"], "fp64", cls, cbc.NCLASS)
         line["speedup_mixed_vs_fp64"] = res["fp64"]["sec"] / res["mixed"]["sec"]
+        if args.workload == "C4":
+            # At 128 sites the compressed state is ill-conditioned (a rounding-level input change
+            # grows ~1.6x per site), so mixed and FP64 results are compared by the weight they
+            # capture; the non-root nodes are isometries, so ||psi'||^2 is the root's squared norm.
+            w = {k: float(sum(abs(x) ** 2 for x in v[0].reshape(-1))) for k, v in outputs.items()}
+            line["full_size_mixed_vs_fp64"] = {
+                "captured_weight": w, "captured_weight_ratio": w["mixed"] / w["fp64"],
+                "fidelity": _chain_fidelity(outputs["mixed"], outputs["fp64"])}
+    del outputs
+    if args.small_steps > 0:
+        line["small_workloads"] = {}
+        for name in ("C1", "C2", "C3"):
+            if name == args.workload:
+                continue
+            line["small_workloads"][name] = small_workload(cbc, name, stream, args.small_steps)
+            print(f"[bench] {name}: mixed {line['small_workloads'][name]['mixed']['value']:.1f} "
+                  f"compressions/s", file=sys.stderr, flush=True)
+        line["naive_baseline"] = naive_run(cbc, "C2", stream, max(2, args.small_steps // 4))
     if args.batch > 1:
-        line["batched"] = batched_run(args, cbc, p, stream)
+        line["batched"] = batched_run(args, cbc, config_problem("C2"), stream)
     if args.uneven > 0:
         line["uneven_batch"] = uneven_run(args.uneven)
-    if args.large_steps > 0 and args.workload != "C4":
-        line["large_bond"] = large_run(cbc, stream, args.large_steps)
-    if not args.no_cpu_baseline:
-        cb, errs = cpu_baseline(p, outputs)
+    if not args.no_cpu_baseline and args.workload == "C4":
+        cb, errs = cpu_baseline_large(cbc)
         line["cpu_baseline"] = cb
-        line["error_vs_oracle"] = errs
+        line["error_vs_oracle"] = {"C4 shape, 10 sites": errs}
     print(json.dumps(line))
 
 

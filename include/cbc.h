@@ -50,12 +50,17 @@
  * argument validation happens on the host before any device work is queued. Failures that can only
  * be seen on the device are recorded in a status word in the call's workspace and read, after the
  * call has finished, with cbc_read_report: a factorisation or eigensolve that meets non-finite
- * values (CBC_ENOTPD), or a bounded wait that expired (CBC_ETIMEOUT). Truncation Gram matrices of
- * dimension above 128 are solved by up to 256 cooperating workgroups that must be resident
- * together. The library orders these solves one after another on each device, across streams and
- * contexts of the process (stream-ordered waits on one device-wide event, also inside graph
- * captures), and their waits are bounded (2 s), so a device shared with other spinning work cannot
- * hang the call: it ends with CBC_ETIMEOUT in the report instead.
+ * values (CBC_ENOTPD), or a bounded wait that expired (CBC_ETIMEOUT).
+ *
+ * Eigensolves (Grams of dimension s): s <= 128 run in one workgroup. Larger Grams of a single
+ * instance queued eagerly or in the library's own graphs use a Householder reduction spread over up
+ * to 256 workgroups that wait for each other (s <= 1272); the library orders these solves one after
+ * another on each device (a device-wide event, across streams and contexts of the process), and
+ * their waits are bounded (2 s), so a device shared with other spinning work cannot hang the call:
+ * it ends with CBC_ETIMEOUT in the report instead. Batches, calls recorded into a caller's stream
+ * capture and Grams above 1272 (up to 2064) use a two-stage reduction (dense to
+ * band on FP64 matrix cores, band to tridiagonal in one workgroup) that has no waits between
+ * workgroups; nothing is recorded into a caller's capture beyond the call's own kernels.
  */
 #ifndef CBC_H
 #define CBC_H

@@ -1139,6 +1139,9 @@ struct Call {
   // batch: instance b uses every buffer advanced by b times its per-instance byte stride
   int batch = 1;
   int64_t ws_inst = 0, st_inst = 0, op_inst = 0, out_inst = 0;
+  bool caller_capture = false;   // recorded into a stream capture of the caller's: eigensolves
+                                 // take the two-stage reduction
+  const int32_t* tables = nullptr;   // device copy of the plan's offset tables
 };
 
 }  // namespace
@@ -1199,12 +1202,12 @@ GemmArgs gemm_args(const Plan& P, const Call& c, const Op& op, int ksplit) {
   g.M = op.M;
   g.N = op.N;
   g.K = op.K;
-  g.offAm = P.d_tables + op.tAm;
-  g.offAk = P.d_tables + op.tAk;
-  g.offBk = P.d_tables + op.tBk;
-  g.offBn = P.d_tables + op.tBn;
-  g.offCm = P.d_tables + op.tCm;
-  g.offCn = P.d_tables + op.tCn;
+  g.offAm = c.tables + op.tAm;
+  g.offAk = c.tables + op.tAk;
+  g.offBk = c.tables + op.tBk;
+  g.offBn = c.tables + op.tBn;
+  g.offCm = c.tables + op.tCm;
+  g.offCn = c.tables + op.tCn;
   g.conjA = op.conjA;
   g.conjB = op.conjB;
   g.a_kfast = op.akf;
@@ -1259,6 +1262,7 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
         a.rec = (cbc_trunc_record*)resolve(P, c, op.rec);
         a.rec_node = op.rec_node;
         a.rec_sweep = op.rec_sweep;
+        a.reduction = eig_pick_reduction(op.s, c.batch, c.caller_capture);
         e = launch_eig(a, st);
         break;
       }
@@ -1607,11 +1611,13 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   s = get_plan(ctx, pr, max_bond, tol > 0.0, prec, method, se, oe, &P);
   if (s != CBC_OK) return s;
   const size_t ws_inst = P->persist_bytes + P->scratch_bytes;
+  hipStream_t st = (hipStream_t)stream;
   if (!workspace || workspace_bytes / (size_t)batch < ws_inst) return CBC_ENOMEM;
   for (int i = 0; i <= pr.n; ++i)
     if (out->offset[i] != P->out_off[i]) return CBC_EINVAL;
   s = upload_tables(P);
   if (s != CBC_OK) return s;
+  const int32_t* tables = P->d_tables;
   // tolerance is a per-call value carried by the eigensolve ops
   for (auto& op : P->ops)
     if (op.kind == K_EIG) op.shift_rel = tol;
@@ -1629,7 +1635,7 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   c.st_inst = 16 * se;
   c.op_inst = 16 * oe;
   c.out_inst = 16 * P->out_off[pr.n];
-  hipStream_t st = (hipStream_t)stream;
+  c.tables = tables;
   const bool profile = stats && stats->profile;
   int replayed = 0;
   if (P->tune && ctx->tune && P->tuned_batch != batch && !(st != nullptr && capturing(st))) {
@@ -1648,6 +1654,7 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
     if (run_ops(*P, c, st, P->events.data()) != hipSuccess) return CBC_EHIP;
   } else if (st != nullptr && capturing(st)) {
     // the caller is capturing this stream into a graph of its own: record the kernels into it
+    c.caller_capture = true;
     if (run_ops(*P, c, st) != hipSuccess) return CBC_EHIP;
   } else if (st != nullptr) {
     // replay a captured graph of the whole launch sequence when the buffers are unchanged

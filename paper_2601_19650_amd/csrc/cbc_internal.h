@@ -94,19 +94,23 @@ struct EigArgs {
   // negative value makes the first wait give up at once (tests of the status path)
   long long timeout_ticks = 200000000LL;
   // reduction to tridiagonal form for s > 128: 0 = two-stage (dense -> band -> tridiagonal),
-  // 1 = one-stage multi-workgroup (s <= 1272; kept for comparison)
+  // 1 = one-stage multi-workgroup (s <= 1272, see eig_pick_reduction)
   int reduction = 0;
 };
 size_t eig_work_doubles(int s, int kmax);
 // largest Gram the eigensolver handles (the multi-workgroup reduction keeps its rows in LDS)
 bool eig_size_supported(int s);
-// the eigensolve of an s x s Gram needs workgroups that wait for each other (must run alone)
+// reduction for a solve of this size (EigArgs::reduction): 1 (one-stage, multi-workgroup) for a
+// single instance outside a caller's stream capture where it applies, otherwise 0 (two-stage)
+int eig_pick_reduction(int s, int batch, bool caller_capture);
+// a solve of this size may take the multi-workgroup reduction, whose workgroups wait for each
+// other (its eager launches and the graphs holding it are ordered device-wide)
 bool eig_needs_gate(int s);
 hipError_t launch_eig(const EigArgs& a, hipStream_t st);
 
 // Device-wide order of the solves whose workgroups wait for each other: mw_gate_enter makes `st`
-// wait for the previous such solve on the current device if that was queued on another stream
-// (eagerly, or in the same graph capture as `st`), mw_gate_leave records the solve just queued.
+// wait for the previous such solve queued eagerly on the current device from another stream,
+// mw_gate_leave records the one just queued. Both do nothing on a capturing stream.
 hipError_t mw_gate_enter(hipStream_t st);
 hipError_t mw_gate_leave(hipStream_t st);
 

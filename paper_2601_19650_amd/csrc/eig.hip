@@ -344,49 +344,49 @@ size_t mw_lds_bytes(int s) { return (size_t)(mw_shape(s).rows + 2) * s * 16; }
 // the two-stage path: panels of up to 2048 rows (two per thread of the panel kernel)
 static constexpr int EIG_MAX_S = 2048 + 16;
 bool eig_size_supported(int s) { return s >= 1 && s <= EIG_MAX_S; }
-// only the one-stage multi-workgroup reduction (selected explicitly) has cross-workgroup waits
-bool eig_needs_gate(int s) { (void)s; return false; }
 static bool mw_size_supported(int s) {
   return s > EIG_LDS_MAX && s <= MW_EPT * MW_THREADS && mw_shape(s).nwg <= MW_MAX_WG &&
          mw_lds_bytes(s) <= MW_LDS_BUDGET;
 }
+// The one-stage multi-workgroup reduction is the faster one where it applies (measured on MI355X,
+// s = 1024: 17 ms against 27 ms for the two-stage path), but its workgroups wait for each other:
+// it is used for single instances queued eagerly or in the library's own graphs, whose launches
+// the device-wide gate orders; batches and calls recorded into a caller's capture take the
+// two-stage path, which has no cross-workgroup waits.
+int eig_pick_reduction(int s, int batch, bool caller_capture) {
+  return mw_size_supported(s) && batch == 1 && !caller_capture ? 1 : 0;
+}
+bool eig_needs_gate(int s) { return mw_size_supported(s); }
 
 // ---- device-wide order of the multi-workgroup reductions ------------------------------------------
 // Two multi-workgroup reductions running at once on one device could each hold part of the compute
-// units while waiting for workgroups of their own that cannot be placed. Every such launch is
-// therefore ordered after the previous one on the device: eagerly queued launches through one
-// event per device, launches recorded into a graph capture through an event tagged with the
-// capture's id (so a capture never waits on work outside it, and eager launches never wait on a
-// record that only exists inside a graph).
+// units while waiting for workgroups of their own that cannot be placed. Every such launch queued
+// eagerly (a kernel, or a graph of the library's that holds one) is therefore ordered after the
+// previous one on the device through one event per device. Nothing is recorded inside a stream
+// capture: a capture of the library's own is launched as a graph, which is ordered as a whole, and
+// calls recorded into a caller's capture use the two-stage reduction instead.
 namespace {
 constexpr int GATE_MAX_DEV = 64;
-struct GateSide {
-  hipEvent_t ev = nullptr;
-  hipStream_t last = nullptr;
-  unsigned long long id = 0;   // capture id (0: eager)
-  bool valid = false;
-};
 struct Gate {
   std::mutex mu;
-  GateSide eager[GATE_MAX_DEV], capture[GATE_MAX_DEV];
+  hipEvent_t ev[GATE_MAX_DEV] = {};
+  hipStream_t last[GATE_MAX_DEV] = {};
 };
 Gate& gate() {
   static Gate g;
   return g;
 }
-hipError_t gate_state(hipStream_t st, int& dev, bool& cap, unsigned long long& id) {
+hipError_t gate_state(hipStream_t st, int& dev, bool& cap) {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= GATE_MAX_DEV) return hipErrorInvalidDevice;
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  id = 0;
   cap = false;
   if (st != nullptr) {
-    e = hipStreamGetCaptureInfo(st, &cs, &id);
+    e = hipStreamIsCapturing(st, &cs);
     if (e != hipSuccess) return e;
-    cap = cs == hipStreamCaptureStatusActive;
+    cap = cs != hipStreamCaptureStatusNone;
   }
-  if (!cap) id = 0;
   return hipSuccess;
 }
 }  // namespace
@@ -394,37 +394,31 @@ hipError_t gate_state(hipStream_t st, int& dev, bool& cap, unsigned long long& i
 hipError_t mw_gate_enter(hipStream_t st) {
   int dev;
   bool cap;
-  unsigned long long id;
-  hipError_t e = gate_state(st, dev, cap, id);
-  if (e != hipSuccess) return e;
+  hipError_t e = gate_state(st, dev, cap);
+  if (e != hipSuccess || cap) return e;
   Gate& g = gate();
   std::lock_guard<std::mutex> lk(g.mu);
-  GateSide& side = cap ? g.capture[dev] : g.eager[dev];
-  if (side.valid && side.last != st && side.id == id) e = hipStreamWaitEvent(st, side.ev, 0);
+  if (g.ev[dev] && g.last[dev] != st) e = hipStreamWaitEvent(st, g.ev[dev], 0);
   return e;
 }
 
 hipError_t mw_gate_leave(hipStream_t st) {
   int dev;
   bool cap;
-  unsigned long long id;
-  hipError_t e = gate_state(st, dev, cap, id);
-  if (e != hipSuccess) return e;
+  hipError_t e = gate_state(st, dev, cap);
+  if (e != hipSuccess || cap) return e;
   Gate& g = gate();
   std::lock_guard<std::mutex> lk(g.mu);
-  GateSide& side = cap ? g.capture[dev] : g.eager[dev];
-  if (!side.ev) {
-    e = hipEventCreateWithFlags(&side.ev, hipEventDisableTiming);
+  if (!g.ev[dev]) {
+    e = hipEventCreateWithFlags(&g.ev[dev], hipEventDisableTiming);
     if (e != hipSuccess) {
-      side.ev = nullptr;
+      g.ev[dev] = nullptr;
       return e;
     }
   }
-  e = hipEventRecord(side.ev, st);
+  e = hipEventRecord(g.ev[dev], st);
   if (e != hipSuccess) return e;
-  side.last = st;
-  side.id = id;
-  side.valid = true;
+  g.last[dev] = st;
   return hipSuccess;
 }
 

@@ -107,7 +107,7 @@ __device__ __forceinline__ double2 sum16_z(double2 v) { return make_double2(sum1
 // Sixteen doubles summed over the wave by recursive halving: afterwards every lane l holds the wave
 // total of value (l >> 2) & 15 in v[0].
 template <int O, int M>
-__device__ __forceinline__ void halve_stage(double v[16], int lane) {
+__device__ __forceinline__ void halve_stage(double* v, int lane) {
   const bool hi = (lane & O) != 0;
 #pragma unroll
   for (int i = 0; i < M / 2; ++i) {
@@ -115,6 +115,15 @@ __device__ __forceinline__ void halve_stage(double v[16], int lane) {
     const double keep = hi ? v[i + M / 2] : v[i];
     v[i] = keep + __shfl_xor(send, O, 64);
   }
+}
+// Eight doubles: afterwards every lane l holds the wave total of value (l >> 3) & 7 in v[0].
+__device__ __forceinline__ void wave_sum8x(double v[8], int lane) {
+  halve_stage<32, 8>(v, lane);
+  halve_stage<16, 4>(v, lane);
+  halve_stage<8, 2>(v, lane);
+  v[0] += __shfl_xor(v[0], 4, 64);
+  v[0] += __shfl_xor(v[0], 2, 64);
+  v[0] += __shfl_xor(v[0], 1, 64);
 }
 __device__ __forceinline__ void wave_sum16x(double v[16], int lane) {
   halve_stage<32, 16>(v, lane);
@@ -161,18 +170,18 @@ __device__ __forceinline__ void panel_column(PanelState<R>& S, int h, int tid, i
     for (int j = 0; j < NB; ++j) pv[j] = S.P[0][j];
   }
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    double v[16];
+  for (int part = 0; part < 4; ++part) {
+    double v[8];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = 0.0;
+    for (int i = 0; i < 8; ++i) v[i] = 0.0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int r = tid + TH * q;
       if (r > C && r < h) {
         const double2 x = S.P[q][C];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-          const int k = half * 8 + i;
+        for (int i = 0; i < 4; ++i) {
+          const int k = part * 4 + i;
           if (k < 15) {
             // k < C: V_k^H x (reflector k is stored in column k); otherwise x^H a_{k+1}
             const double2 pr = k < C ? cjmul(S.P[q][k < C ? k : 0], x)
@@ -185,8 +194,8 @@ __device__ __forceinline__ void panel_column(PanelState<R>& S, int h, int tid, i
         }
       }
     }
-    wave_sum16x(v, lane);
-    if ((lane & 3) == 0) red[wave][half * 16 + ((lane >> 2) & 15)] = v[0];
+    wave_sum8x(v, lane);
+    if ((lane & 7) == 0) red[wave][part * 8 + ((lane >> 3) & 7)] = v[0];
   }
   __syncthreads();
   if (tid < 32) {
@@ -314,25 +323,31 @@ __global__ __launch_bounds__(TH) void k_band_panel(EigArgs a0, int p) {
 }
 
 // ---- stage 1: X = A22 (V T), one row of X per wave, and partial sums of V^H X per workgroup -------
+// V T is staged through LDS in chunks of 64 rows (transposed, so a wave reads 64 consecutive
+// entries of one column), shared by the workgroup's 16 rows.
 __global__ __launch_bounds__(1024) void k_band_x(EigArgs a0, int p) {
   const EigArgs a = eig_inst(a0, blockIdx.y);
   const int s = a.s;
   const int r0 = (p + 1) * NB, h = s - r0;
   const BandWork B = band_layout(a.work + eig_base_doubles(s, a.kmax), s);
   __shared__ double2 xs[XR][NB];
+  __shared__ double2 vts[NB][64];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = blockIdx.x * XR + wave;
   double2 acc[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) acc[j] = make_double2(0.0, 0.0);
-  if (i < h) {
-    const double2* __restrict__ arow = a.G + (size_t)(r0 + i) * s + r0;
-    for (int k = lane; k < h; k += 64) {
-      const double2 x = arow[k];
-      const double2* __restrict__ vt = B.VT + (size_t)k * NB;
-#pragma unroll
-      for (int j = 0; j < NB; ++j) acc[j] = cfma(x, vt[j], acc[j]);
+  const double2* __restrict__ arow = a.G + (size_t)(r0 + min(i, h - 1)) * s + r0;
+  for (int k0 = 0; k0 < h; k0 += 64) {
+    {
+      const int kk = tid >> 4, j = tid & 15;
+      vts[j][kk] = k0 + kk < h ? B.VT[(size_t)(k0 + kk) * NB + j] : make_double2(0.0, 0.0);
     }
+    __syncthreads();
+    const double2 x = i < h && k0 + lane < h ? arow[k0 + lane] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = cfma(x, vts[j][lane], acc[j]);
+    __syncthreads();
   }
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
@@ -358,7 +373,10 @@ __global__ __launch_bounds__(1024) void k_band_x(EigArgs a0, int p) {
   }
 }
 
-// ---- stage 1: W = X - V (T^H S) / 2 with S = V^H X summed over the workgroups in order ------------
+// ---- stage 1: W = X - V (T^H S) / 2 with S = V^H X summed over the X workgroups in order ----------
+// Every workgroup forms S and M = T^H S / 2 itself (the partial sums stay in L2), then 64 rows of W
+// with 16 threads per row (one column of W each).
+static constexpr int WROWS = 64;
 __global__ __launch_bounds__(1024) void k_band_w(EigArgs a0, int p) {
   const EigArgs a = eig_inst(a0, blockIdx.y);
   const int s = a.s;
@@ -381,18 +399,13 @@ __global__ __launch_bounds__(1024) void k_band_w(EigArgs a0, int p) {
     M[ra][cb] = make_double2(0.5 * acc.x, 0.5 * acc.y);
   }
   __syncthreads();
-  for (int r = tid; r < h; r += blockDim.x) {
+  const int r = blockIdx.x * WROWS + (tid >> 4), cb = tid & 15;
+  if (r < h) {
     double2* z = B.Z + (size_t)r * 3 * NB;
-    double2 ve[NB];
+    double2 w = B.X[(size_t)r * NB + cb];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) ve[k] = z[k];
-#pragma unroll 1
-    for (int cb = 0; cb < NB; ++cb) {
-      double2 w = B.X[(size_t)r * NB + cb];
-#pragma unroll
-      for (int k = 0; k < NB; ++k) w = cfms(ve[k], M[k][cb], w);
-      z[NB + cb] = w;
-    }
+    for (int k = 0; k < NB; ++k) w = cfms(z[k], M[k][cb], w);
+    z[NB + cb] = w;
   }
 }
 
@@ -682,7 +695,7 @@ hipError_t launch_band_reduction(const EigArgs& a, hipStream_t st) {
     hipLaunchKernelGGL(k_band_x, dim3((h + XR - 1) / XR, a.batch), dim3(1024), 0, st, a, p);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_band_w, dim3(1, a.batch), dim3(1024), 0, st, a, p);
+    hipLaunchKernelGGL(k_band_w, dim3((h + WROWS - 1) / WROWS, a.batch), dim3(1024), 0, st, a, p);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     // A22 -= [V | W] [W | V]^H on FP64 matrix cores (accumulating into the trailing matrix)

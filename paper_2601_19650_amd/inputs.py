@@ -31,7 +31,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "chain_parent", "kary_parent", "cut_bonds", "random_problem",
-    "config_problem", "batch_problems", "CONFIGS",
+    "config_problem", "batch_problems", "batch_shapes", "CONFIGS",
 ]
 
 
@@ -221,14 +221,9 @@ def config_problem(name, **over):
                           tol=c.get("tol", 0.0), dist=c.get("dist", "gauss"), name=name)
 
 
-def batch_problems(count=256, seed=5, ternary_chi_cap=32, n_range=(16, 64), chi_range=(16, 128)):
-    """The uneven batch workload: per instance a tensor train, binary or ternary tree with
-    N in n_range, d in {2,4}, chi in chi_range, D in [4,12], max_bond = chi.
-
-    Ternary trees have their chi clamped to ``ternary_chi_cap`` (their nodes carry four virtual
-    legs, so an unclamped draw is dominated by a handful of ternary instances). The same sequence of
-    random draws is used whatever the ranges, so instance j keeps its kind, N, d and D.
-    """
+def batch_shapes(count=256, seed=5, ternary_chi_cap=32, n_range=(16, 64), chi_range=(16, 128)):
+    """The shapes of the uneven batch workload without its tensors: per instance
+    (index, kind, N, d, chi, D, tensor seed), drawn exactly as batch_problems draws them."""
     seeds = np.random.SeedSequence(seed).spawn(count)
     out = []
     for j, ss in enumerate(seeds):
@@ -240,7 +235,26 @@ def batch_problems(count=256, seed=5, ternary_chi_cap=32, n_range=(16, 64), chi_
         D = int(rng.integers(4, 13))
         if kind == "ternary":
             chi = min(chi, ternary_chi_cap)
-        sub_seed = int(rng.integers(0, 2**31 - 1))
+        out.append((j, kind, n, d, chi, D, int(rng.integers(0, 2**31 - 1))))
+    return out
+
+
+def batch_problems(count=256, seed=5, ternary_chi_cap=32, n_range=(16, 64), chi_range=(16, 128),
+                   indices=None):
+    """The uneven batch workload: per instance a tensor train, binary or ternary tree with
+    N in n_range, d in {2,4}, chi in chi_range, D in [4,12], max_bond = chi.
+
+    Ternary trees have their chi clamped to ``ternary_chi_cap`` (their nodes carry four virtual
+    legs, so an unclamped draw is dominated by a handful of ternary instances). The same sequence of
+    random draws is used whatever the ranges, so instance j keeps its kind, N, d and D. ``indices``
+    selects instances of the sequence (each is drawn from its own seed, so a selection holds the
+    same tensors as the full draw); None gives all of them.
+    """
+    out = []
+    for j, kind, n, d, chi, D, sub_seed in batch_shapes(count, seed, ternary_chi_cap, n_range,
+                                                         chi_range):
+        if indices is not None and j not in indices:
+            continue
         out.append(random_problem(_parent_of(kind, n), d, chi, D, chi, sub_seed,
                                   name=f"B{j}:{kind}:n{n}:d{d}:chi{chi}:D{D}"))
     return out

@@ -64,11 +64,14 @@ def test_bad_dims_rejected():
 
 
 def test_oversized_truncation_is_unsupported():
-    """A truncation Gram above the eigensolver's limit (1272) is reported at query time, on the
-    host, as CBC_EUNSUP; the largest-bond workload (Grams of 1024) is accepted."""
-    # two-site chain: the first site's joined leg is d * 1 = 1400 wide against chi * D = 1400
-    big = T([-1, 0], phys=1400, chi=[1, 1400], dop=[1, 1])
+    """A truncation Gram above the eigensolver's limit (2064, the two-stage reduction's panel of
+    2048 rows plus the band) is reported at query time, on the host, as CBC_EUNSUP; Grams at the
+    limit and the largest-bond workload (Grams of 1024) are accepted."""
+    # two-site chain: the first site's joined leg is d * 1 = s wide against chi * D = s
+    big = T([-1, 0], phys=2065, chi=[1, 2065], dop=[1, 1])
     assert _query(big, max_bond=64)[0] == -6
+    edge = T([-1, 0], phys=2064, chi=[1, 2064], dop=[1, 1])
+    assert _query(edge, max_bond=64)[0] == 0
     assert _query(cbc.Tree.of(config_problem("C4", n=10)), max_bond=256)[0] == 0
 
 
