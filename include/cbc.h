@@ -58,7 +58,7 @@
  * another on each device (a device-wide event, across streams and contexts of the process), and
  * their waits are bounded (2 s), so a device shared with other spinning work cannot hang the call:
  * it ends with CBC_ETIMEOUT in the report instead. Batches, calls recorded into a caller's stream
- * capture and Grams above 1272 (up to 2064) use a two-stage reduction (dense to
+ * capture, cbc_apply_noalloc and Grams above 1272 (up to 2064) use a two-stage reduction (dense to
  * band on FP64 matrix cores, band to tridiagonal in one workgroup) that has no waits between
  * workgroups; nothing is recorded into a caller's capture beyond the call's own kernels.
  */
@@ -224,6 +224,21 @@ cbc_status cbc_apply_naive(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tens
                            const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
                            void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
                            cbc_stats* stats);
+
+/* For callers that cannot allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): cbc_apply without a workspace argument. Its workspace is a
+ * static device array of 128 MiB per GPU, held by the library until the process ends; the call
+ * copies the plan's offset tables there (first 256-byte-aligned part) and uses the rest as the
+ * workspace cbc_query reports. It calls no hipMalloc, hipFree or other allocating routine and
+ * launches its kernels directly on `stream` (no graph, no autotuning; truncation eigensolves take
+ * the two-stage reduction). Same arguments and results as cbc_apply otherwise. Returns CBC_EUNSUP
+ * if the tables and the workspace need more than 128 MiB (for example the 64-site and 31-node
+ * workloads fit, the 128-site large-bond one does not), CBC_EINVAL if stats->profile is set.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other host threads) race. The call's report cannot be read with cbc_read_report. */
+cbc_status cbc_apply_noalloc(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                             const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
+                             cbc_out* out, void* stream, cbc_stats* stats);
 
 /* Report of the last call that used `workspace` (cbc_apply, cbc_apply_batched or cbc_apply_naive):
  * synchronises `stream` (the call's stream),

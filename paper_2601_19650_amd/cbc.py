@@ -107,6 +107,11 @@ def lib():
                                         ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(_Out),
                                         ctypes.c_void_p, ctypes.POINTER(Stats)]
         L.cbc_apply_batched.restype = ctypes.c_int
+        L.cbc_apply_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tensors),
+                                        ctypes.POINTER(_Tensors), ctypes.POINTER(_Tree),
+                                        ctypes.c_int32, ctypes.c_double, ctypes.c_int,
+                                        ctypes.POINTER(_Out), ctypes.c_void_p, ctypes.POINTER(Stats)]
+        L.cbc_apply_noalloc.restype = ctypes.c_int
         L.cbc_autotune.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
         L.cbc_autotune.restype = ctypes.c_int
         L.cbc_read_report.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
@@ -117,7 +122,8 @@ def lib():
 
 
 EXPORTED = ("cbc_create", "cbc_destroy", "cbc_status_str", "cbc_query", "cbc_plan_bonds",
-            "cbc_apply", "cbc_apply_batched", "cbc_apply_naive", "cbc_autotune", "cbc_read_report")
+            "cbc_apply", "cbc_apply_batched", "cbc_apply_naive", "cbc_autotune", "cbc_read_report",
+            "cbc_apply_noalloc")
 
 
 def _check(code, what):
@@ -242,6 +248,26 @@ class Compressor:
                   self.max_bond, float(tol), self.prec, self.workspace.data_ptr(), self.ws_bytes,
                   ctypes.byref(out), ctypes.c_void_p(stream), ctypes.byref(self.stats)),
                "cbc_apply" if self.method == 0 else "cbc_apply_naive")
+        return self.out, self.bond
+
+    def run_noalloc(self, op_buf, op_off, st_buf, st_off, tol=0.0, stream=None):
+        """The same compression through cbc_apply_noalloc (the library's static per-GPU scratch
+        instead of this object's workspace); results go to self.out as with run()."""
+        import torch
+        op_off = np.ascontiguousarray(op_off, dtype=np.int64)
+        st_off = np.ascontiguousarray(st_off, dtype=np.int64)
+        I64 = ctypes.POINTER(ctypes.c_int64)
+        ttno = _Tensors(op_buf.data_ptr(), op_off.ctypes.data_as(I64))
+        ttns = _Tensors(st_buf.data_ptr(), st_off.ctypes.data_as(I64))
+        out = _Out(self.out.data_ptr(), self.out_off.ctypes.data_as(I64),
+                   self.bond.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stats.profile = 0
+        _check(lib().cbc_apply_noalloc(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns),
+                                       ctypes.byref(self.tree.c), self.max_bond, float(tol),
+                                       self.prec, ctypes.byref(out), ctypes.c_void_p(stream),
+                                       ctypes.byref(self.stats)), "cbc_apply_noalloc")
         return self.out, self.bond
 
     def report(self, instance=0, stream=None, capacity=4096):

@@ -1139,8 +1139,8 @@ struct Call {
   // batch: instance b uses every buffer advanced by b times its per-instance byte stride
   int batch = 1;
   int64_t ws_inst = 0, st_inst = 0, op_inst = 0, out_inst = 0;
-  bool caller_capture = false;   // recorded into a stream capture of the caller's: eigensolves
-                                 // take the two-stage reduction
+  bool caller_capture = false;   // recorded into a stream capture of the caller's (or a call of
+                                 // cbc_apply_noalloc): eigensolves take the two-stage reduction
   const int32_t* tables = nullptr;   // device copy of the plan's offset tables
 };
 
@@ -1587,8 +1587,9 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
                              const cbc_tree* tree, int32_t max_bond, double tol,
                              cbc_precision prec, void* workspace, size_t workspace_bytes,
                              cbc_out* out, void* stream, cbc_stats* stats, int method,
-                             int32_t batch = 1) {
+                             int32_t batch = 1, bool noalloc = false) {
   if (batch < 1 || batch > 65535) return CBC_EINVAL;
+  if (noalloc && (batch != 1 || (stats && stats->profile))) return CBC_EINVAL;
   if (!ctx || !ttno || !ttns || !out || !ttno->data || !ttns->data || !ttno->offset ||
       !ttns->offset || !out->data || !out->offset || !out->bond)
     return CBC_EINVAL;
@@ -1611,13 +1612,31 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   s = get_plan(ctx, pr, max_bond, tol > 0.0, prec, method, se, oe, &P);
   if (s != CBC_OK) return s;
   const size_t ws_inst = P->persist_bytes + P->scratch_bytes;
+  const int32_t* tables = nullptr;
   hipStream_t st = (hipStream_t)stream;
+  if (noalloc) {
+    // the plan's offset tables, then the workspace, in the static scratch array of this device
+    const size_t tbytes = (P->tables.size() * sizeof(int32_t) + 255) & ~(size_t)255;
+    if (tbytes + ws_inst > NOALLOC_SCRATCH_BYTES) return CBC_EUNSUP;
+    void* base = nullptr;
+    if (noalloc_scratch(&base) != hipSuccess) return CBC_EHIP;
+    workspace = (char*)base + tbytes;
+    workspace_bytes = ws_inst;
+    tables = (const int32_t*)base;
+  }
   if (!workspace || workspace_bytes / (size_t)batch < ws_inst) return CBC_ENOMEM;
   for (int i = 0; i <= pr.n; ++i)
     if (out->offset[i] != P->out_off[i]) return CBC_EINVAL;
-  s = upload_tables(P);
-  if (s != CBC_OK) return s;
-  const int32_t* tables = P->d_tables;
+  if (noalloc) {
+    if (!P->tables.empty() &&
+        hipMemcpyAsync((void*)tables, P->tables.data(), P->tables.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+      return CBC_EHIP;
+  } else {
+    s = upload_tables(P);
+    if (s != CBC_OK) return s;
+    tables = P->d_tables;
+  }
   // tolerance is a per-call value carried by the eigensolve ops
   for (auto& op : P->ops)
     if (op.kind == K_EIG) op.shift_rel = tol;
@@ -1638,13 +1657,19 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   c.tables = tables;
   const bool profile = stats && stats->profile;
   int replayed = 0;
-  if (P->tune && ctx->tune && P->tuned_batch != batch && !(st != nullptr && capturing(st))) {
+  if (!noalloc && P->tune && ctx->tune && P->tuned_batch != batch &&
+      !(st != nullptr && capturing(st))) {
     // the contractions' configurations change: a captured graph of the old ones is dropped
     if (tune_plan(ctx, *P, c, st) != hipSuccess) return CBC_EHIP;
     P->tuned_batch = batch;
     P->drop_graphs();
   }
-  if (profile) {
+  if (noalloc) {
+    // no graph, no tuning, no events and no device-wide gate: the kernels go straight onto the
+    // stream, eigensolves through the two-stage reduction
+    c.caller_capture = true;
+    if (run_ops(*P, c, st) != hipSuccess) return CBC_EHIP;
+  } else if (profile) {
     const size_t ne = 2 * P->ops.size();
     while (P->events.size() < ne) {
       hipEvent_t ev;
@@ -1757,6 +1782,13 @@ cbc_status cbc_apply(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* t
                      cbc_stats* stats) {
   return apply_impl(ctx, ttno, ttns, tree, max_bond, tol, prec, workspace, workspace_bytes, out,
                     stream, stats, 0);
+}
+
+cbc_status cbc_apply_noalloc(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                             const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
+                             cbc_out* out, void* stream, cbc_stats* stats) {
+  return apply_impl(ctx, ttno, ttns, tree, max_bond, tol, prec, nullptr, 0, out, stream, stats, 0,
+                    1, true);
 }
 
 cbc_status cbc_apply_batched(cbc_ctx* ctx, int32_t batch, const cbc_tensors* ttno,

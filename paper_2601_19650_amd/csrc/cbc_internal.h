@@ -152,6 +152,11 @@ constexpr int CHOL_LDS_MAX = 88;
 size_t chol_work_doubles(int k);
 hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st);
 
+// Workspace of cbc_apply_noalloc: a static device array of this many bytes per GPU (noalloc.hip);
+// noalloc_scratch gives its address on the current device.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+hipError_t noalloc_scratch(void** ptr);
+
 // Elementwise helpers.
 // Batched elementwise helpers: instance b uses src + b * ss and dst + b * ds (bytes).
 hipError_t launch_convert(const void* src, DType ts, void* dst, DType td, int64_t n, int batch,
