@@ -10,8 +10,9 @@
 //     Q_p = I - V T V^H (compact WY form, T upper triangular), and the trailing matrix is updated
 //     two-sidedly, A22 <- Q_p^H A22 Q_p = A22 - V W^H - W V^H with X = A22 V T and
 //     W = X - V (T^H V^H X) / 2. Four launches per panel: the panel QR (one workgroup, rows in
-//     registers, one workgroup-wide reduction per column), X (row blocks over the GPU, with partial
-//     sums of V^H X), W, and the rank-2NB update as one FP64 MFMA product on the contraction kernel.
+//     registers, one workgroup-wide reduction per column), X (row blocks over the GPU, forming V T
+//     on the way, with partial sums of V^H X), W, and the rank-2NB update as one FP64 MFMA product
+//     on the contraction kernel.
 //   stage 2, band -> tridiagonal by bulge chasing: sweep i annihilates column i below the first
 //     sub-diagonal with a reflector on rows i+1 .. i+NB, and chases the resulting bulge down the band
 //     in steps of NB rows (each step: the previous reflector applied from the right to the block
@@ -150,6 +151,14 @@ __device__ __forceinline__ void reflector_scalars(double2 alpha, double xn2, dou
   scal = make_double2(ar / den, -ai / den);
 }
 
+// a wave-uniform double moved to scalar registers (keeps per-column constants out of the vector
+// register file, which holds the panel rows)
+__device__ __forceinline__ double uni(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+__device__ __forceinline__ double2 uni2(double2 v) { return make_double2(uni(v.x), uni(v.y)); }
+
 // ---- stage 1: panel QR --------------------------------------------------------------------------
 // Thread t holds rows t + TH q (q < R) of the panel (NB complex each) in registers. Column C:
 // one reduction over the rows below the pivot gives |x_1..|^2, x^H a_j for the later columns j and
@@ -169,43 +178,45 @@ __device__ __forceinline__ void panel_column(PanelState<R>& S, int h, int tid, i
 #pragma unroll
     for (int j = 0; j < NB; ++j) pv[j] = S.P[0][j];
   }
+  // value k (0..14): V_k^H x for k < C (reflector k is stored in column k), x^H a_{k+1} otherwise;
+  // value 15: |x|^2. Each is summed over the thread's rows, then over 16-lane rows by DPP; lane 0
+  // of every row stores its partial.
+  const bool row0 = (lane & 15) == 0;
+  double* rp = red[wave * 4 + (lane >> 4)];
 #pragma unroll
-  for (int part = 0; part < 4; ++part) {
-    double v[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = 0.0;
+  for (int k = 0; k < 16; ++k) {
+    double re = 0.0, im = 0.0;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       const int r = tid + TH * q;
       if (r > C && r < h) {
         const double2 x = S.P[q][C];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int k = part * 4 + i;
-          if (k < 15) {
-            // k < C: V_k^H x (reflector k is stored in column k); otherwise x^H a_{k+1}
-            const double2 pr = k < C ? cjmul(S.P[q][k < C ? k : 0], x)
-                                     : cjmul(x, S.P[q][k + 1 < NB ? k + 1 : 0]);
-            v[2 * i] += pr.x;
-            v[2 * i + 1] += pr.y;
-          } else {
-            v[2 * i] += x.x * x.x + x.y * x.y;
-          }
+        if (k == 15) {
+          re += x.x * x.x + x.y * x.y;
+        } else {
+          const double2 pr = k < C ? cjmul(S.P[q][k < C ? k : 0], x)
+                                   : cjmul(x, S.P[q][k + 1 < NB ? k + 1 : 0]);
+          re += pr.x;
+          im += pr.y;
         }
       }
     }
-    wave_sum8x(v, lane);
-    if ((lane & 7) == 0) red[wave][part * 8 + ((lane >> 3) & 7)] = v[0];
+    re = sum16(re);
+    if (row0) rp[2 * k] = re;
+    if (k < 15) {
+      im = sum16(im);
+      if (row0) rp[2 * k + 1] = im;
+    }
   }
   __syncthreads();
-  if (tid < 32) {
+  if (tid < 32 && tid != 31) {
     double acc = 0.0;
 #pragma unroll
-    for (int w = 0; w < TH / 64; ++w) acc += red[w][tid];
+    for (int w = 0; w < 4 * (TH / 64); ++w) acc += red[w][tid];
     tot[tid] = acc;
   }
   __syncthreads();
-  const double2 alpha = pv[C];
+  const double2 alpha = uni2(pv[C]);
   double2 tau, scal;
   double beta;
   reflector_scalars(alpha, tot[30], tau, beta, scal);
@@ -229,7 +240,7 @@ __device__ __forceinline__ void panel_column(PanelState<R>& S, int h, int tid, i
   for (int j = C + 1; j < NB; ++j) {
     const double2 dj = make_double2(tot[2 * (j - 1)], tot[2 * (j - 1) + 1]);
     const double2 zj = cadd(pv[j], cjmul(scal, dj));
-    const double2 f = cmul(ctau, zj);
+    const double2 f = uni2(cmul(ctau, zj));
 #pragma unroll
     for (int q = 0; q < R; ++q) S.P[q][j] = cfms(vr[q], f, S.P[q][j]);
   }
@@ -260,12 +271,21 @@ __global__ __launch_bounds__(TH) void k_band_panel(EigArgs a0, int p) {
   const int c0 = p * NB, r0 = c0 + NB, h = s - r0, ncol = min(NB, h);
   const BandWork B = band_layout(a.work + eig_base_doubles(s, a.kmax), s);
   double2* __restrict__ G = a.G;
-  __shared__ double red[TH / 64][32];
+  __shared__ double red[4 * (TH / 64)][32];
   __shared__ double tot[32];
   __shared__ double2 piv[2][NB];
   __shared__ double2 Tm[NB][NB];
   __shared__ double2 Gq[NB][NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  long long ts0 = a.tstamp && tid == 0 ? wall_clock64() : 0, ts1 = 0;
+  // accumulated phase durations (time stamps of thread 0, optional)
+  auto phase = [&](int slot) {
+    if (a.tstamp && tid == 0) {
+      ts1 = wall_clock64();
+      atomicAdd(reinterpret_cast<unsigned long long*>(a.tstamp + slot), (unsigned long long)(ts1 - ts0));
+      ts0 = ts1;
+    }
+  };
   PanelState<R> S;
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -276,8 +296,10 @@ __global__ __launch_bounds__(TH) void k_band_panel(EigArgs a0, int p) {
   }
   if (tid < NB * NB) Tm[tid / NB][tid % NB] = make_double2(0.0, 0.0);
   __syncthreads();
+  phase(8);
   panel_columns<R, TH, 0>(S, ncol, h, tid, lane, wave, red, tot, piv, Tm, Gq);
   __syncthreads();
+  phase(9);
   // T column by column: T[i, C] = -tau_C sum_{i <= k < C} T[i, k] (V_k^H v_C); lane i owns row i
   if (tid < NB) {
     const int i = tid;
@@ -291,7 +313,8 @@ __global__ __launch_bounds__(TH) void k_band_panel(EigArgs a0, int p) {
     }
   }
   __syncthreads();
-  // R and the reflectors back into G (LAPACK layout), [V | 0 | V] into Z and V T into VT
+  phase(10);
+  // R and the reflectors back into G (LAPACK layout) and [V | 0 | V] into Z
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int r = tid + TH * q;
@@ -310,21 +333,15 @@ __global__ __launch_bounds__(TH) void k_band_panel(EigArgs a0, int p) {
       z[NB + j] = make_double2(0.0, 0.0);
       z[2 * NB + j] = ve[j];
     }
-    double2* vt = B.VT + (size_t)r * NB;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int k = 0; k <= j; ++k) acc = cfma(ve[k], Tm[k][j], acc);
-      vt[j] = acc;
-    }
   }
   if (tid < NB * NB) B.T1[(size_t)p * NB * NB + tid] = Tm[tid / NB][tid % NB];
+  __syncthreads();
+  phase(11);
 }
 
 // ---- stage 1: X = A22 (V T), one row of X per wave, and partial sums of V^H X per workgroup -------
-// V T is staged through LDS in chunks of 64 rows (transposed, so a wave reads 64 consecutive
-// entries of one column), shared by the workgroup's 16 rows.
+// V T is formed in chunks of 64 rows from the explicit V and T and staged through LDS (transposed,
+// so a wave reads 64 consecutive entries of one column), shared by the workgroup's 16 rows.
 __global__ __launch_bounds__(1024) void k_band_x(EigArgs a0, int p) {
   const EigArgs a = eig_inst(a0, blockIdx.y);
   const int s = a.s;
@@ -332,16 +349,25 @@ __global__ __launch_bounds__(1024) void k_band_x(EigArgs a0, int p) {
   const BandWork B = band_layout(a.work + eig_base_doubles(s, a.kmax), s);
   __shared__ double2 xs[XR][NB];
   __shared__ double2 vts[NB][64];
+  __shared__ double2 Ts[NB][NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int i = blockIdx.x * XR + wave;
+  if (tid < NB * NB) Ts[tid / NB][tid % NB] = B.T1[(size_t)p * NB * NB + tid];
+  __syncthreads();
   double2 acc[NB];
 #pragma unroll
   for (int j = 0; j < NB; ++j) acc[j] = make_double2(0.0, 0.0);
   const double2* __restrict__ arow = a.G + (size_t)(r0 + min(i, h - 1)) * s + r0;
   for (int k0 = 0; k0 < h; k0 += 64) {
     {
+      // (V T)[k0 + kk, j] = sum_{m <= j} V[k0 + kk, m] T[m, j]
       const int kk = tid >> 4, j = tid & 15;
-      vts[j][kk] = k0 + kk < h ? B.VT[(size_t)(k0 + kk) * NB + j] : make_double2(0.0, 0.0);
+      double2 acc = make_double2(0.0, 0.0);
+      if (k0 + kk < h) {
+        const double2* __restrict__ vrow = B.Z + (size_t)(k0 + kk) * 3 * NB;
+        for (int m = 0; m <= j; ++m) acc = cfma(vrow[m], Ts[m][j], acc);
+      }
+      vts[j][kk] = acc;
     }
     __syncthreads();
     const double2 x = i < h && k0 + lane < h ? arow[k0 + lane] : make_double2(0.0, 0.0);
@@ -566,6 +592,7 @@ __global__ __launch_bounds__(1024) void k_bulge(EigArgs a0) {
       __hip_atomic_store(&prog[wave], (i + 16) << 12, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   __syncthreads();
+  if (a.tstamp && tid == 0) a.tstamp[12] = wall_clock64() - a.tstamp[0];
   if (tid == 0) W.d[n - 1] = bd[(size_t)(n - 1) * LDB].x;
   __syncthreads();
   if (wave == 0) tri_bounds(W, n, a.tstamp, a.status);
@@ -573,16 +600,19 @@ __global__ __launch_bounds__(1024) void k_bulge(EigArgs a0) {
 
 // ---- back-transformation: u = Q1 Q2 y for BT_NV eigenvectors per workgroup -----------------------
 // Stage-2 reflectors sweep by sweep in reverse (the steps of one sweep touch disjoint rows and run
-// together, 16 lanes each); then the stage-1 panels in reverse, u <- u - V (T (V^H u)).
-static constexpr int BT_THREADS = 512;
+// together, 16 lanes each; the next sweep's reflectors are fetched while the current one is
+// applied); then the stage-1 panels in reverse, u <- u - V (T (V^H u)), one eigenvector at a time.
+static constexpr int BT_THREADS = 1024;
+static constexpr int BT_GROUPS = BT_THREADS / 16;
+static constexpr int BT_MAXST = 3;   // steps per 16-lane group and sweep: T2 <= 3 * 64 (s <= 3073)
 __global__ __launch_bounds__(BT_THREADS) void k_bt_band(EigArgs a0) {
   const EigArgs a = eig_inst(a0, blockIdx.y);
   const int n = a.s, kmax = a.kmax, T2 = band_T2(n), npan = band_npan(n);
   const BandWork B = band_layout(a.work + eig_base_doubles(n, kmax), n);
   EigWork W = eig_layout(a.work, n, kmax);
   extern __shared__ double2 u[];   // BT_NV x n
-  __shared__ double red[BT_THREADS / 64][32];
-  __shared__ double2 wv[BT_NV][NB];
+  __shared__ double red[4 * (BT_THREADS / 64)][32];
+  __shared__ double2 wv[NB];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int t0 = blockIdx.x * BT_NV;
   const int kk = a.kkeep[0];
@@ -591,85 +621,109 @@ __global__ __launch_bounds__(BT_THREADS) void k_bt_band(EigArgs a0) {
     const int t = t0 + vv;
     u[idx] = make_double2(t < kmax && t < kk ? W.Y[(size_t)t * n + i] : 0.0, 0.0);
   }
-  __syncthreads();
   const int g = tid >> 4, rho = tid & 15;
+  // reflectors of sweep i for this lane: steps g, g + BT_GROUPS, ...
+  double2 vn[BT_MAXST], tn[BT_MAXST];
+  auto fetch = [&](int i) {
+#pragma unroll
+    for (int m = 0; m < BT_MAXST; ++m) {
+      const int st = g + m * BT_GROUPS;
+      const bool ok = i >= 0 && st < T2;
+      vn[m] = ok ? B.V2[((size_t)i * T2 + st) * NB + rho] : make_double2(0.0, 0.0);
+      tn[m] = ok ? B.tau2[(size_t)i * T2 + st] : make_double2(0.0, 0.0);
+    }
+  };
+  fetch(n - 2);
+  __syncthreads();
+  const long long tb0 = a.tstamp && tid == 0 && blockIdx.x == 0 ? wall_clock64() : 0;
   for (int i = n - 2; i >= 0; --i) {
     const int Ti = (n - 1 - i + NB - 1) / NB;
-    for (int st = g; st < Ti; st += BT_THREADS / 16) {
+    double2 vc[BT_MAXST], tc[BT_MAXST];
+#pragma unroll
+    for (int m = 0; m < BT_MAXST; ++m) {
+      vc[m] = vn[m];
+      tc[m] = tn[m];
+    }
+    fetch(i - 1);
+#pragma unroll
+    for (int m = 0; m < BT_MAXST; ++m) {
+      const int st = g + m * BT_GROUPS;
+      if (st >= Ti) break;
       const int r = i + 1 + st * NB + rho;
       const bool ok = r < n;
-      const double2 v = B.V2[((size_t)i * T2 + st) * NB + rho];
-      const double2 tau = B.tau2[(size_t)i * T2 + st];
 #pragma unroll
       for (int vv = 0; vv < BT_NV; ++vv) {
         const double2 x = ok ? u[vv * n + r] : make_double2(0.0, 0.0);
-        const double2 d = sum16_z(cjmul(v, x));
-        if (ok) u[vv * n + r] = cfms(cmul(tau, d), v, x);
+        const double2 d = sum16_z(cjmul(vc[m], x));
+        if (ok) u[vv * n + r] = cfms(cmul(tc[m], d), vc[m], x);
       }
     }
     __syncthreads();
   }
+  const bool row0 = (lane & 15) == 0;
+  double* rp = red[wave * 4 + (lane >> 4)];
+  const long long tb1 = a.tstamp && tid == 0 && blockIdx.x == 0 ? wall_clock64() : 0;
+  if (a.tstamp && tid == 0 && blockIdx.x == 0) a.tstamp[13] = tb1 - tb0;
   for (int p = npan - 1; p >= 0; --p) {
     const int c0 = p * NB, r0 = c0 + NB, h = n - r0, ncol = min(NB, h);
-    // W = V^H u over the panel's rows (NB x BT_NV complex), in four passes of 16 doubles
 #pragma unroll 1
-    for (int pass = 0; pass < 2 * BT_NV; ++pass) {
-      const int vv = pass >> 1, a8 = (pass & 1) * 8;
-      double v[16];
+    for (int vv = 0; vv < BT_NV; ++vv) {
+      // w = V^H u over the panel's rows: 16 complex sums, by DPP within 16-lane rows, then LDS
+      double2 part[NB];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) v[k] = 0.0;
+      for (int j = 0; j < NB; ++j) part[j] = make_double2(0.0, 0.0);
       for (int r = tid; r < h; r += blockDim.x) {
         const double2 x = u[vv * n + r0 + r];
         const double2* grow = a.G + (size_t)(r0 + r) * n + c0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const int j = a8 + k;
-          double2 ve = j >= ncol || r < j ? make_double2(0.0, 0.0)
-                                          : (r == j ? make_double2(1.0, 0.0) : grow[j]);
-          const double2 pr = cjmul(ve, x);
-          v[2 * k] += pr.x;
-          v[2 * k + 1] += pr.y;
+        for (int j = 0; j < NB; ++j) {
+          const double2 ve = j >= ncol || r < j ? make_double2(0.0, 0.0)
+                                                : (r == j ? make_double2(1.0, 0.0) : grow[j]);
+          part[j] = cadd(part[j], cjmul(ve, x));
         }
       }
-      wave_sum16x(v, lane);
-      if ((lane & 3) == 0) red[wave][(pass & 1) * 16 + ((lane >> 2) & 15)] = v[0];
-      if (pass & 1) {
-        __syncthreads();
-        if (tid < 32) {
-          double acc = 0.0;
 #pragma unroll
-          for (int w = 0; w < BT_THREADS / 64; ++w) acc += red[w][tid];
-          reinterpret_cast<double*>(wv[vv])[tid] = acc;
+      for (int j = 0; j < NB; ++j) {
+        const double2 sj = sum16_z(part[j]);
+        if (row0) {
+          rp[2 * j] = sj.x;
+          rp[2 * j + 1] = sj.y;
         }
-        __syncthreads();
       }
-    }
-    // W' = T W (T upper triangular)
-    double2 tw = make_double2(0.0, 0.0);
-    if (tid < BT_NV * NB) {
-      const int vv = tid / NB, j = tid % NB;
-      const double2* T = B.T1 + (size_t)p * NB * NB;
-      for (int k = j; k < NB; ++k) tw = cfma(T[j * NB + k], wv[vv][k], tw);
-    }
-    __syncthreads();
-    if (tid < BT_NV * NB) wv[tid / NB][tid % NB] = tw;
-    __syncthreads();
-    for (int r = tid; r < h; r += blockDim.x) {
-      const double2* grow = a.G + (size_t)(r0 + r) * n + c0;
-      double2 ve[NB];
+      __syncthreads();
+      if (tid < 32) {
+        double acc = 0.0;
+        for (int w = 0; w < 4 * (BT_THREADS / 64); ++w) acc += red[w][tid];
+        reinterpret_cast<double*>(wv)[tid] = acc;
+      }
+      __syncthreads();
+      // w' = T w (T upper triangular)
+      double2 tw = make_double2(0.0, 0.0);
+      if (tid < NB) {
+        const double2* T = B.T1 + (size_t)p * NB * NB;
+        for (int k = tid; k < NB; ++k) tw = cfma(T[tid * NB + k], wv[k], tw);
+      }
+      __syncthreads();
+      if (tid < NB) wv[tid] = tw;
+      __syncthreads();
+      double2 wr[NB];
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
-        ve[j] = j >= ncol || r < j ? make_double2(0.0, 0.0) : (r == j ? make_double2(1.0, 0.0) : grow[j]);
-#pragma unroll
-      for (int vv = 0; vv < BT_NV; ++vv) {
+      for (int j = 0; j < NB; ++j) wr[j] = uni2(wv[j]);
+      for (int r = tid; r < h; r += blockDim.x) {
+        const double2* grow = a.G + (size_t)(r0 + r) * n + c0;
         double2 x = u[vv * n + r0 + r];
 #pragma unroll
-        for (int j = 0; j < NB; ++j) x = cfms(ve[j], wv[vv][j], x);
+        for (int j = 0; j < NB; ++j) {
+          const double2 ve = j >= ncol || r < j ? make_double2(0.0, 0.0)
+                                                : (r == j ? make_double2(1.0, 0.0) : grow[j]);
+          x = cfms(ve, wr[j], x);
+        }
         u[vv * n + r0 + r] = x;
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
+  if (a.tstamp && tid == 0 && blockIdx.x == 0) a.tstamp[14] = wall_clock64() - tb1;
   for (int idx = tid; idx < BT_NV * n; idx += blockDim.x) {
     const int vv = idx / n, i = idx % n;
     const int t = t0 + vv;
@@ -687,8 +741,8 @@ hipError_t launch_band_reduction(const EigArgs& a, hipStream_t st) {
   const BandWork B0 = band_layout(a.work + eig_base_doubles(s, a.kmax), s);
   for (int p = 0; p < npan; ++p) {
     const int r0 = (p + 1) * NB, h = s - r0;
-    // two rows per thread: 512 threads leave each wave 256 registers for the 2 x NB complex entries
-    if (h <= 1024) hipLaunchKernelGGL((k_band_panel<2, 512>), dim3(1, a.batch), dim3(512), 0, st, a, p);
+    // one row per thread up to 1024 rows, two above
+    if (h <= 1024) hipLaunchKernelGGL((k_band_panel<1, 1024>), dim3(1, a.batch), dim3(1024), 0, st, a, p);
     else hipLaunchKernelGGL((k_band_panel<2, 1024>), dim3(1, a.batch), dim3(1024), 0, st, a, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -738,7 +792,8 @@ size_t bt_band_lds_bytes(int s) { return (size_t)BT_NV * s * 16; }
 
 hipError_t launch_bt_band(const EigArgs& a, hipStream_t st) {
   const size_t lds = bt_band_lds_bytes(a.s);
-  if (lds + 16 * 32 * 8 + BT_NV * NB * 16 > 160 * 1024 - 512) return hipErrorInvalidValue;
+  if (lds + 4 * (BT_THREADS / 64) * 32 * 8 + NB * 16 > 160 * 1024 - 512) return hipErrorInvalidValue;
+  if (band_T2(a.s) > BT_MAXST * BT_GROUPS) return hipErrorInvalidValue;
   (void)hipFuncSetAttribute((const void*)k_bt_band, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
   hipLaunchKernelGGL(k_bt_band, dim3((a.kmax + BT_NV - 1) / BT_NV, a.batch), dim3(BT_THREADS), lds, st,
