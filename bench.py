@@ -132,6 +132,97 @@ def _chain_fidelity(a, b):
     return abs(ab) ** 2 / (overlap(a, a).real * overlap(b, b).real)
 
 
+def _gpu_children(parent):
+    ch = [[] for _ in parent]
+    for j, q in enumerate(parent):
+        if q >= 0:
+            ch[q].append(j)
+    return ch
+
+
+def _gpu_overlap(parent, A, B):
+    """<A|B> of two tree networks with node legs (sigma, parent, children...) as torch tensors on
+    the device, by a leaves-to-root contraction (plain torch; a measurement helper of this script)."""
+    import torch
+    ch = _gpu_children(parent)
+    root = parent.index(-1)
+    order, stack = [], [root]
+    while stack:
+        i = stack.pop()
+        order.append(i)
+        stack.extend(ch[i])
+    env = {}
+    for i in reversed(order):
+        x = B[i]
+        for pos, c in enumerate(ch[i]):
+            e = env.pop(c)                               # (a_c of A, b_c of B)
+            x = torch.tensordot(x, e, dims=([2 + pos], [1]))   # b_c -> a_c, moved to the end
+            x = torch.movedim(x, -1, 2 + pos)
+        a = A[i].conj()
+        axes = [0] + list(range(2, a.dim()))
+        env[i] = torch.tensordot(a, x, dims=(axes, axes))    # (a_p, b_p)
+    return complex(env[root].reshape(-1)[0].item())
+
+
+def _gpu_product(parent, state, op):
+    """Node tensors of the exact product O|psi> (bonds fused, alpha-major), on the device."""
+    import torch
+    ch = _gpu_children(parent)
+    out = []
+    for i in range(len(parent)):
+        t = torch.from_numpy(state[i]).to("cuda:0")
+        w = torch.from_numpy(op[i]).to("cuda:0")
+        k = t.dim() - 1                                   # virtual legs
+        x = torch.tensordot(w, t, dims=([1], [0]))       # (s', b_1..b_k, a_1..a_k)
+        perm = [0] + [q for j in range(k) for q in (1 + k + j, 1 + j)]
+        x = x.permute(*perm).contiguous()
+        shape = [x.shape[0]] + [x.shape[1 + 2 * j] * x.shape[2 + 2 * j] for j in range(k)]
+        out.append(x.reshape(shape))
+    return out
+
+
+def paper_workloads(cbc, stream, full=False, steps=3):
+    """The random-network workload of Sec. IV A on the GPU: tensor train (L=50, d=3, D=40), T-tree
+    (L=20), balanced binary tree (depth 6, physical legs on the leaves) and fork tensor product
+    structure (L=8), all d=3, D=10, entries U[-0.5, 1]; CBC (mixed and FP64) and the naive
+    contract-then-compress baseline (FP64) over a sweep of target bonds: time per compression and
+    relative error ||O psi - psi'|| / ||O psi||, with O psi contracted exactly on the device."""
+    import dataclasses
+    import torch
+    from paper_2601_19650_amd.inputs import PAPER_WORKLOADS, paper_problem
+    res = {}
+    for kind, (_, L, d, D, sweep) in PAPER_WORKLOADS.items():
+        dbars = sweep if full else [sweep[0], sweep[len(sweep) // 3], sweep[2 * len(sweep) // 3],
+                                    sweep[-1]]
+        base = paper_problem(kind, dbars[-1])
+        P = _gpu_product(base.parent, base.state, base.op)
+        nP = _gpu_overlap(base.parent, P, P).real
+        tree = cbc.Tree.of(base)
+        st, so = cbc.pack(base.state, "cuda:0")
+        op, oo = cbc.pack(base.op, "cuda:0")
+        ctx = new_context(cbc)
+        pts = []
+        for dbar in dbars:
+            pt = {"target_bond": dbar}
+            for method, prec in (("cbc", "mixed"), ("cbc", "fp64"), ("naive", "fp64")):
+                comp = cbc.Compressor(ctx, tree, dbar, prec, method=method, device="cuda:0")
+                sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, 1)
+                out = [torch.from_numpy(t).to("cuda:0") for t in comp.unpack()]
+                nq = _gpu_overlap(base.parent, out, out).real
+                ov = _gpu_overlap(base.parent, P, out).real
+                err = math.sqrt(max(nP - 2.0 * ov + nq, 0.0) / nP)
+                pt[f"{method}_{prec}"] = {"ms": sec * 1e3, "rel_error": err}
+                del comp
+            pts.append(pt)
+            print(f"[bench] paper {kind} target bond {dbar}: " + ", ".join(
+                f"{k} {v['ms']:.2f} ms err {v['rel_error']:.2e}" for k, v in pt.items()
+                if isinstance(v, dict)), file=sys.stderr, flush=True)
+        res[kind] = {"nodes": base.n, "phys": d, "state_bond": D, "operator_bond": D,
+                     "size": L, "points": pts}
+        del P, st, op
+    return res
+
+
 def recorded_traffic(workload, precision, op):
     """HBM bytes per launch of `op` from a committed counter summary (profiles/*_hbm_counters.md),
     or None when there is none for this workload, or a kernel source changed since it was taken."""
@@ -332,6 +423,9 @@ def main():
                     help="instances of the 64-site shape per launch sequence (0: skip)")
     ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven batch workload to time (0: skip)")
+    ap.add_argument("--paper", choices=["off", "short", "full"], default="short",
+                    help="random-network workload of the paper's Sec. IV A: CBC and naive over target "
+                         "bonds (short: four per tree shape)")
     ap.add_argument("--autotune", choices=["on", "off"], default="on",
                     help="tune the contractions' tile and split per shape before timing (cbc_autotune)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -433,6 +527,8 @@ def main():
         line["batched"] = batched_run(args, cbc, config_problem("C2"), stream)
     if args.uneven > 0:
         line["uneven_batch"] = uneven_run(args.uneven)
+    if args.paper != "off":
+        line["paper_random_networks"] = paper_workloads(cbc, stream, full=args.paper == "full")
     if not args.no_cpu_baseline and args.workload == "C4":
         cb, errs = cpu_baseline_large(cbc)
         line["cpu_baseline"] = cb

@@ -32,6 +32,7 @@ import numpy as np
 __all__ = [
     "Problem", "chain_parent", "kary_parent", "cut_bonds", "random_problem",
     "config_problem", "batch_problems", "batch_shapes", "CONFIGS",
+    "t_tree", "balanced_binary", "fork_tree", "paper_problem", "PAPER_WORKLOADS",
 ]
 
 
@@ -258,3 +259,64 @@ def batch_problems(count=256, seed=5, ternary_chi_cap=32, n_range=(16, 64), chi_
         out.append(random_problem(_parent_of(kind, n), d, chi, D, chi, sub_seed,
                                   name=f"B{j}:{kind}:n{n}:d{d}:chi{chi}:D{D}"))
     return out
+
+
+# ---- the random-network workload of Sec. IV A --------------------------------------------------
+# Four tree shapes, entries with real and imaginary parts uniform on [-0.5, 1] (dist="paper"), the
+# TTNO on the same tree as the TTNS. Readings where the text leaves a detail open (the figure that
+# shows the shapes is not part of the text):
+#   * T-tree: the central node (the root) carries no physical leg; each of its three chains has L
+#     nodes with one physical leg each;
+#   * balanced binary tree of depth L: L edges from the root to every leaf (2^(L+1) - 1 nodes),
+#     physical legs on the 2^L leaves only;
+#   * fork tensor product structure: a chain of L virtual nodes (no physical leg; the first is the
+#     root), each with an attached chain of L physical nodes.
+
+def t_tree(L, d):
+    """T-shaped tree: node 0 (root, d = 1) with three chains of L physical nodes."""
+    parent, phys = [-1], [1]
+    for k in range(3):
+        for j in range(L):
+            parent.append(0 if j == 0 else len(parent) - 1)
+            phys.append(d)
+    return parent, phys
+
+
+def balanced_binary(depth, d):
+    """Perfect binary tree of the given depth in heap order; physical legs on the leaves only."""
+    n = 2 ** (depth + 1) - 1
+    parent = kary_parent(n, 2)
+    first_leaf = 2 ** depth - 1
+    phys = [d if i >= first_leaf else 1 for i in range(n)]
+    return parent, phys
+
+
+def fork_tree(L, d):
+    """Fork tensor product structure: virtual chain 0..L-1 (root 0), physical chain of L nodes on
+    every virtual node."""
+    parent = [i - 1 for i in range(L)]
+    phys = [1] * L
+    for k in range(L):
+        for j in range(L):
+            parent.append(k if j == 0 else len(parent) - 1)
+            phys.append(d)
+    return parent, phys
+
+
+# name: (tree builder, system size, d, state and operator bond, target bonds swept in Sec. IV A)
+PAPER_WORKLOADS = {
+    "mps": (lambda L, d: (chain_parent(L), [d] * L), 50, 3, 40, list(range(2, 41, 2))),
+    "ttree": (t_tree, 20, 3, 10, list(range(2, 11, 2))),
+    "binary": (balanced_binary, 6, 3, 10, list(range(2, 11, 2))),
+    "fork": (fork_tree, 8, 3, 10, list(range(2, 11, 2))),
+}
+
+
+def paper_problem(kind, max_bond, size=None, bond=None, seed=7):
+    """An instance of the random-network workload: tree `kind` of PAPER_WORKLOADS (its system size and
+    bonds unless overridden), U[-0.5, 1] entries, target bond `max_bond`."""
+    build, L, d, D, _ = PAPER_WORKLOADS[kind]
+    parent, phys = build(size if size is not None else L, d)
+    D = bond if bond is not None else D
+    return random_problem(parent, phys, D, D, max_bond, seed, dist="paper",
+                          name=f"paper-{kind}-L{size if size is not None else L}-D{D}-Dbar{max_bond}")

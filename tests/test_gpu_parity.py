@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import cbc_tree, cbc_tt, tn  # noqa: E402
 from paper_2601_19650_amd.inputs import (chain_parent, config_problem, kary_parent,  # noqa: E402
-                                         random_problem)
+                                         paper_problem, random_problem)
 
 FP64_BAR = 1e-10
 MIXED_BAR = 1e-5
@@ -423,3 +423,46 @@ def test_c5_subset_parity(lib, c5_subset, prec):
             infid = 1.0 - tn.fidelity(p.parent, got, ref)
             print(f"{p.name}: mixed infidelity {infid:.2e}", flush=True)
             assert infid <= MIXED_BAR, p.name
+
+
+# The random-network experiment of Sec. IV A at its full sizes: tensor train of 50 sites (d = 3,
+# D = 40) and the three T3NS shapes (T-tree L = 20, binary tree of depth 6, fork L = 8; d = 3,
+# D = 10), entries U[-0.5, 1], at the smallest and the largest target bond of the sweep.
+PAPER_CASES = [("mps", 2), ("mps", 40), ("ttree", 2), ("ttree", 10), ("binary", 2), ("binary", 10),
+               ("fork", 2), ("fork", 10)]
+
+
+@pytest.fixture(scope="module")
+def paper_refs():
+    cache = {}
+
+    def get(kind, dbar):
+        if (kind, dbar) not in cache:
+            p = paper_problem(kind, dbar)
+            print(f"oracle {p.name}", flush=True)
+            cache[(kind, dbar)] = (p, cbc_tree(p.parent, p.state, p.op, p.max_bond))
+        return cache[(kind, dbar)]
+    return get
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind,dbar", PAPER_CASES)
+def test_paper_random_networks_parity(lib, paper_refs, kind, dbar, prec):
+    p, ref = paper_refs(kind, dbar)
+    check(lib, p, prec, oracle_out=ref)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("kind", ["ttree", "binary", "fork"])
+def test_paper_random_networks_naive_parity(lib, kind, prec):
+    """The naive baseline on the full-size T3NS shapes of the random-network experiment (product
+    bond 100, a root of three virtual legs in the T-tree and the binary tree) against the oracle's
+    naive method."""
+    p = paper_problem(kind, 6)
+    print(f"naive {p.name} prec={prec}", flush=True)
+    ref = tn.naive_compress(p.parent, p.op, p.state, p.max_bond)
+    out, _ = lib.compress(p, precision=prec, method="naive")
+    if prec == "fp64":
+        assert tn.rel_error(p.parent, out, ref) <= FP64_BAR
+    else:
+        assert 1.0 - tn.fidelity(p.parent, out, ref) <= MIXED_BAR
