@@ -181,7 +181,7 @@ def _gpu_product(parent, state, op):
     return out
 
 
-def paper_workloads(cbc, stream, full=False, steps=3):
+def paper_workloads(cbc, stream, full=False, steps=2):
     """The random-network workload of Sec. IV A on the GPU: tensor train (L=50, d=3, D=40), T-tree
     (L=20), balanced binary tree (depth 6, physical legs on the leaves) and fork tensor product
     structure (L=8), all d=3, D=10, entries U[-0.5, 1]; CBC (mixed and FP64) and the naive
@@ -192,8 +192,8 @@ def paper_workloads(cbc, stream, full=False, steps=3):
     from paper_2601_19650_amd.inputs import PAPER_WORKLOADS, paper_problem
     res = {}
     for kind, (_, L, d, D, sweep) in PAPER_WORKLOADS.items():
-        dbars = sweep if full else [sweep[0], sweep[len(sweep) // 3], sweep[2 * len(sweep) // 3],
-                                    sweep[-1]]
+        dbars = sweep if full or len(sweep) <= 5 else [
+            sweep[0], sweep[len(sweep) // 3], sweep[2 * len(sweep) // 3], sweep[-1]]
         base = paper_problem(kind, dbars[-1])
         P = _gpu_product(base.parent, base.state, base.op)
         nP = _gpu_overlap(base.parent, P, P).real
@@ -425,9 +425,12 @@ def main():
                     help="instances of the uneven batch workload to time (0: skip)")
     ap.add_argument("--paper", choices=["off", "short", "full"], default="short",
                     help="random-network workload of the paper's Sec. IV A: CBC and naive over target "
-                         "bonds (short: four per tree shape)")
+                         "bonds (short: four of the tensor train's twenty)")
     ap.add_argument("--autotune", choices=["on", "off"], default="on",
                     help="tune the contractions' tile and split per shape before timing (cbc_autotune)")
+    ap.add_argument("--sites", type=int, default=0,
+                    help="cut the headline workload to its first N nodes (profiler runs of its bulk "
+                         "node shapes; 0: the full workload)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times) and exit; used to "
                          "scale the HBM byte counters of a profiler run")
@@ -454,7 +457,7 @@ def main():
         print(json.dumps({"copy_calibration": {"bytes_read": n * 4, "bytes_written": n * 4,
                                                "launches": 5}}))
         return
-    p = config_problem(args.workload)
+    p = config_problem(args.workload, n=args.sites) if args.sites > 0 else config_problem(args.workload)
     stream = torch.cuda.Stream()
     precs = [args.only] if args.only else ["mixed", "fp64"]
     res, outputs = measure(cbc, p, precs, args.steps, args.warmup, stream)
@@ -489,7 +492,8 @@ def main():
         "vs_baseline": None,
         "dtype": "c64+f64" if head == "mixed" else "c128",
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "name": args.workload,
+        "config": {"workload": WORKLOADS[args.workload] + (
+                       f", cut to {p.n} sites" if args.sites > 0 else ""), "name": args.workload,
                    "precision": head, "max_bond": p.max_bond, "n_nodes": p.n,
                    "contraction_config": "autotuned" if AUTOTUNE else "fixed policy"},
         "contraction_tflops": contraction_flops / sec / 1e12,
@@ -505,7 +509,7 @@ def main():
     if "fp64" in res and "mixed" in res:
         line["fp64"] = precision_line(res["fp64"], "fp64", cls, cbc.NCLASS)
         line["speedup_mixed_vs_fp64"] = res["fp64"]["sec"] / res["mixed"]["sec"]
-        if args.workload == "C4":
+        if args.workload == "C4" and args.sites == 0:
             # At 128 sites the compressed state is ill-conditioned (a rounding-level input change
             # grows ~1.6x per site), so mixed and FP64 results are compared by the weight they
             # capture; the non-root nodes are isometries, so ||psi'||^2 is the root's squared norm.
@@ -529,7 +533,7 @@ def main():
         line["uneven_batch"] = uneven_run(args.uneven)
     if args.paper != "off":
         line["paper_random_networks"] = paper_workloads(cbc, stream, full=args.paper == "full")
-    if not args.no_cpu_baseline and args.workload == "C4":
+    if not args.no_cpu_baseline and args.workload == "C4" and args.sites == 0:
         cb, errs = cpu_baseline_large(cbc)
         line["cpu_baseline"] = cb
         line["error_vs_oracle"] = {"C4 shape, 10 sites": errs}
