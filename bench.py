@@ -132,6 +132,55 @@ def _chain_fidelity(a, b):
     return abs(ab) ** 2 / (overlap(a, a).real * overlap(b, b).real)
 
 
+def uneven_full_run(stream_count=8):
+    """The whole 256-instance uneven draw (tensor trains, binary and ternary trees, N in [16, 64],
+    d in {2, 4}, chi in [16, 128] with ternary trees at chi <= 32, D in [4, 12], max_bond = chi),
+    mixed precision, forked over `stream_count` streams whose instances share one scratch buffer
+    per stream, captured into graphs of at most UnevenBatch.MAX_GRAPH_LAUNCHES launches each and
+    replayed in order (one launch per graph)."""
+    import torch
+    from paper_2601_19650_amd import cbc
+    from paper_2601_19650_amd.inputs import batch_problems
+    t0 = time.perf_counter()
+    probs = batch_problems()
+    ub = cbc.UnevenBatch(probs, precision="mixed", nstreams=stream_count, autotune=AUTOTUNE,
+                         share_scratch=True)
+    t1 = time.perf_counter()
+    print(f"[bench] uneven full draw: {len(probs)} instances set up in {t1 - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    # first (eager) pass instance by instance: builds every plan's offset tables and its graph
+    for k, (comp, args) in enumerate(ub.items):
+        comp.run(*args, stream=ub.streams[k % stream_count].cuda_stream)
+        if k % 16 == 15:
+            torch.cuda.synchronize()
+            print(f"[bench] uneven full draw: first pass {k + 1} instances, "
+                  f"{time.perf_counter() - t1:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    bad = [comp.report()["status"] for comp, _ in ub.items]
+    bad = [b for b in bad if b != "ok"]
+    t2 = time.perf_counter()
+    ub.capture()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    print(f"[bench] uneven full draw: captured into {len(ub.graphs)} graphs in {t3 - t2:.1f} s",
+          file=sys.stderr, flush=True)
+    ub.run()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t3
+    flops = ub.flops()
+    mem = (sum(c.workspace.numel() for c, _ in ub.items) + sum(x.numel() for x in ub.scratch))
+    print(f"[bench] uneven full draw: one replay {sec:.2f} s", file=sys.stderr, flush=True)
+    return {"instances": len(probs), "value": len(probs) / sec, "unit": "compressions/s",
+            "seconds": sec, "contraction_tflops": flops / sec / 1e12,
+            "planned_contraction_tflop": flops / 1e12, "streams": stream_count,
+            "workspace_gb": mem / 1e9, "failed_instances": len(bad),
+            "launch": f"{len(ub.graphs)} captured graphs replayed in order, scratch shared per stream",
+            "graphs": len(ub.graphs),
+            "first_pass_seconds": t2 - t1,
+            "recipe": "uneven draw (seed 5): MPS/binary/ternary, N 16-64, d 2|4, D 4-12, "
+                      "chi 16-128 (ternary <= 32), all 256 instances"}
+
+
 def _gpu_children(parent):
     ch = [[] for _ in parent]
     for j, q in enumerate(parent):
@@ -423,6 +472,8 @@ def main():
                     help="instances of the 64-site shape per launch sequence (0: skip)")
     ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven batch workload to time (0: skip)")
+    ap.add_argument("--uneven-full", action="store_true",
+                    help="also time the whole 256-instance uneven draw (several minutes)")
     ap.add_argument("--paper", choices=["off", "short", "full"], default="short",
                     help="random-network workload of the paper's Sec. IV A: CBC and naive over target "
                          "bonds (short: four of the tensor train's twenty)")
@@ -531,6 +582,8 @@ def main():
         line["batched"] = batched_run(args, cbc, config_problem("C2"), stream)
     if args.uneven > 0:
         line["uneven_batch"] = uneven_run(args.uneven)
+    if args.uneven_full:
+        line["uneven_full_draw"] = uneven_full_run()
     if args.paper != "off":
         line["paper_random_networks"] = paper_workloads(cbc, stream, full=args.paper == "full")
     if not args.no_cpu_baseline and args.workload == "C4" and args.sites == 0:

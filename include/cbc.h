@@ -196,6 +196,24 @@ cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_p
 cbc_status cbc_plan_bonds(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, int32_t tol_on,
                           int32_t* bond);
 
+/* Planned cost of one call (host only, no device work), for scheduling many problems on one GPU:
+ * the workspace split into the part that lives through the whole call (report, environments,
+ * converted inputs; it starts the workspace) and the scratch reused from node step to node step
+ * (it follows), whose sum is cbc_query's workspace_bytes for the same tol_on; and per kernel class
+ * (CBC_K_*) the kernels launched and their algorithmic flops (a complex multiply-add counts 8, a
+ * Hermitian Gram half its products, an eigensolve 16/3 s^3 + 8 s^2 k, a Cholesky factorisation
+ * with its inverse 8/3 k^3), the same figures cbc_stats reports after the call. `method` as in
+ * cbc_query. */
+typedef struct {
+  size_t persistent_bytes;
+  size_t scratch_bytes;
+  size_t table_bytes;   /* device memory the context holds for the plan's offset tables once it runs */
+  int32_t launches[CBC_K_NCLASS];
+  double flops[CBC_K_NCLASS];
+} cbc_plan_summary;
+cbc_status cbc_plan_info(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
+                         int32_t method, int32_t tol_on, cbc_plan_summary* info);
+
 /* Cholesky-based compression of O|psi> (Sec. III A for chains, Sec. III B for trees).
  * max_bond >= 1 is the target bond dimension (the paper's D-bar); tol >= 0 additionally drops
  * directions whose singular value is at most tol times the largest one at that truncation (tol = 0
@@ -204,6 +222,18 @@ cbc_status cbc_apply(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* t
                      const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
                      void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
                      cbc_stats* stats);
+
+/* cbc_apply with its workspace in two buffers: `workspace` holds what lives through the call (at
+ * least cbc_plan_info's persistent_bytes for this tol; the report is read from it as usual) and
+ * `scratch` what the node steps reuse (at least scratch_bytes). Calls that run one after another on
+ * one stream may share one scratch buffer sized for the largest of them, which is how many problems
+ * of different shapes fit on one GPU at once (their persistent parts are small). Calls that may
+ * overlap (other streams without an ordering between them) must not share it. Returns CBC_EINVAL
+ * for a null scratch and CBC_ENOMEM for a buffer below its size; otherwise as cbc_apply. */
+cbc_status cbc_apply_split(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                           const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
+                           void* workspace, size_t workspace_bytes, void* scratch,
+                           size_t scratch_bytes, cbc_out* out, void* stream, cbc_stats* stats);
 
 /* A batch of `batch` independent compressions of the same shape (same tree, dimensions, max_bond,
  * tol and precision) in one launch sequence: every kernel runs all instances at once. Instance b's

@@ -43,6 +43,12 @@ NCLASS = 6
 CLASSES = ("contract", "gram", "qrmul", "eig", "chol", "other")
 
 
+class PlanSummary(ctypes.Structure):
+    _fields_ = [("persistent_bytes", ctypes.c_size_t), ("scratch_bytes", ctypes.c_size_t),
+                ("table_bytes", ctypes.c_size_t), ("launches", ctypes.c_int32 * NCLASS),
+                ("flops", ctypes.c_double * NCLASS)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("profile", ctypes.c_int32), ("n_kernels", ctypes.c_int32),
                 ("n_eig", ctypes.c_int32), ("max_eig_dim", ctypes.c_int32),
@@ -94,6 +100,10 @@ def lib():
         L.cbc_plan_bonds.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tree), ctypes.c_int32,
                                      ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
         L.cbc_plan_bonds.restype = ctypes.c_int
+        L.cbc_plan_info.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tree), ctypes.c_int32,
+                                    ctypes.c_int, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(PlanSummary)]
+        L.cbc_plan_info.restype = ctypes.c_int
         for name in ("cbc_apply", "cbc_apply_naive"):
             f = getattr(L, name)
             f.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tensors), ctypes.POINTER(_Tensors),
@@ -112,6 +122,13 @@ def lib():
                                         ctypes.c_int32, ctypes.c_double, ctypes.c_int,
                                         ctypes.POINTER(_Out), ctypes.c_void_p, ctypes.POINTER(Stats)]
         L.cbc_apply_noalloc.restype = ctypes.c_int
+        L.cbc_apply_split.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tensors),
+                                      ctypes.POINTER(_Tensors), ctypes.POINTER(_Tree),
+                                      ctypes.c_int32, ctypes.c_double, ctypes.c_int,
+                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.POINTER(_Out), ctypes.c_void_p,
+                                      ctypes.POINTER(Stats)]
+        L.cbc_apply_split.restype = ctypes.c_int
         L.cbc_autotune.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
         L.cbc_autotune.restype = ctypes.c_int
         L.cbc_read_report.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
@@ -123,7 +140,7 @@ def lib():
 
 EXPORTED = ("cbc_create", "cbc_destroy", "cbc_status_str", "cbc_query", "cbc_plan_bonds",
             "cbc_apply", "cbc_apply_batched", "cbc_apply_naive", "cbc_autotune", "cbc_read_report",
-            "cbc_apply_noalloc")
+            "cbc_apply_noalloc", "cbc_plan_info", "cbc_apply_split")
 
 
 def _check(code, what):
@@ -206,7 +223,11 @@ class Compressor:
     """One problem shape: queries sizes once, owns workspace and output buffers, and runs the
     compression (``method`` "cbc" or "naive", ``precision`` "fp64" or "mixed")."""
 
-    def __init__(self, ctx, tree, max_bond, precision="fp64", method="cbc", device="cuda", batch=1):
+    def __init__(self, ctx, tree, max_bond, precision="fp64", method="cbc", device="cuda", batch=1,
+                 scratch=None):
+        """`scratch`: a device byte tensor shared with other Compressors whose calls are ordered
+        with this one's (same stream); the workspace then holds only the part that lives through
+        a call, and run() goes through cbc_apply_split (single instances of the CBC method)."""
         import torch
         self.ctx, self.tree, self.max_bond = ctx, tree, int(max_bond)
         self.batch = int(batch)
@@ -217,7 +238,16 @@ class Compressor:
         _check(lib().cbc_query(ctx.h, ctypes.byref(tree.c), self.max_bond, self.prec, self.method,
                                ctypes.byref(ws), self.out_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))),
                "cbc_query")
-        self.ws_bytes = int(ws.value) * self.batch
+        self.scratch = scratch
+        if scratch is not None:
+            if self.batch != 1 or self.method != 0:
+                raise ValueError("a shared scratch serves single CBC calls only")
+            need = scratch_need(ctx, tree, self.max_bond, precision)
+            if scratch.numel() < need["scratch_bytes"]:
+                raise ValueError("shared scratch smaller than this problem needs")
+            self.ws_bytes = need["persistent_bytes"]
+        else:
+            self.ws_bytes = int(ws.value) * self.batch
         self.workspace = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device)
         self.out = torch.zeros(int(self.out_off[-1]) * self.batch, dtype=torch.complex128,
                                device=device)
@@ -242,6 +272,14 @@ class Compressor:
                                            self.prec, self.workspace.data_ptr(), self.ws_bytes,
                                            ctypes.byref(out), ctypes.c_void_p(stream),
                                            ctypes.byref(self.stats)), "cbc_apply_batched")
+            return self.out, self.bond
+        if self.scratch is not None:
+            _check(lib().cbc_apply_split(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns),
+                                         ctypes.byref(self.tree.c), self.max_bond, float(tol),
+                                         self.prec, self.workspace.data_ptr(), self.ws_bytes,
+                                         self.scratch.data_ptr(), self.scratch.numel(),
+                                         ctypes.byref(out), ctypes.c_void_p(stream),
+                                         ctypes.byref(self.stats)), "cbc_apply_split")
             return self.out, self.bond
         fn = lib().cbc_apply if self.method == 0 else lib().cbc_apply_naive
         _check(fn(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns), ctypes.byref(self.tree.c),
@@ -310,53 +348,98 @@ class Compressor:
         return res
 
 
+def graph_groups(launches, cap):
+    """Consecutive groups of instances whose kernel launches add up to at most `cap` (an instance
+    above `cap` forms a group of its own); returns lists of instance indices."""
+    groups, cur, n = [], [], 0
+    for k, m in enumerate(launches):
+        if cur and n + m > cap:
+            groups.append(cur)
+            cur, n = [], 0
+        cur.append(k)
+        n += m
+    if cur:
+        groups.append(cur)
+    return groups
+
+
 class UnevenBatch:
     """Many instances of different shapes: one Compressor (plan, workspace, captured graph) per
     instance, launched round-robin over `nstreams` side streams so that instances overlap on the
-    GPU. Inputs are packed once and stay resident."""
+    GPU. Inputs are packed once and stay resident. With `share_scratch`, the instances of one stream
+    share one scratch buffer (their calls are ordered by the stream), sized for the largest of them:
+    device memory is then the sum of the small persistent parts plus `nstreams` scratch buffers,
+    instead of the sum of every instance's whole workspace."""
 
-    def __init__(self, problems, precision="mixed", nstreams=8, device="cuda", autotune=False):
+    def __init__(self, problems, precision="mixed", nstreams=8, device="cuda", autotune=False,
+                 share_scratch=False):
         import torch
         self.ctx = Context()
         if autotune:
             self.ctx.autotune()
         self.streams = [torch.cuda.Stream(device=device) for _ in range(nstreams)]
+        trees = [Tree.of(p) for p in problems]
+        self.scratch = []
+        if share_scratch:
+            need = [0] * nstreams
+            for k, (p, t) in enumerate(zip(problems, trees)):
+                b = scratch_need(self.ctx, t, p.max_bond, precision)["scratch_bytes"]
+                need[k % nstreams] = max(need[k % nstreams], b)
+            self.scratch = [torch.empty(max(b, 256), dtype=torch.uint8, device=device)
+                            for b in need]
         self.items = []
-        for p in problems:
-            tree = Tree.of(p)
+        for k, (p, tree) in enumerate(zip(problems, trees)):
             st, so = pack(p.state, device)
             op, oo = pack(p.op, device)
-            comp = Compressor(self.ctx, tree, p.max_bond, precision, device=device)
+            comp = Compressor(self.ctx, tree, p.max_bond, precision, device=device,
+                              scratch=self.scratch[k % nstreams] if share_scratch else None)
             self.items.append((comp, (op, oo, st, so, p.tol)))
 
     def run(self):
         """Launch every instance (asynchronous); call torch.cuda.synchronize() to wait."""
-        if getattr(self, "graph", None) is not None:
-            self.graph.replay()
+        if getattr(self, "graphs", None):
+            for g in self.graphs:
+                g.replay()
             return
         for k, (comp, args) in enumerate(self.items):
             s = self.streams[k % len(self.streams)]
             comp.run(*args, stream=s.cuda_stream)
 
-    def capture(self, graph=None):
-        """Record the whole batch (every instance, forked over the streams and joined) into one
-        graph; run() then replays it with a single launch. Runs the batch once first, eagerly.
-        `graph`: a torch.cuda.CUDAGraph to capture into (default: a new one)."""
+    # Kernel launches recorded into one graph at most. Graphs of up to about 10,500 launches (16
+    # instances of the uneven draw) replay correctly on MI355X; one graph of the whole 256-instance
+    # draw (about 159,000 launches) ended the process with a segmentation fault at its first
+    # replay, so larger batches are recorded as several graphs of at most this many launches.
+    MAX_GRAPH_LAUNCHES = 12000
+
+    def capture(self, graph=None, max_launches=None):
+        """Record the batch (every instance, forked over the streams and joined) into graphs of at
+        most `max_launches` kernel launches each (default MAX_GRAPH_LAUNCHES; consecutive
+        instances, at least one per graph); run() then replays them in order, one launch each.
+        Runs the batch once first, eagerly. `graph`: a torch.cuda.CUDAGraph to capture into when
+        the batch fits one graph (default: a new one)."""
         import torch
-        self.graph = None
+        cap = self.MAX_GRAPH_LAUNCHES if max_launches is None else int(max_launches)
+        self.graphs = []
         self.run()
         torch.cuda.synchronize()
-        g = graph if graph is not None else torch.cuda.CUDAGraph()
+        groups = graph_groups([int(comp.stats.n_kernels) for comp, _ in self.items], cap)
+        if graph is not None and len(groups) > 1:
+            raise ValueError("the batch needs several graphs; capture without `graph`")
         root = torch.cuda.Stream(device=self.streams[0].device)
-        with torch.cuda.graph(g, stream=root):
-            for s in self.streams:
-                s.wait_stream(root)
-            for k, (comp, args) in enumerate(self.items):
-                s = self.streams[k % len(self.streams)]
-                comp.run(*args, stream=s.cuda_stream)
-            for s in self.streams:
-                root.wait_stream(s)
-        self.graph = g
+        graphs = []
+        for grp in groups:
+            g = graph if graph is not None else torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=root):
+                for s in self.streams:
+                    s.wait_stream(root)
+                for k in grp:
+                    comp, args = self.items[k]
+                    s = self.streams[k % len(self.streams)]
+                    comp.run(*args, stream=s.cuda_stream)
+                for s in self.streams:
+                    root.wait_stream(s)
+            graphs.append(g)
+        self.graphs = graphs
 
     def flops(self):
         return sum(c.stats.flops[0] for c, _ in self.items)
@@ -370,6 +453,26 @@ def plan_bonds(tree, max_bond, tol_on=False, ctx=None):
                                 bond.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
            "cbc_plan_bonds")
     return [int(b) for b in bond]
+
+
+def scratch_need(ctx, tree, max_bond, precision):
+    """Persistent and scratch bytes a cbc_apply_split call needs with or without a tolerance."""
+    a = plan_info(tree, max_bond, precision, tol_on=False, ctx=ctx)
+    b = plan_info(tree, max_bond, precision, tol_on=True, ctx=ctx)
+    return {k: max(a[k], b[k]) for k in ("persistent_bytes", "scratch_bytes")}
+
+
+def plan_info(tree, max_bond, precision="fp64", method="cbc", tol_on=False, ctx=None):
+    """Planned workspace split and per-class launches and flops of one call (host only)."""
+    ctx = ctx or Context()
+    info = PlanSummary()
+    _check(lib().cbc_plan_info(ctx.h, ctypes.byref(tree.c), int(max_bond), PRECISIONS[precision],
+                               METHODS[method], int(bool(tol_on)), ctypes.byref(info)),
+           "cbc_plan_info")
+    return {"persistent_bytes": int(info.persistent_bytes), "scratch_bytes": int(info.scratch_bytes),
+            "table_bytes": int(info.table_bytes),
+            "launches": {c: int(info.launches[k]) for k, c in enumerate(CLASSES)},
+            "flops": {c: float(info.flops[k]) for k, c in enumerate(CLASSES)}}
 
 
 def compress(problem, precision="fp64", method="cbc", tol=None, ctx=None, device="cuda"):

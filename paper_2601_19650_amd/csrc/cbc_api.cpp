@@ -22,6 +22,8 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -96,8 +98,12 @@ struct Op {
 
 struct Plan {
   std::vector<Op> ops;
+  // offset tables of the contractions: table_entries int32 values, filled on the host only for plans
+  // that will run (sizes-only plans for queries skip them), freed there once copied to d_tables
   std::vector<int32_t> tables;
   int32_t* d_tables = nullptr;
+  int64_t table_entries = 0;
+  bool has_tables = false;
   size_t persist_bytes = 0, scratch_bytes = 0;
   std::vector<int64_t> out_off;
   std::vector<int32_t> out_bond;
@@ -221,6 +227,7 @@ struct Builder {
   size_t persist = 0, scratch = 0, scratch_max = 0;
 
   bool bad = false;         // an internal planning invariant failed (reported as CBC_ESHAPE)
+  bool fill_tables = true;  // false: sizes only (offsets into the tables are still assigned)
   static constexpr int64_t ELEM_LIMIT = (int64_t)1 << 31;   // 32-bit element offsets
 
   Builder(Plan& p, const Problem& q, int mb, bool tol, cbc_precision prec)
@@ -284,9 +291,11 @@ struct Builder {
                 const std::vector<int64_t>& s2, int64_t& t2) {
     int64_t cnt = 1;
     for (int l : legs) cnt *= legdim[l];
-    const int64_t t1 = (int64_t)P.tables.size();
-    P.tables.resize(P.tables.size() + 2 * cnt);
+    const int64_t t1 = P.table_entries;
+    P.table_entries += 2 * cnt;
     t2 = t1 + cnt;
+    if (!fill_tables) return t1;
+    P.tables.resize((size_t)P.table_entries);
     std::vector<int64_t> idx(legs.size(), 0);
     for (int64_t e = 0; e < cnt; ++e) {
       int64_t o1 = 0, o2 = 0;
@@ -414,7 +423,11 @@ struct Builder {
     return r;
   }
 
-  // X = T_i absorbed with envs (slot -> env tensor [chi, alpha, beta]); then contracted with W_i.
+  // T_i contracted with the environments (slot -> env tensor [chi, alpha, beta]) and with W_i. The
+  // operands are taken one at a time, each step the one whose product with the running result has
+  // the fewest elements (ties: environments in slot order, then W_i). Absorbing every environment
+  // before W_i leaves all of a node's operator legs open at once (chi * alpha * D per leg); at nodes
+  // with three or more environments W_i is taken earlier, which bounds the largest intermediate.
   Ten node_contract(int i, const std::vector<std::pair<int, Ten>>& envs, const std::vector<int>& out,
                     const TRef& dst) {
     const auto sa = slot_alpha(i), sb = slot_beta(i);
@@ -426,19 +439,34 @@ struct Builder {
     W.ref = node_ref(S_OP, i);
     W.legs = {sigp[i], sig[i]};
     for (int l : sb) W.legs.push_back(l);
+    std::vector<Ten> rem;
+    for (const auto& se : envs) rem.push_back(se.second);
+    rem.push_back(W);
     Ten X = T;
-    std::vector<bool> absorbed(sa.size(), false);
-    for (const auto& [slot, E] : envs) {
-      std::vector<int> o;
-      for (int l : X.legs)
-        if (l != sa[slot]) o.push_back(l);
-      o.push_back(E.legs[0]);
-      o.push_back(E.legs[2]);
-      Ten Xn = alloc(o, ct, false);
-      X = contract(X, false, E, false, o, Xn.ref, ct, cacc, 0);
-      absorbed[slot] = true;
+    while (rem.size() > 1) {
+      size_t best = 0;
+      int64_t best_e = -1;
+      std::vector<int> best_legs;
+      for (size_t c = 0; c < rem.size(); ++c) {
+        // a leg of both X and rem[c] is summed; every other leg stays (each leg belongs to at most
+        // two of T_i, W_i and the environments, so a summed leg is needed nowhere later)
+        std::vector<int> o;
+        for (int l : X.legs)
+          if (pos(rem[c].legs, l) < 0) o.push_back(l);
+        for (int l : rem[c].legs)
+          if (pos(X.legs, l) < 0) o.push_back(l);
+        const int64_t e = elems(o);
+        if (best_e < 0 || e < best_e) {
+          best = c;
+          best_e = e;
+          best_legs = o;
+        }
+      }
+      Ten Xn = alloc(best_legs, ct, false);
+      X = contract(X, false, rem[best], false, best_legs, Xn.ref, ct, cacc, 0);
+      rem.erase(rem.begin() + (ptrdiff_t)best);
     }
-    return contract(X, false, W, false, out, dst, ct, cacc, 0);
+    return contract(X, false, rem[0], false, out, dst, ct, cacc, 0);
   }
 
   // A truncation eigensolve op: its record (node, sweep) and the status word.
@@ -735,8 +763,10 @@ cbc_status plan_epilogue(Builder& B, Plan& P) {
   return CBC_OK;
 }
 
-cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc_precision prec) {
+cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc_precision prec,
+                      bool fill_tables) {
   Builder B(P, pr, max_bond, tol_on, prec);
+  B.fill_tables = fill_tables;
   const int n = pr.n;
   B.sig.resize(n);
   B.sigp.resize(n);
@@ -945,8 +975,9 @@ cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc
 // the naive (direct) method of Sec. III C: exact product, canonical form, truncated-SVD sweep
 
 cbc_status build_plan_naive(Plan& P, const Problem& pr, int max_bond, bool tol_on,
-                            cbc_precision prec) {
+                            cbc_precision prec, bool fill_tables) {
   Builder B(P, pr, max_bond, tol_on, prec);
+  B.fill_tables = fill_tables;
   const int n = pr.n;
   B.sig.resize(n);
   B.sigp.resize(n);
@@ -1142,6 +1173,7 @@ struct Call {
   bool caller_capture = false;   // recorded into a stream capture of the caller's (or a call of
                                  // cbc_apply_noalloc): eigensolves take the two-stage reduction
   const int32_t* tables = nullptr;   // device copy of the plan's offset tables
+  char* scr = nullptr;   // scratch given apart from the workspace (cbc_apply_split), else null
 };
 
 }  // namespace
@@ -1160,7 +1192,7 @@ namespace {
 void* resolve(const Plan& P, const Call& c, const TRef& r) {
   switch (r.src) {
     case S_WS: return c.ws + r.off;
-    case S_SCR: return c.ws + c.persist + r.off;
+    case S_SCR: return (c.scr ? c.scr : c.ws + c.persist) + r.off;
     case S_STATE:
       if (r.off < 0) return (void*)c.state;
       if (P.state_conv_off >= 0) return c.ws + P.state_conv_off + 8 * c.st_off[r.off];
@@ -1436,34 +1468,47 @@ hipError_t tune_plan(cbc_ctx* ctx, Plan& P, const Call& c, hipStream_t st) {
   return e;
 }
 
+// The context's plan for a problem. need_tables: the plan will run, so its offset tables are built
+// (a plan cached by a query has sizes only and is rebuilt here). Host allocation failures while
+// planning are reported as CBC_ENOMEM.
 cbc_status get_plan(cbc_ctx* ctx, const Problem& pr, int max_bond, bool tol_on, cbc_precision prec,
-                    int method, int64_t state_span, int64_t op_span, Plan** out) {
+                    int method, int64_t state_span, int64_t op_span, Plan** out,
+                    bool need_tables) {
   auto key = plan_key(pr, max_bond, tol_on, prec, method, state_span, op_span);
   key.push_back(ctx->tune ? 1 : 0);
   auto it = ctx->plans.find(key);
-  if (it != ctx->plans.end()) {
+  if (it != ctx->plans.end() && (!need_tables || it->second->has_tables)) {
     *out = it->second.get();
     return CBC_OK;
   }
-  auto P = std::make_unique<Plan>();
-  P->state_elems = state_span;
-  P->op_elems = op_span;
-  P->tune = ctx->tune;
-  cbc_status s = method == 0 ? build_plan(*P, pr, max_bond, tol_on, prec)
-                              : build_plan_naive(*P, pr, max_bond, tol_on, prec);
-  if (s != CBC_OK) return s;
-  if (P->unsupported) return CBC_EUNSUP;
-  *out = P.get();
-  ctx->plans[key] = std::move(P);
+  try {
+    auto P = std::make_unique<Plan>();
+    P->state_elems = state_span;
+    P->op_elems = op_span;
+    P->tune = ctx->tune;
+    cbc_status s = method == 0 ? build_plan(*P, pr, max_bond, tol_on, prec, need_tables)
+                                : build_plan_naive(*P, pr, max_bond, tol_on, prec, need_tables);
+    if (s != CBC_OK) return s;
+    if (P->unsupported) return CBC_EUNSUP;
+    P->has_tables = need_tables;
+    *out = P.get();
+    ctx->plans[key] = std::move(P);
+  } catch (const std::bad_alloc&) {
+    return CBC_ENOMEM;
+  } catch (const std::length_error&) {
+    return CBC_ENOMEM;
+  }
   return CBC_OK;
 }
 
+// Device copy of the plan's offset tables; the host copy is released once it is made.
 cbc_status upload_tables(Plan* P) {
   if (P->d_tables || P->tables.empty()) return CBC_OK;
   if (hipMalloc(&P->d_tables, P->tables.size() * sizeof(int32_t)) != hipSuccess) return CBC_ENOMEM;
   if (hipMemcpy(P->d_tables, P->tables.data(), P->tables.size() * sizeof(int32_t),
                 hipMemcpyHostToDevice) != hipSuccess)
     return CBC_EHIP;
+  std::vector<int32_t>().swap(P->tables);
   return CBC_OK;
 }
 
@@ -1556,12 +1601,37 @@ cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_p
   // the workspace does not depend on tol; plan with tolerance off and on, report the larger
   size_t ws = 0;
   for (int t = 0; t < 2; ++t) {
-    s = get_plan(ctx, pr, max_bond, t == 1, prec, method, se, oe, &P);
+    s = get_plan(ctx, pr, max_bond, t == 1, prec, method, se, oe, &P, false);
     if (s != CBC_OK) return s;
     ws = std::max(ws, P->persist_bytes + P->scratch_bytes);
   }
   *workspace_bytes = ws;
   for (int i = 0; i <= pr.n; ++i) out_offset[i] = P->out_off[i];
+  return CBC_OK;
+}
+
+cbc_status cbc_plan_info(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
+                         int32_t method, int32_t tol_on, cbc_plan_summary* info) {
+  if (!ctx || !info) return CBC_EINVAL;
+  if (method != 0 && method != 1) return CBC_EINVAL;
+  Problem pr;
+  cbc_status s = common_checks(tree, max_bond, prec, pr);
+  if (s != CBC_OK) return s;
+  int64_t se = 0, oe = 0;
+  for (int i = 0; i < pr.n; ++i) {
+    se += tensor_elems_state(pr, i);
+    oe += tensor_elems_op(pr, i);
+  }
+  Plan* P = nullptr;
+  s = get_plan(ctx, pr, max_bond, tol_on != 0, prec, method, se, oe, &P, false);
+  if (s != CBC_OK) return s;
+  info->persistent_bytes = P->persist_bytes;
+  info->scratch_bytes = P->scratch_bytes;
+  info->table_bytes = (size_t)P->table_entries * sizeof(int32_t);
+  for (int k = 0; k < CBC_K_NCLASS; ++k) {
+    info->launches[k] = P->launches[k];
+    info->flops[k] = P->flops[k];
+  }
   return CBC_OK;
 }
 
@@ -1577,7 +1647,7 @@ cbc_status cbc_plan_bonds(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, 
     oe += tensor_elems_op(pr, i);
   }
   Plan* P = nullptr;
-  s = get_plan(ctx, pr, max_bond, tol_on != 0, CBC_PREC_FP64, 0, se, oe, &P);
+  s = get_plan(ctx, pr, max_bond, tol_on != 0, CBC_PREC_FP64, 0, se, oe, &P, false);
   if (s != CBC_OK) return s;
   for (int i = 0; i < pr.n; ++i) bond[i] = P->out_bond[i];
   return CBC_OK;
@@ -1587,9 +1657,12 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
                              const cbc_tree* tree, int32_t max_bond, double tol,
                              cbc_precision prec, void* workspace, size_t workspace_bytes,
                              cbc_out* out, void* stream, cbc_stats* stats, int method,
-                             int32_t batch = 1, bool noalloc = false) {
+                             int32_t batch = 1, bool noalloc = false, void* scratch = nullptr,
+                             size_t scratch_bytes = 0) {
   if (batch < 1 || batch > 65535) return CBC_EINVAL;
   if (noalloc && (batch != 1 || (stats && stats->profile))) return CBC_EINVAL;
+  const bool split = scratch != nullptr;
+  if (split && (batch != 1 || noalloc)) return CBC_EINVAL;
   if (!ctx || !ttno || !ttns || !out || !ttno->data || !ttns->data || !ttno->offset ||
       !ttns->offset || !out->data || !out->offset || !out->bond)
     return CBC_EINVAL;
@@ -1609,14 +1682,14 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
     if (ttno->offset[i] + tensor_elems_op(pr, i) > oe) return CBC_EINVAL;
   }
   Plan* P = nullptr;
-  s = get_plan(ctx, pr, max_bond, tol > 0.0, prec, method, se, oe, &P);
+  s = get_plan(ctx, pr, max_bond, tol > 0.0, prec, method, se, oe, &P, true);
   if (s != CBC_OK) return s;
   const size_t ws_inst = P->persist_bytes + P->scratch_bytes;
   const int32_t* tables = nullptr;
   hipStream_t st = (hipStream_t)stream;
   if (noalloc) {
     // the plan's offset tables, then the workspace, in the static scratch array of this device
-    const size_t tbytes = (P->tables.size() * sizeof(int32_t) + 255) & ~(size_t)255;
+    const size_t tbytes = ((size_t)P->table_entries * sizeof(int32_t) + 255) & ~(size_t)255;
     if (tbytes + ws_inst > NOALLOC_SCRATCH_BYTES) return CBC_EUNSUP;
     void* base = nullptr;
     if (noalloc_scratch(&base) != hipSuccess) return CBC_EHIP;
@@ -1624,14 +1697,24 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
     workspace_bytes = ws_inst;
     tables = (const int32_t*)base;
   }
-  if (!workspace || workspace_bytes / (size_t)batch < ws_inst) return CBC_ENOMEM;
+  if (split) {
+    if (!workspace || workspace_bytes < P->persist_bytes || scratch_bytes < P->scratch_bytes)
+      return CBC_ENOMEM;
+  } else if (!workspace || workspace_bytes / (size_t)batch < ws_inst) {
+    return CBC_ENOMEM;
+  }
   for (int i = 0; i <= pr.n; ++i)
     if (out->offset[i] != P->out_off[i]) return CBC_EINVAL;
   if (noalloc) {
-    if (!P->tables.empty() &&
-        hipMemcpyAsync((void*)tables, P->tables.data(), P->tables.size() * sizeof(int32_t),
-                       hipMemcpyHostToDevice, st) != hipSuccess)
-      return CBC_EHIP;
+    // from the host copy, or device to device once a cbc_apply call has moved them there
+    const size_t tb = (size_t)P->table_entries * sizeof(int32_t);
+    if (tb > 0) {
+      const hipError_t e =
+          P->tables.empty()
+              ? hipMemcpyAsync((void*)tables, P->d_tables, tb, hipMemcpyDeviceToDevice, st)
+              : hipMemcpyAsync((void*)tables, P->tables.data(), tb, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return CBC_EHIP;
+    }
   } else {
     s = upload_tables(P);
     if (s != CBC_OK) return s;
@@ -1655,6 +1738,7 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   c.op_inst = 16 * oe;
   c.out_inst = 16 * P->out_off[pr.n];
   c.tables = tables;
+  c.scr = (char*)scratch;
   const bool profile = stats && stats->profile;
   int replayed = 0;
   if (!noalloc && P->tune && ctx->tune && P->tuned_batch != batch &&
@@ -1684,7 +1768,7 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   } else if (st != nullptr) {
     // replay a captured graph of the whole launch sequence when the buffers are unchanged
     std::vector<uintptr_t> key{(uintptr_t)c.ws, (uintptr_t)c.state, (uintptr_t)c.op,
-                               (uintptr_t)c.out, (uintptr_t)batch};
+                               (uintptr_t)c.out, (uintptr_t)batch, (uintptr_t)c.scr};
     uint64_t tb;
     memcpy(&tb, &tol, sizeof(tb));
     key.push_back((uintptr_t)tb);
@@ -1789,6 +1873,15 @@ cbc_status cbc_apply_noalloc(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
                              cbc_out* out, void* stream, cbc_stats* stats) {
   return apply_impl(ctx, ttno, ttns, tree, max_bond, tol, prec, nullptr, 0, out, stream, stats, 0,
                     1, true);
+}
+
+cbc_status cbc_apply_split(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                           const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
+                           void* workspace, size_t workspace_bytes, void* scratch,
+                           size_t scratch_bytes, cbc_out* out, void* stream, cbc_stats* stats) {
+  if (!scratch) return CBC_EINVAL;
+  return apply_impl(ctx, ttno, ttns, tree, max_bond, tol, prec, workspace, workspace_bytes, out,
+                    stream, stats, 0, 1, false, scratch, scratch_bytes);
 }
 
 cbc_status cbc_apply_batched(cbc_ctx* ctx, int32_t batch, const cbc_tensors* ttno,

@@ -114,11 +114,6 @@ hipError_t launch_eig(const EigArgs& a, hipStream_t st);
 hipError_t mw_gate_enter(hipStream_t st);
 hipError_t mw_gate_leave(hipStream_t st);
 
-// device status word: store `code` if the word still holds CBC_OK
-__device__ inline void raise_status(int* status, int code) {
-  if (status) atomicCAS(status, 0, code);
-}
-
 // n-side truncation output: L[j, c] = sqrt(max(lam_j, 0)) / sqrt(lam_0) * conj(V[c, j]) for j < kkeep,
 // zero for kkeep <= j < kmax. L is kmax x n, written in the contraction precision.
 hipError_t launch_form_l_nside(const double2* V, const double* lam, const int* kkeep, int n,

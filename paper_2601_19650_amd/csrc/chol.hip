@@ -14,6 +14,7 @@
 #include <algorithm>
 
 #include "cbc_internal.h"
+#include "device_status.h"
 
 namespace cbc {
 

@@ -5,6 +5,7 @@
 #include <float.h>
 
 #include "cbc_internal.h"
+#include "device_status.h"
 
 namespace cbc {
 

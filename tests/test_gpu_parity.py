@@ -403,10 +403,10 @@ def c5_subset():
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_c5_subset_parity(lib, c5_subset, prec):
     """A 16-instance subset of the uneven batch workload launched as the benchmark launches the
-    batch (forked over streams, captured into one graph and replayed): every instance matches the
-    oracle to the bar of its precision."""
+    batch (forked over streams, the instances of each stream sharing one scratch buffer, captured
+    into one graph and replayed): every instance matches the oracle to the bar of its precision."""
     probs, refs = c5_subset
-    ub = lib.UnevenBatch(probs, precision=prec, nstreams=8)
+    ub = lib.UnevenBatch(probs, precision=prec, nstreams=8, share_scratch=True)
     ub.capture()
     for comp, _ in ub.items:
         comp.out.zero_()
@@ -466,3 +466,40 @@ def test_paper_random_networks_naive_parity(lib, kind, prec):
         assert tn.rel_error(p.parent, out, ref) <= FP64_BAR
     else:
         assert 1.0 - tn.fidelity(p.parent, out, ref) <= MIXED_BAR
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_apply_split_matches_apply(lib, prec):
+    """cbc_apply_split (persistent workspace and scratch in separate buffers) returns bitwise what
+    cbc_apply returns, also when two problems of different shapes share one scratch buffer and run
+    one after the other on one stream, each replaying its captured graph."""
+    probs = [config_problem("C3"),
+             random_problem(kary_parent(13, 3), 2, 6, 3, 5, seed=4, name="ter13"),
+             random_problem(chain_parent(10), 3, 9, 4, 7, seed=2, name="mps10d3")]
+    ctx = lib.Context()
+    need = max(lib.scratch_need(ctx, lib.Tree.of(p), p.max_bond, prec)["scratch_bytes"]
+               for p in probs)
+    scratch = torch.empty(need, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    runs = []
+    for p in probs:
+        print(f"split {p.name} prec={prec}", flush=True)
+        tree = lib.Tree.of(p)
+        st, so = lib.pack(p.state, "cuda")
+        op, oo = lib.pack(p.op, "cuda")
+        whole = lib.Compressor(ctx, tree, p.max_bond, prec, device="cuda")
+        split = lib.Compressor(ctx, tree, p.max_bond, prec, device="cuda", scratch=scratch)
+        assert split.ws_bytes < whole.ws_bytes
+        whole.run(op, oo, st, so, 0.0, stream=stream.cuda_stream)
+        runs.append((p, split, (op, oo, st, so), whole.unpack()))
+    for rep in range(2):
+        scratch.fill_(255)
+        torch.cuda.synchronize()
+        for p, split, args, _ in runs:
+            split.run(*args, 0.0, stream=stream.cuda_stream)
+        torch.cuda.synchronize()
+        for p, split, args, ref in runs:
+            got = split.unpack()
+            assert split.report(stream=stream.cuda_stream)["status"] == "ok"
+            for a, b in zip(got, ref):
+                assert a.shape == b.shape and np.array_equal(a, b), (p.name, rep)

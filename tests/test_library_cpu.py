@@ -221,3 +221,105 @@ def test_status_strings():
     for code in range(-8, 1):
         assert L.cbc_status_str(code)
     assert b"wait" in L.cbc_status_str(-8)
+
+
+def test_plan_info_splits_the_queried_workspace():
+    """cbc_plan_info needs no device: its persistent and scratch parts add up to cbc_query's
+    workspace (the larger of the plans with and without a tolerance), and its per-class flops are
+    the planner's algorithmic counts (a 31-node binary tree: Cholesky-QRs of three passes at the
+    non-root nodes whose joined leg exceeds the environment bond, none where Q is the identity)."""
+    p = config_problem("C3")
+    tree = cbc.Tree.of(p)
+    for prec in ("fp64", "mixed"):
+        ctx = cbc.Context()
+        infos = [cbc.plan_info(tree, p.max_bond, prec, tol_on=t, ctx=ctx) for t in (False, True)]
+        rc, ws, _ = _query(tree, p.max_bond, cbc.PRECISIONS[prec])
+        assert rc == 0
+        assert ws == max(i["persistent_bytes"] + i["scratch_bytes"] for i in infos)
+        for i in infos:
+            assert i["persistent_bytes"] > 0 and i["scratch_bytes"] > 0 and i["table_bytes"] > 0
+            nq = i["launches"]["chol"]
+            assert nq % 3 == 0 and 0 < nq <= 3 * (p.n - 1)
+            assert all(v >= 0 for v in i["flops"].values()) and i["flops"]["contract"] > 0
+    # naive plans are described as well
+    assert cbc.plan_info(tree, p.max_bond, "fp64", method="naive")["flops"]["eig"] > 0
+
+
+def test_apply_split_argument_errors_need_no_device():
+    """cbc_apply_split rejects a null scratch and buffers below the planned parts before any
+    device work."""
+    p = config_problem("C1")
+    tree = cbc.Tree.of(p)
+    ctx = cbc.Context()
+    info = cbc.plan_info(tree, p.max_bond, "fp64", ctx=ctx)
+    I64 = ctypes.POINTER(ctypes.c_int64)
+    off = np.zeros(p.n, dtype=np.int64)
+    off[1:] = np.cumsum([t.size for t in p.state])[:-1]
+    ooff = np.zeros(p.n, dtype=np.int64)
+    ooff[1:] = np.cumsum([w.size for w in p.op])[:-1]
+    rc, ws, outoff = _query(tree, p.max_bond)
+    bond = np.zeros(p.n, dtype=np.int32)
+    ttns = cbc._Tensors(0x1000, off.ctypes.data_as(I64))
+    ttno = cbc._Tensors(0x1000, ooff.ctypes.data_as(I64))
+    out = cbc._Out(0x1000, outoff.ctypes.data_as(I64), bond.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    f = cbc.lib().cbc_apply_split
+    pb, sb = info["persistent_bytes"], info["scratch_bytes"]
+    call = lambda wsb, scr, scrb: f(ctx.h, ctypes.byref(ttno), ctypes.byref(ttns), ctypes.byref(tree.c),
+                                    p.max_bond, 0.0, 0, 0x1000, wsb, scr, scrb, ctypes.byref(out),
+                                    None, None)
+    assert call(pb, None, sb) == -1
+    assert call(pb - 1, 0x2000, sb) == -3
+    assert call(pb, 0x2000, sb - 1) == -3
+
+
+def test_ternary_node_contraction_order_fits_offsets():
+    """At a node with a parent and three children the operator tensor is contracted after two of
+    the three environments: taking every environment first would leave sigma * alpha_p * (chi *
+    alpha * D)^3 elements open at once (here 4 * 32 * (32 * 12)^3 = 7.2e9, beyond the kernels'
+    32-bit offsets), while the chosen order peaks at 6.0e8 elements. Ternary trees of the uneven
+    batch workload with d = 4, chi = 32, D = 12 are therefore supported."""
+    parent = kary_parent(13, 3)
+    from paper_2601_19650_amd.inputs import cut_bonds
+    phys = [4] * 13
+    tree = cbc.Tree(parent, phys, cut_bonds(parent, phys, 32, 1), cut_bonds(parent, phys, 12, 2))
+    assert _query(tree, max_bond=32)[0] == 0
+    info = cbc.plan_info(tree, 32, "mixed")
+    # the largest scratch intermediate holds 6.0e8 complex64 elements (two live at once)
+    assert info["scratch_bytes"] < 3 * 8 * 4 * 32 ** 4 * 12 * 12
+
+
+def test_query_plans_without_tables_stay_small():
+    """Plans built for queries hold no offset tables on the host, so sizing the whole 256-instance
+    uneven batch draw in one context takes seconds and little memory."""
+    import resource
+    import time
+    from paper_2601_19650_amd.inputs import _parent_of, batch_shapes, cut_bonds
+    ctx = cbc.Context()
+    t0 = time.perf_counter()
+    rss0 = resource.getrusage(resource.RUSAGE_SELF).ru_maxrss
+    unsupported = 0
+    for j, kind, n, d, chi, D, _ in batch_shapes():
+        parent = _parent_of(kind, n)
+        tree = cbc.Tree(parent, [d] * n, cut_bonds(parent, [d] * n, chi, 1),
+                        cut_bonds(parent, [d] * n, D, 2))
+        ws = ctypes.c_size_t()
+        off = np.zeros(n + 1, dtype=np.int64)
+        rc = cbc.lib().cbc_query(ctx.h, ctypes.byref(tree.c), chi, 1, 0, ctypes.byref(ws),
+                                 off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+        unsupported += rc == -6
+        assert rc in (0, -6)
+    assert unsupported == 0
+    assert time.perf_counter() - t0 < 60
+    assert resource.getrusage(resource.RUSAGE_SELF).ru_maxrss - rss0 < 2_000_000   # KiB
+
+
+def test_uneven_batch_graph_groups():
+    """Batches are recorded as consecutive groups of at most `cap` launches; an instance larger
+    than the cap forms a group of its own, and every instance is in exactly one group."""
+    assert cbc.graph_groups([5, 5, 5], 10) == [[0, 1], [2]]
+    assert cbc.graph_groups([5, 20, 5, 5], 10) == [[0], [1], [2, 3]]
+    assert cbc.graph_groups([], 10) == []
+    counts = [int(x) for x in np.random.default_rng(0).integers(50, 1200, 256)]
+    groups = cbc.graph_groups(counts, cbc.UnevenBatch.MAX_GRAPH_LAUNCHES)
+    assert [k for g in groups for k in g] == list(range(256))
+    assert all(sum(counts[k] for k in g) <= cbc.UnevenBatch.MAX_GRAPH_LAUNCHES for g in groups)
