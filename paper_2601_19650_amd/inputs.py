@@ -32,7 +32,7 @@ import numpy as np
 __all__ = [
     "Problem", "chain_parent", "kary_parent", "cut_bonds", "random_problem",
     "config_problem", "batch_problems", "batch_shapes", "CONFIGS",
-    "t_tree", "balanced_binary", "fork_tree", "paper_problem", "PAPER_WORKLOADS",
+    "t_tree", "balanced_binary", "fork_tree", "paper_problem", "PAPER_WORKLOADS", "sketch_matrices",
 ]
 
 
@@ -320,3 +320,15 @@ def paper_problem(kind, max_bond, size=None, bond=None, seed=7):
     D = bond if bond is not None else D
     return random_problem(parent, phys, D, D, max_bond, seed, dist="paper",
                           name=f"paper-{kind}-L{size if size is not None else L}-D{D}-Dbar{max_bond}")
+
+
+def sketch_matrices(phys, width, seed):
+    """Random sketch matrices of the randomised compression (one per node, d_i x width): complex
+    Gaussian entries (N(0,1) + i N(0,1))/sqrt(2), drawn node by node from default_rng(seed)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for d in phys:
+        re = rng.standard_normal((int(d), int(width)))
+        im = rng.standard_normal((int(d), int(width)))
+        out.append((re + 1j * im) / math.sqrt(2.0))
+    return out

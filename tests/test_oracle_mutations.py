@@ -97,3 +97,74 @@ def test_mutation_is_caught(name, old, new):
     assert ORACLE_SRC.count(old) == 1, f"mutation site not unique: {old!r}"
     failed = _failing_checks(ORACLE_SRC.replace(old, new))
     assert failed, f"no pin catches: {name}"
+
+
+# ---------------------------------------------------------------------------------------------
+# the SRC oracle (oracle/src.py) and its pins (tests/test_oracle_src_pins.py)
+
+import oracle.src as osrc  # noqa: E402
+
+SRC_SRC = open(osrc.__file__).read()
+
+
+def _load_src_pins():
+    spec = importlib.util.spec_from_file_location("src_pins_for_mutation",
+                                                  os.path.join(HERE, "test_oracle_src_pins.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+SRC_PINS = _load_src_pins()
+_C = {c[0]: c[1:] for c in SRC_PINS.CASES}
+
+SRC_CHECKS = [
+    ("dense formulation, chain", lambda: SRC_PINS.test_src_dense_formulation("chain7", *_C["chain7"])),
+    ("dense formulation, binary", lambda: SRC_PINS.test_src_dense_formulation("bin7", *_C["bin7"])),
+    ("dense formulation, ternary", lambda: SRC_PINS.test_src_dense_formulation("ter10", *_C["ter10"])),
+    ("projection, isometries, Eckart-Young", lambda: SRC_PINS.test_src_projection_isometries_and_eckart_young(
+        "uneven9", *_C["uneven9"])),
+    ("exact when the sketch covers the ranks", lambda: SRC_PINS.test_src_exact_when_the_sketch_covers_every_rank()),
+]
+
+SRC_MUTATIONS = [
+    ("sketch conjugated", "    terms.append((om, [sigp, r]))", "    terms.append((om.conj(), [sigp, r]))"),
+    ("sketch on the input physical leg", "    terms.append((om, [sigp, r]))", "    terms.append((om, [sig, r]))"),
+    ("sweep 2 omits the siblings' sketches", "envs[1 + j] = ksub[c]", "pass"),
+    ("sweep 2 omits the parent's sketch", "                envs[0] = epar[i]", "                pass"),
+    ("sweep 3 bases from Z instead of Z E", "            y = zm @ epar[i].reshape(shp[-2] * shp[-1], max_bond)",
+     "            y = zm[:, :max_bond]"),
+    ("R update without conj(Q)", "renv[i] = (q.conj().T @ zm)", "renv[i] = (q.T @ zm)"),
+    ("sweep 3 attaches the children's R in reverse order", "envs = {1 + j: renv[c] for j, c in enumerate(ch[i])}",
+     "envs = {len(ch[i]) - j: renv[c] for j, c in enumerate(ch[i])}"),
+    ("operator legs transposed in the sketch", "    terms.append((w, [sigp, sig] + beta))\n    terms.append((om",
+     "    terms.append((w, [sig, sigp] + beta))\n    terms.append((om"),
+]
+
+
+def _failing_src_checks(src):
+    mod = types.ModuleType("src_oracle_mutant")
+    exec(compile(src, "src_oracle_mutant", "exec"), mod.__dict__)
+    saved = SRC_PINS.src_tree
+    SRC_PINS.src_tree = mod.src_tree
+    failed = []
+    try:
+        for name, fn in SRC_CHECKS:
+            try:
+                fn()
+            except Exception:
+                failed.append(name)
+    finally:
+        SRC_PINS.src_tree = saved
+    return failed
+
+
+def test_unmutated_src_oracle_passes_every_check():
+    assert _failing_src_checks(SRC_SRC) == []
+
+
+@pytest.mark.parametrize("name,old,new", SRC_MUTATIONS, ids=[m[0] for m in SRC_MUTATIONS])
+def test_src_mutation_is_caught(name, old, new):
+    assert SRC_SRC.count(old) == 1, f"mutation site not unique: {old!r}"
+    failed = _failing_src_checks(SRC_SRC.replace(old, new))
+    assert failed, f"no pin catches: {name}"
