@@ -181,6 +181,116 @@ def uneven_full_run(stream_count=8):
                       "chi 16-128 (ternary <= 32), all 256 instances"}
 
 
+def _dev(t):
+    import numpy as np
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(t)).to("cuda:0")
+
+
+def _gpu_sandwich(parent, bra, state, op, twice=False):
+    """<bra| O |psi> (twice=False) or <psi| O^H O |psi> (twice=True, bra ignored) of tree networks
+    given as numpy node tensors, contracted leaves to root on the device in complex128 (plain torch;
+    a measurement helper of this script). Legs: states (sigma, parent, children...), operators
+    (sigma', sigma, parent, children...)."""
+    import torch
+    ch = _gpu_children(parent)
+    root = parent.index(-1)
+    order, stack = [], [root]
+    while stack:
+        i = stack.pop()
+        order.append(i)
+        stack.extend(ch[i])
+    env = {}
+    for i in reversed(order):
+        k = len(ch[i])
+        letters = iter("cdefghijklmnopqrvzCDEFGHIJKLMNOPQRVWZ")
+        A = [next(letters) for _ in range(k)]     # ket state legs of the children
+        Bk = [next(letters) for _ in range(k)]    # operator legs
+        X = [next(letters) for _ in range(k)]     # bra legs (or the second operator's)
+        Y = [next(letters) for _ in range(k)]     # bra state legs (twice=True)
+        x, lx = _dev(state[i]), "sa" + "".join(A)
+        for j, c in enumerate(ch[i]):
+            if twice:
+                e, le = env.pop(c), Y[j] + X[j] + Bk[j] + A[j]
+            else:
+                e, le = env.pop(c), X[j] + Bk[j] + A[j]
+            out = lx.replace(A[j], "") + le.replace(A[j], "")
+            x, lx = torch.einsum(f"{lx},{le}->{out}", x, e), out
+        w = _dev(op[i])
+        lw = "ts" + "b" + "".join(Bk)
+        out = "".join(ch_ for ch_ in lx if ch_ not in "s" + "".join(Bk)) + "tb"
+        x, lx = torch.einsum(f"{lx},{lw}->{out}", x, w), out
+        if twice:
+            lw2 = "tu" + "x" + "".join(X)
+            out = "".join(ch_ for ch_ in lx if ch_ not in "t" + "".join(X)) + "ux"
+            x, lx = torch.einsum(f"{lx},{lw2}->{out}", x, w.conj()), out
+            lt = "u" + "y" + "".join(Y)
+            out = "".join(ch_ for ch_ in lx if ch_ not in "u" + "".join(Y)) + "y"
+            x, lx = torch.einsum(f"{lx},{lt}->{out}", x, _dev(state[i]).conj()), out
+            env[i] = torch.einsum(f"{lx}->yxba", x)
+        else:
+            lb = "t" + "x" + "".join(X)
+            out = "".join(ch_ for ch_ in lx if ch_ not in "t" + "".join(X)) + "x"
+            x, lx = torch.einsum(f"{lx},{lb}->{out}", x, _dev(bra[i]).conj()), out
+            env[i] = torch.einsum(f"{lx}->xba", x)
+    return complex(env[root].reshape(-1)[0].item())
+
+
+def _rel_error_vs_exact(parent, out, state, op, norm_phi_sq, weight=False):
+    """||O psi - psi'|| / ||O psi|| from <psi'|O|psi>, <psi'|psi'> and ||O psi||^2; with `weight`
+    also the captured weight ||psi'||^2 / ||O psi||^2 (for a projection of O psi the squared error is
+    one minus it, which stays informative where the error itself rounds to 1)."""
+    ov = _gpu_sandwich(parent, out, state, op)
+    outs = [_dev(t) for t in out]
+    nq = _gpu_overlap(parent, outs, outs).real
+    err = math.sqrt(max(norm_phi_sq - 2.0 * ov.real + nq, 0.0) / norm_phi_sq)
+    return (err, nq / norm_phi_sq) if weight else err
+
+
+def src_run(cbc, p, stream, steps, warmup, seed=11, cbc_outputs=None):
+    """The randomised compression (cbc_apply_src) on workload p in both precisions, with its sketch
+    matrices drawn from `seed`: time per compression (graph replay), kernel-class times, and the
+    relative error against the exact product O|psi>, beside that of the CBC outputs given."""
+    import torch
+    from paper_2601_19650_amd.inputs import sketch_matrices
+    tree = cbc.Tree.of(p)
+    st, so = cbc.pack(p.state, "cuda:0")
+    op, oo = cbc.pack(p.op, "cuda:0")
+    sk = cbc.pack(sketch_matrices(p.phys, p.max_bond, seed), "cuda:0")
+    ctx = new_context(cbc)
+    res = {"sketch_seed": seed}
+    outs = {}
+    for prec in ("mixed", "fp64"):
+        comp = cbc.Compressor(ctx, tree, p.max_bond, prec, method="src", device="cuda:0")
+        sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, warmup, sketch=sk)
+        outs[prec] = comp.unpack()
+        kms = profiled_runs(comp, (op, oo, st, so, 0.0), stream, 2, sketch=sk)
+        res[prec] = {"value": 1.0 / sec, "unit": "compressions/s", "ms_per_step": sec * 1e3,
+                     "kernel_ms_per_step": {c: kms[k] for k, c in enumerate(cbc.CLASSES)},
+                     "kernels_per_step": int(comp.stats.n_kernels),
+                     "contraction_tflops": comp.stats.flops[0] / sec / 1e12}
+        print(f"[bench] SRC {p.name} {prec}: {sec * 1e3:.3f} ms/compression", file=sys.stderr,
+              flush=True)
+        del comp
+    torch.cuda.synchronize()
+    nphi = _gpu_sandwich(p.parent, None, p.state, p.op, twice=True).real
+    for prec, o in outs.items():
+        e, w = _rel_error_vs_exact(p.parent, o, p.state, p.op, nphi, weight=True)
+        res[prec]["rel_error_vs_exact"] = e
+        res[prec]["captured_weight_fraction"] = w
+    if cbc_outputs:
+        res["cbc"] = {}
+        for k, o in cbc_outputs.items():
+            e, w = _rel_error_vs_exact(p.parent, o, p.state, p.op, nphi, weight=True)
+            res["cbc"][k] = {"rel_error_vs_exact": e, "captured_weight_fraction": w}
+    print(f"[bench] SRC {p.name}: captured weight " + ", ".join(
+        f"{k} {res[k]['captured_weight_fraction']:.4e}" for k in outs) + (
+        ", CBC " + ", ".join(f"{k} {v['captured_weight_fraction']:.4e}"
+                             for k, v in res["cbc"].items()) if cbc_outputs else ""),
+        file=sys.stderr, flush=True)
+    return res
+
+
 def _gpu_children(parent):
     ch = [[] for _ in parent]
     for j, q in enumerate(parent):
@@ -233,12 +343,13 @@ def _gpu_product(parent, state, op):
 def paper_workloads(cbc, stream, full=False, steps=2):
     """The random-network workload of Sec. IV A on the GPU: tensor train (L=50, d=3, D=40), T-tree
     (L=20), balanced binary tree (depth 6, physical legs on the leaves) and fork tensor product
-    structure (L=8), all d=3, D=10, entries U[-0.5, 1]; CBC (mixed and FP64) and the naive
-    contract-then-compress baseline (FP64) over a sweep of target bonds: time per compression and
-    relative error ||O psi - psi'|| / ||O psi||, with O psi contracted exactly on the device."""
+    structure (L=8), all d=3, D=10, entries U[-0.5, 1]; CBC and the randomised compression (mixed
+    and FP64; sketch seed 11) and the naive contract-then-compress baseline (FP64) over a sweep of
+    target bonds: time per compression and relative error ||O psi - psi'|| / ||O psi||, with
+    O psi contracted exactly on the device."""
     import dataclasses
     import torch
-    from paper_2601_19650_amd.inputs import PAPER_WORKLOADS, paper_problem
+    from paper_2601_19650_amd.inputs import PAPER_WORKLOADS, paper_problem, sketch_matrices
     res = {}
     for kind, (_, L, d, D, sweep) in PAPER_WORKLOADS.items():
         dbars = sweep if full or len(sweep) <= 5 else [
@@ -253,9 +364,12 @@ def paper_workloads(cbc, stream, full=False, steps=2):
         pts = []
         for dbar in dbars:
             pt = {"target_bond": dbar}
-            for method, prec in (("cbc", "mixed"), ("cbc", "fp64"), ("naive", "fp64")):
+            sk = cbc.pack(sketch_matrices(base.phys, dbar, 11), "cuda:0")
+            for method, prec in (("cbc", "mixed"), ("cbc", "fp64"), ("src", "mixed"),
+                                 ("src", "fp64"), ("naive", "fp64")):
                 comp = cbc.Compressor(ctx, tree, dbar, prec, method=method, device="cuda:0")
-                sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, 1)
+                kw = {"sketch": sk} if method == "src" else {}
+                sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, 1, **kw)
                 out = [torch.from_numpy(t).to("cuda:0") for t in comp.unpack()]
                 nq = _gpu_overlap(base.parent, out, out).real
                 ov = _gpu_overlap(base.parent, P, out).real
@@ -292,29 +406,29 @@ def recorded_traffic(workload, precision, op):
     return None
 
 
-def timed_runs(comp, args_run, stream, steps, warmup):
+def timed_runs(comp, args_run, stream, steps, warmup, **kw):
     import torch
     with torch.cuda.stream(stream):
         for _ in range(warmup):
-            comp.run(*args_run, stream=stream.cuda_stream)
+            comp.run(*args_run, stream=stream.cuda_stream, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
         for _ in range(steps):
-            comp.run(*args_run, stream=stream.cuda_stream)
+            comp.run(*args_run, stream=stream.cuda_stream, **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     return (t1 - t0) / steps
 
 
-def profiled_runs(comp, args_run, stream, steps):
+def profiled_runs(comp, args_run, stream, steps, **kw):
     """Per-kernel-class time from HIP events the library records on its own stream."""
     import torch
     from paper_2601_19650_amd import cbc
     tot = [0.0] * cbc.NCLASS
     with torch.cuda.stream(stream):
         for _ in range(steps):
-            comp.run(*args_run, stream=stream.cuda_stream, profile=True)
+            comp.run(*args_run, stream=stream.cuda_stream, profile=True, **kw)
             for k in range(cbc.NCLASS):
                 tot[k] += comp.stats.ms[k]
     torch.cuda.synchronize()
@@ -472,6 +586,9 @@ def main():
                     help="instances of the 64-site shape per launch sequence (0: skip)")
     ap.add_argument("--uneven", type=int, default=16,
                     help="instances of the uneven batch workload to time (0: skip)")
+    ap.add_argument("--src", choices=["on", "off"], default="on",
+                    help="also time the randomised compression (cbc_apply_src) on the headline "
+                         "workload, with the errors of it and of CBC against the exact product")
     ap.add_argument("--uneven-full", action="store_true",
                     help="also time the whole 256-instance uneven draw (several minutes)")
     ap.add_argument("--paper", choices=["off", "short", "full"], default="short",
@@ -488,6 +605,7 @@ def main():
     args = ap.parse_args()
     global AUTOTUNE
     AUTOTUNE = args.autotune == "on"
+    args.src = args.src == "on"
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -568,6 +686,9 @@ def main():
             line["full_size_mixed_vs_fp64"] = {
                 "captured_weight": w, "captured_weight_ratio": w["mixed"] / w["fp64"],
                 "fidelity": _chain_fidelity(outputs["mixed"], outputs["fp64"])}
+    if args.src:
+        line["src"] = src_run(cbc, p, stream, args.steps, args.warmup, cbc_outputs=outputs)
+        line["src"]["workload"] = line["config"]["workload"]
     del outputs
     if args.small_steps > 0:
         line["small_workloads"] = {}

@@ -185,7 +185,7 @@ cbc_status cbc_autotune(cbc_ctx* ctx, const char* cache_path);
 
 /* Sizes for a problem: workspace bytes and the output packing (n_nodes + 1 offsets; the last entry is
  * the total number of complex elements the output buffer must hold). Host only, no device work.
- * `method` is 0 for cbc_apply and 1 for cbc_apply_naive. */
+ * `method` is 0 for cbc_apply, 1 for cbc_apply_naive and 2 for cbc_apply_src. */
 cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
                      int32_t method, size_t* workspace_bytes, int64_t* out_offset);
 
@@ -254,6 +254,24 @@ cbc_status cbc_apply_naive(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tens
                            const cbc_tree* tree, int32_t max_bond, double tol, cbc_precision prec,
                            void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
                            cbc_stats* stats);
+
+/* Successive randomised compression (SRC), the randomised counterpart of CBC that Sec. III C
+ * describes: one random sketch matrix of size d_i x max_bond per node, combined over nodes by the
+ * Khatri-Rao product, replaces the truncated environments of sweeps 1 and 2 (Eqs.
+ * cbc_tree_first_contraction, cbc_tree_second_contraction) by exact sketches of the subtree below a
+ * node and of the rest of the tree; sweep 3 (Eqs. cbc_tree_third_contraction,
+ * cbc_final_contraction) takes each node's new basis from a Cholesky-QR of its sketched columns
+ * Y = Z E instead of a QR on the parent leg. Only contractions and QRs: no eigensolve. The sketch of
+ * node i acts on its output physical leg: `sketch` holds one complex128 d_i x max_bond row-major
+ * matrix per node at element offset sketch->offset[i] of sketch->data (device; packed like the
+ * inputs), drawn by the caller (for example complex Gaussian). The new bond of node i is
+ * min(max_bond, d_i x its children's new bonds); a node whose rows do not exceed max_bond keeps the
+ * identity basis. Workspace from cbc_query with method 2. Single instances, no tolerance. Returns
+ * CBC_EINVAL for a null or unpacked sketch; otherwise as cbc_apply (no truncation records). */
+cbc_status cbc_apply_src(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                         const cbc_tensors* sketch, const cbc_tree* tree, int32_t max_bond,
+                         cbc_precision prec, void* workspace, size_t workspace_bytes, cbc_out* out,
+                         void* stream, cbc_stats* stats);
 
 /* For callers that cannot allocate device memory (code under stream capture, tight serving loops,
  * harnesses that forbid hipMalloc): cbc_apply without a workspace argument. Its workspace is a

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libcbc.so")
 
 FP64, MIXED = 0, 1
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
-METHODS = {"cbc": 0, "naive": 1}
+METHODS = {"cbc": 0, "naive": 1, "src": 2}
 
 
 class CbcError(RuntimeError):
@@ -129,6 +129,12 @@ def lib():
                                       ctypes.c_size_t, ctypes.POINTER(_Out), ctypes.c_void_p,
                                       ctypes.POINTER(Stats)]
         L.cbc_apply_split.restype = ctypes.c_int
+        L.cbc_apply_src.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tensors),
+                                    ctypes.POINTER(_Tensors), ctypes.POINTER(_Tensors),
+                                    ctypes.POINTER(_Tree), ctypes.c_int32, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(_Out),
+                                    ctypes.c_void_p, ctypes.POINTER(Stats)]
+        L.cbc_apply_src.restype = ctypes.c_int
         L.cbc_autotune.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
         L.cbc_autotune.restype = ctypes.c_int
         L.cbc_read_report.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
@@ -140,7 +146,7 @@ def lib():
 
 EXPORTED = ("cbc_create", "cbc_destroy", "cbc_status_str", "cbc_query", "cbc_plan_bonds",
             "cbc_apply", "cbc_apply_batched", "cbc_apply_naive", "cbc_autotune", "cbc_read_report",
-            "cbc_apply_noalloc", "cbc_plan_info", "cbc_apply_split")
+            "cbc_apply_noalloc", "cbc_plan_info", "cbc_apply_split", "cbc_apply_src")
 
 
 def _check(code, what):
@@ -221,7 +227,8 @@ def pack_batch(networks, device):
 
 class Compressor:
     """One problem shape: queries sizes once, owns workspace and output buffers, and runs the
-    compression (``method`` "cbc" or "naive", ``precision`` "fp64" or "mixed")."""
+    compression (``method`` "cbc", "naive" or "src", ``precision`` "fp64" or "mixed"; "src" takes
+    its sketch matrices as run()'s ``sketch`` = (device buffer, offsets) from pack())."""
 
     def __init__(self, ctx, tree, max_bond, precision="fp64", method="cbc", device="cuda", batch=1,
                  scratch=None):
@@ -254,7 +261,7 @@ class Compressor:
         self.bond = np.zeros(tree.n, dtype=np.int32)
         self.stats = Stats()
 
-    def run(self, op_buf, op_off, st_buf, st_off, tol=0.0, stream=None, profile=False):
+    def run(self, op_buf, op_off, st_buf, st_off, tol=0.0, stream=None, profile=False, sketch=None):
         import torch
         self.stats.profile = int(bool(profile))
         op_off = np.ascontiguousarray(op_off, dtype=np.int64)
@@ -272,6 +279,17 @@ class Compressor:
                                            self.prec, self.workspace.data_ptr(), self.ws_bytes,
                                            ctypes.byref(out), ctypes.c_void_p(stream),
                                            ctypes.byref(self.stats)), "cbc_apply_batched")
+            return self.out, self.bond
+        if self.method == 2:
+            if sketch is None:
+                raise ValueError("the randomised method needs its sketch matrices")
+            sk_off = np.ascontiguousarray(sketch[1], dtype=np.int64)
+            sk = _Tensors(sketch[0].data_ptr(), sk_off.ctypes.data_as(I64))
+            _check(lib().cbc_apply_src(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns),
+                                       ctypes.byref(sk), ctypes.byref(self.tree.c), self.max_bond,
+                                       self.prec, self.workspace.data_ptr(), self.ws_bytes,
+                                       ctypes.byref(out), ctypes.c_void_p(stream),
+                                       ctypes.byref(self.stats)), "cbc_apply_src")
             return self.out, self.bond
         if self.scratch is not None:
             _check(lib().cbc_apply_split(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns),
@@ -475,14 +493,17 @@ def plan_info(tree, max_bond, precision="fp64", method="cbc", tol_on=False, ctx=
             "flops": {c: float(info.flops[k]) for k, c in enumerate(CLASSES)}}
 
 
-def compress(problem, precision="fp64", method="cbc", tol=None, ctx=None, device="cuda"):
-    """Convenience wrapper: one compression of a Problem from paper_2601_19650_amd.inputs."""
+def compress(problem, precision="fp64", method="cbc", tol=None, ctx=None, device="cuda",
+             sketch=None):
+    """Convenience wrapper: one compression of a Problem from paper_2601_19650_amd.inputs.
+    `sketch`: the randomised method's matrices (one d_i x max_bond numpy array per node)."""
     ctx = ctx or Context()
     tree = Tree.of(problem)
     st, so = pack(problem.state, device)
     op, oo = pack(problem.op, device)
     c = Compressor(ctx, tree, problem.max_bond, precision, method, device)
-    c.run(op, oo, st, so, problem.tol if tol is None else tol)
+    sk = pack(sketch, device) if sketch is not None else None
+    c.run(op, oo, st, so, problem.tol if tol is None else tol, sketch=sk)
     out = c.unpack()
     c.check()
     return out, c

@@ -37,7 +37,7 @@ namespace {
 // ------------------------------------------------------------------------------------------------
 // plan representation
 
-enum Src : int { S_NONE = -1, S_WS = 0, S_SCR = 1, S_STATE = 2, S_OP = 3, S_OUT = 4 };
+enum Src : int { S_NONE = -1, S_WS = 0, S_SCR = 1, S_STATE = 2, S_OP = 3, S_OUT = 4, S_SKETCH = 5 };
 
 struct TRef {
   int src = S_NONE;
@@ -50,7 +50,8 @@ struct Ten {
   std::vector<int> legs;
 };
 
-enum OpKind : int { K_GEMM, K_EIG, K_FORM_N, K_CHOL, K_CONVERT, K_IDENT, K_WRITE, K_ZERO, K_HEADER };
+enum OpKind : int { K_GEMM, K_EIG, K_FORM_N, K_CHOL, K_CONVERT, K_IDENT, K_WRITE, K_ZERO, K_HEADER,
+                     K_NORM };
 
 // Start of every instance's workspace: the call's report (read by cbc_read_report). The kernels
 // store a failure code into `status` (first one wins) and add dropped pivots to `ndrop`; the
@@ -76,6 +77,10 @@ struct Op {
   int M = 0, N = 0, K = 0;
   int64_t tAm = 0, tAk = 0, tBk = 0, tBn = 0, tCm = 0, tCn = 0;
   int conjA = 0, conjB = 0, akf = 0, bkf = 0, tile = 0, ksplit = 1;
+  // a leg shared by A, B and C (element-wise, not summed): zb instances, one per index value, the
+  // operands advanced by zsA / zsB / zsC elements per instance (0 where an operand lacks the leg)
+  int zb = 1;
+  int64_t zsA = 0, zsB = 0, zsC = 0;
   int kcap = 1;   // largest split the scratch `part` has room for
   bool tuned = false;   // tile and split set by the autotuner for the current batch
   TRef part;   // split-K chunk sums (scratch)
@@ -121,8 +126,8 @@ struct Plan {
   std::vector<hipEvent_t> events;
   // misc device slots (persistent workspace offsets)
   int64_t logs_off = 0;
-  int64_t state_conv_off = -1, op_conv_off = -1;
-  int64_t state_elems = 0, op_elems = 0;
+  int64_t state_conv_off = -1, op_conv_off = -1, sketch_conv_off = -1;
+  int64_t state_elems = 0, op_elems = 0, sketch_elems = 0;
   // captured graphs, one per buffer set (key: buffers, offsets, batch, tol), each with an event
   // recorded after its last launch so that it is destroyed only once it has finished
   struct Exec {
@@ -317,16 +322,20 @@ struct Builder {
   Ten contract(const Ten& A, bool conjA, const Ten& B, bool conjB, const std::vector<int>& out,
                const TRef& Cref, DType tc, DType acc, int bucket, double alpha = 1.0,
                TRef adev = TRef(), TRef adev2 = TRef()) {
-    std::vector<int> ml, nl, kl;
+    std::vector<int> ml, nl, kl, zl;
     for (int l : A.legs) {
-      if (pos(out, l) >= 0) ml.push_back(l);
+      if (pos(out, l) >= 0) (pos(B.legs, l) >= 0 ? zl : ml).push_back(l);
       else if (pos(B.legs, l) >= 0) kl.push_back(l);
       else bad = true;   // a leg of A that is neither summed nor kept
     }
     for (int l : B.legs) {
-      if (pos(out, l) >= 0) nl.push_back(l);
-      else if (pos(A.legs, l) < 0) bad = true;
+      if (pos(out, l) >= 0) {
+        if (pos(A.legs, l) < 0) nl.push_back(l);
+      } else if (pos(A.legs, l) < 0) {
+        bad = true;
+      }
     }
+    if (zl.size() > 1) bad = true;   // at most one element-wise leg per contraction
     // the kernels address operands with 32-bit element offsets from tables
     if (elems(A.legs) >= ELEM_LIMIT || elems(B.legs) >= ELEM_LIMIT || elems(out) >= ELEM_LIMIT)
       P.unsupported = true;
@@ -355,6 +364,13 @@ struct Builder {
     op.tAm = table(ml, pick(ml, A.legs, sA), pick(ml, out, sC), op.tCm);
     op.tBn = table(nl, pick(nl, B.legs, sB), pick(nl, out, sC), op.tCn);
     op.tAk = table(kl, pick(kl, A.legs, sA), pick(kl, B.legs, sB), op.tBk);
+    if (!zl.empty()) {
+      const int z = zl[0];
+      op.zb = (int)legdim[z];
+      op.zsA = sA[pos(A.legs, z)];
+      op.zsB = sB[pos(B.legs, z)];
+      op.zsC = sC[pos(out, z)];
+    }
     op.conjA = conjA;
     op.conjB = conjB;
     op.akf = !A.legs.empty() && pos(kl, A.legs.back()) >= 0;
@@ -369,7 +385,9 @@ struct Builder {
     // tile chosen at launch (it depends on the batch); a split reduction needs scratch, so it is
     // decided here, for one instance
     op.tile = GEMM_AUTO;
-    {
+    if (op.zb > 1) {
+      op.kcap = 1;   // the element-wise leg fills the grid's third dimension: no split
+    } else {
       const bool f64 = acc == DT_C128;
       const int t1 = gemm_pick_tile(op.M, op.N, op.K, 1, f64);
       const int ks = gemm_pick_ksplit(op.M, op.N, op.K, 1, t1);
@@ -384,13 +402,13 @@ struct Builder {
       op.kcap = kcap;
       if (kcap > 1) op.part = scr((size_t)kcap * op.M * op.N * (f64 ? 16 : 8), acc);
     }
-    const double f = 8.0 * (double)op.M * op.N * op.K;
+    const double f = 8.0 * (double)op.M * op.N * op.K * op.zb;
     op.cls = bucket == 0 ? CBC_K_CONTRACT : bucket == 1 ? CBC_K_GRAM : bucket == 2 ? CBC_K_QRMUL
                                                                               : CBC_K_OTHER;
     // a Hermitian Gram counts half its complex MACs as algorithmic work; layout copies count none
     op.flops = bucket == 1 ? 0.5 * f : bucket == 3 ? 0.0 : f;
-    op.bytes = (double)esz(op.ta) * op.M * op.K + (double)esz(op.tb) * op.K * op.N +
-               (double)esz(tc) * op.M * op.N;
+    op.bytes = ((double)esz(op.ta) * op.M * op.K + (double)esz(op.tb) * op.K * op.N +
+                (double)esz(tc) * op.M * op.N) * op.zb;
     if (bucket == 0) P.cflops += f;
     else if (bucket == 1) P.gflops += 0.5 * f;
     else if (bucket == 2) P.gflops += f;
@@ -423,38 +441,34 @@ struct Builder {
     return r;
   }
 
-  // T_i contracted with the environments (slot -> env tensor [chi, alpha, beta]) and with W_i. The
-  // operands are taken one at a time, each step the one whose product with the running result has
-  // the fewest elements (ties: environments in slot order, then W_i). Absorbing every environment
-  // before W_i leaves all of a node's operator legs open at once (chi * alpha * D per leg); at nodes
-  // with three or more environments W_i is taken earlier, which bounds the largest intermediate.
-  Ten node_contract(int i, const std::vector<std::pair<int, Ten>>& envs, const std::vector<int>& out,
-                    const TRef& dst) {
-    const auto sa = slot_alpha(i), sb = slot_beta(i);
-    Ten T;
-    T.ref = node_ref(S_STATE, i);
-    T.legs.push_back(sig[i]);
-    for (int l : sa) T.legs.push_back(l);
-    Ten W;
-    W.ref = node_ref(S_OP, i);
-    W.legs = {sigp[i], sig[i]};
-    for (int l : sb) W.legs.push_back(l);
-    std::vector<Ten> rem;
-    for (const auto& se : envs) rem.push_back(se.second);
-    rem.push_back(W);
-    Ten X = T;
+  // Contract X with every tensor of `rem`, one at a time: each step takes the tensor whose product
+  // with the running result has the fewest elements (ties: the order of `rem`). A leg of both
+  // operands is summed unless `out` or a tensor still to come has it, in which case it stays as the
+  // step's element-wise leg. `front`, where an intermediate has it, is moved to its first position
+  // (an element-wise leg then advances every operand by whole blocks).
+  Ten chain(Ten X, std::vector<Ten> rem, const std::vector<int>& out, const TRef& dst,
+            int front = -1) {
     while (rem.size() > 1) {
       size_t best = 0;
       int64_t best_e = -1;
       std::vector<int> best_legs;
       for (size_t c = 0; c < rem.size(); ++c) {
-        // a leg of both X and rem[c] is summed; every other leg stays (each leg belongs to at most
-        // two of T_i, W_i and the environments, so a summed leg is needed nowhere later)
+        auto needed = [&](int l) {
+          if (pos(out, l) >= 0) return true;
+          for (size_t o = 0; o < rem.size(); ++o)
+            if (o != c && pos(rem[o].legs, l) >= 0) return true;
+          return false;
+        };
         std::vector<int> o;
         for (int l : X.legs)
-          if (pos(rem[c].legs, l) < 0) o.push_back(l);
+          if (pos(rem[c].legs, l) < 0 || needed(l)) o.push_back(l);
         for (int l : rem[c].legs)
           if (pos(X.legs, l) < 0) o.push_back(l);
+        const int fp = front >= 0 ? pos(o, front) : -1;
+        if (fp > 0) {
+          o.erase(o.begin() + fp);
+          o.insert(o.begin(), front);
+        }
         const int64_t e = elems(o);
         if (best_e < 0 || e < best_e) {
           best = c;
@@ -467,6 +481,48 @@ struct Builder {
       rem.erase(rem.begin() + (ptrdiff_t)best);
     }
     return contract(X, false, rem[0], false, out, dst, ct, cacc, 0);
+  }
+
+  Ten state_node(int i) const {
+    Ten T;
+    T.ref = node_ref(S_STATE, i);
+    T.legs.push_back(sig[i]);
+    for (int l : slot_alpha(i)) T.legs.push_back(l);
+    return T;
+  }
+  Ten op_node(int i) const {
+    Ten W;
+    W.ref = node_ref(S_OP, i);
+    W.legs = {sigp[i], sig[i]};
+    for (int l : slot_beta(i)) W.legs.push_back(l);
+    return W;
+  }
+
+  // T_i contracted with the environments (slot -> env tensor [chi, alpha, beta]) and with W_i,
+  // through chain(): absorbing every environment before W_i leaves all of a node's operator legs
+  // open at once (chi * alpha * D per leg); at nodes with three or more environments W_i is taken
+  // earlier, which bounds the largest intermediate.
+  Ten node_contract(int i, const std::vector<std::pair<int, Ten>>& envs, const std::vector<int>& out,
+                    const TRef& dst) {
+    std::vector<Ten> rem;
+    for (const auto& se : envs) rem.push_back(se.second);
+    rem.push_back(op_node(i));
+    return chain(state_node(i), rem, out, dst);
+  }
+
+  // X /= ||X||_F in place; the log of the factor to `logslot` if given.
+  void normalize(const Ten& X, TRef logslot = TRef()) {
+    Op o;
+    o.kind = K_NORM;
+    o.dst = X.ref;
+    o.td = X.ref.dt;
+    o.count = elems(X.legs);
+    o.logs = logslot;
+    o.status.src = S_WS;
+    o.status.off = HDR_STATUS;
+    o.work = scr(sizeof(double) * NORM_MAX_BLOCKS, DT_C128);
+    o.bytes = 3.0 * (double)esz(X.ref.dt) * (double)o.count;
+    P.ops.push_back(o);
   }
 
   // A truncation eigensolve op: its record (node, sweep) and the status word.
@@ -597,7 +653,7 @@ struct Builder {
 
   // Orthonormal columns: X with legs (rows..., col somewhere) -> Q with legs (rows..., qcol) spanning
   // the column space of X over `col` (three Cholesky-QR passes, the first shifted; complex128).
-  Ten cholqr_cols(const Ten& X, int col, int qcol, bool persistent) {
+  Ten cholqr_cols(const Ten& X, int col, int qcol, bool persistent, bool qcol_first = false) {
     const std::vector<int> rows = without(X.legs, col);
     const int64_t k = legdim[col];
     const int64_t mrows = elems(rows);
@@ -627,7 +683,8 @@ struct Builder {
       c.bytes = 32.0 * (double)k * k;
       P.ops.push_back(c);
       std::vector<int> qo = rows;
-      qo.push_back(qcol);
+      if (pass == 2 && qcol_first) qo.insert(qo.begin(), qcol);
+      else qo.push_back(qcol);
       Ten Q = alloc(qo, DT_C128, persistent && pass == 2);
       contract(cur, false, Ci, true, qo, Q.ref, DT_C128, DT_C128, 2);
       if (pass == 2) return Q;
@@ -972,6 +1029,221 @@ cbc_status build_plan(Plan& P, const Problem& pr, int max_bond, bool tol_on, cbc
 }
 
 // ------------------------------------------------------------------------------------------------
+// successive randomised compression (Sec. III C, the randomised counterpart of CBC): the truncated
+// environments of sweeps 1 and 2 become exact Khatri-Rao sketches of the subtree below a node (K) and
+// of the rest of the tree (E), and sweep 3 takes each node's basis from a Cholesky-QR of the sketched
+// columns Y = Z E instead of a QR on the parent leg. Sketches and environments are normalised after
+// every node step (only column spaces matter for the sketches; the environments' logs rescale the
+// root output).
+
+cbc_status build_plan_src(Plan& P, const Problem& pr, int max_bond, cbc_precision prec,
+                          bool fill_tables) {
+  Builder B(P, pr, max_bond, false, prec);
+  B.fill_tables = fill_tables;
+  const int n = pr.n;
+  B.sig.resize(n);
+  B.sigp.resize(n);
+  B.ealpha.assign(n, -1);
+  B.ebeta.assign(n, -1);
+  for (int i = 0; i < n; ++i) {
+    B.sig[i] = B.leg(pr.phys[i]);
+    B.sigp[i] = B.leg(pr.phys[i]);
+    if (pr.parent[i] >= 0) {
+      B.ealpha[i] = B.leg(pr.chi[i]);
+      B.ebeta[i] = B.leg(pr.dop[i]);
+    }
+  }
+  B.rootA = B.leg(1);
+  B.rootB = B.leg(1);
+  const int rl = B.leg(max_bond);   // the sketch index, shared by every node (Khatri-Rao product)
+  plan_prologue(B, P, prec, n);
+  P.sketch_elems = 0;
+  for (int i = 0; i < n; ++i) P.sketch_elems += (int64_t)pr.phys[i] * max_bond;
+  if (prec == CBC_PREC_MIXED) {
+    P.sketch_conv_off = (int64_t)B.persist;
+    B.persist += Builder::al(8 * (size_t)P.sketch_elems);
+    Op c;
+    c.kind = K_CONVERT;
+    c.src.src = S_SKETCH;
+    c.src.off = -1;
+    c.ts = DT_C128;
+    c.dst.src = S_WS;
+    c.dst.off = P.sketch_conv_off;
+    c.td = DT_C64;
+    c.count = P.sketch_elems;
+    P.ops.push_back(c);
+  }
+  auto sketch_of = [&](int i) {
+    Ten O;
+    O.ref = B.node_ref(S_SKETCH, i);
+    O.legs = {B.sigp[i], rl};
+    return O;
+  };
+  // output bonds: node i keeps min(rows, max_bond) with rows = sigma'_i x its children's bonds
+  std::vector<int> kout(n, 1);
+  std::vector<int64_t> rows(n, 1);
+  for (int i : pr.post) {
+    rows[i] = pr.phys[i];
+    for (int c : pr.ch[i]) rows[i] *= kout[c];
+    if (i != pr.root) kout[i] = (int)std::min<int64_t>(rows[i], max_bond);
+  }
+  // sketches needed: E at every compressed node and at the non-root ancestors its E is built from;
+  // K of the siblings along the way, and of everything below them
+  std::vector<char> needE(n, 0), needK(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (i == pr.root || rows[i] <= max_bond) continue;
+    for (int q = i; q != pr.root && !needE[q]; q = pr.parent[q]) needE[q] = 1;
+  }
+  std::function<void(int)> mark = [&](int c) {
+    if (needK[c]) return;
+    needK[c] = 1;
+    for (int cc : pr.ch[c]) mark(cc);
+  };
+  for (int k = 0; k < n; ++k) {
+    if (!needE[k]) continue;
+    for (int c : pr.ch[pr.parent[k]])
+      if (c != k) mark(c);
+  }
+  std::vector<Ten> K(n), E(n), R(n);
+  // sweep 1, leaves to root: subtree sketches K^{[i]} [r, alpha_i, beta_i]
+  for (int i : pr.post) {
+    if (!needK[i]) continue;
+    B.reset_scratch();
+    std::vector<Ten> rem;
+    for (int c : pr.ch[i]) rem.push_back(K[c]);
+    rem.push_back(B.op_node(i));
+    rem.push_back(sketch_of(i));
+    const std::vector<int> out{rl, B.ealpha[i], B.ebeta[i]};
+    Ten Kt = B.alloc(out, B.ct, true);
+    K[i] = B.chain(B.state_node(i), rem, out, Kt.ref, rl);
+    B.normalize(K[i]);
+  }
+  // sweep 2, root to leaves: sketches of the rest of the tree E^{[k]} [r, alpha_k, beta_k]
+  {
+    std::vector<int> pre(pr.post.rbegin(), pr.post.rend());
+    for (int i : pre) {
+      for (int k : pr.ch[i]) {
+        if (!needE[k]) continue;
+        B.reset_scratch();
+        std::vector<Ten> rem;
+        if (i != pr.root) rem.push_back(E[i]);
+        for (int c : pr.ch[i])
+          if (c != k) rem.push_back(K[c]);
+        rem.push_back(B.op_node(i));
+        rem.push_back(sketch_of(i));
+        std::vector<int> out{rl};
+        if (i == pr.root) {   // the root's trivial parent legs stay on the result (dimension 1)
+          out.push_back(B.rootA);
+          out.push_back(B.rootB);
+        }
+        out.push_back(B.ealpha[k]);
+        out.push_back(B.ebeta[k]);
+        Ten Et = B.alloc(out, B.ct, true);
+        Et = B.chain(B.state_node(i), rem, out, Et.ref, rl);
+        E[k] = Ten{Et.ref, {rl, B.ealpha[k], B.ebeta[k]}};
+        B.normalize(E[k]);
+      }
+    }
+  }
+  // sweep 3, leaves to root: Z^{[i]}, bases from Y = Z E, environments R = Q^H Z
+  P.out_off.assign(n + 1, 0);
+  P.out_bond.assign(n, 1);
+  for (int i = 0; i < n; ++i) {
+    int64_t e = (int64_t)pr.phys[i] * kout[i];
+    for (int c : pr.ch[i]) e *= kout[c];
+    P.out_off[i + 1] = P.out_off[i] + e;
+    P.out_bond[i] = kout[i];
+  }
+  for (int i : pr.post) {
+    B.reset_scratch();
+    std::vector<std::pair<int, Ten>> envs;
+    std::vector<int> zl{B.sigp[i]};
+    for (size_t j = 0; j < pr.ch[i].size(); ++j) {
+      const int c = pr.ch[i][j];
+      envs.push_back({1 + (int)j, R[c]});
+      zl.push_back(R[c].legs[0]);
+    }
+    if (i == pr.root) {
+      std::vector<int> zr{B.rootA};
+      zr.insert(zr.end(), zl.begin(), zl.end());
+      zr.push_back(B.rootB);
+      Ten Z = B.alloc(zr, B.ct, false);
+      Z = B.node_contract(i, envs, zr, Z.ref);
+      Op w;
+      w.kind = K_WRITE;
+      w.src = Z.ref;
+      w.ts = B.ct;
+      w.a = 1;
+      w.b = pr.phys[i];
+      w.rest = B.elems(zr) / pr.phys[i];
+      w.dst.src = S_OUT;
+      w.dst.off = i;
+      w.logs.src = S_WS;
+      w.logs.off = P.logs_off;
+      w.nlogs = n;
+      P.ops.push_back(w);
+      continue;
+    }
+    zl.push_back(B.ealpha[i]);
+    zl.push_back(B.ebeta[i]);
+    const int64_t ns = rows[i];
+    std::vector<int> rest(zl.begin(), zl.end() - 2);
+    const bool ident = ns <= max_bond;
+    Ten Z = B.alloc(zl, B.ct, ident);
+    Z = B.node_contract(i, envs, zl, Z.ref);
+    if (ident) {
+      // nothing to compress: the basis is the identity and R^{[i]} = Z with (sigma', chi_c...) as
+      // its new leg
+      const int nl = B.leg(ns);
+      R[i] = Ten{Z.ref, {nl, B.ealpha[i], B.ebeta[i]}};
+      TRef q = B.scr(16 * (size_t)ns * ns, DT_C128);
+      Op f;
+      f.kind = K_IDENT;
+      f.dst = q;
+      f.td = DT_C128;
+      f.a = (int)ns;
+      f.b = (int)ns;
+      P.ops.push_back(f);
+      Op w;
+      w.kind = K_WRITE;
+      w.src = q;
+      w.ts = DT_C128;
+      w.a = (int)ns;
+      w.b = pr.phys[i];
+      w.rest = ns / pr.phys[i];
+      w.dst.src = S_OUT;
+      w.dst.off = i;
+      P.ops.push_back(w);
+      continue;
+    }
+    // Y = Z E^{[i]} [sigma', chi_c..., r]
+    std::vector<int> yl = rest;
+    yl.push_back(rl);
+    Ten Y = B.alloc(yl, B.ct, false);
+    Y = B.contract(Z, false, E[i], false, yl, Y.ref, B.ct, B.cacc, 0);
+    const int knew = B.leg(max_bond);
+    Ten Q = B.cholqr_cols(Y, rl, knew, false, true);        // [k, sigma', chi_c...], complex128
+    Ten Rt = B.alloc({knew, B.ealpha[i], B.ebeta[i]}, B.ct, true);
+    R[i] = B.contract(Q, true, Z, false, {knew, B.ealpha[i], B.ebeta[i]}, Rt.ref, B.ct, B.cacc, 0);
+    TRef logslot;
+    logslot.src = S_WS;
+    logslot.off = P.logs_off + 8 * (int64_t)i;
+    B.normalize(R[i], logslot);
+    Op w;
+    w.kind = K_WRITE;
+    w.src = Q.ref;
+    w.ts = DT_C128;
+    w.a = max_bond;
+    w.b = pr.phys[i];
+    w.rest = ns / pr.phys[i];
+    w.dst.src = S_OUT;
+    w.dst.off = i;
+    P.ops.push_back(w);
+  }
+  return plan_epilogue(B, P);
+}
+
+// ------------------------------------------------------------------------------------------------
 // the naive (direct) method of Sec. III C: exact product, canonical form, truncated-SVD sweep
 
 cbc_status build_plan_naive(Plan& P, const Problem& pr, int max_bond, bool tol_on,
@@ -1174,6 +1446,8 @@ struct Call {
                                  // cbc_apply_noalloc): eigensolves take the two-stage reduction
   const int32_t* tables = nullptr;   // device copy of the plan's offset tables
   char* scr = nullptr;   // scratch given apart from the workspace (cbc_apply_split), else null
+  const char* sketch = nullptr;        // the randomised method's sketch matrices (cbc_apply_src)
+  const int64_t* sk_off = nullptr;
 };
 
 }  // namespace
@@ -1202,6 +1476,10 @@ void* resolve(const Plan& P, const Call& c, const TRef& r) {
       if (P.op_conv_off >= 0) return c.ws + P.op_conv_off + 8 * c.op_off[r.off];
       return (void*)(c.op + 16 * c.op_off[r.off]);
     case S_OUT: return c.out + 16 * c.out_off[r.off];
+    case S_SKETCH:
+      if (r.off < 0) return (void*)c.sketch;
+      if (P.sketch_conv_off >= 0) return c.ws + P.sketch_conv_off + 8 * c.sk_off[r.off];
+      return (void*)(c.sketch + 16 * c.sk_off[r.off]);
     default: return nullptr;
   }
 }
@@ -1213,6 +1491,7 @@ int64_t stride_of(const Plan& P, const Call& c, const TRef& r) {
     case S_STATE: return (r.off >= 0 && P.state_conv_off >= 0) ? c.ws_inst : c.st_inst;
     case S_OP: return (r.off >= 0 && P.op_conv_off >= 0) ? c.ws_inst : c.op_inst;
     case S_OUT: return c.out_inst;
+    case S_SKETCH: return (r.off >= 0 && P.sketch_conv_off >= 0) ? c.ws_inst : 0;
     default: return 0;
   }
 }
@@ -1221,6 +1500,7 @@ int64_t stride_of(const Plan& P, const Call& c, const TRef& r) {
 // (the split planned for one instance is reduced when the batch already fills the GPU; without a
 // split the tile is chosen at launch for the batch).
 std::pair<int, int> gemm_config(const Op& op, int batch) {
+  if (op.zb > 1) batch = op.zb;
   if (op.tuned || batch == 1 || op.ksplit == 1) return {op.tile, op.ksplit};
   const int ks = std::min(op.ksplit, gemm_pick_ksplit(op.M, op.N, op.K, batch, op.tile));
   return {ks > 1 ? op.tile : GEMM_AUTO, ks};
@@ -1253,6 +1533,16 @@ GemmArgs gemm_args(const Plan& P, const Call& c, const Op& op, int ksplit) {
   g.bsC = stride_of(P, c, op.C);
   g.bsAlpha = stride_of(P, c, op.adev);
   g.bsAlpha2 = stride_of(P, c, op.adev2);
+  if (op.zb > 1) {
+    // the element-wise leg takes the grid's batch dimension (plans holding one run single calls)
+    auto es = [](DType t) { return (int64_t)(t == DT_C128 ? 16 : 8); };
+    g.batch = op.zb;
+    g.bsA = op.zsA * es(op.ta);
+    g.bsB = op.zsB * es(op.tb);
+    g.bsC = op.zsC * es(op.tc);
+    g.bsAlpha = 0;
+    g.bsAlpha2 = 0;
+  }
   g.mbase = 0;
   g.ksplit = ksplit;
   g.kchunk = ((op.K + ksplit - 1) / ksplit + 15) / 16 * 16;
@@ -1339,6 +1629,12 @@ hipError_t run_ops(const Plan& P, const Call& c, hipStream_t st, hipEvent_t* ev 
       case K_ZERO:
         e = launch_zero(resolve(P, c, op.dst), op.count, c.batch, stride_of(P, c, op.dst), st);
         break;
+      case K_NORM:   // single calls only (plans of the randomised method)
+        e = launch_normalize(resolve(P, c, op.dst), op.td, op.count, (double*)resolve(P, c, op.work),
+                             op.scale.src == S_NONE ? nullptr : (double*)resolve(P, c, op.scale),
+                             op.logs.src == S_NONE ? nullptr : (double*)resolve(P, c, op.logs),
+                             (int*)resolve(P, c, op.status), st);
+        break;
       case K_HEADER:
         e = launch_report_header(resolve(P, c, op.dst), REPORT_MAGIC, (int)op.count, op.rest,
                                  (int64_t)sizeof(cbc_trunc_record), c.batch,
@@ -1418,7 +1714,8 @@ hipError_t tune_plan(cbc_ctx* ctx, Plan& P, const Call& c, hipStream_t st) {
   for (Op& op : P.ops) {
     if (e != hipSuccess) break;
     if (op.kind != K_GEMM) continue;
-    const auto key = tune_key(op, c.batch);
+    const int eb = op.zb > 1 ? op.zb : c.batch;
+    const auto key = tune_key(op, eb);
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end() && it->second.second <= op.kcap) {
       op.tile = it->second.first;
@@ -1429,7 +1726,7 @@ hipError_t tune_plan(cbc_ctx* ctx, Plan& P, const Call& c, hipStream_t st) {
     std::pair<int, int> best{op.tile, op.ksplit};
     float best_ms = 0.0f;
     bool have = false;
-    for (const auto& cf : tune_candidates(op, c.batch)) {
+    for (const auto& cf : tune_candidates(op, eb)) {
       op.tile = cf.first;
       op.ksplit = cf.second;
       // one launch to warm up, then the timed ones; results are recomputed by the call afterwards
@@ -1486,8 +1783,9 @@ cbc_status get_plan(cbc_ctx* ctx, const Problem& pr, int max_bond, bool tol_on, 
     P->state_elems = state_span;
     P->op_elems = op_span;
     P->tune = ctx->tune;
-    cbc_status s = method == 0 ? build_plan(*P, pr, max_bond, tol_on, prec, need_tables)
-                                : build_plan_naive(*P, pr, max_bond, tol_on, prec, need_tables);
+    cbc_status s = method == 0   ? build_plan(*P, pr, max_bond, tol_on, prec, need_tables)
+                   : method == 1 ? build_plan_naive(*P, pr, max_bond, tol_on, prec, need_tables)
+                                 : build_plan_src(*P, pr, max_bond, prec, need_tables);
     if (s != CBC_OK) return s;
     if (P->unsupported) return CBC_EUNSUP;
     P->has_tables = need_tables;
@@ -1588,7 +1886,8 @@ static cbc_status common_checks(const cbc_tree* tree, int32_t max_bond, cbc_prec
 cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
                      int32_t method, size_t* workspace_bytes, int64_t* out_offset) {
   if (!ctx || !workspace_bytes || !out_offset) return CBC_EINVAL;
-  if (method != 0 && method != 1) return CBC_EINVAL;
+  if (method < 0 || method > 2) return CBC_EINVAL;
+  if (method == 2 && max_bond > 65535) return CBC_EUNSUP;
   Problem pr;
   cbc_status s = common_checks(tree, max_bond, prec, pr);
   if (s != CBC_OK) return s;
@@ -1613,7 +1912,8 @@ cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_p
 cbc_status cbc_plan_info(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
                          int32_t method, int32_t tol_on, cbc_plan_summary* info) {
   if (!ctx || !info) return CBC_EINVAL;
-  if (method != 0 && method != 1) return CBC_EINVAL;
+  if (method < 0 || method > 2) return CBC_EINVAL;
+  if (method == 2 && max_bond > 65535) return CBC_EUNSUP;
   Problem pr;
   cbc_status s = common_checks(tree, max_bond, prec, pr);
   if (s != CBC_OK) return s;
@@ -1658,8 +1958,11 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
                              cbc_precision prec, void* workspace, size_t workspace_bytes,
                              cbc_out* out, void* stream, cbc_stats* stats, int method,
                              int32_t batch = 1, bool noalloc = false, void* scratch = nullptr,
-                             size_t scratch_bytes = 0) {
+                             size_t scratch_bytes = 0, const cbc_tensors* sketch = nullptr) {
   if (batch < 1 || batch > 65535) return CBC_EINVAL;
+  if (method == 2 && (!sketch || !sketch->data || !sketch->offset || batch != 1 || noalloc ||
+                      scratch || tol != 0.0))
+    return CBC_EINVAL;
   if (noalloc && (batch != 1 || (stats && stats->profile))) return CBC_EINVAL;
   const bool split = scratch != nullptr;
   if (split && (batch != 1 || noalloc)) return CBC_EINVAL;
@@ -1680,6 +1983,14 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
     if (ttns->offset[i] < 0 || ttno->offset[i] < 0) return CBC_EINVAL;
     if (ttns->offset[i] + tensor_elems_state(pr, i) > se) return CBC_EINVAL;
     if (ttno->offset[i] + tensor_elems_op(pr, i) > oe) return CBC_EINVAL;
+  }
+  if (method == 2) {
+    if (max_bond > 65535) return CBC_EUNSUP;
+    int64_t ke = 0;
+    for (int i = 0; i < pr.n; ++i) ke += (int64_t)pr.phys[i] * max_bond;
+    for (int i = 0; i < pr.n; ++i)
+      if (sketch->offset[i] < 0 || sketch->offset[i] + (int64_t)pr.phys[i] * max_bond > ke)
+        return CBC_EINVAL;
   }
   Plan* P = nullptr;
   s = get_plan(ctx, pr, max_bond, tol > 0.0, prec, method, se, oe, &P, true);
@@ -1739,6 +2050,10 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   c.out_inst = 16 * P->out_off[pr.n];
   c.tables = tables;
   c.scr = (char*)scratch;
+  if (method == 2) {
+    c.sketch = (const char*)sketch->data;
+    c.sk_off = sketch->offset;
+  }
   const bool profile = stats && stats->profile;
   int replayed = 0;
   if (!noalloc && P->tune && ctx->tune && P->tuned_batch != batch &&
@@ -1775,6 +2090,10 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
     for (int i = 0; i < pr.n; ++i) {
       key.push_back((uintptr_t)c.st_off[i]);
       key.push_back((uintptr_t)c.op_off[i]);
+    }
+    if (c.sketch) {
+      key.push_back((uintptr_t)c.sketch);
+      for (int i = 0; i < pr.n; ++i) key.push_back((uintptr_t)c.sk_off[i]);
     }
     auto it = P->graphs.find(key);
     if (it == P->graphs.end()) {
@@ -1882,6 +2201,15 @@ cbc_status cbc_apply_split(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tens
   if (!scratch) return CBC_EINVAL;
   return apply_impl(ctx, ttno, ttns, tree, max_bond, tol, prec, workspace, workspace_bytes, out,
                     stream, stats, 0, 1, false, scratch, scratch_bytes);
+}
+
+cbc_status cbc_apply_src(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                         const cbc_tensors* sketch, const cbc_tree* tree, int32_t max_bond,
+                         cbc_precision prec, void* workspace, size_t workspace_bytes, cbc_out* out,
+                         void* stream, cbc_stats* stats) {
+  if (!sketch) return CBC_EINVAL;
+  return apply_impl(ctx, ttno, ttns, tree, max_bond, 0.0, prec, workspace, workspace_bytes, out,
+                    stream, stats, 2, 1, false, nullptr, 0, sketch);
 }
 
 cbc_status cbc_apply_batched(cbc_ctx* ctx, int32_t batch, const cbc_tensors* ttno,

@@ -156,6 +156,13 @@ hipError_t noalloc_scratch(void** ptr);
 // Batched elementwise helpers: instance b uses src + b * ss and dst + b * ds (bytes).
 hipError_t launch_convert(const void* src, DType ts, void* dst, DType td, int64_t n, int batch,
                           int64_t ss, int64_t ds, hipStream_t st);
+// x *= 1/||x||_F in place (n complex elements of type t, one instance); the factor to scale[0] and
+// its logarithm to logs[0] if given; a non-finite norm stores CBC_ENOTPD in *status (if given).
+// `part` is scratch of NORM_MAX_BLOCKS doubles (per-block partial sums, added in a fixed order).
+constexpr int NORM_MAX_BLOCKS = 512;
+int norm_blocks(int64_t n);
+hipError_t launch_normalize(void* x, DType t, int64_t n, double* part, double* scale, double* logs,
+                            int* status, hipStream_t st);
 hipError_t launch_fill_identity(void* dst, DType t, int rows, int cols, int batch, int64_t ds,
                                 hipStream_t st);
 hipError_t launch_zero(void* dst, int64_t bytes, int batch, int64_t ds, hipStream_t st);

@@ -518,6 +518,90 @@ hipError_t launch_convert(const void* src, DType ts, void* dst, DType td, int64_
   return hipGetLastError();
 }
 
+// x *= 1 / ||x||_F in place. The sum of squares is taken in FP64 in a fixed order: block b of the
+// first kernel sums the elements b, b + nb*256, ... (nb = norm_blocks(n)) into part[b]; every block
+// of the second adds part[0..nb) in order, so all blocks compute the same factor, and scales its
+// share of x. The factor goes to scale[0] and its logarithm to logs[0] where those are given. A zero
+// norm leaves x as it is (factor 1); a non-finite one also stores CBC_ENOTPD in the status word.
+static constexpr int NORM_THREADS = 256;
+
+__global__ __launch_bounds__(NORM_THREADS) void k_norm_partial(const void* x, int t, int64_t n,
+                                                               double* part) {
+  __shared__ double red[NORM_THREADS / 64];
+  const int tid = threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * NORM_THREADS;
+  double s = 0.0;
+  if (t == DT_C128) {
+    const double2* p = reinterpret_cast<const double2*>(x);
+    for (int64_t i = (int64_t)blockIdx.x * NORM_THREADS + tid; i < n; i += stride)
+      s += p[i].x * p[i].x + p[i].y * p[i].y;
+  } else {
+    const float2* p = reinterpret_cast<const float2*>(x);
+    for (int64_t i = (int64_t)blockIdx.x * NORM_THREADS + tid; i < n; i += stride) {
+      const double a = p[i].x, b = p[i].y;
+      s += a * a + b * b;
+    }
+  }
+  s = wsum(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < NORM_THREADS / 64; ++w) tot += red[w];
+    part[blockIdx.x] = tot;
+  }
+}
+
+__global__ __launch_bounds__(NORM_THREADS) void k_norm_apply(void* x, int t, int64_t n,
+                                                             const double* part, int nb,
+                                                             double* scale, double* logs,
+                                                             int* status) {
+  __shared__ double fac;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int b = 0; b < nb; ++b) tot += part[b];
+    double f = 1.0;
+    if (isfinite(tot) && tot > 0.0) f = 1.0 / sqrt(tot);
+    fac = f;
+    if (blockIdx.x == 0) {
+      if (!isfinite(tot)) raise_status(status, CBC_ENOTPD);
+      if (scale) scale[0] = f;
+      if (logs) logs[0] = log(f);
+    }
+  }
+  __syncthreads();
+  const double f = fac;
+  const int64_t stride = (int64_t)gridDim.x * NORM_THREADS;
+  if (t == DT_C128) {
+    double2* p = reinterpret_cast<double2*>(x);
+    for (int64_t i = (int64_t)blockIdx.x * NORM_THREADS + tid; i < n; i += stride)
+      p[i] = make_double2(p[i].x * f, p[i].y * f);
+  } else {
+    float2* p = reinterpret_cast<float2*>(x);
+    const float g = (float)f;
+    for (int64_t i = (int64_t)blockIdx.x * NORM_THREADS + tid; i < n; i += stride)
+      p[i] = make_float2(p[i].x * g, p[i].y * g);
+  }
+}
+
+int norm_blocks(int64_t n) {
+  const int64_t b = (n + NORM_THREADS - 1) / NORM_THREADS;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(b, NORM_MAX_BLOCKS));
+}
+
+hipError_t launch_normalize(void* x, DType t, int64_t n, double* part, double* scale, double* logs,
+                            int* status, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int nb = norm_blocks(n);
+  hipLaunchKernelGGL(k_norm_partial, dim3(nb), dim3(NORM_THREADS), 0, st, x, (int)t, n, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_norm_apply, dim3(nb), dim3(NORM_THREADS), 0, st, x, (int)t, n, part, nb,
+                     scale, logs, status);
+  return hipGetLastError();
+}
+
 __global__ void k_fill_identity(void* dst, int t, int rows, int cols, int64_t ds) {
   dst = inst_ptr(dst, ds, blockIdx.y);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -323,3 +323,24 @@ def test_uneven_batch_graph_groups():
     groups = cbc.graph_groups(counts, cbc.UnevenBatch.MAX_GRAPH_LAUNCHES)
     assert [k for g in groups for k in g] == list(range(256))
     assert all(sum(counts[k] for k in g) <= cbc.UnevenBatch.MAX_GRAPH_LAUNCHES for g in groups)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: config_problem("C1"), lambda: config_problem("C2", n=12), lambda: config_problem("C3"),
+    lambda: random_problem(kary_parent(13, 3), 2, 6, 3, 5, seed=4),
+    lambda: random_problem(kary_parent(7, 2), [1, 1, 1, 2, 2, 2, 2], 4, 4, 3, seed=6)])
+def test_src_plan_sizes_match_oracle(maker):
+    """The randomised method's planned output node sizes equal those of the SRC oracle, and its plan
+    holds no eigensolve (only contractions, Cholesky-QRs and normalisations)."""
+    from oracle.src import src_tree
+    from paper_2601_19650_amd.inputs import sketch_matrices
+    p = maker()
+    tree = cbc.Tree.of(p)
+    for prec in (0, 1):
+        rc, ws, off = _query(tree, p.max_bond, prec, 2)
+        assert rc == 0 and ws > 0
+    ref = src_tree(p.parent, p.state, p.op, p.max_bond, sketch_matrices(p.phys, p.max_bond, 3))
+    assert [int(s) for s in np.diff(off)] == [t.size for t in ref]
+    info = cbc.plan_info(tree, p.max_bond, "mixed", method="src")
+    assert info["launches"]["eig"] == 0 and info["flops"]["eig"] == 0.0
+    assert _query(tree, p.max_bond, 0, 3)[0] == -1
