@@ -6,3 +6,4 @@ never by the library. Shares no code with the GPU path.
 from .cbc import cbc_tt, cbc_tree, truncate_joined, lq  # noqa: F401
 from . import tn  # noqa: F401
 from .src import src_tree  # noqa: F401
+from .dm import dm_tree  # noqa: F401

@@ -168,3 +168,74 @@ def test_src_mutation_is_caught(name, old, new):
     assert SRC_SRC.count(old) == 1, f"mutation site not unique: {old!r}"
     failed = _failing_src_checks(SRC_SRC.replace(old, new))
     assert failed, f"no pin catches: {name}"
+
+
+# ---------------------------------------------------------------------------------------------
+# the DM oracle (oracle/dm.py) and its pins (tests/test_oracle_dm_pins.py)
+
+import oracle.dm as odm  # noqa: E402
+
+DM_SRC = open(odm.__file__).read()
+
+
+def _load_dm_pins():
+    spec = importlib.util.spec_from_file_location("dm_pins_for_mutation",
+                                                  os.path.join(HERE, "test_oracle_dm_pins.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+DM_PINS = _load_dm_pins()
+_D = {c[0]: c[1:] for c in DM_PINS.CASES}
+
+DM_CHECKS = [
+    ("dense formulation, chain", lambda: DM_PINS.test_dm_dense_formulation("chain7", *_D["chain7"])),
+    ("dense formulation, binary", lambda: DM_PINS.test_dm_dense_formulation("bin7", *_D["bin7"])),
+    ("dense formulation, ternary", lambda: DM_PINS.test_dm_dense_formulation("ter10", *_D["ter10"])),
+    ("projection, isometries, bounds", lambda: DM_PINS.test_dm_projection_isometries_and_truncation_bounds(
+        "uneven9", *_D["uneven9"])),
+    ("two-site optimum", lambda: DM_PINS.test_dm_two_site_is_the_optimal_truncation()),
+]
+
+DM_MUTATIONS = [
+    ("bra operator not conjugated", "terms.append((w.conj(), [sigp, sigpp] + betap))",
+     "terms.append((w, [sigp, sigpp] + betap))"),
+    ("bra state not conjugated", "terms.append((t.conj(), [sigpp] + alphap))",
+     "terms.append((t, [sigpp] + alphap))"),
+    ("sweep 2 omits the siblings' environments", "envs[1 + j] = asub[c]", "pass"),
+    ("sweep 2 omits the parent's environment", "                envs[0] = bpar[i]", "                pass"),
+    ("environment legs paired wrongly", "bm = np.transpose(bpar[i], (0, 1, 3, 2)).reshape(ab, ab)",
+     "bm = bpar[i].reshape(ab, ab)"),
+    ("smallest eigenvectors kept", "q = vec[:, ::-1][:, :max_bond]", "q = vec[:, :max_bond]"),
+    ("R update without conj(Q)", "renv[i] = (q.conj().T @ zm)", "renv[i] = (q.T @ zm)"),
+    ("density matrix without the environment", "rho = zm @ bm @ zm.conj().T", "rho = zm @ zm.conj().T"),
+]
+
+
+def _failing_dm_checks(src):
+    mod = types.ModuleType("dm_oracle_mutant")
+    exec(compile(src, "dm_oracle_mutant", "exec"), mod.__dict__)
+    saved = DM_PINS.dm_tree
+    DM_PINS.dm_tree = mod.dm_tree
+    failed = []
+    try:
+        for name, fn in DM_CHECKS:
+            try:
+                fn()
+            except Exception:
+                failed.append(name)
+    finally:
+        DM_PINS.dm_tree = saved
+    return failed
+
+
+def test_unmutated_dm_oracle_passes_every_check():
+    assert _failing_dm_checks(DM_SRC) == []
+
+
+@pytest.mark.parametrize("name,old,new", DM_MUTATIONS, ids=[m[0] for m in DM_MUTATIONS])
+def test_dm_mutation_is_caught(name, old, new):
+    assert DM_SRC.count(old) == 1, f"mutation site not unique: {old!r}"
+    failed = _failing_dm_checks(DM_SRC.replace(old, new))
+    assert failed, f"no pin catches: {name}"
