@@ -148,13 +148,13 @@ def uneven_full_run(stream_count=8):
     t1 = time.perf_counter()
     print(f"[bench] uneven full draw: {len(probs)} instances set up in {t1 - t0:.1f} s",
           file=sys.stderr, flush=True)
-    # first (eager) pass instance by instance: builds every plan's offset tables and its graph
-    for k, (comp, args) in enumerate(ub.items):
-        comp.run(*args, stream=ub.streams[k % stream_count].cuda_stream)
-        if k % 16 == 15:
-            torch.cuda.synchronize()
-            print(f"[bench] uneven full draw: first pass {k + 1} instances, "
-                  f"{time.perf_counter() - t1:.1f} s", file=sys.stderr, flush=True)
+    # first (eager) pass, 16 instances per call: builds every plan's offset tables and its graph
+    for lo in range(0, len(ub.items), 16):
+        hi = min(lo + 16, len(ub.items))
+        ub.run_range(lo, hi)
+        torch.cuda.synchronize()
+        print(f"[bench] uneven full draw: first pass {hi} instances, "
+              f"{time.perf_counter() - t1:.1f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     bad = [comp.report()["status"] for comp, _ in ub.items]
     bad = [b for b in bad if b != "ok"]

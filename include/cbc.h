@@ -145,7 +145,8 @@ typedef struct {
   int32_t node;        /* the edge from `node` to its parent is truncated */
   int32_t sweep;       /* 1: subtree environment (Eq. cbc_tree_first_contraction); 2: environment of
                           the rest of the tree (Eqs. tt_cbc_first_contraction,
-                          cbc_tree_second_contraction); 0: a truncation of the naive method */
+                          cbc_tree_second_contraction); 0: a truncation of the naive method;
+                          3: a basis of the density-matrix method (cbc_apply_dm) */
   int32_t dim;         /* dimension of the Gram matrix that was eigensolved */
   int32_t kmax;        /* directions planned (min(max_bond, Gram dimension)) */
   int32_t kept;        /* directions kept (fewer than kmax only with a tolerance) */
@@ -185,7 +186,7 @@ cbc_status cbc_autotune(cbc_ctx* ctx, const char* cache_path);
 
 /* Sizes for a problem: workspace bytes and the output packing (n_nodes + 1 offsets; the last entry is
  * the total number of complex elements the output buffer must hold). Host only, no device work.
- * `method` is 0 for cbc_apply, 1 for cbc_apply_naive and 2 for cbc_apply_src. */
+ * `method` is 0 for cbc_apply, 1 for cbc_apply_naive, 2 for cbc_apply_src and 3 for cbc_apply_dm. */
 cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
                      int32_t method, size_t* workspace_bytes, int64_t* out_offset);
 
@@ -235,6 +236,39 @@ cbc_status cbc_apply_split(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tens
                            void* workspace, size_t workspace_bytes, void* scratch,
                            size_t scratch_bytes, cbc_out* out, void* stream, cbc_stats* stats);
 
+/* One problem of a cbc_apply_many call: its own tree, networks, target bond, tolerance, workspace,
+ * output and (optional) statistics, with the meanings they have in cbc_apply. */
+typedef struct {
+  const cbc_tree* tree;
+  const cbc_tensors* ttno;
+  const cbc_tensors* ttns;
+  int32_t max_bond;
+  double tol;
+  void* workspace;          /* device; see cbc_apply_many for its size */
+  size_t workspace_bytes;
+  cbc_out* out;
+  cbc_stats* stats;         /* may be NULL */
+} cbc_problem;
+
+#define CBC_MAX_STREAMS 64
+
+/* `count` independent compressions of different shapes (trees, dimensions, max_bond, tol) in one
+ * call, for uneven batches (Sec. III B's sweeps run per problem; problems share nothing but the
+ * scratch below). Problem j runs on stream j % nstreams of the context (1 <= nstreams <=
+ * CBC_MAX_STREAMS, default priority, created on first use); those streams start after the work
+ * queued on `stream` before the call, and `stream` continues only after all problems (event fork
+ * and join), so the call is ordered like a kernel on `stream`. Eagerly, each problem replays its own
+ * captured graph; inside a caller's capture of `stream` the fork, the problems and the join are
+ * recorded into the caller's graph. With scratch == NULL every workspace holds cbc_query's
+ * workspace_bytes; otherwise scratch[s] (scratch_bytes[s] bytes) is shared by the problems of stream
+ * s, one after another, and each workspace holds the persistent part (cbc_plan_info; as for
+ * cbc_apply_split). CBC method, one precision for all. Argument errors are returned before any
+ * device work; a problem that fails stops the launches of the rest, and the call still joins its
+ * streams into `stream`. Each problem's report is read from its workspace (cbc_read_report). */
+cbc_status cbc_apply_many(cbc_ctx* ctx, int32_t count, const cbc_problem* problems,
+                          cbc_precision prec, int32_t nstreams, void* const* scratch,
+                          const size_t* scratch_bytes, void* stream);
+
 /* A batch of `batch` independent compressions of the same shape (same tree, dimensions, max_bond,
  * tol and precision) in one launch sequence: every kernel runs all instances at once. Instance b's
  * node i is at element b * T + offset[i] of each input buffer, where T is the network's total
@@ -272,6 +306,18 @@ cbc_status cbc_apply_src(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensor
                          const cbc_tensors* sketch, const cbc_tree* tree, int32_t max_bond,
                          cbc_precision prec, void* workspace, size_t workspace_bytes, cbc_out* out,
                          void* stream, cbc_stats* stats);
+
+/* Density-matrix compression, the method CBC is built from (Sec. III; Tab. time_scal and mem_scal
+ * give its cost): sweeps 1 and 2 contract the exact environments of <Phi|Phi>, Phi = O|psi>, on
+ * both sides of every bond (legs of both copies of the network: (chi_S D_O)^2 elements per bond), and
+ * sweep 3 (as in CBC, Eqs. cbc_tree_third_contraction, cbc_final_contraction) takes each node's
+ * basis from the top min(max_bond, rows) eigenvectors of its reduced density matrix Z B Z^H (FP64,
+ * through the truncation eigensolver; records with sweep 3). A node whose rows do not exceed
+ * max_bond keeps the identity basis. Workspace from cbc_query with method 3. Single instances, no
+ * tolerance. Otherwise as cbc_apply. */
+cbc_status cbc_apply_dm(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                        const cbc_tree* tree, int32_t max_bond, cbc_precision prec, void* workspace,
+                        size_t workspace_bytes, cbc_out* out, void* stream, cbc_stats* stats);
 
 /* For callers that cannot allocate device memory (code under stream capture, tight serving loops,
  * harnesses that forbid hipMalloc): cbc_apply without a workspace argument. Its workspace is a

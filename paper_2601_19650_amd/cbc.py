@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libcbc.so")
 
 FP64, MIXED = 0, 1
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
-METHODS = {"cbc": 0, "naive": 1, "src": 2}
+METHODS = {"cbc": 0, "naive": 1, "src": 2, "dm": 3}
 
 
 class CbcError(RuntimeError):
@@ -135,6 +135,15 @@ def lib():
                                     ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(_Out),
                                     ctypes.c_void_p, ctypes.POINTER(Stats)]
         L.cbc_apply_src.restype = ctypes.c_int
+        L.cbc_apply_many.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(CProblem),
+                                     ctypes.c_int, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p),
+                                     ctypes.POINTER(ctypes.c_size_t), ctypes.c_void_p]
+        L.cbc_apply_many.restype = ctypes.c_int
+        L.cbc_apply_dm.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Tensors),
+                                   ctypes.POINTER(_Tensors), ctypes.POINTER(_Tree), ctypes.c_int32,
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.POINTER(_Out), ctypes.c_void_p, ctypes.POINTER(Stats)]
+        L.cbc_apply_dm.restype = ctypes.c_int
         L.cbc_autotune.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
         L.cbc_autotune.restype = ctypes.c_int
         L.cbc_read_report.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
@@ -146,7 +155,8 @@ def lib():
 
 EXPORTED = ("cbc_create", "cbc_destroy", "cbc_status_str", "cbc_query", "cbc_plan_bonds",
             "cbc_apply", "cbc_apply_batched", "cbc_apply_naive", "cbc_autotune", "cbc_read_report",
-            "cbc_apply_noalloc", "cbc_plan_info", "cbc_apply_split", "cbc_apply_src")
+            "cbc_apply_noalloc", "cbc_plan_info", "cbc_apply_split", "cbc_apply_src",
+            "cbc_apply_many", "cbc_apply_dm")
 
 
 def _check(code, what):
@@ -227,8 +237,8 @@ def pack_batch(networks, device):
 
 class Compressor:
     """One problem shape: queries sizes once, owns workspace and output buffers, and runs the
-    compression (``method`` "cbc", "naive" or "src", ``precision`` "fp64" or "mixed"; "src" takes
-    its sketch matrices as run()'s ``sketch`` = (device buffer, offsets) from pack())."""
+    compression (``method`` "cbc", "naive", "src" or "dm", ``precision`` "fp64" or "mixed"; "src"
+    takes its sketch matrices as run()'s ``sketch`` = (device buffer, offsets) from pack())."""
 
     def __init__(self, ctx, tree, max_bond, precision="fp64", method="cbc", device="cuda", batch=1,
                  scratch=None):
@@ -298,6 +308,13 @@ class Compressor:
                                          self.scratch.data_ptr(), self.scratch.numel(),
                                          ctypes.byref(out), ctypes.c_void_p(stream),
                                          ctypes.byref(self.stats)), "cbc_apply_split")
+            return self.out, self.bond
+        if self.method == 3:
+            _check(lib().cbc_apply_dm(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns),
+                                      ctypes.byref(self.tree.c), self.max_bond, self.prec,
+                                      self.workspace.data_ptr(), self.ws_bytes, ctypes.byref(out),
+                                      ctypes.c_void_p(stream), ctypes.byref(self.stats)),
+                   "cbc_apply_dm")
             return self.out, self.bond
         fn = lib().cbc_apply if self.method == 0 else lib().cbc_apply_naive
         _check(fn(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns), ctypes.byref(self.tree.c),
@@ -381,13 +398,22 @@ def graph_groups(launches, cap):
     return groups
 
 
+class CProblem(ctypes.Structure):
+    _fields_ = [("tree", ctypes.POINTER(_Tree)), ("ttno", ctypes.POINTER(_Tensors)),
+                ("ttns", ctypes.POINTER(_Tensors)), ("max_bond", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("out", ctypes.POINTER(_Out)),
+                ("stats", ctypes.POINTER(Stats))]
+
+
 class UnevenBatch:
-    """Many instances of different shapes: one Compressor (plan, workspace, captured graph) per
-    instance, launched round-robin over `nstreams` side streams so that instances overlap on the
-    GPU. Inputs are packed once and stay resident. With `share_scratch`, the instances of one stream
-    share one scratch buffer (their calls are ordered by the stream), sized for the largest of them:
-    device memory is then the sum of the small persistent parts plus `nstreams` scratch buffers,
-    instead of the sum of every instance's whole workspace."""
+    """Many instances of different shapes launched by cbc_apply_many: one Compressor (plan,
+    workspace, outputs) per instance; the library spreads them round-robin over `nstreams` streams
+    of its context, forked from and joined into the caller's stream. Inputs are packed once and stay
+    resident. With `share_scratch`, the instances of one stream share one scratch buffer (their
+    calls are ordered by the stream), sized for the largest of them: device memory is then the sum
+    of the small persistent parts plus `nstreams` scratch buffers, instead of the sum of every
+    instance's whole workspace."""
 
     def __init__(self, problems, precision="mixed", nstreams=8, device="cuda", autotune=False,
                  share_scratch=False):
@@ -395,23 +421,57 @@ class UnevenBatch:
         self.ctx = Context()
         if autotune:
             self.ctx.autotune()
-        self.streams = [torch.cuda.Stream(device=device) for _ in range(nstreams)]
+        self.nstreams = int(nstreams)
+        self.prec = PRECISIONS[precision]
         trees = [Tree.of(p) for p in problems]
         self.scratch = []
         if share_scratch:
-            need = [0] * nstreams
-            for k, (p, t) in enumerate(zip(problems, trees)):
-                b = scratch_need(self.ctx, t, p.max_bond, precision)["scratch_bytes"]
-                need[k % nstreams] = max(need[k % nstreams], b)
-            self.scratch = [torch.empty(max(b, 256), dtype=torch.uint8, device=device)
-                            for b in need]
+            # every stream's buffer fits every instance, so that a call over any consecutive range
+            # of the instances (graphs of part of the batch) may use them
+            need = max([scratch_need(self.ctx, t, p.max_bond, precision)["scratch_bytes"]
+                        for p, t in zip(problems, trees)] + [256])
+            self.scratch = [torch.empty(need, dtype=torch.uint8, device=device)
+                            for _ in range(self.nstreams)]
         self.items = []
+        self._keep = []
+        self._problems = (CProblem * len(problems))()
+        I64 = ctypes.POINTER(ctypes.c_int64)
         for k, (p, tree) in enumerate(zip(problems, trees)):
             st, so = pack(p.state, device)
             op, oo = pack(p.op, device)
             comp = Compressor(self.ctx, tree, p.max_bond, precision, device=device,
-                              scratch=self.scratch[k % nstreams] if share_scratch else None)
+                              scratch=self.scratch[0] if share_scratch else None)
             self.items.append((comp, (op, oo, st, so, p.tol)))
+            oo = np.ascontiguousarray(oo, dtype=np.int64)
+            so = np.ascontiguousarray(so, dtype=np.int64)
+            ttno = _Tensors(op.data_ptr(), oo.ctypes.data_as(I64))
+            ttns = _Tensors(st.data_ptr(), so.ctypes.data_as(I64))
+            out = _Out(comp.out.data_ptr(), comp.out_off.ctypes.data_as(I64),
+                       comp.bond.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+            self._keep += [oo, so, ttno, ttns, out]
+            self._problems[k] = CProblem(ctypes.pointer(tree.c), ctypes.pointer(ttno),
+                                         ctypes.pointer(ttns), comp.max_bond, float(p.tol),
+                                         comp.workspace.data_ptr(), comp.ws_bytes,
+                                         ctypes.pointer(out), ctypes.pointer(comp.stats))
+        if share_scratch:
+            self._scr = (ctypes.c_void_p * self.nstreams)(*[x.data_ptr() for x in self.scratch])
+            self._scr_bytes = (ctypes.c_size_t * self.nstreams)(*[x.numel() for x in self.scratch])
+        else:
+            self._scr = self._scr_bytes = None
+
+    def run_range(self, lo, hi, stream=None):
+        """Launch instances lo..hi-1 with one cbc_apply_many call on `stream` (default: the current
+        stream); asynchronous."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        if hi <= lo:
+            return
+        first = ctypes.cast(ctypes.byref(self._problems, lo * ctypes.sizeof(CProblem)),
+                            ctypes.POINTER(CProblem))
+        _check(lib().cbc_apply_many(self.ctx.h, hi - lo, first, self.prec, self.nstreams,
+                                    self._scr, self._scr_bytes, ctypes.c_void_p(stream)),
+               "cbc_apply_many", "cbc_apply_dm")
 
     def run(self):
         """Launch every instance (asynchronous); call torch.cuda.synchronize() to wait."""
@@ -419,9 +479,7 @@ class UnevenBatch:
             for g in self.graphs:
                 g.replay()
             return
-        for k, (comp, args) in enumerate(self.items):
-            s = self.streams[k % len(self.streams)]
-            comp.run(*args, stream=s.cuda_stream)
+        self.run_range(0, len(self.items))
 
     # Kernel launches recorded into one graph at most. Graphs of up to about 10,500 launches (16
     # instances of the uneven draw) replay correctly on MI355X; one graph of the whole 256-instance
@@ -430,11 +488,11 @@ class UnevenBatch:
     MAX_GRAPH_LAUNCHES = 12000
 
     def capture(self, graph=None, max_launches=None):
-        """Record the batch (every instance, forked over the streams and joined) into graphs of at
-        most `max_launches` kernel launches each (default MAX_GRAPH_LAUNCHES; consecutive
-        instances, at least one per graph); run() then replays them in order, one launch each.
-        Runs the batch once first, eagerly. `graph`: a torch.cuda.CUDAGraph to capture into when
-        the batch fits one graph (default: a new one)."""
+        """Record the batch into graphs of at most `max_launches` kernel launches each (default
+        MAX_GRAPH_LAUNCHES; consecutive instances, at least one per graph), each holding one
+        cbc_apply_many call (fork over the library's streams, the instances, join); run() then
+        replays them in order, one launch each. Runs the batch once first, eagerly. `graph`: a
+        torch.cuda.CUDAGraph to capture into when the batch fits one graph (default: a new one)."""
         import torch
         cap = self.MAX_GRAPH_LAUNCHES if max_launches is None else int(max_launches)
         self.graphs = []
@@ -443,19 +501,12 @@ class UnevenBatch:
         groups = graph_groups([int(comp.stats.n_kernels) for comp, _ in self.items], cap)
         if graph is not None and len(groups) > 1:
             raise ValueError("the batch needs several graphs; capture without `graph`")
-        root = torch.cuda.Stream(device=self.streams[0].device)
+        root = torch.cuda.Stream()
         graphs = []
         for grp in groups:
             g = graph if graph is not None else torch.cuda.CUDAGraph()
             with torch.cuda.graph(g, stream=root):
-                for s in self.streams:
-                    s.wait_stream(root)
-                for k in grp:
-                    comp, args = self.items[k]
-                    s = self.streams[k % len(self.streams)]
-                    comp.run(*args, stream=s.cuda_stream)
-                for s in self.streams:
-                    root.wait_stream(s)
+                self.run_range(grp[0], grp[-1] + 1, root.cuda_stream)
             graphs.append(g)
         self.graphs = graphs
 

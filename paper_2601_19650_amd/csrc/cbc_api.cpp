@@ -48,6 +48,7 @@ struct TRef {
 struct Ten {
   TRef ref;
   std::vector<int> legs;
+  bool cj = false;   // enters contractions complex-conjugated (the bra copies of a network)
 };
 
 enum OpKind : int { K_GEMM, K_EIG, K_FORM_N, K_CHOL, K_CONVERT, K_IDENT, K_WRITE, K_ZERO, K_HEADER,
@@ -477,10 +478,10 @@ struct Builder {
         }
       }
       Ten Xn = alloc(best_legs, ct, false);
-      X = contract(X, false, rem[best], false, best_legs, Xn.ref, ct, cacc, 0);
+      X = contract(X, X.cj, rem[best], rem[best].cj, best_legs, Xn.ref, ct, cacc, 0);
       rem.erase(rem.begin() + (ptrdiff_t)best);
     }
-    return contract(X, false, rem[0], false, out, dst, ct, cacc, 0);
+    return contract(X, X.cj, rem[0], rem[0].cj, out, dst, ct, cacc, 0);
   }
 
   Ten state_node(int i) const {
@@ -608,7 +609,7 @@ struct Builder {
   // Top-kmax eigenvectors of a Hermitian FP64 Gram G (s x s, row-major): U (s x kmax) with legs
   // [row legs..., nl] (persistent if asked).
   Ten eig_op(const TRef& G, int s, int kmax, const std::vector<int>& rowlegs, int nl, bool persistent,
-             int node, TRef* lam_out = nullptr, TRef* kk_out = nullptr) {
+             int node, TRef* lam_out = nullptr, TRef* kk_out = nullptr, int sweep = 0) {
     std::vector<int> ul = rowlegs;
     ul.push_back(nl);
     Ten U = alloc(ul, DT_C128, persistent);
@@ -629,7 +630,7 @@ struct Builder {
     e.cls = CBC_K_EIG;
     e.flops = 16.0 / 3.0 * (double)s * s * s + 8.0 * (double)s * s * kmax;
     e.bytes = 16.0 * (double)s * s + 16.0 * (double)s * kmax;
-    add_eig(e, node, 0);
+    add_eig(e, node, sweep);
     P.n_eig++;
     P.max_eig = std::max(P.max_eig, s);
     if (!eig_size_supported(s)) P.unsupported = true;
@@ -1244,6 +1245,237 @@ cbc_status build_plan_src(Plan& P, const Problem& pr, int max_bond, cbc_precisio
 }
 
 // ------------------------------------------------------------------------------------------------
+// density-matrix compression (the method CBC is built from, Sec. III): sweeps 1 and 2 contract the
+// exact environments of <Phi|Phi>, Phi = O|psi> (legs: ket state, ket operator, bra operator, bra
+// state), and sweep 3 takes each node's basis from the top eigenvectors of its reduced density
+// matrix rho = Z B Z^H. The environments are normalised after every node step (a positive factor
+// does not change an eigenvector); R carries its factor in the node's log slot as in CBC.
+
+cbc_status build_plan_dm(Plan& P, const Problem& pr, int max_bond, cbc_precision prec,
+                         bool fill_tables) {
+  Builder B(P, pr, max_bond, false, prec);
+  B.fill_tables = fill_tables;
+  const int n = pr.n;
+  B.sig.resize(n);
+  B.sigp.resize(n);
+  B.ealpha.assign(n, -1);
+  B.ebeta.assign(n, -1);
+  std::vector<int> sigpp(n), ealphap(n, -1), ebetap(n, -1);
+  for (int i = 0; i < n; ++i) {
+    B.sig[i] = B.leg(pr.phys[i]);
+    B.sigp[i] = B.leg(pr.phys[i]);
+    sigpp[i] = B.leg(pr.phys[i]);
+    if (pr.parent[i] >= 0) {
+      B.ealpha[i] = B.leg(pr.chi[i]);
+      B.ebeta[i] = B.leg(pr.dop[i]);
+      ealphap[i] = B.leg(pr.chi[i]);
+      ebetap[i] = B.leg(pr.dop[i]);
+    }
+  }
+  B.rootA = B.leg(1);
+  B.rootB = B.leg(1);
+  const int rootAp = B.leg(1), rootBp = B.leg(1);
+  plan_prologue(B, P, prec, n);
+  // the bra copies: conj(W_i) [sigma', sigma'', beta'...] and conj(T_i) [sigma'', alpha'...]
+  auto op_bra = [&](int i) {
+    Ten W = B.op_node(i);
+    W.legs = {B.sigp[i], sigpp[i], pr.parent[i] >= 0 ? ebetap[i] : rootBp};
+    for (int c : pr.ch[i]) W.legs.push_back(ebetap[c]);
+    W.cj = true;
+    return W;
+  };
+  auto state_bra = [&](int i) {
+    Ten T = B.state_node(i);
+    T.legs = {sigpp[i], pr.parent[i] >= 0 ? ealphap[i] : rootAp};
+    for (int c : pr.ch[i]) T.legs.push_back(ealphap[c]);
+    T.cj = true;
+    return T;
+  };
+  std::vector<int> kout(n, 1);
+  std::vector<int64_t> rows(n, 1);
+  for (int i : pr.post) {
+    rows[i] = pr.phys[i];
+    for (int c : pr.ch[i]) rows[i] *= kout[c];
+    if (i != pr.root) kout[i] = (int)std::min<int64_t>(rows[i], max_bond);
+  }
+  // environments needed: B at every truncated node and the non-root ancestors it is built from; A
+  // of the siblings along the way and of everything below them
+  std::vector<char> needB(n, 0), needA(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (i == pr.root || rows[i] <= max_bond) continue;
+    for (int q = i; q != pr.root && !needB[q]; q = pr.parent[q]) needB[q] = 1;
+  }
+  std::function<void(int)> mark = [&](int c) {
+    if (needA[c]) return;
+    needA[c] = 1;
+    for (int cc : pr.ch[c]) mark(cc);
+  };
+  for (int k = 0; k < n; ++k) {
+    if (!needB[k]) continue;
+    for (int c : pr.ch[pr.parent[k]])
+      if (c != k) mark(c);
+  }
+  std::vector<Ten> A(n), Bv(n), R(n);
+  // sweep 1, leaves to root: A^{[i]} [alpha_i, beta_i, beta'_i, alpha'_i]
+  for (int i : pr.post) {
+    if (!needA[i]) continue;
+    B.reset_scratch();
+    std::vector<Ten> rem;
+    for (int c : pr.ch[i]) rem.push_back(A[c]);
+    rem.push_back(B.op_node(i));
+    rem.push_back(op_bra(i));
+    rem.push_back(state_bra(i));
+    const std::vector<int> out{B.ealpha[i], B.ebeta[i], ebetap[i], ealphap[i]};
+    Ten At = B.alloc(out, B.ct, true);
+    A[i] = B.chain(B.state_node(i), rem, out, At.ref);
+    B.normalize(A[i]);
+  }
+  // sweep 2, root to leaves: B^{[k]} [alpha_k, beta_k, beta'_k, alpha'_k]
+  {
+    std::vector<int> pre(pr.post.rbegin(), pr.post.rend());
+    for (int i : pre) {
+      for (int k : pr.ch[i]) {
+        if (!needB[k]) continue;
+        B.reset_scratch();
+        std::vector<Ten> rem;
+        if (i != pr.root) rem.push_back(Bv[i]);
+        for (int c : pr.ch[i])
+          if (c != k) rem.push_back(A[c]);
+        rem.push_back(B.op_node(i));
+        rem.push_back(op_bra(i));
+        rem.push_back(state_bra(i));
+        std::vector<int> out;
+        if (i == pr.root) {   // the root's trivial parent legs stay on the result (dimension 1)
+          out = {B.rootA, B.rootB, rootBp, rootAp};
+        }
+        out.push_back(B.ealpha[k]);
+        out.push_back(B.ebeta[k]);
+        out.push_back(ebetap[k]);
+        out.push_back(ealphap[k]);
+        Ten Bt = B.alloc(out, B.ct, true);
+        Bt = B.chain(B.state_node(i), rem, out, Bt.ref);
+        Bv[k] = Ten{Bt.ref, {B.ealpha[k], B.ebeta[k], ebetap[k], ealphap[k]}};
+        B.normalize(Bv[k]);
+      }
+    }
+  }
+  // sweep 3, leaves to root: Z^{[i]}, rho = Z B Z^H, top eigenvectors, R = Q^H Z
+  P.out_off.assign(n + 1, 0);
+  P.out_bond.assign(n, 1);
+  for (int i = 0; i < n; ++i) {
+    int64_t e = (int64_t)pr.phys[i] * kout[i];
+    for (int c : pr.ch[i]) e *= kout[c];
+    P.out_off[i + 1] = P.out_off[i] + e;
+    P.out_bond[i] = kout[i];
+  }
+  TRef one = B.wsp(256, DT_C128);
+  {
+    Op f;
+    f.kind = K_IDENT;
+    f.dst = one;
+    f.td = DT_C128;
+    f.a = 1;
+    f.b = 1;
+    P.ops.push_back(f);
+  }
+  for (int i : pr.post) {
+    B.reset_scratch();
+    std::vector<std::pair<int, Ten>> envs;
+    std::vector<int> zl{B.sigp[i]};
+    for (size_t j = 0; j < pr.ch[i].size(); ++j) {
+      const int c = pr.ch[i][j];
+      envs.push_back({1 + (int)j, R[c]});
+      zl.push_back(R[c].legs[0]);
+    }
+    if (i == pr.root) {
+      std::vector<int> zr{B.rootA};
+      zr.insert(zr.end(), zl.begin(), zl.end());
+      zr.push_back(B.rootB);
+      Ten Z = B.alloc(zr, B.ct, false);
+      Z = B.node_contract(i, envs, zr, Z.ref);
+      Op w;
+      w.kind = K_WRITE;
+      w.src = Z.ref;
+      w.ts = B.ct;
+      w.a = 1;
+      w.b = pr.phys[i];
+      w.rest = B.elems(zr) / pr.phys[i];
+      w.dst.src = S_OUT;
+      w.dst.off = i;
+      w.logs.src = S_WS;
+      w.logs.off = P.logs_off;
+      w.nlogs = n;
+      P.ops.push_back(w);
+      continue;
+    }
+    zl.push_back(B.ealpha[i]);
+    zl.push_back(B.ebeta[i]);
+    const int64_t ns = rows[i];
+    std::vector<int> rest(zl.begin(), zl.end() - 2);
+    const bool ident = ns <= max_bond;
+    Ten Z = B.alloc(zl, B.ct, ident);
+    Z = B.node_contract(i, envs, zl, Z.ref);
+    if (ident) {
+      const int nl = B.leg(ns);
+      R[i] = Ten{Z.ref, {nl, B.ealpha[i], B.ebeta[i]}};
+      TRef q = B.scr(16 * (size_t)ns * ns, DT_C128);
+      Op f;
+      f.kind = K_IDENT;
+      f.dst = q;
+      f.td = DT_C128;
+      f.a = (int)ns;
+      f.b = (int)ns;
+      P.ops.push_back(f);
+      Op w;
+      w.kind = K_WRITE;
+      w.src = q;
+      w.ts = DT_C128;
+      w.a = (int)ns;
+      w.b = pr.phys[i];
+      w.rest = ns / pr.phys[i];
+      w.dst.src = S_OUT;
+      w.dst.off = i;
+      P.ops.push_back(w);
+      continue;
+    }
+    // X = Z B over the parent bond's ket legs: [rows..., beta'_i, alpha'_i]
+    std::vector<int> xl = rest;
+    xl.push_back(ebetap[i]);
+    xl.push_back(ealphap[i]);
+    Ten X = B.alloc(xl, B.ct, false);
+    X = B.contract(Z, false, Bv[i], false, xl, X.ref, B.ct, B.cacc, 0);
+    // rho = X conj(Z') over the bra legs, in FP64: [rows..., rows'...]
+    std::vector<int> rowsp;
+    for (int l : rest) rowsp.push_back(B.leg(B.legdim[l]));
+    std::vector<int> zbl = rowsp;
+    zbl.push_back(ealphap[i]);
+    zbl.push_back(ebetap[i]);
+    Ten Zb{Z.ref, zbl, true};
+    std::vector<int> rl = rest;
+    rl.insert(rl.end(), rowsp.begin(), rowsp.end());
+    Ten rho = B.alloc(rl, DT_C128, false);
+    B.contract(X, false, Zb, true, rl, rho.ref, DT_C128, DT_C128, 1);
+    const int knew = B.leg(kout[i]);
+    Ten U = B.eig_op(rho.ref, (int)ns, kout[i], rest, knew, false, i, nullptr, nullptr, 3);
+    Ten Rt = B.alloc({knew, B.ealpha[i], B.ebeta[i]}, B.ct, true);
+    R[i] = B.contract(U, true, Z, false, {knew, B.ealpha[i], B.ebeta[i]}, Rt.ref, B.ct, B.cacc, 0);
+    TRef logslot;
+    logslot.src = S_WS;
+    logslot.off = P.logs_off + 8 * (int64_t)i;
+    B.normalize(R[i], logslot);
+    // output node [sigma', k, chi_c...] from U [sigma', chi_c..., k] (a layout copy)
+    std::vector<int> ol{B.sigp[i], knew};
+    ol.insert(ol.end(), rest.begin() + 1, rest.end());
+    TRef dst;
+    dst.src = S_OUT;
+    dst.off = i;
+    dst.dt = DT_C128;
+    B.contract(U, false, Ten{one, {}}, false, ol, dst, DT_C128, DT_C128, 3);
+  }
+  return plan_epilogue(B, P);
+}
+
+// ------------------------------------------------------------------------------------------------
 // the naive (direct) method of Sec. III C: exact product, canonical form, truncated-SVD sweep
 
 cbc_status build_plan_naive(Plan& P, const Problem& pr, int max_bond, bool tol_on,
@@ -1459,6 +1691,16 @@ struct cbc_ctx {
   bool tune = false;
   std::string tune_path;
   std::map<std::vector<int64_t>, std::pair<int, int>> tuned;
+  // streams of cbc_apply_many (default priority) with the events that fork and join them
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> join_ev;
+  hipEvent_t fork_ev = nullptr;
+  ~cbc_ctx() {
+    plans.clear();   // a plan waits for its graphs' last launches before it goes
+    for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+  }
 };
 
 namespace {
@@ -1785,7 +2027,8 @@ cbc_status get_plan(cbc_ctx* ctx, const Problem& pr, int max_bond, bool tol_on, 
     P->tune = ctx->tune;
     cbc_status s = method == 0   ? build_plan(*P, pr, max_bond, tol_on, prec, need_tables)
                    : method == 1 ? build_plan_naive(*P, pr, max_bond, tol_on, prec, need_tables)
-                                 : build_plan_src(*P, pr, max_bond, prec, need_tables);
+                   : method == 2 ? build_plan_src(*P, pr, max_bond, prec, need_tables)
+                                 : build_plan_dm(*P, pr, max_bond, prec, need_tables);
     if (s != CBC_OK) return s;
     if (P->unsupported) return CBC_EUNSUP;
     P->has_tables = need_tables;
@@ -1886,7 +2129,7 @@ static cbc_status common_checks(const cbc_tree* tree, int32_t max_bond, cbc_prec
 cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
                      int32_t method, size_t* workspace_bytes, int64_t* out_offset) {
   if (!ctx || !workspace_bytes || !out_offset) return CBC_EINVAL;
-  if (method < 0 || method > 2) return CBC_EINVAL;
+  if (method < 0 || method > 3) return CBC_EINVAL;
   if (method == 2 && max_bond > 65535) return CBC_EUNSUP;
   Problem pr;
   cbc_status s = common_checks(tree, max_bond, prec, pr);
@@ -1912,7 +2155,7 @@ cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_p
 cbc_status cbc_plan_info(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
                          int32_t method, int32_t tol_on, cbc_plan_summary* info) {
   if (!ctx || !info) return CBC_EINVAL;
-  if (method < 0 || method > 2) return CBC_EINVAL;
+  if (method < 0 || method > 3) return CBC_EINVAL;
   if (method == 2 && max_bond > 65535) return CBC_EUNSUP;
   Problem pr;
   cbc_status s = common_checks(tree, max_bond, prec, pr);
@@ -1963,6 +2206,7 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   if (method == 2 && (!sketch || !sketch->data || !sketch->offset || batch != 1 || noalloc ||
                       scratch || tol != 0.0))
     return CBC_EINVAL;
+  if (method == 3 && (batch != 1 || noalloc || scratch || tol != 0.0)) return CBC_EINVAL;
   if (noalloc && (batch != 1 || (stats && stats->profile))) return CBC_EINVAL;
   const bool split = scratch != nullptr;
   if (split && (batch != 1 || noalloc)) return CBC_EINVAL;
@@ -2210,6 +2454,62 @@ cbc_status cbc_apply_src(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensor
   if (!sketch) return CBC_EINVAL;
   return apply_impl(ctx, ttno, ttns, tree, max_bond, 0.0, prec, workspace, workspace_bytes, out,
                     stream, stats, 2, 1, false, nullptr, 0, sketch);
+}
+
+cbc_status cbc_apply_many(cbc_ctx* ctx, int32_t count, const cbc_problem* problems,
+                          cbc_precision prec, int32_t nstreams, void* const* scratch,
+                          const size_t* scratch_bytes, void* stream) {
+  if (!ctx || count < 0 || (count > 0 && !problems) || nstreams < 1 || nstreams > CBC_MAX_STREAMS)
+    return CBC_EINVAL;
+  if (scratch && !scratch_bytes) return CBC_EINVAL;
+  for (int32_t j = 0; j < count; ++j) {
+    const cbc_problem& p = problems[j];
+    if (!p.tree || !p.ttno || !p.ttns || !p.out || !p.workspace) return CBC_EINVAL;
+    if (scratch && !scratch[j % nstreams]) return CBC_EINVAL;
+  }
+  if (count == 0) return CBC_OK;
+  while ((int)ctx->streams.size() < nstreams) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return CBC_EHIP;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipStreamDestroy(s);
+      return CBC_EHIP;
+    }
+    ctx->streams.push_back(s);
+    ctx->join_ev.push_back(e);
+  }
+  if (!ctx->fork_ev && hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess)
+    return CBC_EHIP;
+  hipStream_t st = (hipStream_t)stream;
+  const int used = std::min<int32_t>(nstreams, count);
+  // fork: every stream used starts after the work queued on `stream` (inside a capture of `stream`
+  // this makes them part of the same graph)
+  if (hipEventRecord(ctx->fork_ev, st) != hipSuccess) return CBC_EHIP;
+  for (int s = 0; s < used; ++s)
+    if (hipStreamWaitEvent(ctx->streams[s], ctx->fork_ev, 0) != hipSuccess) return CBC_EHIP;
+  cbc_status rc = CBC_OK;
+  for (int32_t j = 0; j < count && rc == CBC_OK; ++j) {
+    const cbc_problem& p = problems[j];
+    const int s = j % nstreams;
+    rc = apply_impl(ctx, p.ttno, p.ttns, p.tree, p.max_bond, p.tol, prec, p.workspace,
+                    p.workspace_bytes, p.out, ctx->streams[s], p.stats, 0, 1, false,
+                    scratch ? scratch[s] : nullptr, scratch ? scratch_bytes[s] : 0);
+  }
+  // join: `stream` continues after every problem (also after a failed call, so that a capture
+  // of `stream` can be ended)
+  for (int s = 0; s < used; ++s) {
+    if (hipEventRecord(ctx->join_ev[s], ctx->streams[s]) != hipSuccess) return CBC_EHIP;
+    if (hipStreamWaitEvent(st, ctx->join_ev[s], 0) != hipSuccess) return CBC_EHIP;
+  }
+  return rc;
+}
+
+cbc_status cbc_apply_dm(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                        const cbc_tree* tree, int32_t max_bond, cbc_precision prec, void* workspace,
+                        size_t workspace_bytes, cbc_out* out, void* stream, cbc_stats* stats) {
+  return apply_impl(ctx, ttno, ttns, tree, max_bond, 0.0, prec, workspace, workspace_bytes, out,
+                    stream, stats, 3);
 }
 
 cbc_status cbc_apply_batched(cbc_ctx* ctx, int32_t batch, const cbc_tensors* ttno,

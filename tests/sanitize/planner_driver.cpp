@@ -134,7 +134,7 @@ int main(int argc, char** argv) {
     const int n = c.n_nodes;
     std::vector<int64_t> off(n + 1, 0);
     for (int prec = 0; prec < 2; ++prec) {
-      for (int method = 0; method < 3; ++method) {
+      for (int method = 0; method < 4; ++method) {
         size_t ws = 0;
         const int rc = cbc_query(ctx, &c, t.max_bond, (cbc_precision)prec, method, &ws, off.data());
         // the naive method forms the exact product, whose Grams exceed the limit sooner
@@ -218,6 +218,14 @@ int main(int argc, char** argv) {
     expect("autotune", "cache", cbc_autotune(ctx, argv[1]), CBC_OK);
   }
   expect("report_null", "rep", cbc_read_report(nullptr, 0, 0, nullptr, nullptr), CBC_EINVAL);
+  expect("many_empty", "many", cbc_apply_many(ctx, 0, nullptr, CBC_PREC_FP64, 4, nullptr, nullptr,
+                                               nullptr), CBC_OK);
+  {
+    cbc_problem probs[2];
+    std::memset(probs, 0, sizeof(probs));
+    expect("many_null_problem", "many", cbc_apply_many(ctx, 2, probs, CBC_PREC_FP64, 2, nullptr,
+                                                       nullptr, nullptr), CBC_EINVAL);
+  }
   cbc_destroy(ctx);
   std::printf("failures %d\n", failures);
   return failures == 0 ? 0 : 1;

@@ -343,4 +343,43 @@ def test_src_plan_sizes_match_oracle(maker):
     assert [int(s) for s in np.diff(off)] == [t.size for t in ref]
     info = cbc.plan_info(tree, p.max_bond, "mixed", method="src")
     assert info["launches"]["eig"] == 0 and info["flops"]["eig"] == 0.0
-    assert _query(tree, p.max_bond, 0, 3)[0] == -1
+    assert _query(tree, p.max_bond, 0, 4)[0] == -1
+
+
+def test_apply_many_argument_errors_need_no_device():
+    """cbc_apply_many checks its arguments (counts, stream count, problems, scratch) before any
+    device work; an empty batch is a no-op."""
+    L = cbc.lib()
+    ctx = cbc.Context()
+    P = ctypes.POINTER(cbc.CProblem)
+    assert L.cbc_apply_many(None, 1, None, 0, 1, None, None, None) == -1
+    assert L.cbc_apply_many(ctx.h, -1, None, 0, 1, None, None, None) == -1
+    assert L.cbc_apply_many(ctx.h, 1, None, 0, 1, None, None, None) == -1
+    assert L.cbc_apply_many(ctx.h, 0, None, 0, 1, None, None, None) == 0
+    probs = (cbc.CProblem * 2)()
+    assert L.cbc_apply_many(ctx.h, 2, ctypes.cast(probs, P), 0, 1, None, None, None) == -1
+    assert L.cbc_apply_many(ctx.h, 0, None, 0, 0, None, None, None) == -1
+    assert L.cbc_apply_many(ctx.h, 0, None, 0, 65, None, None, None) == -1
+    scr = (ctypes.c_void_p * 1)(0x1000)
+    assert L.cbc_apply_many(ctx.h, 0, None, 0, 1, scr, None, None) == -1
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: config_problem("C1"), lambda: config_problem("C2", n=12),
+    lambda: random_problem(kary_parent(13, 3), 2, 6, 3, 5, seed=4),
+    lambda: random_problem(kary_parent(7, 2), [1, 1, 1, 2, 2, 2, 2], 4, 4, 3, seed=6)])
+def test_dm_plan_sizes_match_oracle(maker):
+    """The density-matrix method's planned output node sizes equal those of the DM oracle, and it
+    plans one eigensolve per truncated node."""
+    from oracle.dm import dm_tree
+    p = maker()
+    tree = cbc.Tree.of(p)
+    for prec in (0, 1):
+        rc, ws, off = _query(tree, p.max_bond, prec, 3)
+        assert rc == 0 and ws > 0
+    ref = dm_tree(p.parent, p.state, p.op, p.max_bond)
+    assert [int(s) for s in np.diff(off)] == [t.size for t in ref]
+    info = cbc.plan_info(tree, p.max_bond, "fp64", method="dm")
+    truncated = sum(1 for i, t in enumerate(ref) if p.parent[i] >= 0 and
+                    t.shape[1] < t.size // t.shape[1])
+    assert info["launches"]["eig"] == truncated
