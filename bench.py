@@ -247,47 +247,59 @@ def _rel_error_vs_exact(parent, out, state, op, norm_phi_sq, weight=False):
     return (err, nq / norm_phi_sq) if weight else err
 
 
-def src_run(cbc, p, stream, steps, warmup, seed=11, cbc_outputs=None):
-    """The randomised compression (cbc_apply_src) on workload p in both precisions, with its sketch
-    matrices drawn from `seed`: time per compression (graph replay), kernel-class times, and the
-    relative error against the exact product O|psi>, beside that of the CBC outputs given."""
+def method_run(cbc, p, stream, steps, warmup, method, seed=11, nphi=None):
+    """Another method of the library (method "src": cbc_apply_src with sketch matrices drawn from
+    `seed`; "dm": cbc_apply_dm) on workload p in both precisions: time per compression (graph
+    replay), kernel-class times, and the relative error and captured weight against the exact
+    product O|psi> (||O psi||^2 = nphi)."""
     import torch
     from paper_2601_19650_amd.inputs import sketch_matrices
     tree = cbc.Tree.of(p)
     st, so = cbc.pack(p.state, "cuda:0")
     op, oo = cbc.pack(p.op, "cuda:0")
-    sk = cbc.pack(sketch_matrices(p.phys, p.max_bond, seed), "cuda:0")
+    kw = {}
+    res = {}
+    if method == "src":
+        kw = {"sketch": cbc.pack(sketch_matrices(p.phys, p.max_bond, seed), "cuda:0")}
+        res["sketch_seed"] = seed
     ctx = new_context(cbc)
-    res = {"sketch_seed": seed}
     outs = {}
     for prec in ("mixed", "fp64"):
-        comp = cbc.Compressor(ctx, tree, p.max_bond, prec, method="src", device="cuda:0")
-        sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, warmup, sketch=sk)
+        comp = cbc.Compressor(ctx, tree, p.max_bond, prec, method=method, device="cuda:0")
+        sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, warmup, **kw)
         outs[prec] = comp.unpack()
-        kms = profiled_runs(comp, (op, oo, st, so, 0.0), stream, 2, sketch=sk)
+        kms = profiled_runs(comp, (op, oo, st, so, 0.0), stream, 2, **kw)
         res[prec] = {"value": 1.0 / sec, "unit": "compressions/s", "ms_per_step": sec * 1e3,
                      "kernel_ms_per_step": {c: kms[k] for k, c in enumerate(cbc.CLASSES)},
                      "kernels_per_step": int(comp.stats.n_kernels),
-                     "contraction_tflops": comp.stats.flops[0] / sec / 1e12}
-        print(f"[bench] SRC {p.name} {prec}: {sec * 1e3:.3f} ms/compression", file=sys.stderr,
+                     "contraction_tflops": comp.stats.flops[0] / sec / 1e12,
+                     "workspace_gb": comp.ws_bytes / 1e9}
+        print(f"[bench] {method} {p.name} {prec}: {sec * 1e3:.3f} ms/compression", file=sys.stderr,
               flush=True)
         del comp
     torch.cuda.synchronize()
-    nphi = _gpu_sandwich(p.parent, None, p.state, p.op, twice=True).real
+    if nphi is None:
+        nphi = _gpu_sandwich(p.parent, None, p.state, p.op, twice=True).real
     for prec, o in outs.items():
         e, w = _rel_error_vs_exact(p.parent, o, p.state, p.op, nphi, weight=True)
         res[prec]["rel_error_vs_exact"] = e
         res[prec]["captured_weight_fraction"] = w
-    if cbc_outputs:
-        res["cbc"] = {}
-        for k, o in cbc_outputs.items():
-            e, w = _rel_error_vs_exact(p.parent, o, p.state, p.op, nphi, weight=True)
-            res["cbc"][k] = {"rel_error_vs_exact": e, "captured_weight_fraction": w}
-    print(f"[bench] SRC {p.name}: captured weight " + ", ".join(
-        f"{k} {res[k]['captured_weight_fraction']:.4e}" for k in outs) + (
-        ", CBC " + ", ".join(f"{k} {v['captured_weight_fraction']:.4e}"
-                             for k, v in res["cbc"].items()) if cbc_outputs else ""),
-        file=sys.stderr, flush=True)
+    print(f"[bench] {method} {p.name}: captured weight " + ", ".join(
+        f"{k} {res[k]['captured_weight_fraction']:.4e}" for k in outs), file=sys.stderr, flush=True)
+    return res
+
+
+def other_methods(cbc, p, stream, steps, warmup, cbc_outputs, methods):
+    """SRC and DM beside CBC on the headline workload, with every method's captured weight."""
+    import torch
+    torch.cuda.synchronize()
+    nphi = _gpu_sandwich(p.parent, None, p.state, p.op, twice=True).real
+    res = {"workload": WORKLOADS[p.name] if p.name in WORKLOADS else p.name, "cbc": {}}
+    for k, o in cbc_outputs.items():
+        e, w = _rel_error_vs_exact(p.parent, o, p.state, p.op, nphi, weight=True)
+        res["cbc"][k] = {"rel_error_vs_exact": e, "captured_weight_fraction": w}
+    for m in methods:
+        res[m] = method_run(cbc, p, stream, steps, warmup, m, nphi=nphi)
     return res
 
 
@@ -344,9 +356,9 @@ def paper_workloads(cbc, stream, full=False, steps=2):
     """The random-network workload of Sec. IV A on the GPU: tensor train (L=50, d=3, D=40), T-tree
     (L=20), balanced binary tree (depth 6, physical legs on the leaves) and fork tensor product
     structure (L=8), all d=3, D=10, entries U[-0.5, 1]; CBC and the randomised compression (mixed
-    and FP64; sketch seed 11) and the naive contract-then-compress baseline (FP64) over a sweep of
-    target bonds: time per compression and relative error ||O psi - psi'|| / ||O psi||, with
-    O psi contracted exactly on the device."""
+    and FP64; sketch seed 11), the density-matrix method and the naive contract-then-compress
+    baseline (FP64) over a sweep of target bonds: time per compression and relative error
+    ||O psi - psi'|| / ||O psi||, with O psi contracted exactly on the device."""
     import dataclasses
     import torch
     from paper_2601_19650_amd.inputs import PAPER_WORKLOADS, paper_problem, sketch_matrices
@@ -366,7 +378,7 @@ def paper_workloads(cbc, stream, full=False, steps=2):
             pt = {"target_bond": dbar}
             sk = cbc.pack(sketch_matrices(base.phys, dbar, 11), "cuda:0")
             for method, prec in (("cbc", "mixed"), ("cbc", "fp64"), ("src", "mixed"),
-                                 ("src", "fp64"), ("naive", "fp64")):
+                                 ("src", "fp64"), ("dm", "fp64"), ("naive", "fp64")):
                 comp = cbc.Compressor(ctx, tree, dbar, prec, method=method, device="cuda:0")
                 kw = {"sketch": sk} if method == "src" else {}
                 sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, 1, **kw)
@@ -589,6 +601,9 @@ def main():
     ap.add_argument("--src", choices=["on", "off"], default="on",
                     help="also time the randomised compression (cbc_apply_src) on the headline "
                          "workload, with the errors of it and of CBC against the exact product")
+    ap.add_argument("--dm", choices=["on", "off"], default="on",
+                    help="also time the density-matrix method (cbc_apply_dm) on the headline "
+                         "workload")
     ap.add_argument("--uneven-full", action="store_true",
                     help="also time the whole 256-instance uneven draw (several minutes)")
     ap.add_argument("--paper", choices=["off", "short", "full"], default="short",
@@ -606,6 +621,7 @@ def main():
     global AUTOTUNE
     AUTOTUNE = args.autotune == "on"
     args.src = args.src == "on"
+    args.dm = args.dm == "on"
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -686,9 +702,10 @@ def main():
             line["full_size_mixed_vs_fp64"] = {
                 "captured_weight": w, "captured_weight_ratio": w["mixed"] / w["fp64"],
                 "fidelity": _chain_fidelity(outputs["mixed"], outputs["fp64"])}
-    if args.src:
-        line["src"] = src_run(cbc, p, stream, args.steps, args.warmup, cbc_outputs=outputs)
-        line["src"]["workload"] = line["config"]["workload"]
+    methods = [m for m, on in (("src", args.src), ("dm", args.dm)) if on]
+    if methods:
+        line["other_methods"] = other_methods(cbc, p, stream, args.steps, args.warmup, outputs,
+                                              methods)
     del outputs
     if args.small_steps > 0:
         line["small_workloads"] = {}

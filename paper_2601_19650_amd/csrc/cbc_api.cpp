@@ -1455,8 +1455,14 @@ cbc_status build_plan_dm(Plan& P, const Problem& pr, int max_bond, cbc_precision
     rl.insert(rl.end(), rowsp.begin(), rowsp.end());
     Ten rho = B.alloc(rl, DT_C128, false);
     B.contract(X, false, Zb, true, rl, rho.ref, DT_C128, DT_C128, 1);
+    const int kev = B.leg(kout[i]);
+    Ten Ue = B.eig_op(rho.ref, (int)ns, kout[i], rest, kev, false, i, nullptr, nullptr, 3);
+    // The kept eigenvectors of a rank-deficient rho (a bond whose rank is below the target) include
+    // vectors of its zero eigenvalue, which the eigensolver need not return orthonormal; a
+    // Cholesky-QR of the columns makes the basis a (partial) isometry with the same span, so the
+    // weight-carrying directions and the state are unchanged.
     const int knew = B.leg(kout[i]);
-    Ten U = B.eig_op(rho.ref, (int)ns, kout[i], rest, knew, false, i, nullptr, nullptr, 3);
+    Ten U = B.cholqr_cols(Ue, kev, knew, false);
     Ten Rt = B.alloc({knew, B.ealpha[i], B.ebeta[i]}, B.ct, true);
     R[i] = B.contract(U, true, Z, false, {knew, B.ealpha[i], B.ebeta[i]}, Rt.ref, B.ct, B.cacc, 0);
     TRef logslot;
