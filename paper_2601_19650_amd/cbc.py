@@ -471,7 +471,7 @@ class UnevenBatch:
                             ctypes.POINTER(CProblem))
         _check(lib().cbc_apply_many(self.ctx.h, hi - lo, first, self.prec, self.nstreams,
                                     self._scr, self._scr_bytes, ctypes.c_void_p(stream)),
-               "cbc_apply_many", "cbc_apply_dm")
+               "cbc_apply_many")
 
     def run(self):
         """Launch every instance (asynchronous); call torch.cuda.synchronize() to wait."""
