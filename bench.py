@@ -267,6 +267,7 @@ def method_run(cbc, p, stream, steps, warmup, method, seed=11, nphi=None):
     for prec in ("mixed", "fp64"):
         comp = cbc.Compressor(ctx, tree, p.max_bond, prec, method=method, device="cuda:0")
         sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, warmup, **kw)
+        print(f"[bench] {method} {p.name} {prec}: timed", file=sys.stderr, flush=True)
         outs[prec] = comp.unpack()
         kms = profiled_runs(comp, (op, oo, st, so, 0.0), stream, 2, **kw)
         res[prec] = {"value": 1.0 / sec, "unit": "compressions/s", "ms_per_step": sec * 1e3,
@@ -601,9 +602,10 @@ def main():
     ap.add_argument("--src", choices=["on", "off"], default="on",
                     help="also time the randomised compression (cbc_apply_src) on the headline "
                          "workload, with the errors of it and of CBC against the exact product")
-    ap.add_argument("--dm", choices=["on", "off"], default="on",
+    ap.add_argument("--dm", choices=["on", "off"], default="off",
                     help="also time the density-matrix method (cbc_apply_dm) on the headline "
-                         "workload")
+                         "workload (seconds per compression there; the random-network section "
+                         "times it by default)")
     ap.add_argument("--uneven-full", action="store_true",
                     help="also time the whole 256-instance uneven draw (several minutes)")
     ap.add_argument("--paper", choices=["off", "short", "full"], default="short",

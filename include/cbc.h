@@ -54,11 +54,11 @@
  *
  * Eigensolves (Grams of dimension s): s <= 128 run in one workgroup. Larger Grams of a single
  * instance queued eagerly or in the library's own graphs use a Householder reduction spread over up
- * to 256 workgroups that wait for each other (s <= 1272); the library orders these solves one after
+ * to 256 workgroups that wait for each other (s <= 1536); the library orders these solves one after
  * another on each device (a device-wide event, across streams and contexts of the process), and
  * their waits are bounded (2 s), so a device shared with other spinning work cannot hang the call:
  * it ends with CBC_ETIMEOUT in the report instead. Batches, calls recorded into a caller's stream
- * capture, cbc_apply_noalloc and Grams above 1272 (up to 2064) use a two-stage reduction (dense to
+ * capture, cbc_apply_noalloc and Grams above 1536 (up to 2064) use a two-stage reduction (dense to
  * band on FP64 matrix cores, band to tridiagonal in one workgroup) that has no waits between
  * workgroups; nothing is recorded into a caller's capture beyond the call's own kernels.
  */

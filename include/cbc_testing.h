@@ -41,7 +41,8 @@ int cbc_test_eig(void* G, int s, int kmax, double tol, void* U, void* lam, void*
 
 /* The same eigensolve with the reduction to tridiagonal form chosen for s > 128: reduction 0 is the
  * library's (two-stage: dense -> band of half-bandwidth 16 -> tridiagonal), 1 the one-stage
- * multi-workgroup Householder reduction (s <= 1272), kept to compare the two; other values are
+ * multi-workgroup Householder reduction (s <= 1536), which the library uses for single eager
+ * instances; other values are
  * rejected. */
 int cbc_test_eig_reduction(void* G, int s, int kmax, double tol, int reduction, void* U, void* lam,
                            void* kkeep, void* inv_sqrt_l0, void* tstamp, void* stream);

@@ -94,7 +94,7 @@ struct EigArgs {
   // negative value makes the first wait give up at once (tests of the status path)
   long long timeout_ticks = 200000000LL;
   // reduction to tridiagonal form for s > 128: 0 = two-stage (dense -> band -> tridiagonal),
-  // 1 = one-stage multi-workgroup (s <= 1272, see eig_pick_reduction)
+  // 1 = one-stage multi-workgroup (s <= 1536, see eig_pick_reduction)
   int reduction = 0;
 };
 size_t eig_work_doubles(int s, int kmax);

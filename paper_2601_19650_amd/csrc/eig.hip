@@ -306,30 +306,37 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
 
 // ---- multi-workgroup Householder reduction (s > EIG_LDS_MAX) ------------------------------------
 // The rows of G are dealt cyclically to nwg workgroups (row r to workgroup r mod nwg) and stay in
-// their LDS for the whole reduction. Column j costs one grid-wide barrier:
-//   (1) every workgroup forms y = A v_j on its rows, and its share of v_j^H y;
-//   (2) barrier: each workgroup publishes its arrival in a flag of its own (no shared counter) and
-//       one wave polls all flags;
-//   (3) every workgroup forms w_j = tau y - |tau|^2/2 (y^H v_j)^* v_j from all of y, applies the rank-2
-//       update A -= v_j w_j^H + w_j v_j^H to its rows (the owner of row j+2 publishes that row), and
-//       builds row j+1 of the updated matrix from the row its owner published one column earlier, so
-//       that the next reflector is formed by every workgroup, identically, without another barrier.
+// their LDS for the whole reduction. Thread t of every workgroup owns the columns t, t + 512, ...:
+// the reflector v_j, w_j and the next reflector live in its registers, so that the only LDS traffic
+// of a column is one pass over the rows. Few threads with several columns each keep the per-row
+// wave reductions, which every wave pays, small beside the arithmetic (a wave64 instruction takes
+// four cycles of its SIMD). Column j costs one grid-wide barrier:
+//   (1) barrier: each workgroup publishes its arrival in a flag of its own (no shared counter);
+//       with many workgroups workgroup 0 gathers the flags and releases the others;
+//   (2) every workgroup fetches all of y = A v_j (published by the rows' owners) and the row j+1
+//       its owner published one column earlier, and forms w_j = tau y - |tau|^2/2 (v_j^H y)^* v_j;
+//   (3) it builds row j+1 of the updated matrix (A -= v_j w_j^H + w_j v_j^H) and from it the next
+//       reflector v_{j+1}, identically in every workgroup;
+//   (4) one pass over its rows applies the rank-2 update and accumulates the products
+//       y' = A' v_{j+1} of the next column; the owner of row j+2 publishes that row.
 // Reductions are summed in a fixed order, so every workgroup holds bitwise the same v and w.
 // The barrier waits are bounded: after timeout_ticks of the 100 MHz wall clock (2 s) a workgroup
 // raises a flag, every workgroup leaves at its next barrier, d[0] is set to NaN and the call's
 // status word receives CBC_ETIMEOUT.
-static constexpr int MW_THREADS = 1024;
+static constexpr int MW_THREADS = 512;
 static constexpr int MW_WAVES = MW_THREADS / 64;
-static constexpr int MW_EPT = 2;                    // vector elements per thread: s <= 2048
-static constexpr size_t MW_LDS_BUDGET = 160 * 1024 - 2048;
+static constexpr int MW_EPT = 4;                    // columns per thread, at most: s <= 2048
+static constexpr int MW_ROWS_MAX = 16;              // rows per workgroup (per-row reduction slots)
+static constexpr size_t MW_LDS_BUDGET = 160 * 1024 - 8192;   // the kernel's static LDS is below 8 KiB
 
 struct MwShape {
   int nwg, rows;
 };
-// Workgroup count: enough for the rows to fit in LDS beside v and w, and at least one workgroup per
-// 16 rows (up to 32) so that small matrices still spread their work.
+// Workgroup count: enough for the rows to fit in LDS, and at least one workgroup per 16 rows (up to
+// 32) so that small matrices still spread their work.
 __host__ __device__ inline MwShape mw_shape(int s) {
-  int fit = (int)(MW_LDS_BUDGET / (16 * (size_t)s)) - 2;
+  int fit = (int)(MW_LDS_BUDGET / (16 * (size_t)s));
+  if (fit > MW_ROWS_MAX) fit = MW_ROWS_MAX;
   if (fit < 1) fit = 1;
   int nwg = (s + fit - 1) / fit;
   const int want = (s + 15) / 16 < 32 ? (s + 15) / 16 : 32;
@@ -339,7 +346,7 @@ __host__ __device__ inline MwShape mw_shape(int s) {
   m.rows = (s + nwg - 1) / nwg;
   return m;
 }
-size_t mw_lds_bytes(int s) { return (size_t)(mw_shape(s).rows + 2) * s * 16; }
+size_t mw_lds_bytes(int s) { return (size_t)mw_shape(s).rows * s * 16; }
 
 // the two-stage path: panels of up to 2048 rows (two per thread of the panel kernel)
 static constexpr int EIG_MAX_S = 2048 + 16;
@@ -349,9 +356,9 @@ static bool mw_size_supported(int s) {
          mw_lds_bytes(s) <= MW_LDS_BUDGET;
 }
 // The one-stage multi-workgroup reduction is the faster one where it applies (measured on MI355X,
-// s = 1024: 17 ms against 27 ms for the two-stage path), but its workgroups wait for each other:
-// it is used for single instances queued eagerly or in the library's own graphs, whose launches
-// the device-wide gate orders; batches and calls recorded into a caller's capture take the
+// s = 1024: 11.5 ms against 28 ms for the two-stage path, per solve), but its workgroups wait for
+// each other: it is used for single instances queued eagerly or in the library's own graphs, whose
+// launches the device-wide gate orders; batches and calls recorded into a caller's capture take the
 // two-stage path, which has no cross-workgroup waits.
 int eig_pick_reduction(int s, int batch, bool caller_capture) {
   return mw_size_supported(s) && batch == 1 && !caller_capture ? 1 : 0;
@@ -498,82 +505,36 @@ __device__ bool mw_sync(unsigned* sync, int nwg, unsigned it, int* ok_sh, long l
   return *ok_sh != 0;
 }
 
-// block-wide sum of a complex value in a fixed order; result in every thread
-__device__ inline double2 mw_block_sum(double re, double im, double2* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+// Block-wide sum of every thread's complex value in a fixed order; `red` holds one slot per wave and
+// is read by every thread after the caller's next __syncthreads (sum_red below).
+__device__ __forceinline__ void put_red(double re, double im, double2* red) {
   re = wave_sum(re);
   im = wave_sum(im);
-  if (lane == 0) red[wave] = make_double2(re, im);
-  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_double2(re, im);
+}
+__device__ __forceinline__ double2 sum_red(const double2* red) {
   double2 t = make_double2(0.0, 0.0);
 #pragma unroll
   for (int q = 0; q < MW_WAVES; ++q) {
     t.x += red[q].x;
     t.y += red[q].y;
   }
-  __syncthreads();
   return t;
 }
 
-// Reflector j from the pivot row x (row j of the partly reduced matrix, valid from column j): the
-// column below the diagonal is conj(x[j+1..]). Writes v_j to v (zero up to j, 1 at j+1) and returns
-// tau_j; the writer stores d_j, e_j, tau_j and v_j. For j = s-1 only d_j is stored.
-__device__ double2 mw_reflector(int j, int s, const double2* x, double2* v, EigWork& W, bool writer,
-                                double2* red) {
-  const int tid = threadIdx.x;
-  if (j >= s - 1) {
-    if (writer && tid == 0) W.d[j] = x[j].x;
-    return make_double2(0.0, 0.0);
-  }
-  double xn2 = 0.0;
-  for (int c = j + 2 + tid; c < s; c += MW_THREADS) xn2 += x[c].x * x[c].x + x[c].y * x[c].y;
-  xn2 = mw_block_sum(xn2, 0.0, red).x;
-  const double2 alpha = cconj(x[j + 1]);
-  double2 t = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
-  double beta = alpha.x;
-  if (!(xn2 == 0.0 && alpha.y == 0.0)) {
-    const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
-    beta = alpha.x >= 0.0 ? -nrm : nrm;
-    const double ar = alpha.x - beta, ai = alpha.y;
-    // 1/beta and 1/|alpha - beta|^2 (both of the size of the column norm) are independent
-    const double rb = 1.0 / beta, rden = 1.0 / (ar * ar + ai * ai);
-    t = make_double2(-ar * rb, -ai * rb);
-    scal = make_double2(ar * rden, -ai * rden);
-  }
-  const double djj = x[j].x;
-  for (int c = tid; c < s; c += MW_THREADS) {
-    double2 val = make_double2(0.0, 0.0);
-    if (c == j + 1) val = make_double2(1.0, 0.0);
-    else if (c > j + 1) val = cmul(cconj(x[c]), scal);
-    v[c] = val;
-    if (writer && c > j) W.V[(size_t)j * s + c] = val;
-  }
-  if (writer && tid == 0) {
-    W.tau[j] = t;
-    W.e[j] = beta;
-    W.d[j] = djj;
-  }
-  __syncthreads();
-  return t;
-}
-
+template <int EPT>   // columns per thread: s <= EPT * MW_THREADS
 __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) {
   const EigArgs a = eig_inst(a0, blockIdx.y);
   const int wg = blockIdx.x;
   const int s = a.s;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rows = (s + nwg - 1) / nwg;
   const int nr = wg < s ? (s - wg + nwg - 1) / nwg : 0;   // rows owned: wg, wg + nwg, ...
-  // waves per owned row (a row's columns are split over its waves), rows per round
-  const int wpr = nr >= MW_WAVES ? 1 : MW_WAVES / nr;
-  const int rstep = MW_WAVES / wpr;
-  const int sub = wave % wpr;
   extern __shared__ double smem[];
-  double2* Ar = reinterpret_cast<double2*>(smem);   // rows x s
-  double2* v = Ar + (size_t)rows * s;               // s
-  double2* w = v + s;                               // s
-  __shared__ double2 red[MW_WAVES];
-  __shared__ double2 rowred[MW_WAVES];
+  double2* Ar = reinterpret_cast<double2*>(smem);   // nr x s
+  __shared__ double2 red_c[MW_WAVES], red_n[MW_WAVES];
+  __shared__ double2 racc[MW_ROWS_MAX][MW_WAVES];
+  __shared__ double2 rv[MW_ROWS_MAX], ry[MW_ROWS_MAX];   // v_j and y at the owned rows' indices
+  __shared__ double2 bc[3];                               // y[j+1]; row j+1 at j+1 and j+2
   __shared__ int ok_sh;
   EigWork W = eig_layout(a.work, s, a.kmax);
   const bool writer = wg == 0;
@@ -582,9 +543,90 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
     const double2* src = a.G + (size_t)(wg + (size_t)q * nwg) * s;
     for (int c = tid; c < s; c += MW_THREADS) Ar[(size_t)q * s + c] = src[c];
   }
-  for (int c = tid; c < s; c += MW_THREADS) w[c] = a.G[c];
+  // the owned row slot of a column index (-1: not owned here)
+  auto slot_of = [&](int c) {
+    const int d = c - wg;
+    return (d >= 0 && d % nwg == 0 && d / nwg < nr) ? d / nwg : -1;
+  };
+  // reflector J from its row x (valid from column J): v[c] for the own columns, tau returned;
+  // row entries J and J+1 come from bcx (broadcast), the norm below J+1 from red_n
+  auto reflector = [&](int J, const double2 x[EPT], double2 xj, double2 xj1, double xn2,
+                       double2 v[EPT]) {
+    const double2 alpha = cconj(xj1);
+    double2 t = make_double2(0.0, 0.0), scal = make_double2(0.0, 0.0);
+    double beta = alpha.x;
+    if (!(xn2 == 0.0 && alpha.y == 0.0)) {
+      const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xn2);
+      beta = alpha.x >= 0.0 ? -nrm : nrm;
+      const double ar = alpha.x - beta, ai = alpha.y;
+      const double rb = 1.0 / beta, rden = 1.0 / (ar * ar + ai * ai);
+      t = make_double2(-ar * rb, -ai * rb);
+      scal = make_double2(ar * rden, -ai * rden);
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int c = tid + e * MW_THREADS;
+      double2 val = make_double2(0.0, 0.0);
+      if (c == J + 1) val = make_double2(1.0, 0.0);
+      else if (c > J + 1 && c < s) val = cmul(cconj(x[e]), scal);
+      v[e] = val;
+      if (writer && c > J && c < s) W.V[(size_t)J * s + c] = val;
+    }
+    if (writer && tid == 0) {
+      W.tau[J] = t;
+      W.e[J] = beta;
+      W.d[J] = xj.x;
+    }
+    return t;
+  };
+  double2 v[EPT], x[EPT];
+  // reflector 0 from row 0
+  double xn2 = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int c = tid + e * MW_THREADS;
+    x[e] = c < s ? a.G[c] : make_double2(0.0, 0.0);
+    if (c >= 2 && c < s) xn2 += x[e].x * x[e].x + x[e].y * x[e].y;
+  }
+  put_red(xn2, 0.0, red_n);
   __syncthreads();
-  double2 t = mw_reflector(0, s, w, v, W, writer, red);
+  double2 t = reflector(0, x, a.G[0], s > 1 ? a.G[1] : make_double2(0.0, 0.0), sum_red(red_n).x, v);
+  // products of column 0 (rows r > 0), one pass over the rows
+  auto products = [&](int j, const double2 vv[EPT]) {
+    for (int q = 0; q < nr; ++q) {
+      double pr = 0.0, pi = 0.0;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int c = tid + e * MW_THREADS;
+        if (c > j && c < s) {
+          const double2 av = Ar[(size_t)q * s + c];
+          pr += av.x * vv[e].x - av.y * vv[e].y;
+          pi += av.x * vv[e].y + av.y * vv[e].x;
+        }
+      }
+      pr = wave_sum(pr);
+      pi = wave_sum(pi);
+      if (lane == 0) racc[q][wave] = make_double2(pr, pi);
+    }
+  };
+  auto publish_products = [&](int j) {
+    // thread q sums row q's wave partials in order and publishes y[r] for the rows r > j
+    if (tid < nr) {
+      const int r = wg + tid * nwg;
+      if (r > j) {
+        double2 yv = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < MW_WAVES; ++q) {
+          yv.x += racc[tid][q].x;
+          yv.y += racc[tid][q].y;
+        }
+        cstore(&W.ybuf[(size_t)(j & 1) * s + r], yv);
+      }
+    }
+  };
+  products(0, v);
+  __syncthreads();
+  publish_products(0);
   // phase times (tests only) accumulate in LDS, so that they take no registers of the other threads
   const bool stamp = a.tstamp && writer && tid == 0;
   __shared__ long long ph[8];
@@ -599,152 +641,115 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
   };
   for (int j = 0; j < s - 1; ++j) {
     if (stamp) ph[7] = wall_clock64();
-    // (1) y = A v_j on the owned rows r > j; share of v_j^H y
-    double2* ybuf = W.ybuf + (size_t)(j & 1) * s;
-    double pr = 0.0, pi = 0.0;
-    auto row_dot = [&](int q, int r, double& yr, double& yi) {
-      yr = 0.0;
-      yi = 0.0;
-      if (r > j) {
-        const double2* row = Ar + (size_t)q * s;
-        // four independent accumulators keep several LDS loads in flight
-        const int cs = 64 * wpr;
-        double y2r = 0.0, y2i = 0.0, y3r = 0.0, y3i = 0.0, y4r = 0.0, y4i = 0.0;
-        int c = j + 1 + sub * 64 + lane;
-        for (; c + 3 * cs < s; c += 4 * cs) {
-          const double2 a1 = row[c], a2 = row[c + cs], a3 = row[c + 2 * cs], a4 = row[c + 3 * cs];
-          const double2 b1 = v[c], b2 = v[c + cs], b3 = v[c + 2 * cs], b4 = v[c + 3 * cs];
-          yr += a1.x * b1.x - a1.y * b1.y;
-          yi += a1.x * b1.y + a1.y * b1.x;
-          y2r += a2.x * b2.x - a2.y * b2.y;
-          y2i += a2.x * b2.y + a2.y * b2.x;
-          y3r += a3.x * b3.x - a3.y * b3.y;
-          y3i += a3.x * b3.y + a3.y * b3.x;
-          y4r += a4.x * b4.x - a4.y * b4.y;
-          y4i += a4.x * b4.y + a4.y * b4.x;
-        }
-        for (; c < s; c += cs) {
-          const double2 av = row[c], vv = v[c];
-          yr += av.x * vv.x - av.y * vv.y;
-          yi += av.x * vv.y + av.y * vv.x;
-        }
-        yr += (y2r + y3r) + y4r;
-        yi += (y2i + y3i) + y4i;
-      }
-      yr = wave_sum(yr);
-      yi = wave_sum(yi);
-    };
-    auto take = [&](int r, double yr, double yi) {
-      cstore(&ybuf[r], make_double2(yr, yi));
-      const double2 vr = v[r];
-      pr += vr.x * yr + vr.y * yi;
-      pi += vr.x * yi - vr.y * yr;
-    };
-    if (wpr > 1) {
-      // fewer rows than waves: each row's columns are split over wpr waves (one round)
-      const int q = wave / wpr;
-      const int r = wg + q * nwg;
-      double yr = 0.0, yi = 0.0;
-      if (q < nr) row_dot(q, r, yr, yi);
-      if (lane == 0) rowred[wave] = make_double2(yr, yi);
-      __syncthreads();
-      if (q < nr && r > j && sub == 0 && lane == 0) {
-        yr = 0.0;
-        yi = 0.0;
-        for (int u = 0; u < wpr; ++u) {
-          yr += rowred[q * wpr + u].x;
-          yi += rowred[q * wpr + u].y;
-        }
-        take(r, yr, yi);
-      }
-    } else {
-      for (int q = wave; q < nr; q += MW_WAVES) {
-        const int r = wg + q * nwg;
-        double yr, yi;
-        row_dot(q, r, yr, yi);
-        if (r > j && lane == 0) take(r, yr, yi);
-      }
-    }
-    const double2 ps = mw_block_sum(pr, pi, red);
-    if (tid == 0) cstore(&W.part[(size_t)(j & 1) * MW_MAX_WG + wg], ps);
-    lap(0);
-    // (2)
+    // (1)
     if (!mw_sync(W.sync, nwg, (unsigned)(j + 1), &ok_sh, a.timeout_ticks)) {
       if (writer && tid == 0) W.d[0] = __builtin_nan("");
       if (tid == 0) raise_status(a.status, CBC_ETIMEOUT);
       return;
     }
-    lap(1);
-    // (3) everything published for this column is fetched at once
+    lap(0);
+    // (2) everything published for this column, fetched at once into the own columns
     const double2* prev = j == 0 ? a.G + s : W.prow + (size_t)(j & 1) * s;
-    double2 yv[MW_EPT], pv[MW_EPT];
+    double2 y[EPT], pv[EPT];
+    double cr = 0.0, ci = 0.0;
 #pragma unroll
-    for (int e = 0; e < MW_EPT; ++e) {
-      const int c = j + 1 + tid + e * MW_THREADS;
-      yv[e] = c < s ? cload(&ybuf[c]) : make_double2(0.0, 0.0);
-      pv[e] = c < s ? (j == 0 ? prev[c] : cload(&prev[c])) : make_double2(0.0, 0.0);
+    for (int e = 0; e < EPT; ++e) {
+      const int c = tid + e * MW_THREADS;
+      const bool in = c > j && c < s;
+      y[e] = in ? cload(&W.ybuf[(size_t)(j & 1) * s + c]) : make_double2(0.0, 0.0);
+      pv[e] = in ? (j == 0 ? prev[c] : cload(&prev[c])) : make_double2(0.0, 0.0);
+      cr += v[e].x * y[e].x + v[e].y * y[e].y;     // conj(v) y
+      ci += v[e].x * y[e].y - v[e].y * y[e].x;
+      if (c == j + 1) bc[0] = y[e];
+      const int q = slot_of(c);
+      if (q >= 0) {
+        ry[q] = y[e];
+        rv[q] = v[e];
+      }
     }
-    const double2 pp = tid < nwg ? cload(&W.part[(size_t)(j & 1) * MW_MAX_WG + tid]) : make_double2(0.0, 0.0);
-    const double2 cs = mw_block_sum(pp.x, pp.y, red);
-    lap(2);
-    // a2 = -|tau|^2 / 2 * conj(v^H y)
+    put_red(cr, ci, red_c);
+    __syncthreads();
+    const double2 cs = sum_red(red_c);
+    lap(1);
+    // (3) w = tau y + a2 v with a2 = -|tau|^2 / 2 * conj(v^H y); row j+1 after the update
     const double tt = t.x * t.x + t.y * t.y;
     const double2 a2 = make_double2(-0.5 * tt * cs.x, 0.5 * tt * cs.y);
+    double2 w[EPT];
 #pragma unroll
-    for (int e = 0; e < MW_EPT; ++e) {
-      const int c = j + 1 + tid + e * MW_THREADS;
-      if (c < s) {
-        const double2 vc = v[c];
-        const double2 ty = cmul(t, yv[e]);
-        w[c] = make_double2(ty.x + a2.x * vc.x - a2.y * vc.y, ty.y + a2.x * vc.y + a2.y * vc.x);
-      }
+    for (int e = 0; e < EPT; ++e) {
+      const double2 ty = cmul(t, y[e]);
+      w[e] = make_double2(ty.x + a2.x * v[e].x - a2.y * v[e].y, ty.y + a2.x * v[e].y + a2.y * v[e].x);
     }
+    // v_j is 1 at j+1
+    const double2 ty1 = cmul(t, bc[0]);
+    const double2 w1 = make_double2(ty1.x + a2.x, ty1.y + a2.y);
+    xn2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int c = tid + e * MW_THREADS;
+      double2 xv = pv[e];
+      // x -= v1 conj(w_c) + w1 conj(v_c), v1 = 1
+      xv.x -= w[e].x + (w1.x * v[e].x + w1.y * v[e].y);
+      xv.y -= -w[e].y + (w1.y * v[e].x - w1.x * v[e].y);
+      x[e] = xv;
+      if (c == j + 1) bc[1] = xv;
+      if (c == j + 2) bc[2] = xv;
+      if (c > j + 2 && c < s) xn2 += xv.x * xv.x + xv.y * xv.y;
+    }
+    put_red(xn2, 0.0, red_n);
     __syncthreads();
-    lap(3);
-    // rank-2 update of the owned rows r > j+1 on the columns > j+1; the owner of row j+2 publishes it
+    if (j + 1 >= s - 1) {
+      // the last diagonal entry; no reflector, no further column
+      if (writer && tid == 0) W.d[j + 1] = bc[1].x;
+      break;
+    }
+    double2 vn[EPT];
+    const double2 t1 = reflector(j + 1, x, bc[1], bc[2], sum_red(red_n).x, vn);
+    lap(2);
+    // (4) rank-2 update of the owned rows r > j+1 on the columns > j+1, the owner of row j+2
+    // publishing it, and the products with v_{j+1} of the next column
     double2* pnext = W.prow + (size_t)((j + 1) & 1) * s;
-    for (int q = wave / wpr; q < nr; q += rstep) {
+    for (int q = 0; q < nr; ++q) {
       const int r = wg + q * nwg;
-      if (r <= j + 1) continue;
-      double2* row = Ar + (size_t)q * s;
-      const double2 vr = v[r], wr = w[r];
-#pragma unroll 2
-      for (int c = j + 2 + sub * 64 + lane; c < s; c += 64 * wpr) {
-        const double2 vc = v[c], wc = w[c];
-        double2 x = row[c];
-        x.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
-        x.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
-        row[c] = x;
-        if (r == j + 2) cstore(&pnext[c], x);
-      }
-    }
-    // row j+1 of the updated matrix from its published predecessor
-    const double2 v1 = v[j + 1], w1 = w[j + 1];
-    __syncthreads();
-    lap(4);
+      double pr = 0.0, pi = 0.0;
+      if (r > j + 1) {
+        const double2 vr = rv[q];
+        const double2 tyr = cmul(t, ry[q]);
+        const double2 wr = make_double2(tyr.x + a2.x * vr.x - a2.y * vr.y,
+                                        tyr.y + a2.x * vr.y + a2.y * vr.x);
 #pragma unroll
-    for (int e = 0; e < MW_EPT; ++e) {
-      const int c = j + 1 + tid + e * MW_THREADS;
-      if (c < s) {
-        const double2 vc = v[c], wc = w[c];
-        double2 x = pv[e];
-        x.x -= (v1.x * wc.x + v1.y * wc.y) + (w1.x * vc.x + w1.y * vc.y);
-        x.y -= (v1.y * wc.x - v1.x * wc.y) + (w1.y * vc.x - w1.x * vc.y);
-        w[c] = x;
+        for (int e = 0; e < EPT; ++e) {
+          const int c = tid + e * MW_THREADS;
+          if (c > j + 1 && c < s) {
+            double2 xv = Ar[(size_t)q * s + c];
+            xv.x -= (vr.x * w[e].x + vr.y * w[e].y) + (wr.x * v[e].x + wr.y * v[e].y);
+            xv.y -= (vr.y * w[e].x - vr.x * w[e].y) + (wr.y * v[e].x - wr.x * v[e].y);
+            Ar[(size_t)q * s + c] = xv;
+            if (r == j + 2) cstore(&pnext[c], xv);
+            pr += xv.x * vn[e].x - xv.y * vn[e].y;
+            pi += xv.x * vn[e].y + xv.y * vn[e].x;
+          }
+        }
       }
+      pr = wave_sum(pr);
+      pi = wave_sum(pi);
+      if (lane == 0) racc[q][wave] = make_double2(pr, pi);
     }
     __syncthreads();
-    lap(5);
-    t = mw_reflector(j + 1, s, w, v, W, writer, red);
-    lap(6);
+    publish_products(j + 1);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) v[e] = vn[e];
+    t = t1;
+    lap(3);
   }
   if (stamp) {
-    // phases: 4 products, 5 barrier, 6 the rest (8..12 its parts: fetch, w, update, next row,
-    // reflector)
+    // phases: 4 barrier, 5 fetch and v^H y, 6 the rest (8..9 its parts: next reflector, update
+    // fused with the next products)
     a.tstamp[4] = ph[0];
     a.tstamp[5] = ph[1];
-    a.tstamp[6] = ph[2] + ph[3] + ph[4] + ph[5] + ph[6];
-    for (int i = 0; i < 5; ++i) a.tstamp[8 + i] = ph[2 + i];
+    a.tstamp[6] = ph[2] + ph[3];
+    a.tstamp[8] = ph[2];
+    a.tstamp[9] = ph[3];
   }
   if (writer) {
     __syncthreads();
@@ -1252,12 +1257,21 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
     EigWork W = eig_layout(a.work, a.s, a.kmax);
     hipError_t z = launch_zero(W.sync, MW_SYNC_BYTES, a.batch, a.bs, st);
     if (z != hipSuccess) return z;
-    (void)hipFuncSetAttribute((const void*)k_tridiag_mw, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
+    // columns per thread: the smallest instantiation that covers s
+    const int ept = (a.s + MW_THREADS - 1) / MW_THREADS;
+    const void* fn = ept <= 1 ? (const void*)k_tridiag_mw<1>
+                   : ept <= 2 ? (const void*)k_tridiag_mw<2>
+                   : ept <= 3 ? (const void*)k_tridiag_mw<3>
+                              : (const void*)k_tridiag_mw<4>;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     // its workgroups wait for each other: no other such solve may hold compute units meanwhile
     z = mw_gate_enter(st);
     if (z != hipSuccess) return z;
-    hipLaunchKernelGGL(k_tridiag_mw, dim3(m.nwg, a.batch), dim3(MW_THREADS), lds, st, a, m.nwg);
+    const dim3 grid(m.nwg, a.batch);
+    if (ept <= 1) hipLaunchKernelGGL(k_tridiag_mw<1>, grid, dim3(MW_THREADS), lds, st, a, m.nwg);
+    else if (ept <= 2) hipLaunchKernelGGL(k_tridiag_mw<2>, grid, dim3(MW_THREADS), lds, st, a, m.nwg);
+    else if (ept <= 3) hipLaunchKernelGGL(k_tridiag_mw<3>, grid, dim3(MW_THREADS), lds, st, a, m.nwg);
+    else hipLaunchKernelGGL(k_tridiag_mw<4>, grid, dim3(MW_THREADS), lds, st, a, m.nwg);
     z = hipGetLastError();
     if (z != hipSuccess) return z;
     z = mw_gate_leave(st);

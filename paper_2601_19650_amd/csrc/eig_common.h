@@ -83,7 +83,6 @@ struct EigWork {
   double* lu;     // kmax * 5 * s
   // multi-workgroup reduction only (each double-buffered by the parity of the column)
   double2* ybuf;  // 2 * s       products A v of the current column
-  double2* part;  // 2 * MW_MAX_WG  per-workgroup partial sums of v^H A v
   double2* prow;  // 2 * s       next pivot row, published by its owner
   unsigned* sync; // MW_MAX_WG + 16 words: last barrier reached per workgroup, then a time-out flag
 };
@@ -97,8 +96,7 @@ __host__ __device__ inline EigWork eig_layout(double* w, int s, int kmax) {
   L.Y = w + 4 * (size_t)s + 8 + 2 * (size_t)s * s;
   L.lu = L.Y + (size_t)kmax * s;
   L.ybuf = reinterpret_cast<double2*>(L.lu + 5 * (size_t)kmax * s);
-  L.part = L.ybuf + 2 * (size_t)s;
-  L.prow = L.part + 2 * MW_MAX_WG;
+  L.prow = L.ybuf + 2 * (size_t)s;
   L.sync = reinterpret_cast<unsigned*>(L.prow + 2 * (size_t)s);
   return L;
 }
@@ -106,7 +104,7 @@ static constexpr int MW_SYNC_BYTES = 4 * (MW_MAX_WG + 16);
 // doubles of the layout above (the two-stage reduction's scratch follows it)
 __host__ __device__ inline size_t eig_base_doubles(int s, int kmax) {
   return 4 * (size_t)s + 8 + 2 * (size_t)s * s + (size_t)kmax * s + 5 * (size_t)kmax * s +
-         4 * (size_t)s + 4 * MW_MAX_WG + 4 * (size_t)s + MW_SYNC_BYTES / 8 + 64;
+         4 * (size_t)s + 4 * (size_t)s + MW_SYNC_BYTES / 8 + 64;
 }
 // two-stage reduction (eig_band.hip): scratch beyond eig_base_doubles, the reduction of G to T
 // (d, e and the Gershgorin bounds in the common layout) and the back-transformation into U

@@ -88,8 +88,11 @@ EIG_CASES = [(1, 1), (2, 1), (2, 2), (7, 3), (64, 32), (128, 64), (200, 100), (9
              (1041, 100), (1500, 256), (2064, 64)]
 
 
+MW_CASES = [(129, 64), (200, 100), (300, 300), (700, 200), (1024, 256), (1272, 128), (1536, 200)]
+
+
 @pytest.mark.parametrize("s,kmax,reduction",
-                         [(s, k, 0) for s, k in EIG_CASES] + [(200, 100, 1), (700, 200, 1)])
+                         [(s, k, 0) for s, k in EIG_CASES] + [(s, k, 1) for s, k in MW_CASES])
 def test_eig_topk(lib, s, kmax, reduction):
     """Top-kmax eigenpairs against numpy.linalg.eigh: the single-workgroup reduction (s <= 128), the
     two-stage reduction (above; panels of up to 1024 and up to 2048 rows, band edges) and, for
@@ -150,14 +153,15 @@ def test_eig_rank_deficient_and_tol(lib):
     assert np.abs(U2.cpu().numpy()[:, 10:]).max() == 0.0
 
 
-@pytest.mark.parametrize("s,kind", [(5, "diagonal"), (40, "diagonal"), (128, "diagonal"),
-                                    (40, "blocks"), (128, "blocks"), (200, "blocks"),
-                                    (300, "diagonal"), (333, "blocks")])
-def test_eig_structured(lib, s, kind):
+@pytest.mark.parametrize("s,kind,reduction", [
+    (5, "diagonal", 0), (40, "diagonal", 0), (128, "diagonal", 0), (40, "blocks", 0),
+    (128, "blocks", 0), (200, "blocks", 0), (300, "diagonal", 0), (333, "blocks", 0),
+    (300, "diagonal", 1), (333, "blocks", 1)])
+def test_eig_structured(lib, s, kind, reduction):
     """Grams whose reduction meets columns with nothing below the diagonal (a reflector that is the
     identity, tau = 0): a diagonal Gram (every column) and a block-diagonal one (the last column of
-    every block), in the single-workgroup and the two-stage reductions (zero panels and zero band
-    columns)."""
+    every block), in the single-workgroup, the two-stage (zero panels and zero band columns) and
+    the one-stage multi-workgroup reductions."""
     print(f"eig structured s={s} {kind}", flush=True)
     rng = np.random.default_rng(40 + s)
     if kind == "diagonal":
@@ -174,7 +178,7 @@ def test_eig_structured(lib, s, kind):
         if i0 < s:
             g[i0:, i0:] = herm_psd(rng, s - i0)
     kmax = min(s, 16)
-    U, lam, kk, _ = lib.test_eig(torch.from_numpy(g).cuda(), kmax)
+    U, lam, kk, _ = lib.test_eig(torch.from_numpy(g).cuda(), kmax, reduction=reduction)
     U = U.cpu().numpy()
     lam = lam.cpu().numpy()
     w = np.linalg.eigvalsh(g)[::-1]
