@@ -7,3 +7,4 @@ from .cbc import cbc_tt, cbc_tree, truncate_joined, lq  # noqa: F401
 from . import tn  # noqa: F401
 from .src import src_tree  # noqa: F401
 from .dm import dm_tree  # noqa: F401
+from .zipup import zipup_tree  # noqa: F401

@@ -239,3 +239,76 @@ def test_dm_mutation_is_caught(name, old, new):
     assert DM_SRC.count(old) == 1, f"mutation site not unique: {old!r}"
     failed = _failing_dm_checks(DM_SRC.replace(old, new))
     assert failed, f"no pin catches: {name}"
+
+
+# ---------------------------------------------------------------------------------------------
+# the Zip-Up oracle (oracle/zipup.py) and its pins (tests/test_oracle_zipup_pins.py)
+
+import oracle.zipup as ozu  # noqa: E402
+
+ZIPUP_SRC = open(ozu.__file__).read()
+
+
+def _load_zipup_pins():
+    spec = importlib.util.spec_from_file_location("zipup_pins_for_mutation",
+                                                  os.path.join(HERE, "test_oracle_zipup_pins.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+ZIPUP_PINS = _load_zipup_pins()
+_Z = {c[0]: c[1:] for c in ZIPUP_PINS.CASES}
+
+ZIPUP_CHECKS = [
+    ("dense formulation, chain", lambda: ZIPUP_PINS.test_zipup_dense_formulation("chain7", *_Z["chain7"])),
+    ("dense formulation, binary", lambda: ZIPUP_PINS.test_zipup_dense_formulation("bin7", *_Z["bin7"])),
+    ("dense formulation, ternary", lambda: ZIPUP_PINS.test_zipup_dense_formulation("ter10", *_Z["ter10"])),
+    ("projection, isometries, lower bound", lambda: ZIPUP_PINS.test_zipup_projection_isometries_and_lower_bound(
+        "uneven9", *_Z["uneven9"])),
+    ("exact case", lambda: ZIPUP_PINS.test_zipup_exact_when_the_bond_covers_every_rank()),
+    ("identity operator = TT-SVD", lambda: ZIPUP_PINS.test_zipup_identity_operator_on_canonical_chain_is_tt_svd(
+        6, 2, 6, 3, 11)),
+    ("two-site brute force", lambda: ZIPUP_PINS.test_zipup_two_site_brute_force()),
+]
+
+ZIPUP_MUTATIONS = [
+    ("R update without conj(Q)", "renv[i] = (q.conj().T @ zm)", "renv[i] = (q.T @ zm)"),
+    ("smallest singular vectors kept", "q = u[:, :max_bond]", "q = u[:, ::-1][:, :max_bond]"),
+    ("basis from the conjugated unfolding", "np.linalg.svd(zm,", "np.linalg.svd(zm.conj(),"),
+    ("unfolding with the bond legs first", "zm = z.reshape(rows, cols)",
+     "zm = np.moveaxis(z.reshape(rows, cols).reshape(cols, rows), 0, 1).copy()"),
+    ("children's R attached in reverse order", "envs = {1 + j: renv[c] for j, c in enumerate(ch[i])}",
+     "envs = {len(ch[i]) - j: renv[c] for j, c in enumerate(ch[i])}"),
+    ("no truncation", "if rows <= max_bond:", "if True:"),
+    ("root conjugated", "out[i] = z.reshape(shp[:-2])[:, None]", "out[i] = z.conj().reshape(shp[:-2])[:, None]"),
+    ("no completion of the singular vectors", "full_matrices=cols < max_bond", "full_matrices=False"),
+]
+
+
+def _failing_zipup_checks(src):
+    mod = types.ModuleType("zipup_oracle_mutant")
+    exec(compile(src, "zipup_oracle_mutant", "exec"), mod.__dict__)
+    saved = ZIPUP_PINS.zipup_tree
+    ZIPUP_PINS.zipup_tree = mod.zipup_tree
+    failed = []
+    try:
+        for name, fn in ZIPUP_CHECKS:
+            try:
+                fn()
+            except Exception:
+                failed.append(name)
+    finally:
+        ZIPUP_PINS.zipup_tree = saved
+    return failed
+
+
+def test_unmutated_zipup_oracle_passes_every_check():
+    assert _failing_zipup_checks(ZIPUP_SRC) == []
+
+
+@pytest.mark.parametrize("name,old,new", ZIPUP_MUTATIONS, ids=[m[0] for m in ZIPUP_MUTATIONS])
+def test_zipup_mutation_is_caught(name, old, new):
+    assert ZIPUP_SRC.count(old) == 1, f"mutation site not unique: {old!r}"
+    failed = _failing_zipup_checks(ZIPUP_SRC.replace(old, new))
+    assert failed, f"no pin catches: {name}"
