@@ -249,7 +249,7 @@ def _rel_error_vs_exact(parent, out, state, op, norm_phi_sq, weight=False):
 
 def method_run(cbc, p, stream, steps, warmup, method, seed=11, nphi=None):
     """Another method of the library (method "src": cbc_apply_src with sketch matrices drawn from
-    `seed`; "dm": cbc_apply_dm) on workload p in both precisions: time per compression (graph
+    `seed`; "zipup": cbc_apply_zipup; "dm": cbc_apply_dm) on workload p in both precisions: time per compression (graph
     replay), kernel-class times, and the relative error and captured weight against the exact
     product O|psi> (||O psi||^2 = nphi)."""
     import torch
@@ -291,7 +291,8 @@ def method_run(cbc, p, stream, steps, warmup, method, seed=11, nphi=None):
 
 
 def other_methods(cbc, p, stream, steps, warmup, cbc_outputs, methods):
-    """SRC and DM beside CBC on the headline workload, with every method's captured weight."""
+    """SRC, Zip-Up and DM beside CBC on the headline workload, with every method's captured
+    weight."""
     import torch
     torch.cuda.synchronize()
     nphi = _gpu_sandwich(p.parent, None, p.state, p.op, twice=True).real
@@ -356,9 +357,9 @@ def _gpu_product(parent, state, op):
 def paper_workloads(cbc, stream, full=False, steps=2):
     """The random-network workload of Sec. IV A on the GPU: tensor train (L=50, d=3, D=40), T-tree
     (L=20), balanced binary tree (depth 6, physical legs on the leaves) and fork tensor product
-    structure (L=8), all d=3, D=10, entries U[-0.5, 1]; CBC and the randomised compression (mixed
-    and FP64; sketch seed 11), the density-matrix method and the naive contract-then-compress
-    baseline (FP64) over a sweep of target bonds: time per compression and relative error
+    structure (L=8), all d=3, D=10, entries U[-0.5, 1]; CBC, the randomised compression (sketch
+    seed 11) and Zip-Up (mixed and FP64), the density-matrix method and the naive
+    contract-then-compress baseline (FP64) over a sweep of target bonds: time per compression and relative error
     ||O psi - psi'|| / ||O psi||, with O psi contracted exactly on the device."""
     import dataclasses
     import torch
@@ -379,7 +380,8 @@ def paper_workloads(cbc, stream, full=False, steps=2):
             pt = {"target_bond": dbar}
             sk = cbc.pack(sketch_matrices(base.phys, dbar, 11), "cuda:0")
             for method, prec in (("cbc", "mixed"), ("cbc", "fp64"), ("src", "mixed"),
-                                 ("src", "fp64"), ("dm", "fp64"), ("naive", "fp64")):
+                                 ("src", "fp64"), ("zipup", "mixed"), ("zipup", "fp64"),
+                                 ("dm", "fp64"), ("naive", "fp64")):
                 comp = cbc.Compressor(ctx, tree, dbar, prec, method=method, device="cuda:0")
                 kw = {"sketch": sk} if method == "src" else {}
                 sec = timed_runs(comp, (op, oo, st, so, 0.0), stream, steps, 1, **kw)
@@ -602,6 +604,8 @@ def main():
     ap.add_argument("--src", choices=["on", "off"], default="on",
                     help="also time the randomised compression (cbc_apply_src) on the headline "
                          "workload, with the errors of it and of CBC against the exact product")
+    ap.add_argument("--zipup", choices=["on", "off"], default="on",
+                    help="also time Zip-Up (cbc_apply_zipup) on the headline workload")
     ap.add_argument("--dm", choices=["on", "off"], default="off",
                     help="also time the density-matrix method (cbc_apply_dm) on the headline "
                          "workload (seconds per compression there; the random-network section "
@@ -624,6 +628,7 @@ def main():
     AUTOTUNE = args.autotune == "on"
     args.src = args.src == "on"
     args.dm = args.dm == "on"
+    args.zipup = args.zipup == "on"
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -704,7 +709,7 @@ def main():
             line["full_size_mixed_vs_fp64"] = {
                 "captured_weight": w, "captured_weight_ratio": w["mixed"] / w["fp64"],
                 "fidelity": _chain_fidelity(outputs["mixed"], outputs["fp64"])}
-    methods = [m for m, on in (("src", args.src), ("dm", args.dm)) if on]
+    methods = [m for m, on in (("src", args.src), ("zipup", args.zipup), ("dm", args.dm)) if on]
     if methods:
         line["other_methods"] = other_methods(cbc, p, stream, args.steps, args.warmup, outputs,
                                               methods)

@@ -146,7 +146,8 @@ typedef struct {
   int32_t sweep;       /* 1: subtree environment (Eq. cbc_tree_first_contraction); 2: environment of
                           the rest of the tree (Eqs. tt_cbc_first_contraction,
                           cbc_tree_second_contraction); 0: a truncation of the naive method;
-                          3: a basis of the density-matrix method (cbc_apply_dm) */
+                          3: a basis of the density-matrix method (cbc_apply_dm); 4: a basis of
+                          the Zip-Up method (cbc_apply_zipup) */
   int32_t dim;         /* dimension of the Gram matrix that was eigensolved */
   int32_t kmax;        /* directions planned (min(max_bond, Gram dimension)) */
   int32_t kept;        /* directions kept (fewer than kmax only with a tolerance) */
@@ -186,7 +187,8 @@ cbc_status cbc_autotune(cbc_ctx* ctx, const char* cache_path);
 
 /* Sizes for a problem: workspace bytes and the output packing (n_nodes + 1 offsets; the last entry is
  * the total number of complex elements the output buffer must hold). Host only, no device work.
- * `method` is 0 for cbc_apply, 1 for cbc_apply_naive, 2 for cbc_apply_src and 3 for cbc_apply_dm. */
+ * `method` is 0 for cbc_apply, 1 for cbc_apply_naive, 2 for cbc_apply_src, 3 for cbc_apply_dm and 4
+ * for cbc_apply_zipup. */
 cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
                      int32_t method, size_t* workspace_bytes, int64_t* out_offset);
 
@@ -318,6 +320,20 @@ cbc_status cbc_apply_src(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensor
 cbc_status cbc_apply_dm(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
                         const cbc_tree* tree, int32_t max_bond, cbc_precision prec, void* workspace,
                         size_t workspace_bytes, cbc_out* out, void* stream, cbc_stats* stats);
+
+/* Zip-Up (Sec. III C; Tab. time_scal and mem_scal give its cost): one sweep, leaves to root, in which
+ * each node is compressed on the spot from its own product with the already compressed children,
+ * Z = T W prod_c R^{[c]} (Eqs. cbc_tree_third_contraction, cbc_final_contraction), with no environment
+ * of the rest of the network: the node's basis is the top min(max_bond, rows) eigenvectors of Z Z^H
+ * over its parent bond (the left singular vectors of its unfolding; FP64, through the truncation
+ * eigensolver; records with sweep 4), R = Q^H Z carries the rest upward and the root keeps Z. The
+ * input state is used in the gauge it is given. A node whose rows do not exceed max_bond keeps the
+ * identity basis. Workspace from cbc_query with method 4. Single instances, no tolerance. Otherwise
+ * as cbc_apply. */
+cbc_status cbc_apply_zipup(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                           const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
+                           void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
+                           cbc_stats* stats);
 
 /* For callers that cannot allocate device memory (code under stream capture, tight serving loops,
  * harnesses that forbid hipMalloc): cbc_apply without a workspace argument. Its workspace is a

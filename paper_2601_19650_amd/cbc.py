@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libcbc.so")
 
 FP64, MIXED = 0, 1
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
-METHODS = {"cbc": 0, "naive": 1, "src": 2, "dm": 3}
+METHODS = {"cbc": 0, "naive": 1, "src": 2, "dm": 3, "zipup": 4}
 
 
 class CbcError(RuntimeError):
@@ -144,6 +144,8 @@ def lib():
                                    ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t,
                                    ctypes.POINTER(_Out), ctypes.c_void_p, ctypes.POINTER(Stats)]
         L.cbc_apply_dm.restype = ctypes.c_int
+        L.cbc_apply_zipup.argtypes = L.cbc_apply_dm.argtypes
+        L.cbc_apply_zipup.restype = ctypes.c_int
         L.cbc_autotune.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
         L.cbc_autotune.restype = ctypes.c_int
         L.cbc_read_report.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
@@ -156,7 +158,7 @@ def lib():
 EXPORTED = ("cbc_create", "cbc_destroy", "cbc_status_str", "cbc_query", "cbc_plan_bonds",
             "cbc_apply", "cbc_apply_batched", "cbc_apply_naive", "cbc_autotune", "cbc_read_report",
             "cbc_apply_noalloc", "cbc_plan_info", "cbc_apply_split", "cbc_apply_src",
-            "cbc_apply_many", "cbc_apply_dm")
+            "cbc_apply_many", "cbc_apply_dm", "cbc_apply_zipup")
 
 
 def _check(code, what):
@@ -237,7 +239,7 @@ def pack_batch(networks, device):
 
 class Compressor:
     """One problem shape: queries sizes once, owns workspace and output buffers, and runs the
-    compression (``method`` "cbc", "naive", "src" or "dm", ``precision`` "fp64" or "mixed"; "src"
+    compression (``method`` "cbc", "naive", "src", "dm" or "zipup", ``precision`` "fp64" or "mixed"; "src"
     takes its sketch matrices as run()'s ``sketch`` = (device buffer, offsets) from pack())."""
 
     def __init__(self, ctx, tree, max_bond, precision="fp64", method="cbc", device="cuda", batch=1,
@@ -309,12 +311,13 @@ class Compressor:
                                          ctypes.byref(out), ctypes.c_void_p(stream),
                                          ctypes.byref(self.stats)), "cbc_apply_split")
             return self.out, self.bond
-        if self.method == 3:
-            _check(lib().cbc_apply_dm(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns),
-                                      ctypes.byref(self.tree.c), self.max_bond, self.prec,
-                                      self.workspace.data_ptr(), self.ws_bytes, ctypes.byref(out),
-                                      ctypes.c_void_p(stream), ctypes.byref(self.stats)),
-                   "cbc_apply_dm")
+        if self.method in (3, 4):
+            name = "cbc_apply_dm" if self.method == 3 else "cbc_apply_zipup"
+            _check(getattr(lib(), name)(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns),
+                                        ctypes.byref(self.tree.c), self.max_bond, self.prec,
+                                        self.workspace.data_ptr(), self.ws_bytes,
+                                        ctypes.byref(out), ctypes.c_void_p(stream),
+                                        ctypes.byref(self.stats)), name)
             return self.out, self.bond
         fn = lib().cbc_apply if self.method == 0 else lib().cbc_apply_naive
         _check(fn(self.ctx.h, ctypes.byref(ttno), ctypes.byref(ttns), ctypes.byref(self.tree.c),

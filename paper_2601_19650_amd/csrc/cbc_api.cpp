@@ -1244,6 +1244,145 @@ cbc_status build_plan_src(Plan& P, const Problem& pr, int max_bond, cbc_precisio
   return plan_epilogue(B, P);
 }
 
+// Sweep 3 of the density-matrix and Zip-Up methods (as in CBC, Eqs. cbc_tree_third_contraction,
+// cbc_final_contraction): Z^{[i]} = T W prod_c R^{[c]}, leaves to root; a node whose rows exceed its
+// new bond takes its basis from the top eigenvectors of rho = Z B Z^H (density-matrix method, B the
+// exact environment of the rest of the tree) or rho = Z Z^H (Zip-Up, no environment: the node's own
+// product with its compressed children), FP64 through the truncation eigensolver; R^{[i]} = Q^H Z
+// carries its normalisation in the node's log slot; the root writes Z.
+static void sweep3_density(Builder& B, Plan& P, const Problem& pr, const std::vector<int>& kout,
+                           const std::vector<int64_t>& rows, const std::vector<Ten>* env,
+                           const std::vector<int>& ealphap, const std::vector<int>& ebetap,
+                           int rec_sweep) {
+  const int n = pr.n;
+  std::vector<Ten> R(n);
+  P.out_off.assign(n + 1, 0);
+  P.out_bond.assign(n, 1);
+  for (int i = 0; i < n; ++i) {
+    int64_t e = (int64_t)pr.phys[i] * kout[i];
+    for (int c : pr.ch[i]) e *= kout[c];
+    P.out_off[i + 1] = P.out_off[i] + e;
+    P.out_bond[i] = kout[i];
+  }
+  TRef one = B.wsp(256, DT_C128);
+  {
+    Op f;
+    f.kind = K_IDENT;
+    f.dst = one;
+    f.td = DT_C128;
+    f.a = 1;
+    f.b = 1;
+    P.ops.push_back(f);
+  }
+  for (int i : pr.post) {
+    B.reset_scratch();
+    std::vector<std::pair<int, Ten>> envs;
+    std::vector<int> zl{B.sigp[i]};
+    for (size_t j = 0; j < pr.ch[i].size(); ++j) {
+      const int c = pr.ch[i][j];
+      envs.push_back({1 + (int)j, R[c]});
+      zl.push_back(R[c].legs[0]);
+    }
+    if (i == pr.root) {
+      std::vector<int> zr{B.rootA};
+      zr.insert(zr.end(), zl.begin(), zl.end());
+      zr.push_back(B.rootB);
+      Ten Z = B.alloc(zr, B.ct, false);
+      Z = B.node_contract(i, envs, zr, Z.ref);
+      Op w;
+      w.kind = K_WRITE;
+      w.src = Z.ref;
+      w.ts = B.ct;
+      w.a = 1;
+      w.b = pr.phys[i];
+      w.rest = B.elems(zr) / pr.phys[i];
+      w.dst.src = S_OUT;
+      w.dst.off = i;
+      w.logs.src = S_WS;
+      w.logs.off = P.logs_off;
+      w.nlogs = n;
+      P.ops.push_back(w);
+      continue;
+    }
+    zl.push_back(B.ealpha[i]);
+    zl.push_back(B.ebeta[i]);
+    const int64_t ns = rows[i];
+    std::vector<int> rest(zl.begin(), zl.end() - 2);
+    const bool ident = ns <= kout[i];
+    Ten Z = B.alloc(zl, B.ct, ident);
+    Z = B.node_contract(i, envs, zl, Z.ref);
+    if (ident) {
+      const int nl = B.leg(ns);
+      R[i] = Ten{Z.ref, {nl, B.ealpha[i], B.ebeta[i]}};
+      TRef q = B.scr(16 * (size_t)ns * ns, DT_C128);
+      Op f;
+      f.kind = K_IDENT;
+      f.dst = q;
+      f.td = DT_C128;
+      f.a = (int)ns;
+      f.b = (int)ns;
+      P.ops.push_back(f);
+      Op w;
+      w.kind = K_WRITE;
+      w.src = q;
+      w.ts = DT_C128;
+      w.a = (int)ns;
+      w.b = pr.phys[i];
+      w.rest = ns / pr.phys[i];
+      w.dst.src = S_OUT;
+      w.dst.off = i;
+      P.ops.push_back(w);
+      continue;
+    }
+    std::vector<int> rowsp;
+    for (int l : rest) rowsp.push_back(B.leg(B.legdim[l]));
+    std::vector<int> rl = rest;
+    rl.insert(rl.end(), rowsp.begin(), rowsp.end());
+    Ten rho = B.alloc(rl, DT_C128, false);
+    if (env) {
+      // X = Z B over the parent bond's ket legs: [rows..., beta'_i, alpha'_i]
+      std::vector<int> xl = rest;
+      xl.push_back(ebetap[i]);
+      xl.push_back(ealphap[i]);
+      Ten X = B.alloc(xl, B.ct, false);
+      X = B.contract(Z, false, (*env)[i], false, xl, X.ref, B.ct, B.cacc, 0);
+      // rho = X conj(Z') over the bra legs, in FP64: [rows..., rows'...]
+      std::vector<int> zbl = rowsp;
+      zbl.push_back(ealphap[i]);
+      zbl.push_back(ebetap[i]);
+      B.contract(X, false, Ten{Z.ref, zbl, true}, true, rl, rho.ref, DT_C128, DT_C128, 1);
+    } else {
+      // rho = Z conj(Z') over the parent bond (alpha_i, beta_i), in FP64: [rows..., rows'...]
+      std::vector<int> zbl = rowsp;
+      zbl.push_back(B.ealpha[i]);
+      zbl.push_back(B.ebeta[i]);
+      B.contract(Z, false, Ten{Z.ref, zbl, true}, true, rl, rho.ref, DT_C128, DT_C128, 1);
+    }
+    const int kev = B.leg(kout[i]);
+    Ten Ue = B.eig_op(rho.ref, (int)ns, kout[i], rest, kev, false, i, nullptr, nullptr, rec_sweep);
+    // The kept eigenvectors of a rank-deficient rho (a bond whose rank is below the target) include
+    // vectors of its zero eigenvalue, which the eigensolver need not return orthonormal; a
+    // Cholesky-QR of the columns makes the basis a (partial) isometry with the same span, so the
+    // weight-carrying directions and the state are unchanged.
+    const int knew = B.leg(kout[i]);
+    Ten U = B.cholqr_cols(Ue, kev, knew, false);
+    Ten Rt = B.alloc({knew, B.ealpha[i], B.ebeta[i]}, B.ct, true);
+    R[i] = B.contract(U, true, Z, false, {knew, B.ealpha[i], B.ebeta[i]}, Rt.ref, B.ct, B.cacc, 0);
+    TRef logslot;
+    logslot.src = S_WS;
+    logslot.off = P.logs_off + 8 * (int64_t)i;
+    B.normalize(R[i], logslot);
+    // output node [sigma', k, chi_c...] from U [sigma', chi_c..., k] (a layout copy)
+    std::vector<int> ol{B.sigp[i], knew};
+    ol.insert(ol.end(), rest.begin() + 1, rest.end());
+    TRef dst;
+    dst.src = S_OUT;
+    dst.off = i;
+    dst.dt = DT_C128;
+    B.contract(U, false, Ten{one, {}}, false, ol, dst, DT_C128, DT_C128, 3);
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // density-matrix compression (the method CBC is built from, Sec. III): sweeps 1 and 2 contract the
 // exact environments of <Phi|Phi>, Phi = O|psi> (legs: ket state, ket operator, bra operator, bra
@@ -1315,7 +1454,7 @@ cbc_status build_plan_dm(Plan& P, const Problem& pr, int max_bond, cbc_precision
     for (int c : pr.ch[pr.parent[k]])
       if (c != k) mark(c);
   }
-  std::vector<Ten> A(n), Bv(n), R(n);
+  std::vector<Ten> A(n), Bv(n);
   // sweep 1, leaves to root: A^{[i]} [alpha_i, beta_i, beta'_i, alpha'_i]
   for (int i : pr.post) {
     if (!needA[i]) continue;
@@ -1359,125 +1498,44 @@ cbc_status build_plan_dm(Plan& P, const Problem& pr, int max_bond, cbc_precision
       }
     }
   }
-  // sweep 3, leaves to root: Z^{[i]}, rho = Z B Z^H, top eigenvectors, R = Q^H Z
-  P.out_off.assign(n + 1, 0);
-  P.out_bond.assign(n, 1);
+  sweep3_density(B, P, pr, kout, rows, &Bv, ealphap, ebetap, 3);
+  return plan_epilogue(B, P);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Zip-Up (Sec. III C): one sweep, leaves to root, each node compressed on the spot from its own
+// product with the already compressed children: sweep 3 of the density-matrix method with no
+// environment, the basis from the top eigenvectors of Z Z^H (the left singular vectors of Z's
+// unfolding (sigma', children's bonds) x (alpha_p, beta_p)).
+
+cbc_status build_plan_zipup(Plan& P, const Problem& pr, int max_bond, cbc_precision prec,
+                            bool fill_tables) {
+  Builder B(P, pr, max_bond, false, prec);
+  B.fill_tables = fill_tables;
+  const int n = pr.n;
+  B.sig.resize(n);
+  B.sigp.resize(n);
+  B.ealpha.assign(n, -1);
+  B.ebeta.assign(n, -1);
   for (int i = 0; i < n; ++i) {
-    int64_t e = (int64_t)pr.phys[i] * kout[i];
-    for (int c : pr.ch[i]) e *= kout[c];
-    P.out_off[i + 1] = P.out_off[i] + e;
-    P.out_bond[i] = kout[i];
+    B.sig[i] = B.leg(pr.phys[i]);
+    B.sigp[i] = B.leg(pr.phys[i]);
+    if (pr.parent[i] >= 0) {
+      B.ealpha[i] = B.leg(pr.chi[i]);
+      B.ebeta[i] = B.leg(pr.dop[i]);
+    }
   }
-  TRef one = B.wsp(256, DT_C128);
-  {
-    Op f;
-    f.kind = K_IDENT;
-    f.dst = one;
-    f.td = DT_C128;
-    f.a = 1;
-    f.b = 1;
-    P.ops.push_back(f);
-  }
+  B.rootA = B.leg(1);
+  B.rootB = B.leg(1);
+  plan_prologue(B, P, prec, n);
+  std::vector<int> kout(n, 1);
+  std::vector<int64_t> rows(n, 1);
   for (int i : pr.post) {
-    B.reset_scratch();
-    std::vector<std::pair<int, Ten>> envs;
-    std::vector<int> zl{B.sigp[i]};
-    for (size_t j = 0; j < pr.ch[i].size(); ++j) {
-      const int c = pr.ch[i][j];
-      envs.push_back({1 + (int)j, R[c]});
-      zl.push_back(R[c].legs[0]);
-    }
-    if (i == pr.root) {
-      std::vector<int> zr{B.rootA};
-      zr.insert(zr.end(), zl.begin(), zl.end());
-      zr.push_back(B.rootB);
-      Ten Z = B.alloc(zr, B.ct, false);
-      Z = B.node_contract(i, envs, zr, Z.ref);
-      Op w;
-      w.kind = K_WRITE;
-      w.src = Z.ref;
-      w.ts = B.ct;
-      w.a = 1;
-      w.b = pr.phys[i];
-      w.rest = B.elems(zr) / pr.phys[i];
-      w.dst.src = S_OUT;
-      w.dst.off = i;
-      w.logs.src = S_WS;
-      w.logs.off = P.logs_off;
-      w.nlogs = n;
-      P.ops.push_back(w);
-      continue;
-    }
-    zl.push_back(B.ealpha[i]);
-    zl.push_back(B.ebeta[i]);
-    const int64_t ns = rows[i];
-    std::vector<int> rest(zl.begin(), zl.end() - 2);
-    const bool ident = ns <= max_bond;
-    Ten Z = B.alloc(zl, B.ct, ident);
-    Z = B.node_contract(i, envs, zl, Z.ref);
-    if (ident) {
-      const int nl = B.leg(ns);
-      R[i] = Ten{Z.ref, {nl, B.ealpha[i], B.ebeta[i]}};
-      TRef q = B.scr(16 * (size_t)ns * ns, DT_C128);
-      Op f;
-      f.kind = K_IDENT;
-      f.dst = q;
-      f.td = DT_C128;
-      f.a = (int)ns;
-      f.b = (int)ns;
-      P.ops.push_back(f);
-      Op w;
-      w.kind = K_WRITE;
-      w.src = q;
-      w.ts = DT_C128;
-      w.a = (int)ns;
-      w.b = pr.phys[i];
-      w.rest = ns / pr.phys[i];
-      w.dst.src = S_OUT;
-      w.dst.off = i;
-      P.ops.push_back(w);
-      continue;
-    }
-    // X = Z B over the parent bond's ket legs: [rows..., beta'_i, alpha'_i]
-    std::vector<int> xl = rest;
-    xl.push_back(ebetap[i]);
-    xl.push_back(ealphap[i]);
-    Ten X = B.alloc(xl, B.ct, false);
-    X = B.contract(Z, false, Bv[i], false, xl, X.ref, B.ct, B.cacc, 0);
-    // rho = X conj(Z') over the bra legs, in FP64: [rows..., rows'...]
-    std::vector<int> rowsp;
-    for (int l : rest) rowsp.push_back(B.leg(B.legdim[l]));
-    std::vector<int> zbl = rowsp;
-    zbl.push_back(ealphap[i]);
-    zbl.push_back(ebetap[i]);
-    Ten Zb{Z.ref, zbl, true};
-    std::vector<int> rl = rest;
-    rl.insert(rl.end(), rowsp.begin(), rowsp.end());
-    Ten rho = B.alloc(rl, DT_C128, false);
-    B.contract(X, false, Zb, true, rl, rho.ref, DT_C128, DT_C128, 1);
-    const int kev = B.leg(kout[i]);
-    Ten Ue = B.eig_op(rho.ref, (int)ns, kout[i], rest, kev, false, i, nullptr, nullptr, 3);
-    // The kept eigenvectors of a rank-deficient rho (a bond whose rank is below the target) include
-    // vectors of its zero eigenvalue, which the eigensolver need not return orthonormal; a
-    // Cholesky-QR of the columns makes the basis a (partial) isometry with the same span, so the
-    // weight-carrying directions and the state are unchanged.
-    const int knew = B.leg(kout[i]);
-    Ten U = B.cholqr_cols(Ue, kev, knew, false);
-    Ten Rt = B.alloc({knew, B.ealpha[i], B.ebeta[i]}, B.ct, true);
-    R[i] = B.contract(U, true, Z, false, {knew, B.ealpha[i], B.ebeta[i]}, Rt.ref, B.ct, B.cacc, 0);
-    TRef logslot;
-    logslot.src = S_WS;
-    logslot.off = P.logs_off + 8 * (int64_t)i;
-    B.normalize(R[i], logslot);
-    // output node [sigma', k, chi_c...] from U [sigma', chi_c..., k] (a layout copy)
-    std::vector<int> ol{B.sigp[i], knew};
-    ol.insert(ol.end(), rest.begin() + 1, rest.end());
-    TRef dst;
-    dst.src = S_OUT;
-    dst.off = i;
-    dst.dt = DT_C128;
-    B.contract(U, false, Ten{one, {}}, false, ol, dst, DT_C128, DT_C128, 3);
+    rows[i] = pr.phys[i];
+    for (int c : pr.ch[i]) rows[i] *= kout[c];
+    if (i != pr.root) kout[i] = (int)std::min<int64_t>(rows[i], max_bond);
   }
+  sweep3_density(B, P, pr, kout, rows, nullptr, {}, {}, 4);
   return plan_epilogue(B, P);
 }
 
@@ -2034,7 +2092,8 @@ cbc_status get_plan(cbc_ctx* ctx, const Problem& pr, int max_bond, bool tol_on, 
     cbc_status s = method == 0   ? build_plan(*P, pr, max_bond, tol_on, prec, need_tables)
                    : method == 1 ? build_plan_naive(*P, pr, max_bond, tol_on, prec, need_tables)
                    : method == 2 ? build_plan_src(*P, pr, max_bond, prec, need_tables)
-                                 : build_plan_dm(*P, pr, max_bond, prec, need_tables);
+                   : method == 3 ? build_plan_dm(*P, pr, max_bond, prec, need_tables)
+                                 : build_plan_zipup(*P, pr, max_bond, prec, need_tables);
     if (s != CBC_OK) return s;
     if (P->unsupported) return CBC_EUNSUP;
     P->has_tables = need_tables;
@@ -2135,7 +2194,7 @@ static cbc_status common_checks(const cbc_tree* tree, int32_t max_bond, cbc_prec
 cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
                      int32_t method, size_t* workspace_bytes, int64_t* out_offset) {
   if (!ctx || !workspace_bytes || !out_offset) return CBC_EINVAL;
-  if (method < 0 || method > 3) return CBC_EINVAL;
+  if (method < 0 || method > 4) return CBC_EINVAL;
   if (method == 2 && max_bond > 65535) return CBC_EUNSUP;
   Problem pr;
   cbc_status s = common_checks(tree, max_bond, prec, pr);
@@ -2161,7 +2220,7 @@ cbc_status cbc_query(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_p
 cbc_status cbc_plan_info(cbc_ctx* ctx, const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
                          int32_t method, int32_t tol_on, cbc_plan_summary* info) {
   if (!ctx || !info) return CBC_EINVAL;
-  if (method < 0 || method > 3) return CBC_EINVAL;
+  if (method < 0 || method > 4) return CBC_EINVAL;
   if (method == 2 && max_bond > 65535) return CBC_EUNSUP;
   Problem pr;
   cbc_status s = common_checks(tree, max_bond, prec, pr);
@@ -2212,7 +2271,7 @@ static cbc_status apply_impl(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_te
   if (method == 2 && (!sketch || !sketch->data || !sketch->offset || batch != 1 || noalloc ||
                       scratch || tol != 0.0))
     return CBC_EINVAL;
-  if (method == 3 && (batch != 1 || noalloc || scratch || tol != 0.0)) return CBC_EINVAL;
+  if (method >= 3 && (batch != 1 || noalloc || scratch || tol != 0.0)) return CBC_EINVAL;
   if (noalloc && (batch != 1 || (stats && stats->profile))) return CBC_EINVAL;
   const bool split = scratch != nullptr;
   if (split && (batch != 1 || noalloc)) return CBC_EINVAL;
@@ -2516,6 +2575,14 @@ cbc_status cbc_apply_dm(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors
                         size_t workspace_bytes, cbc_out* out, void* stream, cbc_stats* stats) {
   return apply_impl(ctx, ttno, ttns, tree, max_bond, 0.0, prec, workspace, workspace_bytes, out,
                     stream, stats, 3);
+}
+
+cbc_status cbc_apply_zipup(cbc_ctx* ctx, const cbc_tensors* ttno, const cbc_tensors* ttns,
+                           const cbc_tree* tree, int32_t max_bond, cbc_precision prec,
+                           void* workspace, size_t workspace_bytes, cbc_out* out, void* stream,
+                           cbc_stats* stats) {
+  return apply_impl(ctx, ttno, ttns, tree, max_bond, 0.0, prec, workspace, workspace_bytes, out,
+                    stream, stats, 4);
 }
 
 cbc_status cbc_apply_batched(cbc_ctx* ctx, int32_t batch, const cbc_tensors* ttno,

@@ -134,7 +134,7 @@ int main(int argc, char** argv) {
     const int n = c.n_nodes;
     std::vector<int64_t> off(n + 1, 0);
     for (int prec = 0; prec < 2; ++prec) {
-      for (int method = 0; method < 4; ++method) {
+      for (int method = 0; method < 5; ++method) {
         size_t ws = 0;
         const int rc = cbc_query(ctx, &c, t.max_bond, (cbc_precision)prec, method, &ws, off.data());
         // the naive method forms the exact product, whose Grams exceed the limit sooner

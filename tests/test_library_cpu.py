@@ -343,7 +343,7 @@ def test_src_plan_sizes_match_oracle(maker):
     assert [int(s) for s in np.diff(off)] == [t.size for t in ref]
     info = cbc.plan_info(tree, p.max_bond, "mixed", method="src")
     assert info["launches"]["eig"] == 0 and info["flops"]["eig"] == 0.0
-    assert _query(tree, p.max_bond, 0, 4)[0] == -1
+    assert _query(tree, p.max_bond, 0, 5)[0] == -1
 
 
 def test_apply_many_argument_errors_need_no_device():
@@ -383,3 +383,27 @@ def test_dm_plan_sizes_match_oracle(maker):
     truncated = sum(1 for i, t in enumerate(ref) if p.parent[i] >= 0 and
                     t.shape[1] < t.size // t.shape[1])
     assert info["launches"]["eig"] == truncated
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: config_problem("C1"), lambda: config_problem("C2", n=12),
+    lambda: random_problem(kary_parent(13, 3), 2, 6, 3, 5, seed=4),
+    lambda: random_problem(kary_parent(7, 2), [1, 1, 1, 2, 2, 2, 2], 4, 4, 3, seed=6)])
+def test_zipup_plan_sizes_match_oracle(maker):
+    """Zip-Up's planned output node sizes equal those of the Zip-Up oracle; it plans one eigensolve
+    per truncated node and no environment sweeps (fewer contraction flops than the density-matrix
+    method on the same problem)."""
+    from oracle.zipup import zipup_tree
+    p = maker()
+    tree = cbc.Tree.of(p)
+    for prec in (0, 1):
+        rc, ws, off = _query(tree, p.max_bond, prec, 4)
+        assert rc == 0 and ws > 0
+    ref = zipup_tree(p.parent, p.state, p.op, p.max_bond)
+    assert [int(s) for s in np.diff(off)] == [t.size for t in ref]
+    info = cbc.plan_info(tree, p.max_bond, "fp64", method="zipup")
+    truncated = sum(1 for i, t in enumerate(ref) if p.parent[i] >= 0 and
+                    t.shape[1] < t.size // t.shape[1])
+    assert info["launches"]["eig"] == truncated
+    dm = cbc.plan_info(tree, p.max_bond, "fp64", method="dm")
+    assert info["flops"]["contract"] < dm["flops"]["contract"]
