@@ -329,21 +329,27 @@ static constexpr int MW_EPT = 4;                    // columns per thread, at mo
 static constexpr int MW_ROWS_MAX = 16;              // rows per workgroup (per-row reduction slots)
 static constexpr size_t MW_LDS_BUDGET = 160 * 1024 - 8192;   // the kernel's static LDS is below 8 KiB
 
+static constexpr int MW_TARGET_WG = 208;            // workgroups aimed at (see mw_shape)
+
 struct MwShape {
   int nwg, rows;
 };
-// Workgroup count: enough for the rows to fit in LDS, and at least one workgroup per 16 rows (up to
-// 32) so that small matrices still spread their work.
+// Rows per workgroup: as few as keep the workgroup count near MW_TARGET_WG, and no more than fit in
+// LDS. Fewer rows shorten the per-column update and product pass of every workgroup, more
+// workgroups lengthen the grid barrier; measured on MI355X at s = 1024 (per column: update,
+// barrier): 9 rows / 114 workgroups 4.26 + 2.45 us, 6 / 171 2.94 + 2.65, 5 / 205 2.49 + 2.86,
+// 4 / 256 2.04 + 3.70. Per solve, against the former rule (as many rows as fit in LDS, at least
+// one workgroup per 16 rows): s = 256 2.45 -> 1.66 ms, 420 4.44 -> 3.2, 700 8.3 -> 5.9, 1024
+// 12.0 -> 10.7 (targets of 128 and 256 workgroups were slower above s = 420).
 __host__ __device__ inline MwShape mw_shape(int s) {
   int fit = (int)(MW_LDS_BUDGET / (16 * (size_t)s));
   if (fit > MW_ROWS_MAX) fit = MW_ROWS_MAX;
   if (fit < 1) fit = 1;
-  int nwg = (s + fit - 1) / fit;
-  const int want = (s + 15) / 16 < 32 ? (s + 15) / 16 : 32;
-  if (nwg < want) nwg = want;
+  int rows = (s + MW_TARGET_WG - 1) / MW_TARGET_WG;
+  if (rows > fit) rows = fit;
   MwShape m;
-  m.nwg = nwg;
-  m.rows = (s + nwg - 1) / nwg;
+  m.nwg = (s + rows - 1) / rows;
+  m.rows = (s + m.nwg - 1) / m.nwg;
   return m;
 }
 size_t mw_lds_bytes(int s) { return (size_t)mw_shape(s).rows * s * 16; }
