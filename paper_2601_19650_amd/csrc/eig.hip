@@ -19,8 +19,9 @@
 //      points of the current interval per round).
 //   3. eigenvectors of T by a twisted factorisation T - lambda I = N_r Delta N_r^T, one wave per
 //      eigenpair; eigenvalues closer than 1e-3 ||T|| form clusters that are re-orthogonalised (or,
-//      for near-exact degeneracies, computed by inverse iteration); then the back-transformation with
-//      the reflectors streamed from L2, one wave per eigenpair (three launches).
+//      for near-exact degeneracies, computed by inverse iteration); then the back-transformation:
+//      for s <= 256 one wave per eigenpair applying the reflectors streamed from L2, above that in
+//      blocks of 32 reflectors (compact WY, k_bt_tfactor and k_bt_wy).
 #include <float.h>
 
 #include <mutex>
@@ -1237,6 +1238,196 @@ __global__ __launch_bounds__(256) void k_backtransform(EigArgs a0) {
     atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 3), (unsigned long long)wall_clock64());
 }
 
+// ---- blocked back-transformation (s > 256): compact WY, u = Q y with Q = B_0 B_1 ... B_{nb-1} ------
+// Block b holds the reflectors j0 = BT_NB b ... j0 + n - 1 and equals I - V_b T_b V_b^H with T_b upper
+// triangular: T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] (V_b[:, 0:i]^H v_i). The factors are formed
+// once per solve (k_bt_tfactor, one workgroup per block); k_bt_wy then applies the blocks, last one
+// first, to CPW eigenvectors per workgroup held in LDS: w = V_b^H x, w' = T_b w, x -= V_b w'. Each
+// block costs one dependent step instead of BT_NB reflector-by-reflector reductions, and the
+// reflectors are read with unit stride in both passes. Measured on MI355X (eigenvectors of T and
+// back-transformation, k = 256): s = 1024 1.62 -> 0.83 ms, 1272 5.4 -> 1.15, 1536 7.75 -> 1.52
+// against one wave per eigenvector applying the reflectors one at a time; one eigenvector per
+// workgroup (256 workgroups) was faster than two (0.91 ms at s = 1024).
+static constexpr int BT_CHUNK = 64;   // rows of a block staged in LDS for its Gram
+static constexpr int BT_CPW = 1;      // eigenvectors per workgroup of k_bt_wy
+
+__global__ __launch_bounds__(256) void k_bt_tfactor(EigArgs a0) {
+  const EigArgs a = eig_inst(a0, blockIdx.y);
+  const int s = a.s, tid = threadIdx.x;
+  EigWork W = eig_layout(a.work, s, a.kmax);
+  const int b = blockIdx.x, j0 = b * BT_NB;
+  const int n = s - 1 - j0 < BT_NB ? s - 1 - j0 : BT_NB;
+  __shared__ double2 vs[BT_NB][BT_CHUNK + 1];
+  __shared__ double2 G[BT_NB][BT_NB + 1];
+  __shared__ double2 T[BT_NB][BT_NB + 1];
+  // Gram entries G[p][q] = v_p^H v_q, p < q (nonzero rows: r > j0 + q), four entries per thread
+  double2 acc[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) acc[m] = make_double2(0.0, 0.0);
+  for (int r0 = j0 + 1; r0 < s; r0 += BT_CHUNK) {
+    __syncthreads();
+    for (int e = tid; e < BT_NB * BT_CHUNK; e += 256) {
+      const int i = e / BT_CHUNK, l = e % BT_CHUNK, r = r0 + l, J = j0 + i;
+      vs[i][l] = (i < n && r < s && r > J) ? W.V[(size_t)J * s + r] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int pq = tid + 256 * m, p = pq / BT_NB, q = pq % BT_NB;
+      if (p < q && q < n) {
+        double2 g = acc[m];
+        for (int l = 0; l < BT_CHUNK; ++l) {
+          const double2 x = vs[p][l], y = vs[q][l];
+          g.x += x.x * y.x + x.y * y.y;
+          g.y += x.x * y.y - x.y * y.x;
+        }
+        acc[m] = g;
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int pq = tid + 256 * m, p = pq / BT_NB, q = pq % BT_NB;
+    if (p < q && q < n) G[p][q] = acc[m];
+  }
+  __syncthreads();
+  // row p of T in lane p, column by column (each lane reads only its own row of T)
+  if (tid < BT_NB) {
+    const int p = tid;
+    for (int i = 0; i < BT_NB; ++i) {
+      double2 v = make_double2(0.0, 0.0);
+      if (i < n) {
+        const double2 ti = W.tau[j0 + i];
+        if (p == i) {
+          v = ti;
+        } else if (p < i) {
+          double2 sm = make_double2(0.0, 0.0);
+          for (int k = p; k < i; ++k) {
+            const double2 c = cmul(T[p][k], G[k][i]);
+            sm.x += c.x;
+            sm.y += c.y;
+          }
+          const double2 c = cmul(ti, sm);
+          v = make_double2(-c.x, -c.y);
+        }
+      }
+      T[p][i] = v;
+    }
+    double2* dst = W.tfac + (size_t)b * BT_NB * BT_NB + (size_t)p * BT_NB;
+    for (int i = 0; i < BT_NB; ++i) dst[i] = T[p][i];
+  }
+}
+
+template <int CPW>   // eigenvectors per workgroup
+__global__ __launch_bounds__(256) void k_bt_wy(EigArgs a0) {
+  const EigArgs a = eig_inst(a0, blockIdx.y);
+  const int s = a.s, kmax = a.kmax, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  EigWork W = eig_layout(a.work, s, kmax);
+  const int t0 = blockIdx.x * CPW;
+  extern __shared__ double smem[];
+  double2* X = reinterpret_cast<double2*>(smem);   // X[r * CPW + c]
+  __shared__ double2 Ws[BT_NB][CPW], Wq[BT_NB][CPW];
+  for (int e = tid; e < s * CPW; e += 256) {
+    const int r = e / CPW, t = t0 + e % CPW;
+    X[e] = make_double2(t < kmax ? W.Y[(size_t)t * s + r] : 0.0, 0.0);
+  }
+  __syncthreads();
+  constexpr int PW = BT_NB / 4;   // reflectors per wave in the first pass
+  for (int b = bt_blocks(s) - 1; b >= 0; --b) {
+    const int j0 = b * BT_NB;
+    const int n = s - 1 - j0 < BT_NB ? s - 1 - j0 : BT_NB;
+    // (1) w = V_b^H x: wave w takes the reflectors w, w + 4, ...; lanes run over the rows
+    double2 acc[PW][CPW];
+#pragma unroll
+    for (int m = 0; m < PW; ++m)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) acc[m][c] = make_double2(0.0, 0.0);
+    for (int r = j0 + 1 + lane; r < s; r += 64) {
+      // loads issued together from in-bounds addresses (reflector index clamped to s - 2); the
+      // entries outside a reflector's support are replaced by zeros below
+      double2 vv[PW];
+#pragma unroll
+      for (int m = 0; m < PW; ++m) {
+        const int J = j0 + wave + 4 * m;
+        vv[m] = W.V[(size_t)(J < s - 1 ? J : s - 2) * s + r];
+      }
+      double2 x[CPW];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) x[c] = X[r * CPW + c];
+#pragma unroll
+      for (int m = 0; m < PW; ++m) {
+        const int i = wave + 4 * m;
+        const double2 v = (i < n && r > j0 + i) ? vv[m] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          acc[m][c].x += v.x * x[c].x + v.y * x[c].y;
+          acc[m][c].y += v.x * x[c].y - v.y * x[c].x;
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < PW; ++m)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const double re = wave_sum(acc[m][c].x), im = wave_sum(acc[m][c].y);
+        if (lane == 0) Ws[wave + 4 * m][c] = make_double2(re, im);
+      }
+    __syncthreads();
+    // (2) w' = T_b w (T_b is zero outside the block's n x n upper triangle)
+    if (tid < BT_NB * CPW) {
+      const int i = tid / CPW, c = tid % CPW;
+      const double2* trow = W.tfac + (size_t)b * BT_NB * BT_NB + (size_t)i * BT_NB;
+      double2 tr[BT_NB];
+#pragma unroll
+      for (int k = 0; k < BT_NB; ++k) tr[k] = trow[k];
+      double2 sm = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < BT_NB; ++k) {
+        const double2 p = cmul(tr[k], Ws[k][c]);
+        sm.x += p.x;
+        sm.y += p.y;
+      }
+      Wq[i][c] = sm;
+    }
+    __syncthreads();
+    // (3) x -= V_b w', one row per thread; the block's reflectors at the row are loaded together
+    for (int r = j0 + 1 + tid; r < s; r += 256) {
+      const int imax = r - j0 < n ? r - j0 : n;   // reflector i is nonzero at row r iff r > j0 + i
+      double2 vv[BT_NB];
+#pragma unroll
+      for (int i = 0; i < BT_NB; ++i) vv[i] = W.V[(size_t)(j0 + i < s - 1 ? j0 + i : s - 2) * s + r];
+#pragma unroll
+      for (int i = 0; i < BT_NB; ++i)
+        if (i >= imax) vv[i] = make_double2(0.0, 0.0);
+      double2 u[CPW];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) u[c] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int i = 0; i < BT_NB; ++i) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          const double2 p = cmul(vv[i], Wq[i][c]);
+          u[c].x += p.x;
+          u[c].y += p.y;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        X[r * CPW + c].x -= u[c].x;
+        X[r * CPW + c].y -= u[c].y;
+      }
+    }
+    __syncthreads();
+  }
+  const int kk = a.kkeep[0];
+  for (int e = tid; e < s * CPW; e += 256) {
+    const int r = e / CPW, t = t0 + e % CPW;
+    if (t < kmax) a.U[(size_t)r * kmax + t] = t < kk ? X[e] : make_double2(0.0, 0.0);
+  }
+  if (a.tstamp && tid == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(a.tstamp + 3), (unsigned long long)wall_clock64());
+}
+
 size_t eig_lds_bytes(int s) { return (size_t)16 * (s * (size_t)(s + 1) / 2) + (size_t)s * (3 * 16) + 64; }
 
 hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
@@ -1310,7 +1501,17 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
   if (e != hipSuccess) return e;
   if (two_stage) return launch_bt_band(a, st);
   const dim3 gb(a.spread * ((a.kmax + 3) / 4), a.batch);
-  if (a.s <= 64) {
+  if (a.s > 256 && a.spread == 1) {
+    hipLaunchKernelGGL(k_bt_tfactor, dim3(bt_blocks(a.s), a.batch), dim3(256), 0, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t ldsx = (size_t)a.s * BT_CPW * 16;
+    if (ldsx > 160 * 1024 - 8192) return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute((const void*)k_bt_wy<BT_CPW>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsx);
+    hipLaunchKernelGGL(k_bt_wy<BT_CPW>, dim3((a.kmax + BT_CPW - 1) / BT_CPW, a.batch), dim3(256),
+                       ldsx, st, a);
+  } else if (a.s <= 64) {
     hipLaunchKernelGGL((k_backtransform<1, 4>), gb, dim3(256), 0, st, a);
   } else if (a.s <= 128) {
     hipLaunchKernelGGL((k_backtransform<2, 4>), gb, dim3(256), 0, st, a);

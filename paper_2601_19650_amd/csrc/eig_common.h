@@ -84,8 +84,12 @@ struct EigWork {
   // multi-workgroup reduction only (each double-buffered by the parity of the column)
   double2* ybuf;  // 2 * s       products A v of the current column
   double2* prow;  // 2 * s       next pivot row, published by its owner
+  // blocked back-transformation: the triangular factor of each block of BT_NB reflectors
+  double2* tfac;  // bt_blocks(s) * BT_NB * BT_NB
   unsigned* sync; // MW_MAX_WG + 16 words: last barrier reached per workgroup, then a time-out flag
 };
+static constexpr int BT_NB = 32;   // reflectors per block of the blocked back-transformation
+__host__ __device__ inline int bt_blocks(int s) { return s > 1 ? (s - 1 + BT_NB - 1) / BT_NB : 0; }
 __host__ __device__ inline EigWork eig_layout(double* w, int s, int kmax) {
   EigWork L;
   L.d = w;
@@ -97,14 +101,16 @@ __host__ __device__ inline EigWork eig_layout(double* w, int s, int kmax) {
   L.lu = L.Y + (size_t)kmax * s;
   L.ybuf = reinterpret_cast<double2*>(L.lu + 5 * (size_t)kmax * s);
   L.prow = L.ybuf + 2 * (size_t)s;
-  L.sync = reinterpret_cast<unsigned*>(L.prow + 2 * (size_t)s);
+  L.tfac = L.prow + 2 * (size_t)s;
+  L.sync = reinterpret_cast<unsigned*>(L.tfac + (size_t)bt_blocks(s) * BT_NB * BT_NB);
   return L;
 }
 static constexpr int MW_SYNC_BYTES = 4 * (MW_MAX_WG + 16);
 // doubles of the layout above (the two-stage reduction's scratch follows it)
 __host__ __device__ inline size_t eig_base_doubles(int s, int kmax) {
   return 4 * (size_t)s + 8 + 2 * (size_t)s * s + (size_t)kmax * s + 5 * (size_t)kmax * s +
-         4 * (size_t)s + 4 * (size_t)s + MW_SYNC_BYTES / 8 + 64;
+         4 * (size_t)s + 4 * (size_t)s + 2 * (size_t)bt_blocks(s) * BT_NB * BT_NB +
+         MW_SYNC_BYTES / 8 + 64;
 }
 // two-stage reduction (eig_band.hip): scratch beyond eig_base_doubles, the reduction of G to T
 // (d, e and the Gershgorin bounds in the common layout) and the back-transformation into U
