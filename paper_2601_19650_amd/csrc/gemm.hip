@@ -226,7 +226,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
 // from global memory into registers while the MFMAs consume the current one from LDS, and the LDS
 // tiles are double-buffered so each k-tile costs one barrier.
 template <typename TA, typename TB, typename TC, int BM, int BN>
-__global__ __launch_bounds__(256) void k_cgemm_pipe(GemmArgs g) {
+__device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int MB = WM / 16, NB = WN / 16;
@@ -393,6 +393,19 @@ __global__ __launch_bounds__(256) void k_cgemm_pipe(GemmArgs g) {
     }
 }
 
+// Entry points of the pipelined kernel. With FP32 operands the register budget is capped at four
+// waves per SIMD (128 registers, no spills), so that a launch of up to 1024 64 x 64 tiles runs in
+// one round on the 256 compute units; operands read in FP64 keep the compiler's own budget (the cap
+// would spill their staging registers).
+template <typename TA, typename TB, typename TC, int BM, int BN>
+__global__ __launch_bounds__(256) void k_cgemm_pipe(GemmArgs g) {
+  cgemm_pipe_body<TA, TB, TC, BM, BN>(g);
+}
+template <typename TA, typename TB, typename TC, int BM, int BN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cgemm_pipe4(GemmArgs g) {
+  cgemm_pipe_body<TA, TB, TC, BM, BN>(g);
+}
+
 // Tile choice by shape (measured on MI355X): with FP32 accumulation the pipelined 64x64 kernel
 // whenever there are at least 64 such output tiles (split along K below 512 tiles, see
 // gemm_pick_ksplit); otherwise, and for FP64 accumulation, the table-driven 32x32 kernel, whose many
@@ -441,9 +454,12 @@ static hipError_t launch_t(const GemmArgs& a0, int tile, hipStream_t s) {
     a.mbase = mb;
     const int rows = a0.M - mb < max_rows ? a0.M - mb : max_rows;
     const dim3 grid((a.N + BMt - 1) / BMt, (rows + BMt - 1) / BMt, a.batch * a.ksplit);
-    if (tile == GEMM_PIPE64)
-      hipLaunchKernelGGL((k_cgemm_pipe<TA, TB, TC, 64, 64>), grid, dim3(256), 0, s, a);
-    else if (tile == GEMM_TILE64)
+    if (tile == GEMM_PIPE64) {
+      if constexpr (sizeof(TA) == 4 && sizeof(TB) == 4)
+        hipLaunchKernelGGL((k_cgemm_pipe4<TA, TB, TC, 64, 64>), grid, dim3(256), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_cgemm_pipe<TA, TB, TC, 64, 64>), grid, dim3(256), 0, s, a);
+    } else if (tile == GEMM_TILE64)
       hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
     else
       hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 32, 32>), grid, dim3(256), 0, s, a);
