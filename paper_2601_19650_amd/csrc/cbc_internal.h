@@ -47,6 +47,9 @@ struct GemmArgs {
   // m * sCm + n * sCn instead of table lookups
   int64_t sAm = 0, sAk = 0, sBk = 0, sBn = 0, sCm = 0, sCn = 0;
   int accum = 0;        // 1: C += alpha * op(A) op(B)
+  // 1: C is Hermitian by construction (B is the conjugate of A over relabelled legs, M == N): only
+  // entries m >= n are computed, and each strictly lower one is also written, conjugated, at (n, m)
+  int herm = 0;
 };
 // pointer of instance b for a per-instance byte stride
 template <typename T>

@@ -58,6 +58,8 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
   const int bz = blockIdx.z / g.ksplit, kz = blockIdx.z % g.ksplit;
   const int kbeg = g.ksplit > 1 ? kz * g.kchunk : 0;
   const int K = g.ksplit > 1 ? min(g.K, kbeg + g.kchunk) : g.K;
+  // a Hermitian product computes the tiles on and below the diagonal only (BM == BN)
+  if (g.herm && n0 >= m0 + BM) return;
   const CA* __restrict__ A = reinterpret_cast<const CA*>(inst_ptr(g.A, g.bsA, bz));
   const CB* __restrict__ B = reinterpret_cast<const CB*>(inst_ptr(g.B, g.bsB, bz));
   const ACC sa = g.conjA ? ACC(-1) : ACC(1);
@@ -170,7 +172,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
         // FP64 MFMA -> row l/16 + 4*r (column l%16 in both)
         const int rb = sizeof(ACC) == 8 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
         const int m = m0 + wr * WM + i * 16 + rb;
-        if (m < M) {
+        if (m < M && (!g.herm || m >= n)) {
           const int64_t ci = (g.offAm ? (int64_t)g.offCm[m] : m * g.sCm) + cn;
           double xr = double(accr[i][j][r]) * alpha, xi = double(acci[i][j][r]) * alpha;
           if (g.accum) {
@@ -182,6 +184,10 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
           out.x = TC(xr);
           out.y = TC(xi);
           C[ci] = out;
+          if (g.herm && m > n) {
+            out.y = -out.y;
+            C[(g.offAm ? (int64_t)g.offCm[n] + g.offCn[m] : n * g.sCm + m * g.sCn)] = out;
+          }
         }
       }
     }
@@ -196,18 +202,23 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t mn = (int64_t)g.M * g.N;
   if (idx >= mn) return;
-  const CP* P = reinterpret_cast<const CP*>(inst_ptr(g.part, g.bsPart, b)) + idx;
+  const int m = (int)(idx / g.N), n = (int)(idx % g.N);
+  // a Hermitian product has chunk sums on and below the diagonal only: (m, n) above it is the
+  // conjugate of (n, m)
+  const bool mirror = g.herm && m < n;
+  const CP* P = reinterpret_cast<const CP*>(inst_ptr(g.part, g.bsPart, b)) +
+                (mirror ? (int64_t)n * g.N + m : idx);
   double re = 0.0, im = 0.0;
   for (int z = 0; z < g.ksplit; ++z) {
     const CP v = P[(int64_t)z * mn];
     re += double(v.x);
     im += double(v.y);
   }
+  if (mirror) im = -im;
   double alpha = g.alpha;
   if (g.alpha_dev) alpha *= inst_ptr(g.alpha_dev, g.bsAlpha, b)[0];
   if (g.alpha_dev2) alpha *= inst_ptr(g.alpha_dev2, g.bsAlpha2, b)[0];
   CC* C = reinterpret_cast<CC*>(inst_ptr(g.C, g.bsC, b));
-  const int m = (int)(idx / g.N), n = (int)(idx % g.N);
   const int64_t ci = g.offAm ? (int64_t)g.offCm[m] + g.offCn[n] : m * g.sCm + n * g.sCn;
   double xr = re * alpha, xi = im * alpha;
   if (g.accum) {
@@ -221,25 +232,28 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
   C[ci] = out;
 }
 
-// Pipelined variant for FP32 accumulation and large tiles (BM x BN = 128 x 128 or 64 x 64, BK = 16):
-// the row / column offsets of the tile are read once into registers, the next k-tile is fetched
-// from global memory into registers while the MFMAs consume the current one from LDS, and the LDS
-// tiles are double-buffered so each k-tile costs one barrier.
-template <typename TA, typename TB, typename TC, int BM, int BN>
+// Pipelined variant with 64 x 64 tiles (BK = 16 with FP32 accumulation, 8 with FP64): the row /
+// column offsets of the tile are read once into registers, the next k-tile is fetched from global
+// memory into registers while the MFMAs consume the current one from LDS, and the LDS tiles are
+// double-buffered so each k-tile costs one barrier. A Hermitian product (g.herm) computes the tiles
+// on and below the diagonal and writes each strictly lower entry also, conjugated, at its mirror.
+template <typename TA, typename TB, typename TC, typename ACC, int BM, int BN>
 __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
-  constexpr int BK = 16;
+  constexpr bool F64 = sizeof(ACC) == 8;
+  constexpr int BK = F64 ? 8 : 16;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int MB = WM / 16, NB = WN / 16;
-  constexpr int PAD = 4;
+  constexpr int PAD = F64 ? 1 : 4;
   constexpr int EA = BM * BK / 256, EB = BN * BK / 256;   // elements per thread and k-tile
   using CA = typename Cplx<TA>::type;
   using CB = typename Cplx<TB>::type;
   using CC = typename Cplx<TC>::type;
+  using V4 = typename Acc4<ACC>::type;
 
-  __shared__ float sAr[2][BK][BM + PAD];
-  __shared__ float sAi[2][BK][BM + PAD];
-  __shared__ float sBr[2][BK][BN + PAD];
-  __shared__ float sBi[2][BK][BN + PAD];
+  __shared__ ACC sAr[2][BK][BM + PAD];
+  __shared__ ACC sAi[2][BK][BM + PAD];
+  __shared__ ACC sBr[2][BK][BN + PAD];
+  __shared__ ACC sBi[2][BK][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -247,14 +261,15 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
   const int wr = wave >> 1, wc = wave & 1;
   const int m0 = g.mbase + blockIdx.y * BM;
   const int n0 = blockIdx.x * BN;
+  if (g.herm && n0 >= m0 + BM) return;   // strictly above the diagonal (BM == BN)
   const int M = g.M, N = g.N;
   const int bz = blockIdx.z / g.ksplit, kz = blockIdx.z % g.ksplit;
   const int kbeg = g.ksplit > 1 ? kz * g.kchunk : 0;
   const int K = g.ksplit > 1 ? min(g.K, kbeg + g.kchunk) : g.K;
   const CA* __restrict__ A = reinterpret_cast<const CA*>(inst_ptr(g.A, g.bsA, bz));
   const CB* __restrict__ B = reinterpret_cast<const CB*>(inst_ptr(g.B, g.bsB, bz));
-  const float sa = g.conjA ? -1.0f : 1.0f;
-  const float sb = g.conjB ? -1.0f : 1.0f;
+  const ACC sa = g.conjA ? ACC(-1) : ACC(1);
+  const ACC sb = g.conjB ? ACC(-1) : ACC(1);
   const bool akf = g.a_kfast, bkf = g.b_kfast;
 
   // this thread's load slots: element u of a k-tile is (row ra(u), k ka(u)) of A, (k kb(u), col cb(u)) of B
@@ -290,23 +305,23 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
   auto stash = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < EA; ++u) {
-      sAr[buf][ka(u)][ra(u)] = float(ra_v[u].x);
-      sAi[buf][ka(u)][ra(u)] = sa * float(ra_v[u].y);
+      sAr[buf][ka(u)][ra(u)] = ACC(ra_v[u].x);
+      sAi[buf][ka(u)][ra(u)] = sa * ACC(ra_v[u].y);
     }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
-      sBr[buf][kb(u)][cb(u)] = float(rb_v[u].x);
-      sBi[buf][kb(u)][cb(u)] = sb * float(rb_v[u].y);
+      sBr[buf][kb(u)][cb(u)] = ACC(rb_v[u].x);
+      sBi[buf][kb(u)][cb(u)] = sb * ACC(rb_v[u].y);
     }
   };
 
-  f4v accr[MB][NB], acci[MB][NB];
+  V4 accr[MB][NB], acci[MB][NB];
 #pragma unroll
   for (int i = 0; i < MB; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      accr[i][j] = f4v{0, 0, 0, 0};
-      acci[i][j] = f4v{0, 0, 0, 0};
+      accr[i][j] = V4{0, 0, 0, 0};
+      acci[i][j] = V4{0, 0, 0, 0};
     }
 
   fetch(kbeg);
@@ -319,7 +334,7 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4);
-      float ar[MB], ai[MB], br[NB], bi[NB];
+      ACC ar[MB], ai[MB], br[NB], bi[NB];
 #pragma unroll
       for (int i = 0; i < MB; ++i) {
         ar[i] = sAr[buf][kr][wr * WM + i * 16 + (lane & 15)];
@@ -352,9 +367,13 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
     buf ^= 1;
   }
 
+  // output rows of a 16x16 block: FP32 MFMA lane l, register r -> row 4*(l/16) + r; FP64 MFMA ->
+  // row l/16 + 4*r (column l%16 in both)
+  auto row_of = [&](int r) { return F64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r; };
   if (g.ksplit > 1) {
     // raw chunk sums, row-major M x N per (instance, chunk)
-    float2* __restrict__ P = reinterpret_cast<float2*>(inst_ptr(g.part, g.bsPart, bz)) + (int64_t)kz * M * N;
+    using CP = typename Cplx<ACC>::type;
+    CP* __restrict__ P = reinterpret_cast<CP*>(inst_ptr(g.part, g.bsPart, bz)) + (int64_t)kz * M * N;
 #pragma unroll
     for (int i = 0; i < MB; ++i)
 #pragma unroll
@@ -363,8 +382,8 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
         if (n >= N) continue;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wr * WM + i * 16 + 4 * (lane >> 4) + r;
-          if (m < M) P[(int64_t)m * N + n] = make_float2(accr[i][j][r], acci[i][j][r]);
+          const int m = m0 + wr * WM + i * 16 + row_of(r);
+          if (m < M) P[(int64_t)m * N + n] = CP{accr[i][j][r], acci[i][j][r]};
         }
       }
     return;
@@ -382,28 +401,32 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
       const int32_t cn = g.offCn[n];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wr * WM + i * 16 + 4 * (lane >> 4) + r;
-        if (m < M) {
+        const int m = m0 + wr * WM + i * 16 + row_of(r);
+        if (m < M && (!g.herm || m >= n)) {
           CC out;
           out.x = TC(double(accr[i][j][r]) * alpha);
           out.y = TC(double(acci[i][j][r]) * alpha);
           C[(int64_t)g.offCm[m] + cn] = out;
+          if (g.herm && m > n) {
+            out.y = -out.y;
+            C[(int64_t)g.offCm[n] + g.offCn[m]] = out;
+          }
         }
       }
     }
 }
 
-// Entry points of the pipelined kernel. With FP32 operands the register budget is capped at four
-// waves per SIMD (128 registers, no spills), so that a launch of up to 1024 64 x 64 tiles runs in
-// one round on the 256 compute units; operands read in FP64 keep the compiler's own budget (the cap
-// would spill their staging registers).
-template <typename TA, typename TB, typename TC, int BM, int BN>
+// Entry points of the pipelined kernel. With FP32 operands and accumulation the register budget is
+// capped at four waves per SIMD (128 registers, no spills), so that a launch of up to 1024 64 x 64
+// tiles runs in one round on the 256 compute units; the other instantiations keep the compiler's
+// own budget (the cap would spill their staging registers).
+template <typename TA, typename TB, typename TC, typename ACC, int BM, int BN>
 __global__ __launch_bounds__(256) void k_cgemm_pipe(GemmArgs g) {
-  cgemm_pipe_body<TA, TB, TC, BM, BN>(g);
+  cgemm_pipe_body<TA, TB, TC, ACC, BM, BN>(g);
 }
-template <typename TA, typename TB, typename TC, int BM, int BN>
+template <typename TA, typename TB, typename TC, typename ACC, int BM, int BN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cgemm_pipe4(GemmArgs g) {
-  cgemm_pipe_body<TA, TB, TC, BM, BN>(g);
+  cgemm_pipe_body<TA, TB, TC, ACC, BM, BN>(g);
 }
 
 // Tile choice by shape (measured on MI355X): with FP32 accumulation the pipelined 64x64 kernel
@@ -439,8 +462,9 @@ static hipError_t launch_t(const GemmArgs& a0, int tile, hipStream_t s) {
   if (a0.M <= 0 || a0.N <= 0 || a0.batch <= 0) return hipSuccess;
   if (tile == GEMM_AUTO) tile = gemm_pick_tile(a0.M, a0.N, a0.K, a0.batch, sizeof(ACC) == 8);
   if (tile != GEMM_TILE32 && tile != GEMM_TILE64 && tile != GEMM_PIPE64) return hipErrorInvalidValue;
-  // the pipelined kernel: FP32 accumulation, offset tables, no accumulation into C
-  if (tile == GEMM_PIPE64 && (sizeof(ACC) == 8 || !a0.offAm || a0.accum)) tile = GEMM_TILE64;
+  // the pipelined kernel: offset tables, no accumulation into C
+  if (tile == GEMM_PIPE64 && (!a0.offAm || a0.accum)) tile = GEMM_TILE64;
+  if (a0.herm && (a0.M != a0.N || a0.accum)) return hipErrorInvalidValue;
   const bool split = a0.ksplit > 1;
   if (split && (tile == GEMM_TILE64 || !a0.part || a0.kchunk % 16 != 0 ||
                 (int64_t)a0.kchunk * a0.ksplit < a0.K))
@@ -455,10 +479,10 @@ static hipError_t launch_t(const GemmArgs& a0, int tile, hipStream_t s) {
     const int rows = a0.M - mb < max_rows ? a0.M - mb : max_rows;
     const dim3 grid((a.N + BMt - 1) / BMt, (rows + BMt - 1) / BMt, a.batch * a.ksplit);
     if (tile == GEMM_PIPE64) {
-      if constexpr (sizeof(TA) == 4 && sizeof(TB) == 4)
-        hipLaunchKernelGGL((k_cgemm_pipe4<TA, TB, TC, 64, 64>), grid, dim3(256), 0, s, a);
+      if constexpr (sizeof(TA) == 4 && sizeof(TB) == 4 && sizeof(ACC) == 4)
+        hipLaunchKernelGGL((k_cgemm_pipe4<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
       else
-        hipLaunchKernelGGL((k_cgemm_pipe<TA, TB, TC, 64, 64>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_cgemm_pipe<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
     } else if (tile == GEMM_TILE64)
       hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
     else
