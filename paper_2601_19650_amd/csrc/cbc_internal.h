@@ -50,6 +50,10 @@ struct GemmArgs {
   // 1: C is Hermitian by construction (B is the conjugate of A over relabelled legs, M == N): only
   // entries m >= n are computed, and each strictly lower one is also written, conjugated, at (n, m)
   int herm = 0;
+  // optional device flag per instance (advancing by bsSkip bytes): the launch does nothing where it
+  // is set (the blocked Cholesky's steps after an identity shortcut)
+  const int* skip = nullptr;
+  int64_t bsSkip = 0;
 };
 // pointer of instance b for a per-instance byte stride
 template <typename T>
@@ -144,6 +148,7 @@ struct CholArgs {
   int ld = 0;
   const double* thresh_dev = nullptr;
   int* status = nullptr;   // optional device status word (CBC_ENOTPD on a non-finite Gram)
+  const int* skip = nullptr;   // internal: device flag; the kernel does nothing where it is set
 };
 // largest k factorised by one LDS-resident workgroup; larger ones are blocked and need `work`
 constexpr int CHOL_LDS_MAX = 88;

@@ -41,6 +41,7 @@ __device__ inline CholArgs chol_inst(const CholArgs& a0, int b) {
   a.work = inst_ptr(a0.work, a0.bs, b);
   a.thresh_dev = inst_ptr(a0.thresh_dev, a0.bs, b);
   a.status = inst_ptr(a0.status, a0.bs, b);
+  a.skip = inst_ptr(a0.skip, a0.bs, b);
   return a;
 }
 
@@ -121,6 +122,7 @@ __device__ inline void chol_panel(double2* M, int ld, int k, int p, int pe, doub
 
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_inv_lds(CholArgs a0) {
   const CholArgs a = chol_inst(a0, blockIdx.x);
+  if (a.skip && *a.skip) return;
   extern __shared__ double2 M[];
   __shared__ double red[32];
   __shared__ double sh_thresh;
@@ -361,8 +363,35 @@ size_t chol_work_doubles(int k) {
 }
 
 // trace -> log-scale / scale, diagonal shift, pivot threshold (one workgroup per instance)
+// A re-orthogonalisation pass (no shift) of the blocked factorisation whose Gram is the identity to
+// rounding (the criterion of the LDS kernel): C^{-1} = I is written and `flag` set, so that the
+// blocked steps after it do nothing; otherwise `flag` is cleared. One workgroup per instance.
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_ident(CholArgs a0, int* flag) {
+  const CholArgs a = chol_inst(a0, blockIdx.x);
+  flag = inst_ptr(flag, a0.bs, blockIdx.x);
+  __shared__ double red[32];
+  const int k = a.k, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwave = blockDim.x >> 6;
+  double dev = 0.0;
+  for (int i = tid; i < k * k; i += blockDim.x) {
+    const int r = i / k, c = i % k;
+    const double2 g = a.G[(size_t)r * k + c];
+    dev = fmax(dev, fmax(fabs(g.x - (r == c ? 1.0 : 0.0)), fabs(g.y)));
+  }
+  dev = wmax(dev);
+  if (lane == 0) red[wave] = dev;
+  __syncthreads();
+  double m = 0.0;
+  for (int w = 0; w < nwave; ++w) m = fmax(m, red[w]);
+  const bool ident = m <= 4.0 * k * DBL_EPSILON * 0.5;   // NaN entries fail the test
+  if (ident)
+    for (int idx = tid; idx < k * k; idx += blockDim.x)
+      a.Cinv[idx] = make_double2(idx / k == idx % k ? 1.0 : 0.0, 0.0);
+  if (tid == 0) *flag = ident ? 1 : 0;
+}
+
 __global__ __launch_bounds__(CHOL_THREADS) void k_chol_prep(CholArgs a0, double* thresh_out) {
   const CholArgs a = chol_inst(a0, blockIdx.x);
+  if (a.skip && *a.skip) return;
   thresh_out = inst_ptr(thresh_out, a0.bs, blockIdx.x);
   __shared__ double red[32];
   __shared__ double sh_trace;
@@ -425,6 +454,8 @@ static hipError_t dense_gemm(const CholArgs& a, int M, int N, int K, const doubl
   g.bsA = g.bsB = g.bsC = a.bs;
   g.bsAlpha = g.bsAlpha2 = 0;
   g.accum = accum;
+  g.skip = a.skip;
+  g.bsSkip = a.bs;
   return launch_gemm(g, DT_C128, DT_C128, DT_C128, DT_C128, GEMM_TILE32, st);
 }
 
@@ -444,17 +475,26 @@ hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st) {
   double2* Cf = a.work;                                      // k x k factor panels
   double2* T = a.work + (size_t)k * k;                       // CHOL_NB x k
   double* thr = reinterpret_cast<double*>(T + (size_t)CHOL_NB * k);
-  hipLaunchKernelGGL(k_chol_prep, dim3(a.batch), dim3(CHOL_THREADS), 0, st, a, thr);
-  hipError_t e = hipGetLastError();
+  int* flag = reinterpret_cast<int*>(thr + 1);
+  hipError_t e = launch_zero(X, (int64_t)16 * k * k, a.batch, a.bs, st);
   if (e != hipSuccess) return e;
-  e = launch_zero(X, (int64_t)16 * k * k, a.batch, a.bs, st);
+  CholArgs b = a;
+  if (a.shift_rel == 0.0 && !a.thresh_dev) {
+    // a re-orthogonalisation pass: the identity shortcut, and every later step skips where it holds
+    hipLaunchKernelGGL(k_chol_ident, dim3(a.batch), dim3(CHOL_THREADS), 0, st, a, flag);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    b.skip = flag;
+  }
+  hipLaunchKernelGGL(k_chol_prep, dim3(b.batch), dim3(CHOL_THREADS), 0, st, b, thr);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t lds = chol_lds_bytes(CHOL_NB);
   (void)hipFuncSetAttribute((const void*)k_chol_inv_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
   for (int o = 0; o < k; o += CHOL_NB) {
     const int bp = k - o < CHOL_NB ? k - o : CHOL_NB;
-    CholArgs d = a;
+    CholArgs d = b;
     d.G = G + (size_t)o * k + o;
     d.Cinv = X + (size_t)o * k + o;
     d.k = bp;
@@ -470,20 +510,20 @@ hipError_t launch_chol_inv(const CholArgs& a, hipStream_t st) {
     const int r0 = o + bp, rows = k - r0;
     if (rows <= 0) break;
     // panel: Cf[r, c] = sum_l G[r, l] conj(X_pp[c, l])
-    e = dense_gemm(a, rows, bp, bp, G + (size_t)r0 * k + o, k, 1, X + (size_t)o * k + o, 1, k, 1,
+    e = dense_gemm(b, rows, bp, bp, G + (size_t)r0 * k + o, k, 1, X + (size_t)o * k + o, 1, k, 1,
                    Cf + (size_t)r0 * k + o, k, 1, 1.0, 0, st);
     if (e != hipSuccess) return e;
     // trailing: G[r, r'] -= sum_c Cf[r, c] conj(Cf[r', c])
-    e = dense_gemm(a, rows, rows, bp, Cf + (size_t)r0 * k + o, k, 1, Cf + (size_t)r0 * k + o, 1, k, 1,
+    e = dense_gemm(b, rows, rows, bp, Cf + (size_t)r0 * k + o, k, 1, Cf + (size_t)r0 * k + o, 1, k, 1,
                    G + (size_t)r0 * k + r0, k, 1, -1.0, 1, st);
     if (e != hipSuccess) return e;
   }
   // inverse, block rows i >= 1: T = Cf[i, <i] X[<i, <i]; X[i, <i] = -X_ii T
   for (int oi = CHOL_NB; oi < k; oi += CHOL_NB) {
     const int bi = k - oi < CHOL_NB ? k - oi : CHOL_NB;
-    e = dense_gemm(a, bi, oi, oi, Cf + (size_t)oi * k, k, 1, X, k, 1, 0, T, k, 1, 1.0, 0, st);
+    e = dense_gemm(b, bi, oi, oi, Cf + (size_t)oi * k, k, 1, X, k, 1, 0, T, k, 1, 1.0, 0, st);
     if (e != hipSuccess) return e;
-    e = dense_gemm(a, bi, oi, bi, X + (size_t)oi * k + oi, k, 1, T, k, 1, 0, X + (size_t)oi * k, k, 1,
+    e = dense_gemm(b, bi, oi, bi, X + (size_t)oi * k + oi, k, 1, T, k, 1, 0, X + (size_t)oi * k, k, 1,
                    -1.0, 0, st);
     if (e != hipSuccess) return e;
   }

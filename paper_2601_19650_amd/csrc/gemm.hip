@@ -60,6 +60,7 @@ __global__ __launch_bounds__(256) void k_cgemm(GemmArgs g) {
   const int K = g.ksplit > 1 ? min(g.K, kbeg + g.kchunk) : g.K;
   // a Hermitian product computes the tiles on and below the diagonal only (BM == BN)
   if (g.herm && n0 >= m0 + BM) return;
+  if (g.skip && *inst_ptr(g.skip, g.bsSkip, bz)) return;
   const CA* __restrict__ A = reinterpret_cast<const CA*>(inst_ptr(g.A, g.bsA, bz));
   const CB* __restrict__ B = reinterpret_cast<const CB*>(inst_ptr(g.B, g.bsB, bz));
   const ACC sa = g.conjA ? ACC(-1) : ACC(1);
@@ -202,6 +203,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t mn = (int64_t)g.M * g.N;
   if (idx >= mn) return;
+  if (g.skip && *inst_ptr(g.skip, g.bsSkip, b)) return;
   const int m = (int)(idx / g.N), n = (int)(idx % g.N);
   // a Hermitian product has chunk sums on and below the diagonal only: (m, n) above it is the
   // conjugate of (n, m)
@@ -264,6 +266,7 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
   if (g.herm && n0 >= m0 + BM) return;   // strictly above the diagonal (BM == BN)
   const int M = g.M, N = g.N;
   const int bz = blockIdx.z / g.ksplit, kz = blockIdx.z % g.ksplit;
+  if (g.skip && *inst_ptr(g.skip, g.bsSkip, bz)) return;
   const int kbeg = g.ksplit > 1 ? kz * g.kchunk : 0;
   const int K = g.ksplit > 1 ? min(g.K, kbeg + g.kchunk) : g.K;
   const CA* __restrict__ A = reinterpret_cast<const CA*>(inst_ptr(g.A, g.bsA, bz));

@@ -218,13 +218,14 @@ def test_chol_inv(lib, k):
     assert np.abs(np.triu(Ci, 1)).max() == 0.0
 
 
+@pytest.mark.parametrize("k", [64, 200])
 @pytest.mark.parametrize("eps", [1e-16, 1e-9])
-def test_chol_inv_near_identity(lib, eps):
+def test_chol_inv_near_identity(lib, eps, k):
     """A re-orthogonalisation pass (no shift) on a Gram within rounding of the identity returns the
     identity; a larger deviation is factorised as usual. Both are the inverse Cholesky factor to
-    rounding."""
+    rounding. k = 200 takes the blocked factorisation, whose steps all stand down after the
+    identity check."""
     rng = np.random.default_rng(5)
-    k = 64
     e = crand(rng, k, k) * eps
     g = np.eye(k) + (e + e.conj().T) / 2
     Ci, nd = lib.test_chol_inv(torch.from_numpy(g).cuda())
