@@ -17,8 +17,9 @@ extern "C" {
 /* C (M x N) = op(A) op(B), op(X) = X, X^T, conj(X) or X^H by (trans, conj). A is stored M x K (or
  * K x M if transA), B is K x N (or N x K if transB). acc_fp64 selects FP64 MFMA accumulation,
  * otherwise FP32 MFMA. tile: -1 = the compression's policy (tile by shape, split reduction where it
- * would split), 0 = 32x32, 1 = 64x64, 2 = pipelined 64x64 (FP32 accumulation only; FP64 falls back
- * to 1); other values are rejected. This is the contraction kernel of every sweep. */
+ * would split), 0 = 32x32, 1 = 64x64, 2 = pipelined 64x64, 3 = pipelined 128x128 on eight waves
+ * (FP32 accumulation; FP64 takes 2); other values are rejected. This is the contraction kernel of
+ * every sweep. */
 int cbc_test_gemm(int M, int N, int K, const void* A, int a_c128, int transA, int conjA,
                   const void* B, int b_c128, int transB, int conjB, void* C, int c_c128,
                   int acc_fp64, int tile, void* stream);

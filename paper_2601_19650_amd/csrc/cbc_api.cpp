@@ -2012,8 +2012,9 @@ std::vector<int64_t> tune_key(const Op& op, int batch) {
 std::vector<std::pair<int, int>> tune_candidates(const Op& op, int batch) {
   std::vector<std::pair<int, int>> cand;
   const bool f64 = op.acc == DT_C128;
-  for (int tile : {GEMM_TILE32, GEMM_TILE64, GEMM_PIPE64}) {
-    if (tile == GEMM_PIPE64 && f64) continue;
+  for (int tile : {GEMM_TILE32, GEMM_TILE64, GEMM_PIPE64, GEMM_PIPE128}) {
+    if ((tile == GEMM_PIPE64 || tile == GEMM_PIPE128) && f64) continue;
+    if (tile == GEMM_PIPE128 && (op.M < 128 || op.N < 128)) continue;
     for (int ks = 1; ks <= TUNE_KS; ks *= 2) {
       if (ks > 1 && (tile == GEMM_TILE64 || ks > op.kcap)) continue;
       const int kchunk = ((op.K + ks - 1) / ks + 15) / 16 * 16;
@@ -2171,7 +2172,8 @@ cbc_status cbc_autotune(cbc_ctx* ctx, const char* cache_path) {
     bool ok = std::strcmp(tag, "cbc-gemm") == 0;
     for (int i = 0; ok && i < 10; ++i) ok = std::fscanf(f, "%lld", &v[i]) == 1;
     ok = ok && std::fscanf(f, "%d %d %lf", &tile, &ks, &ms) == 3;
-    ok = ok && (tile == GEMM_TILE32 || tile == GEMM_TILE64 || tile == GEMM_PIPE64) &&
+    ok = ok && (tile == GEMM_TILE32 || tile == GEMM_TILE64 || tile == GEMM_PIPE64 ||
+                tile == GEMM_PIPE128) &&
          (ks == 1 || ks == 2 || ks == 4 || ks == 8);
     if (ok) ctx->tuned[std::vector<int64_t>(v, v + 10)] = {tile, ks};
     int ch;

@@ -63,10 +63,10 @@ __host__ __device__ inline T* inst_ptr(T* p, int64_t stride, int b) {
            : p;
 }
 
-// Tile configurations of the contraction GEMM: table-driven 32x32 / 64x64 tiles, or (FP32
-// accumulation only) the pipelined kernel with 64x64 tiles; GEMM_AUTO picks by shape. Split-K
-// works with the 32x32 and the pipelined tiles.
-enum GemmTile : int { GEMM_AUTO = -1, GEMM_TILE32 = 0, GEMM_TILE64 = 1, GEMM_PIPE64 = 2 };
+// Tile configurations of the contraction GEMM: table-driven 32x32 / 64x64 tiles, the pipelined
+// kernel with 64x64 tiles, or (FP32 accumulation only) the pipelined kernel with 128x128 tiles on
+// eight waves; GEMM_AUTO picks by shape. Split-K works with the 32x32 and the pipelined tiles.
+enum GemmTile : int { GEMM_AUTO = -1, GEMM_TILE32 = 0, GEMM_TILE64 = 1, GEMM_PIPE64 = 2, GEMM_PIPE128 = 3 };
 int gemm_pick_tile(int M, int N, int K, int batch, bool fp64_acc);
 // number of K chunks for a launch with too few output tiles for its tile size (1: no split)
 int gemm_pick_ksplit(int M, int N, int K, int batch, int tile);

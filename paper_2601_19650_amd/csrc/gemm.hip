@@ -239,14 +239,17 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
 // memory into registers while the MFMAs consume the current one from LDS, and the LDS tiles are
 // double-buffered so each k-tile costs one barrier. A Hermitian product (g.herm) computes the tiles
 // on and below the diagonal and writes each strictly lower entry also, conjugated, at its mirror.
-template <typename TA, typename TB, typename TC, typename ACC, int BM, int BN>
+template <typename TA, typename TB, typename TC, typename ACC, int BM, int BN, int WGM = 2,
+          int WGN = 2>
 __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
   constexpr bool F64 = sizeof(ACC) == 8;
-  constexpr int BK = F64 ? 8 : 16;
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int NT = 64 * WGM * WGN;                       // threads: a WGM x WGN grid of waves
+  constexpr int BK = (F64 || BM * BN > 64 * 64) ? 8 : 16;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int MB = WM / 16, NB = WN / 16;
   constexpr int PAD = F64 ? 1 : 4;
-  constexpr int EA = BM * BK / 256, EB = BN * BK / 256;   // elements per thread and k-tile
+  constexpr int EA = BM * BK / NT, EB = BN * BK / NT;     // elements per thread and k-tile
+  static_assert(EA * NT == BM * BK && EB * NT == BN * BK, "tile loads must divide evenly");
   using CA = typename Cplx<TA>::type;
   using CB = typename Cplx<TB>::type;
   using CC = typename Cplx<TC>::type;
@@ -260,7 +263,7 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WGN, wc = wave % WGN;
   const int m0 = g.mbase + blockIdx.y * BM;
   const int n0 = blockIdx.x * BN;
   if (g.herm && n0 >= m0 + BM) return;   // strictly above the diagonal (BM == BN)
@@ -276,10 +279,10 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
   const bool akf = g.a_kfast, bkf = g.b_kfast;
 
   // this thread's load slots: element u of a k-tile is (row ra(u), k ka(u)) of A, (k kb(u), col cb(u)) of B
-  auto ra = [&](int u) { return akf ? tid / BK + (256 / BK) * u : tid % BM; };
-  auto ka = [&](int u) { return akf ? tid % BK : tid / BM + (256 / BM) * u; };
-  auto cb = [&](int u) { return bkf ? tid / BK + (256 / BK) * u : tid % BN; };
-  auto kb = [&](int u) { return bkf ? tid % BK : tid / BN + (256 / BN) * u; };
+  auto ra = [&](int u) { return akf ? tid / BK + (NT / BK) * u : tid % BM; };
+  auto ka = [&](int u) { return akf ? tid % BK : tid / BM + (NT / BM) * u; };
+  auto cb = [&](int u) { return bkf ? tid / BK + (NT / BK) * u : tid % BN; };
+  auto kb = [&](int u) { return bkf ? tid % BK : tid / BN + (NT / BN) * u; };
   int offm[EA], offn[EB];
 #pragma unroll
   for (int u = 0; u < EA; ++u) {
@@ -293,17 +296,28 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
   }
   CA ra_v[EA];
   CB rb_v[EB];
-  auto fetch = [&](int k0) {
+  // the k offsets of a k-tile are read one tile ahead of its data (fetch_k), so that a data fetch
+  // does not wait for its table lookup; -1 marks k >= K
+  int koA[EA], koB[EB];
+  auto fetch_k = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < EA; ++u) {
       const int k = k0 + ka(u);
-      ra_v[u] = (offm[u] >= 0 && k < K) ? A[(int64_t)offm[u] + g.offAk[k]] : CA{0, 0};
+      koA[u] = k < K ? g.offAk[k] : -1;
     }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const int k = k0 + kb(u);
-      rb_v[u] = (offn[u] >= 0 && k < K) ? B[(int64_t)g.offBk[k] + offn[u]] : CB{0, 0};
+      koB[u] = k < K ? g.offBk[k] : -1;
     }
+  };
+  auto fetch = [&]() {
+#pragma unroll
+    for (int u = 0; u < EA; ++u)
+      ra_v[u] = (offm[u] >= 0 && koA[u] >= 0) ? A[(int64_t)offm[u] + koA[u]] : CA{0, 0};
+#pragma unroll
+    for (int u = 0; u < EB; ++u)
+      rb_v[u] = (offn[u] >= 0 && koB[u] >= 0) ? B[(int64_t)koB[u] + offn[u]] : CB{0, 0};
   };
   auto stash = [&](int buf) {
 #pragma unroll
@@ -327,13 +341,18 @@ __device__ __forceinline__ void cgemm_pipe_body(const GemmArgs& g) {
       acci[i][j] = V4{0, 0, 0, 0};
     }
 
-  fetch(kbeg);
+  fetch_k(kbeg);
+  fetch();
   stash(0);
+  fetch_k(kbeg + BK);
   __syncthreads();
   int buf = 0;
   for (int k0 = kbeg; k0 < K; k0 += BK) {
     const bool more = k0 + BK < K;
-    if (more) fetch(k0 + BK);
+    if (more) {
+      fetch();                  // tile k0 + BK, offsets read during the previous tile
+      fetch_k(k0 + 2 * BK);     // offsets of the tile after it
+    }
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4);
@@ -431,6 +450,12 @@ template <typename TA, typename TB, typename TC, typename ACC, int BM, int BN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_cgemm_pipe4(GemmArgs g) {
   cgemm_pipe_body<TA, TB, TC, ACC, BM, BN>(g);
 }
+// 128 x 128 tiles on eight waves (2 x 4, each 64 x 32), k-tiles of 8: a quarter of the 64 x 64
+// tile's operand traffic per product, for the largest FP32 contractions
+template <typename TA, typename TB, typename TC, typename ACC>
+__global__ __launch_bounds__(512) void k_cgemm_pipe128(GemmArgs g) {
+  cgemm_pipe_body<TA, TB, TC, ACC, 128, 128, 2, 4>(g);
+}
 
 // Tile choice by shape (measured on MI355X): with FP32 accumulation the pipelined 64x64 kernel
 // whenever there are at least 64 such output tiles (split along K below 512 tiles, see
@@ -464,16 +489,19 @@ template <typename TA, typename TB, typename TC, typename ACC>
 static hipError_t launch_t(const GemmArgs& a0, int tile, hipStream_t s) {
   if (a0.M <= 0 || a0.N <= 0 || a0.batch <= 0) return hipSuccess;
   if (tile == GEMM_AUTO) tile = gemm_pick_tile(a0.M, a0.N, a0.K, a0.batch, sizeof(ACC) == 8);
-  if (tile != GEMM_TILE32 && tile != GEMM_TILE64 && tile != GEMM_PIPE64) return hipErrorInvalidValue;
-  // the pipelined kernel: offset tables, no accumulation into C
-  if (tile == GEMM_PIPE64 && (!a0.offAm || a0.accum)) tile = GEMM_TILE64;
+  if (tile != GEMM_TILE32 && tile != GEMM_TILE64 && tile != GEMM_PIPE64 && tile != GEMM_PIPE128)
+    return hipErrorInvalidValue;
+  // the pipelined kernels: offset tables, no accumulation into C; 128 x 128 tiles with FP32
+  // accumulation only
+  if (tile == GEMM_PIPE128 && sizeof(ACC) == 8) tile = GEMM_PIPE64;
+  if ((tile == GEMM_PIPE64 || tile == GEMM_PIPE128) && (!a0.offAm || a0.accum)) tile = GEMM_TILE64;
   if (a0.herm && (a0.M != a0.N || a0.accum)) return hipErrorInvalidValue;
   const bool split = a0.ksplit > 1;
   if (split && (tile == GEMM_TILE64 || !a0.part || a0.kchunk % 16 != 0 ||
                 (int64_t)a0.kchunk * a0.ksplit < a0.K))
     return hipErrorInvalidValue;
   if ((int64_t)a0.batch * a0.ksplit > 65535) return hipErrorInvalidValue;
-  const int BMt = tile == GEMM_TILE32 ? 32 : 64;
+  const int BMt = tile == GEMM_TILE32 ? 32 : tile == GEMM_PIPE128 ? 128 : 64;
   const int max_rows = 65535 * BMt;   // grid y limit per launch
   if (split && a0.M > max_rows) return hipErrorInvalidValue;
   for (int mb = 0; mb < a0.M; mb += max_rows) {
@@ -481,7 +509,10 @@ static hipError_t launch_t(const GemmArgs& a0, int tile, hipStream_t s) {
     a.mbase = mb;
     const int rows = a0.M - mb < max_rows ? a0.M - mb : max_rows;
     const dim3 grid((a.N + BMt - 1) / BMt, (rows + BMt - 1) / BMt, a.batch * a.ksplit);
-    if (tile == GEMM_PIPE64) {
+    if (tile == GEMM_PIPE128) {
+      if constexpr (sizeof(ACC) == 4)
+        hipLaunchKernelGGL((k_cgemm_pipe128<TA, TB, TC, ACC>), grid, dim3(512), 0, s, a);
+    } else if (tile == GEMM_PIPE64) {
       if constexpr (sizeof(TA) == 4 && sizeof(TB) == 4 && sizeof(ACC) == 4)
         hipLaunchKernelGGL((k_cgemm_pipe4<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
       else

@@ -27,10 +27,11 @@ def test_gemm_fp64(lib, M, N, K, tile):
 
 @pytest.mark.parametrize("tA,cA,tB,cB", [(1, 1, 0, 0), (0, 0, 1, 1), (1, 0, 1, 0), (0, 1, 0, 1)])
 @pytest.mark.parametrize("M,N,K,tile", [(45, 33, 70, 0), (200, 150, 70, 2), (1700, 2100, 37, 1),
-                                        (1700, 2100, 37, -1)])
+                                        (1700, 2100, 37, -1), (300, 270, 45, 3)])
 def test_gemm_transpose_conj(lib, tA, cA, tB, cB, M, N, K, tile):
     """Every operand layout (k fastest or not) through both tile sizes of the table-driven kernel
-    and the pipelined FP32 kernel (FP64 accumulation falls back to the table-driven 64 x 64 tiles)."""
+    and the pipelined kernels (64 x 64 with either accumulation; 128 x 128 with FP32, whose FP64
+    requests take the 64 x 64 pipeline)."""
     rng = np.random.default_rng(7)
     a = crand(rng, K, M) if tA else crand(rng, M, K)
     b = crand(rng, N, K) if tB else crand(rng, K, N)
@@ -48,7 +49,7 @@ def test_gemm_transpose_conj(lib, tA, cA, tB, cB, M, N, K, tile):
         assert np.abs(C - ref).max() <= tol * np.sqrt(K) * 4, (acc, np.abs(C - ref).max())
 
 
-@pytest.mark.parametrize("tile", [-1, 0, 1, 2])
+@pytest.mark.parametrize("tile", [-1, 0, 1, 2, 3])
 @pytest.mark.parametrize("M,N,K", [(32, 32, 16), (100, 200, 300), (257, 65, 64), (64, 64, 16),
                                    (2049, 1793, 100), (4096, 1024, 256)])
 def test_gemm_fp32(lib, M, N, K, tile):
