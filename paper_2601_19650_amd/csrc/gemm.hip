@@ -519,6 +519,10 @@ static hipError_t launch_t(const GemmArgs& a0, int tile, hipStream_t s) {
         hipLaunchKernelGGL((k_cgemm_pipe<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
     } else if (tile == GEMM_TILE64)
       hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 64, 64>), grid, dim3(256), 0, s, a);
+    else if (a.offAm && !a.accum)
+      // 32 x 32 tiles from offset tables: the pipelined body (same products in the same order,
+      // the next k-tile fetched while the current one is consumed)
+      hipLaunchKernelGGL((k_cgemm_pipe<TA, TB, TC, ACC, 32, 32>), grid, dim3(256), 0, s, a);
     else
       hipLaunchKernelGGL((k_cgemm<TA, TB, TC, ACC, 32, 32>), grid, dim3(256), 0, s, a);
     const hipError_t e = hipGetLastError();
