@@ -53,10 +53,20 @@ def measure(cbc, p, precs, steps, warmup, stream):
     op, oo = cbc.pack(p.op, "cuda:0")
     ctx = new_context(cbc)
     res, outputs = {}, {}
+    run_args = (op, oo, st, so, 0.0)
+    comps = {prec: cbc.Compressor(ctx, tree, p.max_bond, prec, device="cuda:0") for prec in precs}
     for prec in precs:
-        comp = cbc.Compressor(ctx, tree, p.max_bond, prec, device="cuda:0")
-        run_args = (op, oo, st, so, 0.0)
-        sec = timed_runs(comp, run_args, stream, steps, warmup)
+        timed_runs(comps[prec], run_args, stream, 0, warmup)
+    # the forms' timed calls alternate, each between device synchronisations, so that a drift of
+    # the device's speed during the run (the eigensolve's grid barrier varies by several per cent)
+    # falls on every form alike
+    total = {prec: 0.0 for prec in precs}
+    for _ in range(steps):
+        for prec in precs:
+            total[prec] += timed_runs(comps[prec], run_args, stream, 1, 0)
+    for prec in precs:
+        comp = comps[prec]
+        sec = total[prec] / steps
         replayed = int(comp.stats.graph_replayed)
         outputs[prec] = comp.unpack()
         kms = profiled_runs(comp, run_args, stream, max(2, min(steps, 10)))
@@ -65,7 +75,7 @@ def measure(cbc, p, precs, steps, warmup, stream):
                          n_kernels=int(comp.stats.n_kernels))
         print(f"[bench] {p.name} {prec}: {sec * 1e3:.3f} ms/compression, kernels/call "
               f"{comp.stats.n_kernels}, graph replay {replayed}", file=sys.stderr, flush=True)
-        del comp
+    del comps
     return res, outputs
 
 
@@ -433,7 +443,7 @@ def timed_runs(comp, args_run, stream, steps, warmup, **kw):
             comp.run(*args_run, stream=stream.cuda_stream, **kw)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return (t1 - t0) / steps
+    return (t1 - t0) / steps if steps > 0 else 0.0
 
 
 def profiled_runs(comp, args_run, stream, steps, **kw):

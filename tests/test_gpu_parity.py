@@ -129,6 +129,15 @@ def test_c4_reduced_parity(lib, c4_small, prec):
     assert comp.stats.max_eig_dim == 1024
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c4_reduced_autotuned_parity(lib, c4_small, prec):
+    """The large-bond shape with autotuned contractions, as the benchmark runs it: its 4096 x 1024
+    and 1024 x 4096 contractions are where the tuner takes the 128 x 128 pipelined tiles and the
+    split pipelined products. Parity with the oracle at the same bars."""
+    p, ref = c4_small
+    check(lib, p, prec, oracle_out=ref, ctx=lib.Context().autotune())
+
+
 @pytest.fixture(scope="module")
 def c4_24():
     """The large-bond shape on 24 sites, the longest chain at which the oracle's own output stays
