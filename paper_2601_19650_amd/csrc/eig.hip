@@ -452,12 +452,15 @@ __device__ __forceinline__ double2 cload(const double2* p) {
   return v;
 }
 
-// Barrier number `it`. sync[q] = last barrier workgroup q reached; sync[MW_MAX_WG] = time-out flag;
-// sync[MW_MAX_WG + 1] = last barrier released by workgroup 0. Up to MW_GATHER_MIN workgroups every
-// workgroup polls all arrival flags; above it (where polling traffic grows with the square of the
-// count) workgroup 0 gathers the flags and releases the others through one word (measured on
-// MI355X: 7.1 -> 4.4 us per barrier at 147 workgroups).
+// Barrier number `it`; sync[MW_MAX_WG] = time-out flag. Below MW_GATHER_MIN workgroups sync[q] is
+// the last barrier workgroup q reached and every workgroup polls all flags. From MW_GATHER_MIN on
+// (where that polling traffic grows with the square of the count) workgroup q adds one to the
+// arrival counter of its group q mod 8, sync[(q mod 8) * MW_CTR_STRIDE] (eight counters on lines of
+// their own, so that the additions spread), and every workgroup polls the eight counters, one per
+// lane, until each holds `it` times its group's workgroup count.
 static constexpr int MW_GATHER_MIN = 64;
+static constexpr int MW_CTR_STRIDE = 32;   // words: one 128-byte line per counter
+static_assert(8 * MW_CTR_STRIDE <= MW_MAX_WG, "the counters share the per-workgroup flag words");
 
 __device__ bool mw_sync(unsigned* sync, int nwg, unsigned it, int* ok_sh, long long timeout) {
   // every wave's exchanged-data stores have completed before the workgroup publishes its arrival
@@ -466,44 +469,37 @@ __device__ bool mw_sync(unsigned* sync, int nwg, unsigned it, int* ok_sh, long l
   __syncthreads();
   const int tid = threadIdx.x;
   if (tid < 64) {
-    if (tid == 0)
-      __hip_atomic_store(&sync[blockIdx.x], it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool count = nwg >= MW_GATHER_MIN;
+    if (tid == 0) {
+      if (count)
+        __hip_atomic_fetch_add(&sync[(blockIdx.x & 7) * MW_CTR_STRIDE], 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      else
+        __hip_atomic_store(&sync[blockIdx.x], it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     int ok = 1;
     const long long t0 = wall_clock64();
-    const bool gather = nwg >= MW_GATHER_MIN;
-    auto failed = [&]() {
+    // arrivals group `tid` must have counted (count mode, lanes 0..7; every group is non-empty)
+    const unsigned need = tid < 8 ? it * (unsigned)((nwg - tid + 7) / 8) : 0u;
+    for (;;) {
+      int done = 1;
+      if (count) {
+        if (tid < 8)
+          done = __hip_atomic_load(&sync[tid * MW_CTR_STRIDE], __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT) >= need;
+      } else {
+        for (int q = tid; q < nwg; q += 64)
+          done &= __hip_atomic_load(&sync[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= it;
+      }
+      if (__all(done)) break;
       const int err =
           __hip_atomic_load(&sync[MW_MAX_WG], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
       if (__any(err) || timeout < 0 || wall_clock64() - t0 > timeout) {
         if (tid == 0) __hip_atomic_store(&sync[MW_MAX_WG], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return true;
+        ok = 0;
+        break;
       }
-      return false;
-    };
-    if (!gather || blockIdx.x == 0) {
-      for (;;) {
-        int done = 1;
-        for (int q = tid; q < nwg; q += 64)
-          done &= __hip_atomic_load(&sync[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= it;
-        if (__all(done)) break;
-        if (failed()) {
-          ok = 0;
-          break;
-        }
-        if (!gather) __builtin_amdgcn_s_sleep(1);
-      }
-      if (gather && ok && tid == 0)
-        __hip_atomic_store(&sync[MW_MAX_WG + 1], it, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      for (;;) {
-        if (__hip_atomic_load(&sync[MW_MAX_WG + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= it)
-          break;
-        if (failed()) {
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
+      __builtin_amdgcn_s_sleep(1);
     }
     if (tid == 0) *ok_sh = ok;
   }

@@ -86,7 +86,7 @@ struct EigWork {
   double2* prow;  // 2 * s       next pivot row, published by its owner
   // blocked back-transformation: the triangular factor of each block of BT_NB reflectors
   double2* tfac;  // bt_blocks(s) * BT_NB * BT_NB
-  unsigned* sync; // MW_MAX_WG + 16 words: last barrier reached per workgroup, then a time-out flag
+  unsigned* sync; // MW_MAX_WG + 16 words: barrier flags or arrival counters, then a time-out flag
 };
 static constexpr int BT_NB = 32;   // reflectors per block of the blocked back-transformation
 __host__ __device__ inline int bt_blocks(int s) { return s > 1 ? (s - 1 + BT_NB - 1) / BT_NB : 0; }
