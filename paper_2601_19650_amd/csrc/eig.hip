@@ -13,8 +13,8 @@
 //      w^H v and w' are formed once by wave 0 (sums in a fixed order: bitwise reproducible); while
 //      15 waves apply the rank-2 update (again 8 lanes per row), wave 0 updates the next column
 //      itself and forms its reflector (look-ahead), so a column costs two workgroup barriers.
-//      Larger s use k_tridiag_mw: the rows are spread over many workgroups and every column costs
-//      one grid-wide barrier.
+//      Larger s use k_tridiag_mw: the rows are spread over many workgroups (held in registers)
+//      and every column costs one grid-wide barrier.
 //   2. k_eigvals, one wave per eigenvalue over many workgroups: multisection on Sturm counts (64
 //      points of the current interval per round).
 //   3. eigenvectors of T by a twisted factorisation T - lambda I = N_r Delta N_r^T, one wave per
@@ -326,24 +326,30 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
 // status word receives CBC_ETIMEOUT.
 static constexpr int MW_THREADS = 512;
 static constexpr int MW_WAVES = MW_THREADS / 64;
-static constexpr int MW_EPT = 4;                    // columns per thread, at most: s <= 2048
+static constexpr int MW_EPT = 3;                    // columns per thread, at most: s <= 1536
 static constexpr int MW_ROWS_MAX = 16;              // rows per workgroup (per-row reduction slots)
-static constexpr size_t MW_LDS_BUDGET = 160 * 1024 - 8192;   // the kernel's static LDS is below 8 KiB
+// The rows a workgroup owns live in its threads' registers, EPT entries of each row per thread. The
+// cap on a workgroup's row bytes below keeps that share at 21 complex entries per thread at most.
+static constexpr size_t MW_ROW_BUDGET = 152 * 1024;
+// rows per workgroup of the instantiated kernels, at most, by columns per thread
+__host__ __device__ constexpr int mw_rows_max(int ept) {
+  return ept == 1 ? 3 : ept == 2 ? 5 : ept == 3 ? 7 : 0;
+}
 
 static constexpr int MW_TARGET_WG = 208;            // workgroups aimed at (see mw_shape)
 
 struct MwShape {
   int nwg, rows;
 };
-// Rows per workgroup: as few as keep the workgroup count near MW_TARGET_WG, and no more than fit in
-// LDS. Fewer rows shorten the per-column update and product pass of every workgroup, more
+// Rows per workgroup: as few as keep the workgroup count near MW_TARGET_WG, and no more than the
+// row budget. Fewer rows shorten the per-column update and product pass of every workgroup, more
 // workgroups lengthen the grid barrier; measured on MI355X at s = 1024 (per column: update,
 // barrier): 9 rows / 114 workgroups 4.26 + 2.45 us, 6 / 171 2.94 + 2.65, 5 / 205 2.49 + 2.86,
 // 4 / 256 2.04 + 3.70. Per solve, against the former rule (as many rows as fit in LDS, at least
 // one workgroup per 16 rows): s = 256 2.45 -> 1.66 ms, 420 4.44 -> 3.2, 700 8.3 -> 5.9, 1024
 // 12.0 -> 10.7 (targets of 128 and 256 workgroups were slower above s = 420).
 __host__ __device__ inline MwShape mw_shape(int s) {
-  int fit = (int)(MW_LDS_BUDGET / (16 * (size_t)s));
+  int fit = (int)(MW_ROW_BUDGET / (16 * (size_t)s));
   if (fit > MW_ROWS_MAX) fit = MW_ROWS_MAX;
   if (fit < 1) fit = 1;
   int rows = (s + MW_TARGET_WG - 1) / MW_TARGET_WG;
@@ -353,14 +359,15 @@ __host__ __device__ inline MwShape mw_shape(int s) {
   m.rows = (s + m.nwg - 1) / m.nwg;
   return m;
 }
-size_t mw_lds_bytes(int s) { return (size_t)mw_shape(s).rows * s * 16; }
+static size_t mw_row_bytes(int s) { return (size_t)mw_shape(s).rows * s * 16; }
 
 // the two-stage path: panels of up to 2048 rows (two per thread of the panel kernel)
 static constexpr int EIG_MAX_S = 2048 + 16;
 bool eig_size_supported(int s) { return s >= 1 && s <= EIG_MAX_S; }
 static bool mw_size_supported(int s) {
   return s > EIG_LDS_MAX && s <= MW_EPT * MW_THREADS && mw_shape(s).nwg <= MW_MAX_WG &&
-         mw_lds_bytes(s) <= MW_LDS_BUDGET;
+         mw_row_bytes(s) <= MW_ROW_BUDGET &&
+         mw_shape(s).rows <= mw_rows_max((s + MW_THREADS - 1) / MW_THREADS);
 }
 // The one-stage multi-workgroup reduction is the faster one where it applies (measured on MI355X,
 // s = 1024: 11.5 ms against 28 ms for the two-stage path, per solve), but its workgroups wait for
@@ -525,15 +532,13 @@ __device__ __forceinline__ double2 sum_red(const double2* red) {
   return t;
 }
 
-template <int EPT>   // columns per thread: s <= EPT * MW_THREADS
+template <int EPT, int R>   // columns per thread (s <= EPT * MW_THREADS), rows per workgroup at most
 __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) {
   const EigArgs a = eig_inst(a0, blockIdx.y);
   const int wg = blockIdx.x;
   const int s = a.s;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nr = wg < s ? (s - wg + nwg - 1) / nwg : 0;   // rows owned: wg, wg + nwg, ...
-  extern __shared__ double smem[];
-  double2* Ar = reinterpret_cast<double2*>(smem);   // nr x s
   __shared__ double2 red_c[MW_WAVES], red_n[MW_WAVES];
   __shared__ double2 racc[MW_ROWS_MAX][MW_WAVES];
   __shared__ double2 rv[MW_ROWS_MAX], ry[MW_ROWS_MAX];   // v_j and y at the owned rows' indices
@@ -542,9 +547,15 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
   EigWork W = eig_layout(a.work, s, a.kmax);
   const bool writer = wg == 0;
   if (a.tstamp && writer && tid == 0) a.tstamp[0] = wall_clock64();
-  for (int q = 0; q < nr; ++q) {
-    const double2* src = a.G + (size_t)(wg + (size_t)q * nwg) * s;
-    for (int c = tid; c < s; c += MW_THREADS) Ar[(size_t)q * s + c] = src[c];
+  // the owned rows, in registers: Ar[q][e] is row wg + q nwg at column tid + e MW_THREADS
+  double2 Ar[R][EPT];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int c = tid + e * MW_THREADS;
+      Ar[q][e] = q < nr && c < s ? a.G[(size_t)(wg + q * nwg) * s + c] : make_double2(0.0, 0.0);
+    }
   }
   // the owned row slot of a column index (-1: not owned here)
   auto slot_of = [&](int c) {
@@ -596,13 +607,15 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
   double2 t = reflector(0, x, a.G[0], s > 1 ? a.G[1] : make_double2(0.0, 0.0), sum_red(red_n).x, v);
   // products of column 0 (rows r > 0), one pass over the rows
   auto products = [&](int j, const double2 vv[EPT]) {
-    for (int q = 0; q < nr; ++q) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (q >= nr) break;
       double pr = 0.0, pi = 0.0;
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const int c = tid + e * MW_THREADS;
         if (c > j && c < s) {
-          const double2 av = Ar[(size_t)q * s + c];
+          const double2 av = Ar[q][e];
           pr += av.x * vv[e].x - av.y * vv[e].y;
           pi += av.x * vv[e].y + av.y * vv[e].x;
         }
@@ -712,7 +725,9 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
     // (4) rank-2 update of the owned rows r > j+1 on the columns > j+1, the owner of row j+2
     // publishing it, and the products with v_{j+1} of the next column
     double2* pnext = W.prow + (size_t)((j + 1) & 1) * s;
-    for (int q = 0; q < nr; ++q) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (q >= nr) break;
       const int r = wg + q * nwg;
       double pr = 0.0, pi = 0.0;
       if (r > j + 1) {
@@ -724,10 +739,10 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
         for (int e = 0; e < EPT; ++e) {
           const int c = tid + e * MW_THREADS;
           if (c > j + 1 && c < s) {
-            double2 xv = Ar[(size_t)q * s + c];
+            double2 xv = Ar[q][e];
             xv.x -= (vr.x * w[e].x + vr.y * w[e].y) + (wr.x * v[e].x + wr.y * v[e].y);
             xv.y -= (vr.y * w[e].x - vr.x * w[e].y) + (wr.y * v[e].x - wr.x * v[e].y);
-            Ar[(size_t)q * s + c] = xv;
+            Ar[q][e] = xv;
             if (r == j + 2) cstore(&pnext[c], xv);
             pr += xv.x * vn[e].x - xv.y * vn[e].y;
             pi += xv.x * vn[e].y + xv.y * vn[e].x;
@@ -758,6 +773,23 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
     __syncthreads();
     if (wave == 0) tri_bounds(W, s, a.tstamp, a.status);
   }
+}
+
+// the instantiation for EPT columns per thread with at least `rows` rows (nullptr: none)
+static const void* mw_kernel(int ept, int rows) {
+  if (ept == 1)
+    return rows <= 1 ? (const void*)k_tridiag_mw<1, 1>
+         : rows <= 2 ? (const void*)k_tridiag_mw<1, 2>
+         : rows <= 3 ? (const void*)k_tridiag_mw<1, 3> : nullptr;
+  if (ept == 2)
+    return rows <= 3 ? (const void*)k_tridiag_mw<2, 3>
+         : rows <= 4 ? (const void*)k_tridiag_mw<2, 4>
+         : rows <= 5 ? (const void*)k_tridiag_mw<2, 5> : nullptr;
+  if (ept == 3)
+    return rows <= 5 ? (const void*)k_tridiag_mw<3, 5>
+         : rows <= 6 ? (const void*)k_tridiag_mw<3, 6>
+         : rows <= 7 ? (const void*)k_tridiag_mw<3, 7> : nullptr;
+  return nullptr;
 }
 
 // ---- eigenvalues: one wave per eigenvalue -------------------------------------------------------
@@ -1443,28 +1475,22 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
     if (z != hipSuccess) return z;
   } else {
     const MwShape m = mw_shape(a.s);
-    const size_t lds = mw_lds_bytes(a.s);
-    if (m.nwg > MW_MAX_WG || lds > MW_LDS_BUDGET || a.s > MW_EPT * MW_THREADS)
-      return hipErrorInvalidValue;
+    if (!mw_size_supported(a.s)) return hipErrorInvalidValue;
     // the barrier words start at zero for every call
     EigWork W = eig_layout(a.work, a.s, a.kmax);
     hipError_t z = launch_zero(W.sync, MW_SYNC_BYTES, a.batch, a.bs, st);
     if (z != hipSuccess) return z;
-    // columns per thread: the smallest instantiation that covers s
-    const int ept = (a.s + MW_THREADS - 1) / MW_THREADS;
-    const void* fn = ept <= 1 ? (const void*)k_tridiag_mw<1>
-                   : ept <= 2 ? (const void*)k_tridiag_mw<2>
-                   : ept <= 3 ? (const void*)k_tridiag_mw<3>
-                              : (const void*)k_tridiag_mw<4>;
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // columns per thread and rows per workgroup: the smallest instantiation that covers both
+    const void* fn = mw_kernel((a.s + MW_THREADS - 1) / MW_THREADS, m.rows);
+    if (!fn) return hipErrorInvalidValue;
     // its workgroups wait for each other: no other such solve may hold compute units meanwhile
     z = mw_gate_enter(st);
     if (z != hipSuccess) return z;
-    const dim3 grid(m.nwg, a.batch);
-    if (ept <= 1) hipLaunchKernelGGL(k_tridiag_mw<1>, grid, dim3(MW_THREADS), lds, st, a, m.nwg);
-    else if (ept <= 2) hipLaunchKernelGGL(k_tridiag_mw<2>, grid, dim3(MW_THREADS), lds, st, a, m.nwg);
-    else if (ept <= 3) hipLaunchKernelGGL(k_tridiag_mw<3>, grid, dim3(MW_THREADS), lds, st, a, m.nwg);
-    else hipLaunchKernelGGL(k_tridiag_mw<4>, grid, dim3(MW_THREADS), lds, st, a, m.nwg);
+    EigArgs ka = a;
+    int knwg = m.nwg;
+    void* kargs[] = {(void*)&ka, (void*)&knwg};
+    z = hipLaunchKernel(fn, dim3(m.nwg, a.batch), dim3(MW_THREADS), kargs, 0, st);
+    if (z != hipSuccess) return z;
     z = hipGetLastError();
     if (z != hipSuccess) return z;
     z = mw_gate_leave(st);
