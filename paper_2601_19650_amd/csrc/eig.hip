@@ -540,7 +540,7 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int nr = wg < s ? (s - wg + nwg - 1) / nwg : 0;   // rows owned: wg, wg + nwg, ...
   __shared__ double2 red_c[MW_WAVES], red_n[MW_WAVES];
-  __shared__ double2 racc[MW_ROWS_MAX][MW_WAVES];
+  __shared__ double2 racc[R][MW_WAVES * 8];            // row partials of groups of 8 lanes
   __shared__ double2 rv[MW_ROWS_MAX], ry[MW_ROWS_MAX];   // v_j and y at the owned rows' indices
   __shared__ double2 bc[3];                               // y[j+1]; row j+1 at j+1 and j+2
   __shared__ int ok_sh;
@@ -620,24 +620,26 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
           pi += av.x * vv[e].y + av.y * vv[e].x;
         }
       }
-      pr = wave_sum(pr);
-      pi = wave_sum(pi);
-      if (lane == 0) racc[q][wave] = make_double2(pr, pi);
+      pr = sum8(pr);
+      pi = sum8(pi);
+      if ((lane & 7) == 0) racc[q][wave * 8 + (lane >> 3)] = make_double2(pr, pi);
     }
   };
   auto publish_products = [&](int j) {
-    // thread q sums row q's wave partials in order and publishes y[r] for the rows r > j
-    if (tid < nr) {
-      const int r = wg + tid * nwg;
-      if (r > j) {
-        double2 yv = make_double2(0.0, 0.0);
+    // lanes 8q..8q+7 of wave 0 sum row q's 64 partials in a fixed order (eight each, then across
+    // the eight lanes) and the first publishes y[r] for the rows r > j
+    if (tid < 8 * nr) {
+      const int q = tid >> 3, part = tid & 7;
+      double yr = 0.0, yi = 0.0;
 #pragma unroll
-        for (int q = 0; q < MW_WAVES; ++q) {
-          yv.x += racc[tid][q].x;
-          yv.y += racc[tid][q].y;
-        }
-        cstore(&W.ybuf[(size_t)(j & 1) * s + r], yv);
+      for (int i = 0; i < 8; ++i) {
+        yr += racc[q][part * 8 + i].x;
+        yi += racc[q][part * 8 + i].y;
       }
+      yr = sum8(yr);
+      yi = sum8(yi);
+      const int r = wg + q * nwg;
+      if (part == 0 && r > j) cstore(&W.ybuf[(size_t)(j & 1) * s + r], make_double2(yr, yi));
     }
   };
   products(0, v);
@@ -749,9 +751,9 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
           }
         }
       }
-      pr = wave_sum(pr);
-      pi = wave_sum(pi);
-      if (lane == 0) racc[q][wave] = make_double2(pr, pi);
+      pr = sum8(pr);
+      pi = sum8(pi);
+      if ((lane & 7) == 0) racc[q][wave * 8 + (lane >> 3)] = make_double2(pr, pi);
     }
     __syncthreads();
     publish_products(j + 1);
