@@ -307,19 +307,19 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
 
 // ---- multi-workgroup Householder reduction (s > EIG_LDS_MAX) ------------------------------------
 // The rows of G are dealt cyclically to nwg workgroups (row r to workgroup r mod nwg) and stay in
-// their LDS for the whole reduction. Thread t of every workgroup owns the columns t, t + 512, ...:
-// the reflector v_j, w_j and the next reflector live in its registers, so that the only LDS traffic
-// of a column is one pass over the rows. Few threads with several columns each keep the per-row
-// wave reductions, which every wave pays, small beside the arithmetic (a wave64 instruction takes
-// four cycles of its SIMD). Column j costs one grid-wide barrier:
-//   (1) barrier: each workgroup publishes its arrival in a flag of its own (no shared counter);
-//       with many workgroups workgroup 0 gathers the flags and releases the others;
+// their threads' registers for the whole reduction. Thread t of every workgroup owns the columns t,
+// t + 512, ...: its entries of the owned rows, of the reflector v_j, of w_j and of the next
+// reflector live in its registers, so that a column moves no row data through LDS. Column j costs
+// one grid-wide barrier:
+//   (1) barrier: each workgroup adds its arrival to one of eight counters and waits until all
+//       eight have counted every workgroup of their group;
 //   (2) every workgroup fetches all of y = A v_j (published by the rows' owners) and the row j+1
 //       its owner published one column earlier, and forms w_j = tau y - |tau|^2/2 (v_j^H y)^* v_j;
 //   (3) it builds row j+1 of the updated matrix (A -= v_j w_j^H + w_j v_j^H) and from it the next
 //       reflector v_{j+1}, identically in every workgroup;
 //   (4) one pass over its rows applies the rank-2 update and accumulates the products
-//       y' = A' v_{j+1} of the next column; the owner of row j+2 publishes that row.
+//       y' = A' v_{j+1} of the next column (reduced over groups of eight lanes, then from LDS); the
+//       owner of row j+2 publishes that row.
 // Reductions are summed in a fixed order, so every workgroup holds bitwise the same v and w.
 // The barrier waits are bounded: after timeout_ticks of the 100 MHz wall clock (2 s) a workgroup
 // raises a flag, every workgroup leaves at its next barrier, d[0] is set to NaN and the call's
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
 static constexpr int MW_THREADS = 512;
 static constexpr int MW_WAVES = MW_THREADS / 64;
 static constexpr int MW_EPT = 3;                    // columns per thread, at most: s <= 1536
-static constexpr int MW_ROWS_MAX = 16;              // rows per workgroup (per-row reduction slots)
+static constexpr int MW_ROWS_MAX = 16;              // rows per workgroup, at most (row slots in LDS)
 // The rows a workgroup owns live in its threads' registers, EPT entries of each row per thread. The
 // cap on a workgroup's row bytes below keeps that share at 21 complex entries per thread at most.
 static constexpr size_t MW_ROW_BUDGET = 152 * 1024;
