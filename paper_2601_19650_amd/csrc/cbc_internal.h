@@ -105,7 +105,7 @@ struct EigArgs {
   int reduction = 0;
 };
 size_t eig_work_doubles(int s, int kmax);
-// largest Gram the eigensolver handles (the multi-workgroup reduction keeps its rows in LDS)
+// largest Gram the eigensolver handles
 bool eig_size_supported(int s);
 // reduction for a solve of this size (EigArgs::reduction): 1 (one-stage, multi-workgroup) for a
 // single instance outside a caller's stream capture where it applies, otherwise 0 (two-stage)

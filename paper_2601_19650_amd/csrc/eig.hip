@@ -111,7 +111,7 @@ __device__ inline double2 householder(double2 alpha, double xn2, int C, double a
 // workspace.
 __device__ inline void next_reflector(const double2 xin[2], int s, int j, bool upd,
                                       const double2 vr[2], const double2 wr[2], double2* vnext,
-                                      double2& tau, EigWork& W, int lane) {
+                                      double2& tau, EigWork& W, int ldv, int lane) {
   const int C = j + 1, n = s - C;
   double2 x[2] = {xin[0], xin[1]};
   if (upd) {
@@ -135,7 +135,7 @@ __device__ inline void next_reflector(const double2 xin[2], int s, int j, bool u
   const double2 scal = householder(alpha, xn2, C, acc, tau, W, lane);
   if (lane == 0) {
     vnext[0] = make_double2(1.0, 0.0);
-    W.V[(size_t)C * s + C + 1] = make_double2(1.0, 0.0);
+    W.V[(size_t)C * ldv + C + 1] = make_double2(1.0, 0.0);
   }
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
@@ -143,7 +143,7 @@ __device__ inline void next_reflector(const double2 xin[2], int s, int j, bool u
     if (r >= 2 && r < n) {
       const double2 v = cmul(x[k], scal);
       vnext[r - 1] = v;
-      W.V[(size_t)C * s + C + r] = v;
+      W.V[(size_t)C * ldv + C + r] = v;
     }
   }
 }
@@ -155,7 +155,11 @@ __device__ __forceinline__ void load_column(const double2* P, int s, int C, int 
 }
 
 
-__global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
+// With sfull > a.s the kernel reduces the trailing a.s x a.s block (rows and columns from
+// sfull - a.s on, stored densely in G with row stride a.s) that the multi-workgroup reduction of an
+// sfull x sfull Gram left after its first sfull - a.s reflectors, and records its reflectors, d and
+// e at those offsets of the sfull layout; the Gershgorin interval is then that of the whole T.
+__global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0, int sfull) {
   const EigArgs a = eig_inst(a0, blockIdx.x);
   extern __shared__ double smem[];
   __shared__ TriShared sh;
@@ -167,8 +171,14 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
   double2* vb = P + tri(s);     // reflectors of the current and the next column (by parity)
   double2* ww = vb + 2 * s;
   double2* A = a.G;
-  EigWork W = eig_layout(a.work, s, a.kmax);
-  if (a.tstamp && tid == 0) a.tstamp[0] = wall_clock64();
+  const int off = sfull - s, ldv = sfull;
+  EigWork Wf = eig_layout(a.work, sfull, a.kmax);
+  EigWork W = Wf;
+  W.d += off;
+  W.e += off;
+  W.tau += off;
+  W.V += (size_t)off * sfull + off;
+  if (a.tstamp && tid == 0 && off == 0) a.tstamp[0] = wall_clock64();
   if (tid == 0) sh.zero = make_double2(0.0, 0.0);
   for (int idx = tid; idx < tri(s); idx += nthr) {
     int r = (int)((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
@@ -181,7 +191,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
   if (wave == 0) {
     double2 x0[2];
     load_column(P, s, 0, lane, x0);
-    next_reflector(x0, s, -1, false, x0, x0, vb, sh.tau[0], W, lane);
+    next_reflector(x0, s, -1, false, x0, x0, vb, sh.tau[0], W, ldv, lane);
   }
   __syncthreads();
   const int grp = tid / RG, gl = tid % RG, ngrp = nthr / RG;
@@ -262,7 +272,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     }
     if (stamp) { const long long t1 = wall_clock64(); tB += t1 - t0; t0 = t1; }
     if (wave == 0) {
-      next_reflector(xcol, s, j, upd, vk, wk, vn, sh.tau[(j + 1) & 1], W, lane);
+      next_reflector(xcol, s, j, upd, vk, wk, vn, sh.tau[(j + 1) & 1], W, ldv, lane);
       if (stamp) tL += wall_clock64() - t0;
     } else if (upd) {
       // A -= v w'^H + w' v^H on rows r >= 1 and columns 1 <= c <= r of the trailing matrix (column 0
@@ -296,13 +306,13 @@ __global__ __launch_bounds__(EIG_THREADS) void k_tridiag(EigArgs a0) {
     __syncthreads();
     if (stamp) tD += wall_clock64() - t0;
   }
-  if (stamp) {
+  if (stamp && off == 0) {
     a.tstamp[4] = tL;
     a.tstamp[5] = tB;
     a.tstamp[6] = tD;
   }
   // the Gershgorin interval of T (used by the two later kernels)
-  if (wave == 0) tri_bounds(W, s, a.tstamp, a.status);
+  if (wave == 0) tri_bounds(Wf, sfull, a.tstamp, a.status);
 }
 
 // ---- multi-workgroup Householder reduction (s > EIG_LDS_MAX) ------------------------------------
@@ -337,6 +347,9 @@ __host__ __device__ constexpr int mw_rows_max(int ept) {
 }
 
 static constexpr int MW_TARGET_WG = 208;            // workgroups aimed at (see mw_shape)
+// The last MW_TAIL columns are reduced by the one-workgroup kernel (LDS-resident packed triangle),
+// whose column costs less than a grid barrier once the trailing matrix is that small.
+static constexpr int MW_TAIL = EIG_LDS_MAX;
 
 struct MwShape {
   int nwg, rows;
@@ -533,7 +546,7 @@ __device__ __forceinline__ double2 sum_red(const double2* red) {
 }
 
 template <int EPT, int R>   // columns per thread (s <= EPT * MW_THREADS), rows per workgroup at most
-__global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) {
+__global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg, int tail) {
   const EigArgs a = eig_inst(a0, blockIdx.y);
   const int wg = blockIdx.x;
   const int s = a.s;
@@ -657,7 +670,9 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
       ph[7] = t1;
     }
   };
-  for (int j = 0; j < s - 1; ++j) {
+  // with a tail, the reflectors from column s - tail on are left to the one-workgroup kernel
+  const int jend = tail > 0 ? s - tail : s - 1;
+  for (int j = 0; j < jend; ++j) {
     if (stamp) ph[7] = wall_clock64();
     // (1)
     if (!mw_sync(W.sync, nwg, (unsigned)(j + 1), &ok_sh, a.timeout_ticks)) {
@@ -721,8 +736,16 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
       if (writer && tid == 0) W.d[j + 1] = bc[1].x;
       break;
     }
+    // the last column before the tail: the update only (no next reflector, no products)
+    const bool last = j + 1 == jend;
     double2 vn[EPT];
-    const double2 t1 = reflector(j + 1, x, bc[1], bc[2], sum_red(red_n).x, vn);
+    double2 t1 = make_double2(0.0, 0.0);
+    if (last) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) vn[e] = make_double2(0.0, 0.0);
+    } else {
+      t1 = reflector(j + 1, x, bc[1], bc[2], sum_red(red_n).x, vn);
+    }
     lap(2);
     // (4) rank-2 update of the owned rows r > j+1 on the columns > j+1, the owner of row j+2
     // publishing it, and the products with v_{j+1} of the next column
@@ -756,6 +779,36 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
       if ((lane & 7) == 0) racc[q][wave * 8 + (lane >> 3)] = make_double2(pr, pi);
     }
     __syncthreads();
+    if (last) {
+      // the trailing block (rows and columns from c0 = j + 1 = s - tail on) for the one-workgroup
+      // kernel, densely with row stride `tail`, into G (whose rows every workgroup read at the
+      // start): the rows' owners write their entries right of column c0; row c0 is the updated row
+      // every workgroup holds in x, and workgroup 0 writes it and, conjugated, column c0 below it
+      const int c0 = j + 1;
+      double2* Tb = a.G;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int r = wg + q * nwg;
+        if (q < nr && r > c0) {
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const int c = tid + e * MW_THREADS;
+            if (c > c0 && c < s) Tb[(size_t)(r - c0) * tail + (c - c0)] = Ar[q][e];
+          }
+        }
+      }
+      if (writer) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const int c = tid + e * MW_THREADS;
+          if (c >= c0 && c < s) {
+            Tb[c - c0] = x[e];
+            if (c > c0) Tb[(size_t)(c - c0) * tail] = cconj(x[e]);
+          }
+        }
+      }
+      break;
+    }
     publish_products(j + 1);
 #pragma unroll
     for (int e = 0; e < EPT; ++e) v[e] = vn[e];
@@ -771,7 +824,7 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg) 
     a.tstamp[8] = ph[2];
     a.tstamp[9] = ph[3];
   }
-  if (writer) {
+  if (writer && tail == 0) {
     __syncthreads();
     if (wave == 0) tri_bounds(W, s, a.tstamp, a.status);
   }
@@ -1471,7 +1524,7 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
     const size_t lds = eig_lds_bytes(a.s);
     (void)hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);
-    hipLaunchKernelGGL(k_tridiag, dim3(a.batch), dim3(EIG_THREADS), lds, st, a);
+    hipLaunchKernelGGL(k_tridiag, dim3(a.batch), dim3(EIG_THREADS), lds, st, a, a.s);
   } else if (two_stage) {
     const hipError_t z = launch_band_reduction(a, st);
     if (z != hipSuccess) return z;
@@ -1489,13 +1542,22 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
     z = mw_gate_enter(st);
     if (z != hipSuccess) return z;
     EigArgs ka = a;
-    int knwg = m.nwg;
-    void* kargs[] = {(void*)&ka, (void*)&knwg};
+    int knwg = m.nwg, ktail = MW_TAIL;
+    void* kargs[] = {(void*)&ka, (void*)&knwg, (void*)&ktail};
     z = hipLaunchKernel(fn, dim3(m.nwg, a.batch), dim3(MW_THREADS), kargs, 0, st);
     if (z != hipSuccess) return z;
     z = hipGetLastError();
     if (z != hipSuccess) return z;
     z = mw_gate_leave(st);
+    if (z != hipSuccess) return z;
+    // the last MW_TAIL columns in one workgroup, from the block the reduction left in G
+    EigArgs ta = a;
+    ta.s = MW_TAIL;
+    const size_t tlds = eig_lds_bytes(MW_TAIL);
+    (void)hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)tlds);
+    hipLaunchKernelGGL(k_tridiag, dim3(a.batch), dim3(EIG_THREADS), tlds, st, ta, a.s);
+    z = hipGetLastError();
     if (z != hipSuccess) return z;
   }
   hipError_t e = hipGetLastError();
