@@ -21,7 +21,8 @@
 //      eigenpair; eigenvalues closer than 1e-3 ||T|| form clusters that are re-orthogonalised (or,
 //      for near-exact degeneracies, computed by inverse iteration); then the back-transformation:
 //      for s <= 256 one wave per eigenpair applying the reflectors streamed from L2, above that in
-//      blocks of 32 reflectors (compact WY, k_bt_tfactor and k_bt_wy).
+//      blocks of 32 reflectors (compact WY: the factors formed alongside the eigenvalues, then
+//      k_bt_wy).
 #include <float.h>
 
 #include <mutex>
@@ -850,7 +851,88 @@ static const void* mw_kernel(int ept, int rows) {
 // ---- eigenvalues: one wave per eigenvalue -------------------------------------------------------
 static constexpr int EV_WAVES = 4;
 
+// The triangular factor of block b of the reflectors (one workgroup of 256 threads; run by extra
+// workgroups of k_eigvals, which do not need it, so that it overlaps the eigenvalues: 0.18 ms at
+// s = 1024 as a kernel of its own). The layout and use of the factors are described with k_bt_wy.
+static constexpr int BT_CHUNK = 64;   // rows of a block staged in LDS for its Gram
+__device__ void bt_tfactor_block(const EigArgs& a0, int b, int inst) {
+  const EigArgs a = eig_inst(a0, inst);
+  const int s = a.s, tid = threadIdx.x;
+  EigWork W = eig_layout(a.work, s, a.kmax);
+  const int j0 = b * BT_NB;
+  const int n = s - 1 - j0 < BT_NB ? s - 1 - j0 : BT_NB;
+  __shared__ double2 vs[BT_NB][BT_CHUNK + 1];
+  __shared__ double2 G[BT_NB][BT_NB + 1];
+  __shared__ double2 T[BT_NB][BT_NB + 1];
+  // Gram entries G[p][q] = v_p^H v_q, p < q (nonzero rows: r > j0 + q), four entries per thread
+  double2 acc[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) acc[m] = make_double2(0.0, 0.0);
+  for (int r0 = j0 + 1; r0 < s; r0 += BT_CHUNK) {
+    __syncthreads();
+    for (int e = tid; e < BT_NB * BT_CHUNK; e += 256) {
+      const int i = e / BT_CHUNK, l = e % BT_CHUNK, r = r0 + l, J = j0 + i;
+      vs[i][l] = (i < n && r < s && r > J) ? W.V[(size_t)J * s + r] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int pq = tid + 256 * m, p = pq / BT_NB, q = pq % BT_NB;
+      if (p < q && q < n) {
+        double2 g = acc[m];
+        for (int l = 0; l < BT_CHUNK; ++l) {
+          const double2 x = vs[p][l], y = vs[q][l];
+          g.x += x.x * y.x + x.y * y.y;
+          g.y += x.x * y.y - x.y * y.x;
+        }
+        acc[m] = g;
+      }
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int pq = tid + 256 * m, p = pq / BT_NB, q = pq % BT_NB;
+    if (p < q && q < n) G[p][q] = acc[m];
+  }
+  __syncthreads();
+  // row p of T in lane p, column by column (each lane reads only its own row of T)
+  if (tid < BT_NB) {
+    const int p = tid;
+    for (int i = 0; i < BT_NB; ++i) {
+      double2 v = make_double2(0.0, 0.0);
+      if (i < n) {
+        const double2 ti = W.tau[j0 + i];
+        if (p == i) {
+          v = ti;
+        } else if (p < i) {
+          double2 sm = make_double2(0.0, 0.0);
+          for (int k = p; k < i; ++k) {
+            const double2 c = cmul(T[p][k], G[k][i]);
+            sm.x += c.x;
+            sm.y += c.y;
+          }
+          const double2 c = cmul(ti, sm);
+          v = make_double2(-c.x, -c.y);
+        }
+      }
+      T[p][i] = v;
+    }
+    double2* dst = W.tfac + (size_t)b * BT_NB * BT_NB + (size_t)p * BT_NB;
+    for (int i = 0; i < BT_NB; ++i) dst[i] = T[p][i];
+  }
+}
+
+// With TF, the last bt_blocks(s) workgroups of the grid form the back-transformation's triangular
+// factors instead (plain grids only).
+template <bool TF>
 __global__ __launch_bounds__(64 * EV_WAVES) void k_eigvals(EigArgs a0) {
+  if (TF) {
+    const int nev_wg = (int)gridDim.x - bt_blocks(a0.s);
+    if ((int)blockIdx.x >= nev_wg) {
+      bt_tfactor_block(a0, (int)blockIdx.x - nev_wg, blockIdx.y);
+      return;
+    }
+  }
   if (!xcd_own(a0.spread)) return;
   const EigArgs a = eig_inst(a0, blockIdx.y);
   extern __shared__ double smem[];
@@ -1324,82 +1406,15 @@ __global__ __launch_bounds__(256) void k_backtransform(EigArgs a0) {
 // ---- blocked back-transformation (s > 256): compact WY, u = Q y with Q = B_0 B_1 ... B_{nb-1} ------
 // Block b holds the reflectors j0 = BT_NB b ... j0 + n - 1 and equals I - V_b T_b V_b^H with T_b upper
 // triangular: T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] (V_b[:, 0:i]^H v_i). The factors are formed
-// once per solve (k_bt_tfactor, one workgroup per block); k_bt_wy then applies the blocks, last one
+// once per solve (bt_tfactor_block, one workgroup per block); k_bt_wy then applies the blocks, last one
 // first, to CPW eigenvectors per workgroup held in LDS: w = V_b^H x, w' = T_b w, x -= V_b w'. Each
 // block costs one dependent step instead of BT_NB reflector-by-reflector reductions, and the
 // reflectors are read with unit stride in both passes. Measured on MI355X (eigenvectors of T and
 // back-transformation, k = 256): s = 1024 1.62 -> 0.83 ms, 1272 5.4 -> 1.15, 1536 7.75 -> 1.52
 // against one wave per eigenvector applying the reflectors one at a time; one eigenvector per
 // workgroup (256 workgroups) was faster than two (0.91 ms at s = 1024).
-static constexpr int BT_CHUNK = 64;   // rows of a block staged in LDS for its Gram
 static constexpr int BT_CPW = 1;      // eigenvectors per workgroup of k_bt_wy
 
-__global__ __launch_bounds__(256) void k_bt_tfactor(EigArgs a0) {
-  const EigArgs a = eig_inst(a0, blockIdx.y);
-  const int s = a.s, tid = threadIdx.x;
-  EigWork W = eig_layout(a.work, s, a.kmax);
-  const int b = blockIdx.x, j0 = b * BT_NB;
-  const int n = s - 1 - j0 < BT_NB ? s - 1 - j0 : BT_NB;
-  __shared__ double2 vs[BT_NB][BT_CHUNK + 1];
-  __shared__ double2 G[BT_NB][BT_NB + 1];
-  __shared__ double2 T[BT_NB][BT_NB + 1];
-  // Gram entries G[p][q] = v_p^H v_q, p < q (nonzero rows: r > j0 + q), four entries per thread
-  double2 acc[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) acc[m] = make_double2(0.0, 0.0);
-  for (int r0 = j0 + 1; r0 < s; r0 += BT_CHUNK) {
-    __syncthreads();
-    for (int e = tid; e < BT_NB * BT_CHUNK; e += 256) {
-      const int i = e / BT_CHUNK, l = e % BT_CHUNK, r = r0 + l, J = j0 + i;
-      vs[i][l] = (i < n && r < s && r > J) ? W.V[(size_t)J * s + r] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int pq = tid + 256 * m, p = pq / BT_NB, q = pq % BT_NB;
-      if (p < q && q < n) {
-        double2 g = acc[m];
-        for (int l = 0; l < BT_CHUNK; ++l) {
-          const double2 x = vs[p][l], y = vs[q][l];
-          g.x += x.x * y.x + x.y * y.y;
-          g.y += x.x * y.y - x.y * y.x;
-        }
-        acc[m] = g;
-      }
-    }
-  }
-#pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const int pq = tid + 256 * m, p = pq / BT_NB, q = pq % BT_NB;
-    if (p < q && q < n) G[p][q] = acc[m];
-  }
-  __syncthreads();
-  // row p of T in lane p, column by column (each lane reads only its own row of T)
-  if (tid < BT_NB) {
-    const int p = tid;
-    for (int i = 0; i < BT_NB; ++i) {
-      double2 v = make_double2(0.0, 0.0);
-      if (i < n) {
-        const double2 ti = W.tau[j0 + i];
-        if (p == i) {
-          v = ti;
-        } else if (p < i) {
-          double2 sm = make_double2(0.0, 0.0);
-          for (int k = p; k < i; ++k) {
-            const double2 c = cmul(T[p][k], G[k][i]);
-            sm.x += c.x;
-            sm.y += c.y;
-          }
-          const double2 c = cmul(ti, sm);
-          v = make_double2(-c.x, -c.y);
-        }
-      }
-      T[p][i] = v;
-    }
-    double2* dst = W.tfac + (size_t)b * BT_NB * BT_NB + (size_t)p * BT_NB;
-    for (int i = 0; i < BT_NB; ++i) dst[i] = T[p][i];
-  }
-}
 
 template <int CPW>   // eigenvectors per workgroup
 __global__ __launch_bounds__(256) void k_bt_wy(EigArgs a0) {
@@ -1564,8 +1579,14 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
   if (e != hipSuccess) return e;
   const size_t lds2 = (size_t)16 * a.s;
   const int nev = a.kmax < a.s ? a.kmax + 1 : a.kmax;
-  hipLaunchKernelGGL(k_eigvals, dim3(a.spread * ((nev + EV_WAVES - 1) / EV_WAVES), a.batch),
-                     dim3(64 * EV_WAVES), lds2, st, a);
+  // the blocked back-transformation's factors are formed by extra workgroups of this launch
+  const bool blocked_bt = !two_stage && a.s > 256 && a.spread == 1;
+  const unsigned nev_wg = (unsigned)(a.spread * ((nev + EV_WAVES - 1) / EV_WAVES));
+  if (blocked_bt)
+    hipLaunchKernelGGL(k_eigvals<true>, dim3(nev_wg + bt_blocks(a.s), a.batch), dim3(64 * EV_WAVES),
+                       lds2, st, a);
+  else
+    hipLaunchKernelGGL(k_eigvals<false>, dim3(nev_wg, a.batch), dim3(64 * EV_WAVES), lds2, st, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int nw = a.s <= 1000 ? 4 : (a.s <= 1900 ? 2 : 1);
@@ -1587,10 +1608,7 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
   if (e != hipSuccess) return e;
   if (two_stage) return launch_bt_band(a, st);
   const dim3 gb(a.spread * ((a.kmax + 3) / 4), a.batch);
-  if (a.s > 256 && a.spread == 1) {
-    hipLaunchKernelGGL(k_bt_tfactor, dim3(bt_blocks(a.s), a.batch), dim3(256), 0, st, a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+  if (blocked_bt) {
     const size_t ldsx = (size_t)a.s * BT_CPW * 16;
     if (ldsx > 160 * 1024 - 8192) return hipErrorInvalidValue;
     (void)hipFuncSetAttribute((const void*)k_bt_wy<BT_CPW>,
