@@ -89,7 +89,10 @@ EIG_CASES = [(1, 1), (2, 1), (2, 2), (7, 3), (64, 32), (128, 64), (200, 100), (9
              (1041, 100), (1500, 256), (2064, 64)]
 
 
-MW_CASES = [(129, 64), (200, 100), (300, 300), (700, 200), (1024, 256), (1272, 128), (1536, 200)]
+# one-stage sizes: one column before the one-workgroup tail (129) and two (130), the edges of the
+# kernel instantiations (columns per thread 1 -> 2 at 512, 2 -> 3 at 1024; rows per workgroup 3 to 7)
+MW_CASES = [(129, 64), (130, 130), (200, 100), (300, 300), (512, 100), (513, 256), (700, 200),
+            (1024, 256), (1025, 128), (1272, 128), (1300, 64), (1536, 200)]
 
 
 @pytest.mark.parametrize("s,kmax,reduction",
@@ -136,6 +139,39 @@ def test_eig_multi_workgroup_repeatable(lib):
     assert np.abs(g @ U0 - U0 * l0[None, :]).max() <= 1e-11 * w[0]
 
 
+def test_eig_multi_workgroup_one_stage_repeatable(lib):
+    """The one-stage multi-workgroup reduction (and its one-workgroup tail) sums in a fixed order as
+    well: repeated solves are bitwise identical."""
+    rng = np.random.default_rng(22)
+    s, kmax = 1024, 256
+    g = herm_psd(rng, s)
+    G = torch.from_numpy(g).cuda()
+    runs = [lib.test_eig(G, kmax, reduction=1) for _ in range(3)]
+    U0, l0 = runs[0][0].cpu().numpy(), runs[0][1].cpu().numpy()
+    for U, lam, _, _ in runs[1:]:
+        assert np.array_equal(U.cpu().numpy(), U0) and np.array_equal(lam.cpu().numpy(), l0)
+    w = np.linalg.eigvalsh(g)[::-1]
+    assert np.abs(l0 - w[:kmax]).max() <= 1e-12 * w[0] * s
+
+
+@pytest.mark.parametrize("reduction", [0, 1])
+def test_eig_rank_deficient_large(lib, reduction):
+    """A Gram of rank 300 at s = 700 (the trailing matrix vanishes to rounding long before the
+    one-workgroup tail): the top-300 eigenpairs are reproduced and orthonormal. (The vectors of the
+    numerically null cluster beyond the rank are not checked: they carry no weight, and the
+    Cholesky-QR that follows in a compression drops directions that repeat.)"""
+    rng = np.random.default_rng(23)
+    s, r, kmax = 700, 300, 400
+    g = herm_psd(rng, s, rank=r)
+    U, lam, kk, _ = lib.test_eig(torch.from_numpy(g).cuda(), kmax, reduction=reduction)
+    U = U.cpu().numpy()
+    w = np.linalg.eigvalsh(g)[::-1]
+    assert np.abs(lam.cpu().numpy()[:r] - w[:r]).max() <= 1e-11 * w[0]
+    p = U[:, :r] @ U[:, :r].conj().T
+    assert np.abs(p @ g - g).max() <= 1e-10 * w[0]
+    assert np.abs(U[:, :r].conj().T @ U[:, :r] - np.eye(r)).max() <= 1e-11
+
+
 def test_eig_rank_deficient_and_tol(lib):
     rng = np.random.default_rng(3)
     s, r = 60, 20
@@ -157,7 +193,7 @@ def test_eig_rank_deficient_and_tol(lib):
 @pytest.mark.parametrize("s,kind,reduction", [
     (5, "diagonal", 0), (40, "diagonal", 0), (128, "diagonal", 0), (40, "blocks", 0),
     (128, "blocks", 0), (200, "blocks", 0), (300, "diagonal", 0), (333, "blocks", 0),
-    (300, "diagonal", 1), (333, "blocks", 1)])
+    (300, "diagonal", 1), (333, "blocks", 1), (1024, "diagonal", 1), (1024, "blocks", 1)])
 def test_eig_structured(lib, s, kind, reduction):
     """Grams whose reduction meets columns with nothing below the diagonal (a reflector that is the
     identity, tau = 0): a diagonal Gram (every column) and a block-diagonal one (the last column of
