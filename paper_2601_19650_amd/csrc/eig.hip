@@ -1440,6 +1440,7 @@ __global__ __launch_bounds__(256) void k_bt_wy(EigArgs a0) {
     for (int m = 0; m < PW; ++m)
 #pragma unroll
       for (int c = 0; c < CPW; ++c) acc[m][c] = make_double2(0.0, 0.0);
+#pragma unroll 2
     for (int r = j0 + 1 + lane; r < s; r += 64) {
       // loads issued together from in-bounds addresses (reflector index clamped to s - 2); the
       // entries outside a reflector's support are replaced by zeros below
