@@ -473,13 +473,13 @@ __device__ __forceinline__ double2 cload(const double2* p) {
   return v;
 }
 
-// Barrier number `it`; sync[MW_MAX_WG] = time-out flag. Below MW_GATHER_MIN workgroups sync[q] is
-// the last barrier workgroup q reached and every workgroup polls all flags. From MW_GATHER_MIN on
+// Barrier number `it`; sync[MW_MAX_WG] = time-out flag. Below MW_COUNT_MIN workgroups sync[q] is
+// the last barrier workgroup q reached and every workgroup polls all flags. From MW_COUNT_MIN on
 // (where that polling traffic grows with the square of the count) workgroup q adds one to the
 // arrival counter of its group q mod 8, sync[(q mod 8) * MW_CTR_STRIDE] (eight counters on lines of
 // their own, so that the additions spread), and every workgroup polls the eight counters, one per
 // lane, until each holds `it` times its group's workgroup count.
-static constexpr int MW_GATHER_MIN = 64;
+static constexpr int MW_COUNT_MIN = 64;
 static constexpr int MW_CTR_STRIDE = 32;   // words: one 128-byte line per counter
 static_assert(8 * MW_CTR_STRIDE <= MW_MAX_WG, "the counters share the per-workgroup flag words");
 
@@ -490,7 +490,7 @@ __device__ bool mw_sync(unsigned* sync, int nwg, unsigned it, int* ok_sh, long l
   __syncthreads();
   const int tid = threadIdx.x;
   if (tid < 64) {
-    const bool count = nwg >= MW_GATHER_MIN;
+    const bool count = nwg >= MW_COUNT_MIN;
     if (tid == 0) {
       if (count)
         __hip_atomic_fetch_add(&sync[(blockIdx.x & 7) * MW_CTR_STRIDE], 1u, __ATOMIC_RELAXED,
