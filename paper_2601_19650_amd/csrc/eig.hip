@@ -1414,10 +1414,11 @@ __global__ __launch_bounds__(256) void k_backtransform(EigArgs a0) {
 // against one wave per eigenvector applying the reflectors one at a time; one eigenvector per
 // workgroup (256 workgroups) was faster than two (0.91 ms at s = 1024).
 static constexpr int BT_CPW = 1;      // eigenvectors per workgroup of k_bt_wy
+static constexpr int BT_THREADS = 512; // threads per workgroup of k_bt_wy
 
 
 template <int CPW>   // eigenvectors per workgroup
-__global__ __launch_bounds__(256) void k_bt_wy(EigArgs a0) {
+__global__ __launch_bounds__(BT_THREADS) void k_bt_wy(EigArgs a0) {
   const EigArgs a = eig_inst(a0, blockIdx.y);
   const int s = a.s, kmax = a.kmax, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   EigWork W = eig_layout(a.work, s, kmax);
@@ -1425,16 +1426,17 @@ __global__ __launch_bounds__(256) void k_bt_wy(EigArgs a0) {
   extern __shared__ double smem[];
   double2* X = reinterpret_cast<double2*>(smem);   // X[r * CPW + c]
   __shared__ double2 Ws[BT_NB][CPW], Wq[BT_NB][CPW];
-  for (int e = tid; e < s * CPW; e += 256) {
+  for (int e = tid; e < s * CPW; e += BT_THREADS) {
     const int r = e / CPW, t = t0 + e % CPW;
     X[e] = make_double2(t < kmax ? W.Y[(size_t)t * s + r] : 0.0, 0.0);
   }
   __syncthreads();
-  constexpr int PW = BT_NB / 4;   // reflectors per wave in the first pass
+  constexpr int NWV = BT_THREADS / 64;
+  constexpr int PW = BT_NB / NWV;   // reflectors per wave in the first pass
   for (int b = bt_blocks(s) - 1; b >= 0; --b) {
     const int j0 = b * BT_NB;
     const int n = s - 1 - j0 < BT_NB ? s - 1 - j0 : BT_NB;
-    // (1) w = V_b^H x: wave w takes the reflectors w, w + 4, ...; lanes run over the rows
+    // (1) w = V_b^H x: wave w takes the reflectors w, w + NWV, ...; lanes run over the rows
     double2 acc[PW][CPW];
 #pragma unroll
     for (int m = 0; m < PW; ++m)
@@ -1447,7 +1449,7 @@ __global__ __launch_bounds__(256) void k_bt_wy(EigArgs a0) {
       double2 vv[PW];
 #pragma unroll
       for (int m = 0; m < PW; ++m) {
-        const int J = j0 + wave + 4 * m;
+        const int J = j0 + wave + NWV * m;
         vv[m] = W.V[(size_t)(J < s - 1 ? J : s - 2) * s + r];
       }
       double2 x[CPW];
@@ -1455,7 +1457,7 @@ __global__ __launch_bounds__(256) void k_bt_wy(EigArgs a0) {
       for (int c = 0; c < CPW; ++c) x[c] = X[r * CPW + c];
 #pragma unroll
       for (int m = 0; m < PW; ++m) {
-        const int i = wave + 4 * m;
+        const int i = wave + NWV * m;
         const double2 v = (i < n && r > j0 + i) ? vv[m] : make_double2(0.0, 0.0);
 #pragma unroll
         for (int c = 0; c < CPW; ++c) {
@@ -1469,7 +1471,7 @@ __global__ __launch_bounds__(256) void k_bt_wy(EigArgs a0) {
 #pragma unroll
       for (int c = 0; c < CPW; ++c) {
         const double re = wave_sum(acc[m][c].x), im = wave_sum(acc[m][c].y);
-        if (lane == 0) Ws[wave + 4 * m][c] = make_double2(re, im);
+        if (lane == 0) Ws[wave + NWV * m][c] = make_double2(re, im);
       }
     __syncthreads();
     // (2) w' = T_b w (T_b is zero outside the block's n x n upper triangle)
@@ -1489,25 +1491,32 @@ __global__ __launch_bounds__(256) void k_bt_wy(EigArgs a0) {
       Wq[i][c] = sm;
     }
     __syncthreads();
-    // (3) x -= V_b w', one row per thread; the block's reflectors at the row are loaded together
-    for (int r = j0 + 1 + tid; r < s; r += 256) {
+    // (3) x -= V_b w', one row per thread; the block's reflectors at the row are loaded together,
+    // half a block at a time
+    for (int r = j0 + 1 + tid; r < s; r += BT_THREADS) {
       const int imax = r - j0 < n ? r - j0 : n;   // reflector i is nonzero at row r iff r > j0 + i
-      double2 vv[BT_NB];
-#pragma unroll
-      for (int i = 0; i < BT_NB; ++i) vv[i] = W.V[(size_t)(j0 + i < s - 1 ? j0 + i : s - 2) * s + r];
-#pragma unroll
-      for (int i = 0; i < BT_NB; ++i)
-        if (i >= imax) vv[i] = make_double2(0.0, 0.0);
       double2 u[CPW];
 #pragma unroll
       for (int c = 0; c < CPW; ++c) u[c] = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int i = 0; i < BT_NB; ++i) {
+      for (int h = 0; h < BT_NB; h += BT_NB / 2) {
+        double2 vv[BT_NB / 2];
 #pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-          const double2 p = cmul(vv[i], Wq[i][c]);
-          u[c].x += p.x;
-          u[c].y += p.y;
+        for (int i = 0; i < BT_NB / 2; ++i) {
+          const int J = j0 + h + i;
+          vv[i] = W.V[(size_t)(J < s - 1 ? J : s - 2) * s + r];
+        }
+#pragma unroll
+        for (int i = 0; i < BT_NB / 2; ++i)
+          if (h + i >= imax) vv[i] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < BT_NB / 2; ++i) {
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            const double2 p = cmul(vv[i], Wq[h + i][c]);
+            u[c].x += p.x;
+            u[c].y += p.y;
+          }
         }
       }
 #pragma unroll
@@ -1519,7 +1528,7 @@ __global__ __launch_bounds__(256) void k_bt_wy(EigArgs a0) {
     __syncthreads();
   }
   const int kk = a.kkeep[0];
-  for (int e = tid; e < s * CPW; e += 256) {
+  for (int e = tid; e < s * CPW; e += BT_THREADS) {
     const int r = e / CPW, t = t0 + e % CPW;
     if (t < kmax) a.U[(size_t)r * kmax + t] = t < kk ? X[e] : make_double2(0.0, 0.0);
   }
@@ -1614,8 +1623,8 @@ hipError_t launch_eig(const EigArgs& a0, hipStream_t st) {
     if (ldsx > 160 * 1024 - 8192) return hipErrorInvalidValue;
     (void)hipFuncSetAttribute((const void*)k_bt_wy<BT_CPW>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)ldsx);
-    hipLaunchKernelGGL(k_bt_wy<BT_CPW>, dim3((a.kmax + BT_CPW - 1) / BT_CPW, a.batch), dim3(256),
-                       ldsx, st, a);
+    hipLaunchKernelGGL(k_bt_wy<BT_CPW>, dim3((a.kmax + BT_CPW - 1) / BT_CPW, a.batch),
+                       dim3(BT_THREADS), ldsx, st, a);
   } else if (a.s <= 64) {
     hipLaunchKernelGGL((k_backtransform<1, 4>), gb, dim3(256), 0, st, a);
   } else if (a.s <= 128) {
