@@ -14,7 +14,7 @@
 //      15 waves apply the rank-2 update (again 8 lanes per row), wave 0 updates the next column
 //      itself and forms its reflector (look-ahead), so a column costs two workgroup barriers.
 //      Larger s use k_tridiag_mw: the rows are spread over many workgroups (held in registers)
-//      and every column costs one grid-wide barrier.
+//      and every column costs one grid-wide barrier; its last 128 columns are left to k_tridiag.
 //   2. k_eigvals, one wave per eigenvalue over many workgroups: multisection on Sturm counts (64
 //      points of the current interval per round).
 //   3. eigenvectors of T by a twisted factorisation T - lambda I = N_r Delta N_r^T, one wave per
