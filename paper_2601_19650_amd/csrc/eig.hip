@@ -531,6 +531,19 @@ __device__ bool mw_sync(unsigned* sync, int nwg, unsigned it, int* ok_sh, long l
 
 // Block-wide sum of every thread's complex value in a fixed order; `red` holds one slot per wave and
 // is read by every thread after the caller's next __syncthreads (sum_red below).
+// the same for a real value (the slot's imaginary part is not written)
+__device__ __forceinline__ void put_red_re(double re, double2* red) {
+  re = wave_sum(re);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6].x = re;
+}
+// the real part of sum_red
+template <int NW_>
+__device__ __forceinline__ double sum_red_re(const double2* red) {
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < NW_; ++q) t += red[q].x;
+  return t;
+}
 __device__ __forceinline__ void put_red(double re, double im, double2* red) {
   re = wave_sum(re);
   im = wave_sum(im);
@@ -616,9 +629,10 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg, 
     x[e] = c < s ? a.G[c] : make_double2(0.0, 0.0);
     if (c >= 2 && c < s) xn2 += x[e].x * x[e].x + x[e].y * x[e].y;
   }
-  put_red(xn2, 0.0, red_n);
+  put_red_re(xn2, red_n);
   __syncthreads();
-  double2 t = reflector(0, x, a.G[0], s > 1 ? a.G[1] : make_double2(0.0, 0.0), sum_red(red_n).x, v);
+  double2 t = reflector(0, x, a.G[0], s > 1 ? a.G[1] : make_double2(0.0, 0.0),
+                        sum_red_re<MW_WAVES>(red_n), v);
   // products of column 0 (rows r > 0), one pass over the rows
   auto products = [&](int j, const double2 vv[EPT]) {
 #pragma unroll
@@ -730,7 +744,7 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg, 
       if (c == j + 2) bc[2] = xv;
       if (c > j + 2 && c < s) xn2 += xv.x * xv.x + xv.y * xv.y;
     }
-    put_red(xn2, 0.0, red_n);
+    put_red_re(xn2, red_n);
     __syncthreads();
     if (j + 1 >= s - 1) {
       // the last diagonal entry; no reflector, no further column
@@ -745,7 +759,7 @@ __global__ __launch_bounds__(MW_THREADS) void k_tridiag_mw(EigArgs a0, int nwg, 
 #pragma unroll
       for (int e = 0; e < EPT; ++e) vn[e] = make_double2(0.0, 0.0);
     } else {
-      t1 = reflector(j + 1, x, bc[1], bc[2], sum_red(red_n).x, vn);
+      t1 = reflector(j + 1, x, bc[1], bc[2], sum_red_re<MW_WAVES>(red_n), vn);
     }
     lap(2);
     // (4) rank-2 update of the owned rows r > j+1 on the columns > j+1, the owner of row j+2
