@@ -384,7 +384,7 @@ static bool mw_size_supported(int s) {
          mw_shape(s).rows <= mw_rows_max((s + MW_THREADS - 1) / MW_THREADS);
 }
 // The one-stage multi-workgroup reduction is the faster one where it applies (measured on MI355X,
-// s = 1024: 7.1 ms against 25.6 ms for the two-stage path, per solve), but its workgroups wait for
+// s = 1024: 6.8 ms against 25.6 ms for the two-stage path, per solve), but its workgroups wait for
 // each other: it is used for single instances queued eagerly or in the library's own graphs, whose
 // launches the device-wide gate orders; batches and calls recorded into a caller's capture take the
 // two-stage path, which has no cross-workgroup waits.
